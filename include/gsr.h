@@ -1,0 +1,198 @@
+/*
+ * gsr.h -- C ABI of libgsr, a batched 3D Gaussian Splatting renderer for
+ * thousands of rigid-body simulation environments per step on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * What it renders: the batch renderer of GS-Playground (arXiv 2604.25459),
+ * Sec. "Batch Renderer Optimization" and Sec. "System Overview" (data flow:
+ * the physics engine's rigid-body poses drive Gaussian clusters through
+ * Rigid-Link Gaussian Kinematics, RLGK; the renderer returns RGB images and
+ * depth maps per environment).  The image model is standard 3D Gaussian
+ * Splatting (Kerbl et al. 2023, the representation the paper renders with;
+ * the renderer is built on gsplat): EWA projection, spherical-harmonic colour,
+ * tile binning by a (image, tile, depth) key sort, front-to-back alpha
+ * compositing with alpha = min(0.99, o exp(-q/2)), Gaussians below alpha 1/255
+ * skipped, pixels stopped once transmittance would fall below 1e-4.
+ *
+ * Conventions (fixed by this library where the paper is silent):
+ *   - world right-handed; cameras OpenCV style (x right, y down, z forward);
+ *     a viewmat is the 3x4 world->camera matrix [R | t], row-major floats;
+ *   - quaternions are (w, x, y, z), normalised on use;
+ *   - scales are linear (> 0), opacities are activated values in [0, 1];
+ *   - body poses are world-from-body (qw, qx, qy, qz, tx, ty, tz);
+ *   - Gaussian index g = storage order: static background first, then the
+ *     Gaussians of body 0, body 1, ... (ranges given by body_offsets);
+ *   - pixel (x, y) has its centre at (x + 0.5, y + 0.5);
+ *   - images are ordered camera-slot-major: image i = c * n_envs + e.
+ *
+ * Threading: a context may be used from several host threads; calls on one
+ * context are serialised internally except gsr_submit / gsr_wait of a server.
+ *
+ * Errors: every call returns GSR_OK (0) or a negative GSR_E_* code.  Arguments
+ * are validated before any device work is enqueued; on failure nothing is
+ * enqueued and gsr_last_error() (per host thread) describes the problem.  An
+ * asynchronous device fault is sticky: the context reports GSR_E_DEVICE from
+ * then on.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSR_OK 0
+#define GSR_E_INVALID (-1)   /* bad argument (null pointer, size, degree, ...) */
+#define GSR_E_OOM (-2)       /* device or host allocation failed */
+#define GSR_E_DEVICE (-3)    /* no gfx950 device, or a HIP call failed */
+#define GSR_E_NOT_FOUND (-4) /* unknown scene id or ticket */
+#define GSR_E_BUSY (-5)      /* scene still referenced by in-flight work */
+#define GSR_E_REJECTED (-6)  /* request can never fit the server's memory budget */
+#define GSR_E_OVERFLOW (-7)  /* internal capacity exceeded (only surfaced if a retry fails) */
+#define GSR_E_TIMEOUT (-8)   /* gsr_wait timed out */
+
+#define GSR_STORAGE_F32 0    /* attributes and SH stored as float32 */
+#define GSR_STORAGE_F16 1    /* scales, rotations, opacity and SH as IEEE half; means stay float32 */
+#define GSR_STORAGE_BF16 2   /* same with bfloat16 */
+
+#define GSR_MEM_HOST 0       /* scene arrays are host pointers */
+#define GSR_MEM_DEVICE 1     /* scene arrays are device pointers on the context's device */
+
+typedef struct gsr_ctx gsr_ctx;
+typedef struct gsr_server gsr_server;
+
+/* Context options; zero-initialise for defaults. */
+typedef struct {
+    int tile_size;          /* 8, 16 or 32 pixels; 0 = 16 */
+    int images_per_thread;  /* images one projection thread handles (1..16); 0 = 4 */
+    int64_t chunk_bytes;    /* device working-memory budget per render chunk; 0 = 24 GiB */
+    float cutoff;           /* splat radius in standard deviations; 0 = 3.33 (conservative for alpha >= 1/255) */
+    int profile;            /* 1 = record HIP events around every pipeline stage (see gsr_stage_times) */
+    int reserved[7];
+} gsr_options;
+
+/* A scene: static background plus Gaussian clusters bound to rigid bodies
+ * (RLGK, Sec. "Batch Renderer Optimization").  All arrays are float32,
+ * row-major, of the given shapes. */
+typedef struct {
+    int64_t n;                    /* Gaussians, >= 0 */
+    int sh_degree;                /* 0..3; K = (sh_degree + 1)^2 coefficients per channel */
+    int storage;                  /* GSR_STORAGE_* */
+    int mem_kind;                 /* GSR_MEM_HOST or GSR_MEM_DEVICE for the arrays below */
+    int n_bodies;                 /* B >= 0 */
+    const float* means;           /* [n][3]; body Gaussians in their body frame */
+    const float* scales;          /* [n][3] */
+    const float* quats;           /* [n][4] (w, x, y, z) */
+    const float* opacities;       /* [n] */
+    const float* sh;              /* [n][K][3] (coefficient-major, channel-minor) */
+    const int64_t* body_offsets;  /* host, [B + 1]: [0, off[0]) static, body b owns [off[b], off[b+1]), off[B] = n */
+} gsr_scene_desc;
+
+/* One camera slot.  Every environment has one camera per slot; slots may
+ * differ in resolution and intrinsics. */
+typedef struct {
+    int width, height;            /* pixels, 1..8192 */
+    float fx, fy, cx, cy;         /* pinhole intrinsics in pixels */
+    float near_plane;             /* Gaussians with camera depth <= near_plane are culled; > 0 */
+} gsr_camera;
+
+/* One render call: n_envs environments x n_cams camera slots. */
+typedef struct {
+    uint64_t scene_id;
+    int n_envs;                   /* E >= 1 */
+    int n_cams;                   /* C, 1..8 */
+    const gsr_camera* cams;       /* host, [C] */
+    const float* viewmats;        /* device, [C][E][3][4] world->camera */
+    const float* body_poses;      /* device, [E][B][7] world-from-body; may be NULL when B = 0 */
+    float bg[3];                  /* background colour */
+    float* out_rgb;               /* device; slot c is a contiguous [E][H_c][W_c][3] block, slots in order */
+    float* out_depth;             /* device; slot c is [E][H_c][W_c]; normalised expected depth, 0 where empty */
+    float* out_alpha;             /* device, optional (NULL): 1 - final transmittance, same layout as depth */
+} gsr_render_desc;
+
+/* Materialised binning of one image (for parity checks). */
+typedef struct {
+    int64_t capacity;             /* in: entries available in keys / values */
+    uint64_t* keys;               /* host, [capacity]: (global tile << 32) | float32 bits of depth */
+    uint32_t* values;             /* host, [capacity]: Gaussian index g */
+    uint32_t* ranges;             /* host, [tiles][2]: [start, end) of each tile of the image in keys/values; may be NULL */
+    int64_t ranges_capacity;      /* in: tiles available in ranges */
+    int64_t n_pairs;              /* out */
+    int64_t n_visible;            /* out */
+    int32_t tiles_x, tiles_y;     /* out */
+    int64_t tile_base;            /* out: global tile id of the image's first tile */
+} gsr_bins_out;
+
+/* Per-Gaussian projection of one image (for parity checks).  Host arrays of
+ * the scene's n entries. */
+typedef struct {
+    int64_t n;                    /* in: must equal the scene's Gaussian count */
+    uint32_t* zkey;               /* [n] float32 bits of camera depth; 0xFFFFFFFF where culled */
+    int32_t* rect;                /* [n][4] tile rectangle x0, x1, y0, y1 (half-open); unspecified where culled */
+    float* rec;                   /* [n][12] u, v, A, B, C, log2(o), z, r, R, G, B, 0 where
+                                     log2(alpha) = A dx^2 + B dx dy + C dy^2 + log2(o); unspecified where culled */
+} gsr_proj_out;
+
+/* ---- context ---------------------------------------------------------
+ * gsr_create: opens `device` (HIP ordinal), which must be a gfx950 GPU
+ * (GSR_E_DEVICE otherwise).  `opt` may be NULL.  The library owns the context,
+ * its scenes and working memory.  gsr_destroy waits for in-flight work and
+ * frees everything the context owns; NULL is accepted. */
+int gsr_create(int device, const gsr_options* opt, gsr_ctx** out);
+int gsr_destroy(gsr_ctx* ctx);
+
+/* ---- scenes ----------------------------------------------------------
+ * gsr_scene_create copies the caller's arrays into device memory in the
+ * requested storage format and returns an id; the caller may free its arrays
+ * when the call returns (it synchronises with the copy).  Validation: n >= 0,
+ * sh_degree in 0..3, storage and mem_kind known, non-NULL arrays when n > 0,
+ * body_offsets non-decreasing with off[B] = n.
+ * gsr_scene_destroy frees a scene; GSR_E_BUSY if a render using it is still
+ * in flight, GSR_E_NOT_FOUND for an unknown id. */
+int gsr_scene_create(gsr_ctx* ctx, const gsr_scene_desc* desc, uint64_t* scene_id);
+int gsr_scene_destroy(gsr_ctx* ctx, uint64_t scene_id);
+/* Gaussians and bodies of a resident scene, and its resident size in bytes. */
+int gsr_scene_info(gsr_ctx* ctx, uint64_t scene_id, int64_t* n, int* n_bodies, int64_t* bytes);
+
+/* ---- rendering -------------------------------------------------------
+ * gsr_render: renders every (camera slot, env) image of `desc` on `stream`
+ * (a hipStream_t; NULL = default stream).  Images of all slots go through one
+ * batched pipeline: RLGK posing + EWA projection + SH colour, a segmented
+ * depth radix sort, stable tile binning, and one rasterisation launch per
+ * memory chunk.  Inputs and outputs are caller-owned device memory and must
+ * stay valid until the stream passes this call.  The call blocks the host
+ * thread once per chunk until that chunk's pair count is known (to size the
+ * tile lists), then returns with rasterisation still in flight.
+ * gsr_render_plain: same contract and results, one image at a time (one
+ * launch chain per image, per-image sort): the reference per-environment path. */
+int gsr_render(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
+int gsr_render_plain(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
+
+/* Binning and projection of image `image` (camera-slot-major index) of
+ * `desc`, copied to host arrays.  Synchronous.  Output pointers of `desc` are
+ * not used.  GSR_E_INVALID if out->capacity is smaller than the number of
+ * pairs (n_pairs is still reported). */
+int gsr_debug_bins(gsr_ctx* ctx, const gsr_render_desc* desc, int image, gsr_bins_out* out);
+int gsr_debug_project(gsr_ctx* ctx, const gsr_render_desc* desc, int image, gsr_proj_out* out);
+
+/* Stage timers of a context created with profile = 1: device milliseconds
+ * accumulated over the renders since the last reset, measured with HIP events
+ * recorded on the render stream.  ms[0] compose + project, ms[1] depth sort,
+ * ms[2] tile count, ms[3] tile scatter, ms[4] raster, ms[5] launches of the
+ * raster kernel, ms[6] renders timed.  `n` is the capacity of `ms` (>= 7).
+ * Waits for the timed work to finish.  reset = 1 clears the accumulators. */
+int gsr_stage_times(gsr_ctx* ctx, double* ms, int n, int reset);
+
+/* Description of the last error on this host thread ("" if none). */
+const char* gsr_last_error(void);
+/* Library version string. */
+const char* gsr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

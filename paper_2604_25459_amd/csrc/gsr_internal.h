@@ -1,0 +1,119 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libgsr (batched 3D Gaussian Splatting for rigid-body environments).
+//
+// Every file of the library is compiled with -ffp-contract=off: the binning
+// arithmetic (projection, culls, radius, tile rectangle, depth key) is
+// specified operation by operation in IEEE binary32 so that sort keys and tile
+// lists are reproducible bit for bit.  Kernels that want fused multiply-adds
+// (the rasteriser) call fmaf() explicitly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsr {
+
+constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;  // depth-key slot of a culled Gaussian
+constexpr int kMaxShDegree = 3;
+
+// Attribute storage formats of a resident scene.
+enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
+
+// Per-image description inside one launch chunk (device resident).
+struct ImageInfo {
+    int width, height;
+    int tiles_x, tiles_y;
+    float fx, fy, cx, cy, near_plane;
+    int cam;              // camera slot c
+    int env;              // environment e
+    int pad0;
+    uint32_t key_tile_base;   // first global tile id of the image in the whole batch (sort keys)
+    uint32_t pad1;
+    uint64_t out_pixel;   // index of the image's first pixel in the caller's output (camera-slot-major)
+};
+
+// Resident scene, device pointers.
+struct SceneDev {
+    int64_t n;            // Gaussians
+    int64_t n_pad;        // plane stride (n rounded up to 64)
+    int degree;           // SH degree 0..3
+    int storage;          // Storage
+    int n_bodies;
+    int sh_chunks;        // 16-byte chunks of SH per Gaussian
+    const float4* pos;    // [n] (x, y, z, opacity); means are always float32
+    const void* rot;      // F32: float4 quaternion [n]; F16/BF16: uint4 = 8 halves (qw qx qy qz sx sy sz 0) [n]
+    const float4* scale;  // F32 only: (sx, sy, sz, 0) [n]
+    const void* sh;       // planes [sh_chunks][n_pad] of 16 bytes
+    const int* body_off;  // [n_bodies + 1] (int32): [0, off[0]) static, body b = [off[b], off[b+1])
+};
+
+// Segment of the chunk that shares one camera slot (uniform resolution).
+struct RasterSeg {
+    uint32_t first_tile;   // first block id of the segment
+    uint32_t first_image;  // first chunk-local image
+    uint32_t n_images;
+    uint32_t tiles_per_image;
+};
+constexpr int kMaxSegs = 8;
+
+// Per-chunk device buffers and sizes handed to the kernels.
+struct ChunkDev {
+    uint64_t n;                // Gaussians of the scene (dense row length)
+    int n_img;
+    int t_max;                 // largest tile count of an image in the chunk
+    int sort_blocks;           // depth-sort blocks per image (pass 0: ceil(n / kSortItems))
+    int tile_blocks;           // tile-pass blocks per image (ceil(n / kTileGauss))
+    const ImageInfo* img;      // [n_img]
+    float* xform;              // [n_img][n_bodies + 1][16]
+    uint32_t* keyz;            // [n_img][n] depth bits or kInvalidKey
+    uint2* rect;               // [n_img][n] (x0 | x1 << 16, y0 | y1 << 16)
+    float4* rec;               // [n_img][n][3] raster records
+    uint32_t* sk[2];           // depth-sort keys, ping-pong [n_img][n]
+    uint32_t* sv[2];           // depth-sort values (Gaussian ids)
+    uint32_t* sort_hist;       // [n_img][sort_blocks][256]
+    uint32_t* vis_count;       // [n_img] visible Gaussians V_i
+    uint32_t* tile_hist;       // [n_img][tile_blocks][t_max] counts, then offsets
+    uint32_t* tile_range;      // [n_img][t_max][2] local [start, end)
+    uint32_t* pair_count;      // [n_img] P_i
+    uint64_t* pair_base;       // [n_img + 1] exclusive prefix of P_i (last = total)
+    uint32_t* pairs;           // [total pairs] Gaussian id per (tile, depth)-sorted entry
+};
+
+// Depth sort geometry.
+constexpr int kSortBlock = 256;
+constexpr int kSortIpt = 8;
+constexpr int kSortItems = kSortBlock * kSortIpt;   // 2048 items per block
+// Tile pass geometry: one wave per block, kTileGauss depth-ordered Gaussians per block.
+constexpr int kTileGauss = 4096;
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `stream` and return hipGetLastError().
+hipError_t launch_compose(const SceneDev& s, const ChunkDev& c, const float* viewmats, const float* poses,
+                          int n_envs_total, hipStream_t stream);
+hipError_t launch_project(const SceneDev& s, const ChunkDev& c, int ts, float cutoff, int img_per_thread,
+                          hipStream_t stream);
+hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
+hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
+hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
+struct RasterParams {
+    int ts;
+    int n_segs;
+    RasterSeg segs[kMaxSegs];
+    uint32_t n_blocks;
+    float bg[3];
+    float* out_rgb;
+    float* out_depth;
+    float* out_alpha;      // may be null
+};
+hipError_t launch_raster(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream);
+
+// Scene upload: convert caller float32 attributes to resident storage.
+hipError_t launch_scene_convert(int storage, int64_t n, int64_t n_pad, int degree, const float* means,
+                                const float* scales, const float* quats, const float* opac, const float* sh,
+                                float4* pos, void* rot, float4* scale, void* sh_planes, hipStream_t stream);
+
+// Debug: 64-bit keys of one image from its sorted pairs.
+hipError_t launch_debug_keys(const ChunkDev& c, int image, uint64_t n, const uint32_t* pairs, uint64_t n_pairs,
+                             uint64_t* keys_out, hipStream_t stream);
+
+}  // namespace gsr

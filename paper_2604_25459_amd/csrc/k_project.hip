@@ -1,0 +1,408 @@
+// Rigid-link posing, EWA projection, culling, tile rectangle and spherical-
+// harmonic colour of every (image, Gaussian) pair.
+//
+// Posing follows the paper's Rigid-Link Gaussian Kinematics (Sec. "Batch
+// Renderer Optimization"): a Gaussian cluster bound to a rigid body moves with
+// that body, so its camera-from-local transform is A = R_c R(q_b),
+// a = R_c t_b + t_c (static background: A = R_c, a = t_c).  Projection is the
+// standard 3D Gaussian Splatting / EWA model the paper renders with.
+//
+// The binning quantities are computed in the library's binary32
+// specification: one rounding per operation (this file is compiled with
+// -ffp-contract=off), sums left to right, correctly rounded division and
+// square root, constants as float literals.
+#include "gsr_internal.h"
+
+#include <hip/hip_fp16.h>
+
+namespace gsr {
+namespace {
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ float f16_to_f32(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+
+// Round-to-nearest-even float32 -> bfloat16 bits (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ uint16_t f32_to_f16(float f) { return __half_as_ushort(__float2half_rn(f)); }
+
+template <int ST>
+__device__ __forceinline__ float decode(uint16_t h)
+{
+    return ST == kBF16 ? bf16_to_f32(h) : f16_to_f32(h);
+}
+template <int ST>
+__device__ __forceinline__ uint16_t encode(float f)
+{
+    return ST == kBF16 ? f32_to_bf16(f) : f32_to_f16(f);
+}
+
+// Rotation matrix of a (w, x, y, z) quaternion, normalised first (spec).
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float R[9])
+{
+    const float n = sqrtf(((w * w + x * x) + y * y) + z * z);
+    w = w / n;
+    x = x / n;
+    y = y / n;
+    z = z / n;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float xy = x * y, xz = x * z, yz = y * z;
+    const float wx = w * x, wy = w * y, wz = w * z;
+    R[0] = 1.0f - 2.0f * (yy + zz);
+    R[1] = 2.0f * (xy - wz);
+    R[2] = 2.0f * (xz + wy);
+    R[3] = 2.0f * (xy + wz);
+    R[4] = 1.0f - 2.0f * (xx + zz);
+    R[5] = 2.0f * (yz - wx);
+    R[6] = 2.0f * (xz - wy);
+    R[7] = 2.0f * (yz + wx);
+    R[8] = 1.0f - 2.0f * (xx + yy);
+}
+
+// C = A B for row-major 3x3, each entry ((a0 b0 + a1 b1) + a2 b2).
+__device__ __forceinline__ void mat3_mul(const float A[9], const float B[9], float C[9])
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = (A[3 * i + 0] * B[0 + j] + A[3 * i + 1] * B[3 + j]) + A[3 * i + 2] * B[6 + j];
+}
+
+// ---------------------------------------------------------------- compose
+// One thread per (image, body slot).  xform row: A (9, row-major), a (3),
+// camera centre expressed in the slot's local frame (3), unused (1).
+__global__ __launch_bounds__(256) void k_compose(SceneDev s, ChunkDev c, const float* __restrict__ viewmats,
+                                                 const float* __restrict__ poses, int n_envs_total)
+{
+    const int slots = s.n_bodies + 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= c.n_img * slots) return;
+    const int i = idx / slots;
+    const int slot = idx - i * slots;
+    const ImageInfo im = c.img[i];
+    const float* vm = viewmats + ((size_t)im.cam * n_envs_total + im.env) * 12;
+    const float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
+    const float tc[3] = {vm[3], vm[7], vm[11]};
+    // camera centre in world: C = -R_c^T t_c (continuous quantity, colour only)
+    const float Cw[3] = {-(Rc[0] * tc[0] + Rc[3] * tc[1] + Rc[6] * tc[2]),
+                         -(Rc[1] * tc[0] + Rc[4] * tc[1] + Rc[7] * tc[2]),
+                         -(Rc[2] * tc[0] + Rc[5] * tc[1] + Rc[8] * tc[2])};
+    float* out = c.xform + (size_t)idx * 16;
+    if (slot == 0) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[k] = Rc[k];
+        out[9] = tc[0];
+        out[10] = tc[1];
+        out[11] = tc[2];
+        out[12] = Cw[0];
+        out[13] = Cw[1];
+        out[14] = Cw[2];
+        out[15] = 0.0f;
+        return;
+    }
+    const float* p = poses + ((size_t)im.env * s.n_bodies + (slot - 1)) * 7;
+    float Rb[9], A[9];
+    quat_rot(p[0], p[1], p[2], p[3], Rb);
+    mat3_mul(Rc, Rb, A);
+    const float tb[3] = {p[4], p[5], p[6]};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k] = A[k];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        out[9 + r] = ((Rc[3 * r + 0] * tb[0] + Rc[3 * r + 1] * tb[1]) + Rc[3 * r + 2] * tb[2]) + tc[r];
+    // camera centre in the body frame: R_b^T (C - t_b)
+    const float d[3] = {Cw[0] - tb[0], Cw[1] - tb[1], Cw[2] - tb[2]};
+    out[12] = Rb[0] * d[0] + Rb[3] * d[1] + Rb[6] * d[2];
+    out[13] = Rb[1] * d[0] + Rb[4] * d[1] + Rb[7] * d[2];
+    out[14] = Rb[2] * d[0] + Rb[5] * d[1] + Rb[8] * d[2];
+    out[15] = 0.0f;
+}
+
+// ---------------------------------------------------------------- SH colour
+// Real SH up to degree 3 in the coefficient order used by 3DGS (real
+// harmonics with the Condon-Shortley phase, m = -l..l within each band).
+template <int DEG>
+__device__ __forceinline__ void sh_rgb(const float* f, float x, float y, float z, float rgb[3])
+{
+    constexpr float kC0 = 0.28209479177387814f;     // 1/(2 sqrt(pi))
+    constexpr float kC1 = 0.48860251190291992f;     // sqrt(3)/(2 sqrt(pi))
+    float Y[16];
+    Y[0] = kC0;
+    if (DEG >= 1) {
+        Y[1] = -kC1 * y;
+        Y[2] = kC1 * z;
+        Y[3] = -kC1 * x;
+    }
+    if (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = 1.0925484305920792f * x * y;                     // sqrt(15)/(2 sqrt(pi))
+        Y[5] = -1.0925484305920792f * y * z;
+        Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);    // sqrt(5)/(4 sqrt(pi))
+        Y[7] = -1.0925484305920792f * x * z;
+        Y[8] = 0.54627421529603959f * (xx - yy);                // sqrt(15)/(4 sqrt(pi))
+        if (DEG >= 3) {
+            Y[9] = -0.59004358992664352f * y * (3.0f * xx - yy);        // sqrt(35/2)/(4 sqrt(pi))
+            Y[10] = 2.8906114426405538f * x * y * z;                    // sqrt(105)/(2 sqrt(pi))
+            Y[11] = -0.45704579946446572f * y * (4.0f * zz - xx - yy);  // sqrt(21/2)/(4 sqrt(pi))
+            Y[12] = 0.37317633259011540f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);   // sqrt(7)/(4 sqrt(pi))
+            Y[13] = -0.45704579946446572f * x * (4.0f * zz - xx - yy);
+            Y[14] = 1.4453057213202769f * z * (xx - yy);                // sqrt(105)/(4 sqrt(pi))
+            Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
+        }
+    }
+    constexpr int K = (DEG + 1) * (DEG + 1);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.5f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc = fmaf(Y[k], f[3 * k + ch], acc);
+        rgb[ch] = fmaxf(acc, 0.0f);
+    }
+}
+
+// ---------------------------------------------------------------- project
+// Grid: x = Gaussian blocks of 256, y = groups of `ipt` images.  A thread loads
+// its Gaussian once and projects it into each image of its group.
+template <int ST, int DEG>
+__global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts, float cutoff, int ipt)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= s.n) return;
+    const int i_begin = blockIdx.y * ipt;
+
+    int slot = 0;
+    if (s.n_bodies > 0 && g >= s.body_off[0]) {
+        int lo = 0, hi = s.n_bodies - 1;        // largest b with off[b] <= g
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s.body_off[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        slot = lo + 1;
+    }
+
+    const float4 pm = s.pos[g];
+    float q[4], sc[3];
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    float f[3 * K];
+    if (ST == kF32) {
+        const float4 qq = ((const float4*)s.rot)[g];
+        const float4 ss = s.scale[g];
+        q[0] = qq.x; q[1] = qq.y; q[2] = qq.z; q[3] = qq.w;
+        sc[0] = ss.x; sc[1] = ss.y; sc[2] = ss.z;
+        const float4* planes = (const float4*)s.sh;
+        constexpr int NCH = (3 * K + 3) / 4;
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            const float4 v = planes[(size_t)j * s.n_pad + g];
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (4 * j + k < 3 * K) f[4 * j + k] = vv[k];
+        }
+    } else {
+        const uint4 hq = ((const uint4*)s.rot)[g];
+        q[0] = decode<ST>(hq.x & 0xFFFF); q[1] = decode<ST>(hq.x >> 16);
+        q[2] = decode<ST>(hq.y & 0xFFFF); q[3] = decode<ST>(hq.y >> 16);
+        sc[0] = decode<ST>(hq.z & 0xFFFF); sc[1] = decode<ST>(hq.z >> 16);
+        sc[2] = decode<ST>(hq.w & 0xFFFF);
+        const uint4* planes = (const uint4*)s.sh;
+        constexpr int NCH = (3 * K + 7) / 8;
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            const uint4 v = planes[(size_t)j * s.n_pad + g];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (8 * j + k < 3 * K) f[8 * j + k] = decode<ST>((uint16_t)(w[k >> 1] >> (16 * (k & 1))));
+        }
+    }
+    float Rg[9];
+    quat_rot(q[0], q[1], q[2], q[3], Rg);
+    const float mu[3] = {pm.x, pm.y, pm.z};
+    const float op = pm.w;
+    const float alpha_min = 1.0f / 255.0f;
+    const float tsf = (float)ts;
+
+    for (int ii = 0; ii < ipt; ++ii) {
+        const int i = i_begin + ii;
+        if (i >= c.n_img) break;
+        const ImageInfo im = c.img[i];
+        const float* X = c.xform + ((size_t)i * (s.n_bodies + 1) + slot) * 16;
+        float A[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) A[k] = X[k];
+        const float tx = ((A[0] * mu[0] + A[1] * mu[1]) + A[2] * mu[2]) + X[9];
+        const float ty = ((A[3] * mu[0] + A[4] * mu[1]) + A[5] * mu[2]) + X[10];
+        const float tz = ((A[6] * mu[0] + A[7] * mu[1]) + A[8] * mu[2]) + X[11];
+
+        float M[9];
+        mat3_mul(A, Rg, M);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) M[3 * r + k] = M[3 * r + k] * sc[k];
+
+        const float fx = im.fx, fy = im.fy;
+        const float lx = 1.3f * ((0.5f * (float)im.width) / fx);
+        const float ly = 1.3f * ((0.5f * (float)im.height) / fy);
+        const float xcl = fminf(lx, fmaxf(-lx, tx / tz)) * tz;
+        const float ycl = fminf(ly, fmaxf(-ly, ty / tz)) * tz;
+        const float tz2 = tz * tz;
+        const float j00 = fx / tz;
+        const float j02 = -((fx * xcl) / tz2);
+        const float j11 = fy / tz;
+        const float j12 = -((fy * ycl) / tz2);
+        float v1[3], v2[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v1[k] = j00 * M[k] + j02 * M[6 + k];
+            v2[k] = j11 * M[3 + k] + j12 * M[6 + k];
+        }
+        const float n1 = (v1[0] * v1[0] + v1[1] * v1[1]) + v1[2] * v1[2];
+        const float n2 = (v2[0] * v2[0] + v2[1] * v2[1]) + v2[2] * v2[2];
+        const float ca = n1 + 0.3f;
+        const float cc = n2 + 0.3f;
+        const float cb = (v1[0] * v2[0] + v1[1] * v2[1]) + v1[2] * v2[2];
+        const float w0 = v1[1] * v2[2] - v1[2] * v2[1];
+        const float w1 = v1[2] * v2[0] - v1[0] * v2[2];
+        const float w2 = v1[0] * v2[1] - v1[1] * v2[0];
+        const float det = (((w0 * w0 + w1 * w1) + w2 * w2) + 0.3f * (n1 + n2)) + 0.09f;
+        const float m = 0.5f * (ca + cc);
+        const float h = 0.5f * (ca - cc);
+        const float lam = m + sqrtf(fmaxf(0.1f, h * h + cb * cb));
+        const float r = ceilf(cutoff * sqrtf(lam));
+        const float u = (fx * tx) / tz + im.cx;
+        const float v = (fy * ty) / tz + im.cy;
+        const float x0 = fminf(fmaxf(floorf((u - r) / tsf), 0.0f), (float)im.tiles_x);
+        const float x1 = fminf(fmaxf(floorf((u + r) / tsf) + 1.0f, 0.0f), (float)im.tiles_x);
+        const float y0 = fminf(fmaxf(floorf((v - r) / tsf), 0.0f), (float)im.tiles_y);
+        const float y1 = fminf(fmaxf(floorf((v + r) / tsf) + 1.0f, 0.0f), (float)im.tiles_y);
+
+        bool vis = isfinite(tx) && isfinite(ty) && isfinite(tz) && tz > im.near_plane && op >= alpha_min &&
+                   isfinite(det) && det > 0.0f && isfinite(r) && isfinite(u) && isfinite(v);
+        const int ix0 = vis ? (int)x0 : 0, ix1 = vis ? (int)x1 : 0;
+        const int iy0 = vis ? (int)y0 : 0, iy1 = vis ? (int)y1 : 0;
+        vis = vis && ix1 > ix0 && iy1 > iy0;
+
+        const size_t o = (size_t)i * (size_t)s.n + (size_t)g;
+        c.keyz[o] = vis ? __float_as_uint(tz) : kInvalidKey;
+        if (!vis) continue;
+        c.rect[o] = make_uint2((uint32_t)ix0 | ((uint32_t)ix1 << 16), (uint32_t)iy0 | ((uint32_t)iy1 << 16));
+
+        // Raster record: conic pre-scaled so that log2(alpha) = p + log2(o)
+        // with p = A dx^2 + B dx dy + C dy^2.
+        const float ica = cc / det, icb = -cb / det, icc = ca / det;
+        constexpr float kLog2e = 1.4426950408889634f;
+        float rgb[3];
+        {
+            float dx = mu[0] - X[12], dy = mu[1] - X[13], dz = mu[2] - X[14];
+            const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            sh_rgb<DEG>(f, dx * inv, dy * inv, dz * inv, rgb);
+        }
+        float4* rec = c.rec + 3 * o;
+        rec[0] = make_float4(u, v, -0.5f * kLog2e * ica, -kLog2e * icb);
+        rec[1] = make_float4(-0.5f * kLog2e * icc, log2f(op), tz, r);
+        rec[2] = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+    }
+}
+
+// ---------------------------------------------------------------- scene upload
+template <int ST>
+__global__ __launch_bounds__(256) void k_scene_convert(int64_t n, int64_t n_pad, int degree, const float* means,
+                                                       const float* scales, const float* quats, const float* opac,
+                                                       const float* sh, float4* pos, void* rot, float4* scale,
+                                                       void* sh_planes)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n) return;
+    const int K = (degree + 1) * (degree + 1);
+    const float* f = sh + (size_t)g * 3 * K;
+    if (ST == kF32) {
+        pos[g] = make_float4(means[3 * g], means[3 * g + 1], means[3 * g + 2], opac[g]);
+        ((float4*)rot)[g] = make_float4(quats[4 * g], quats[4 * g + 1], quats[4 * g + 2], quats[4 * g + 3]);
+        scale[g] = make_float4(scales[3 * g], scales[3 * g + 1], scales[3 * g + 2], 0.0f);
+        const int nch = (3 * K + 3) / 4;
+        for (int j = 0; j < nch; ++j) {
+            float v[4];
+            for (int k = 0; k < 4; ++k) v[k] = (4 * j + k < 3 * K) ? f[4 * j + k] : 0.0f;
+            ((float4*)sh_planes)[(size_t)j * n_pad + g] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+    } else {
+        const uint16_t hop = encode<ST>(opac[g]);
+        pos[g] = make_float4(means[3 * g], means[3 * g + 1], means[3 * g + 2], decode<ST>(hop));
+        uint16_t h[8];
+        for (int k = 0; k < 4; ++k) h[k] = encode<ST>(quats[4 * g + k]);
+        for (int k = 0; k < 3; ++k) h[4 + k] = encode<ST>(scales[3 * g + k]);
+        h[7] = 0;
+        ((uint4*)rot)[g] = make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
+                                      h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
+        const int nch = (3 * K + 7) / 8;
+        for (int j = 0; j < nch; ++j) {
+            uint32_t w[4];
+            for (int k = 0; k < 4; ++k) {
+                const int a = 8 * j + 2 * k, b = a + 1;
+                const uint16_t lo = a < 3 * K ? encode<ST>(f[a]) : 0;
+                const uint16_t hi = b < 3 * K ? encode<ST>(f[b]) : 0;
+                w[k] = lo | ((uint32_t)hi << 16);
+            }
+            ((uint4*)sh_planes)[(size_t)j * n_pad + g] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_compose(const SceneDev& s, const ChunkDev& c, const float* viewmats, const float* poses,
+                          int n_envs_total, hipStream_t stream)
+{
+    const int total = c.n_img * (s.n_bodies + 1);
+    hipLaunchKernelGGL(k_compose, dim3((total + 255) / 256), dim3(256), 0, stream, s, c, viewmats, poses,
+                       n_envs_total);
+    return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t project_st(const SceneDev& s, const ChunkDev& c, int ts, float cutoff, int ipt, hipStream_t st)
+{
+    const dim3 grid((unsigned)((s.n + 255) / 256), (unsigned)((c.n_img + ipt - 1) / ipt));
+    switch (s.degree) {
+    case 0: hipLaunchKernelGGL((k_project<ST, 0>), grid, dim3(256), 0, st, s, c, ts, cutoff, ipt); break;
+    case 1: hipLaunchKernelGGL((k_project<ST, 1>), grid, dim3(256), 0, st, s, c, ts, cutoff, ipt); break;
+    case 2: hipLaunchKernelGGL((k_project<ST, 2>), grid, dim3(256), 0, st, s, c, ts, cutoff, ipt); break;
+    default: hipLaunchKernelGGL((k_project<ST, 3>), grid, dim3(256), 0, st, s, c, ts, cutoff, ipt); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const SceneDev& s, const ChunkDev& c, int ts, float cutoff, int ipt, hipStream_t stream)
+{
+    if (s.n == 0 || c.n_img == 0) return hipSuccess;
+    if (s.storage == kF16) return project_st<kF16>(s, c, ts, cutoff, ipt, stream);
+    if (s.storage == kBF16) return project_st<kBF16>(s, c, ts, cutoff, ipt, stream);
+    return project_st<kF32>(s, c, ts, cutoff, ipt, stream);
+}
+
+hipError_t launch_scene_convert(int storage, int64_t n, int64_t n_pad, int degree, const float* means,
+                                const float* scales, const float* quats, const float* opac, const float* sh,
+                                float4* pos, void* rot, float4* scale, void* sh_planes, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (storage == kF16)
+        hipLaunchKernelGGL(k_scene_convert<kF16>, grid, dim3(256), 0, stream, n, n_pad, degree, means, scales,
+                           quats, opac, sh, pos, rot, scale, sh_planes);
+    else if (storage == kBF16)
+        hipLaunchKernelGGL(k_scene_convert<kBF16>, grid, dim3(256), 0, stream, n, n_pad, degree, means, scales,
+                           quats, opac, sh, pos, rot, scale, sh_planes);
+    else
+        hipLaunchKernelGGL(k_scene_convert<kF32>, grid, dim3(256), 0, stream, n, n_pad, degree, means, scales,
+                           quats, opac, sh, pos, rot, scale, sh_planes);
+    return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -1,0 +1,202 @@
+// Segmented, stable LSD radix sort of each image's visible Gaussians by the
+// 32-bit pattern of their camera-space depth (the low word of the 64-bit
+// (tile, depth) key; depth > near > 0, so the float bits order like the
+// values).  Values are Gaussian indices.  Pass 0 reads the dense per-image
+// key array in index order and drops culled entries, so equal depths keep
+// ascending index -- the tie rule of the key sort.
+//
+// Per pass (8-bit digit): a histogram kernel, a per-image scan kernel and a
+// scatter kernel.  No block waits on another block.  Local ranks inside a
+// block are stable: each wave owns a contiguous quarter of the block's items,
+// walks it in order 64 items at a time, and ranks equal digits with a ballot
+// match (peers = lanes with the same digit) and a per-wave running counter in
+// LDS.
+#include "gsr_internal.h"
+
+namespace gsr {
+namespace {
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const int lane = __lane_id();
+    return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// Lanes whose `key` equals this lane's, among lanes with `active` set.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_bits(uint32_t key, bool active)
+{
+    uint64_t peers = __ballot(active);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const bool bit = (key >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+// Exclusive scan over the 256 threads of a block; returns the block total.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* total, uint32_t* lds8)
+{
+    const int lane = __lane_id();
+    const int w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds8[w] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t s = lds8[k];
+        if (k < w) pre += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ counts,
+                                                   uint64_t n, int shift, uint32_t* __restrict__ hist, int blocks)
+{
+    __shared__ uint32_t h[256];
+    const int i = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
+    const uint64_t cnt = FIRST ? n : counts[i];
+    const uint64_t base = (uint64_t)b * kSortItems;
+    if (base >= cnt) return;            // block-uniform: no barrier skipped by part of the block
+    h[tid] = 0;
+    __syncthreads();
+    const uint32_t* kin = keys + (size_t)i * n;
+#pragma unroll
+    for (int k = 0; k < kSortIpt; ++k) {
+        const uint64_t idx = base + (uint64_t)k * 256 + tid;
+        if (idx < cnt) {
+            const uint32_t key = kin[idx];
+            if (!FIRST || key != kInvalidKey) atomicAdd(&h[(key >> shift) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    hist[((size_t)i * blocks + b) * 256 + tid] = h[tid];
+}
+
+// Per image: digit-major, block-minor exclusive offsets (in place).  Pass 0
+// also records the number of visible Gaussians.
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, int blocks, uint32_t* __restrict__ counts,
+                                                   uint64_t n)
+{
+    __shared__ uint32_t lds8[8];
+    const int i = blockIdx.x, d = threadIdx.x;
+    const uint64_t cnt = FIRST ? n : counts[i];
+    const int nb = (int)((cnt + kSortItems - 1) / kSortItems);
+    uint32_t* H = hist + (size_t)i * blocks * 256;
+    uint32_t tot = 0;
+    for (int b = 0; b < nb; ++b) tot += H[(size_t)b * 256 + d];
+    uint32_t total;
+    uint32_t run = block_excl_scan256(tot, &total, lds8);
+    if (FIRST && d == 0) counts[i] = total;
+    for (int b = 0; b < nb; ++b) {
+        const uint32_t v = H[(size_t)b * 256 + d];
+        H[(size_t)b * 256 + d] = run;
+        run += v;
+    }
+}
+
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                      const uint32_t* __restrict__ counts, uint64_t n, int shift,
+                                                      const uint32_t* __restrict__ hist, int blocks)
+{
+    __shared__ uint32_t cnt[4][256];
+    const int i = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
+    const int w = tid >> 6, lane = __lane_id();
+    const uint64_t count = FIRST ? n : counts[i];
+    const uint64_t base = (uint64_t)b * kSortItems;
+    if (base >= count) return;          // block-uniform
+    const size_t seg = (size_t)i * n;
+
+    uint32_t key[kSortIpt], val[kSortIpt];
+    bool ok[kSortIpt];
+#pragma unroll
+    for (int k = 0; k < kSortIpt; ++k) {
+        const uint64_t idx = base + (uint64_t)w * (kSortIpt * 64) + (uint64_t)k * 64 + lane;
+        ok[k] = idx < count;
+        key[k] = ok[k] ? kin[seg + idx] : kInvalidKey;
+        if (FIRST) {
+            ok[k] = ok[k] && key[k] != kInvalidKey;
+            val[k] = (uint32_t)idx;
+        } else {
+            val[k] = ok[k] ? vin[seg + idx] : 0u;
+        }
+    }
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) cnt[ww][tid] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortIpt; ++k)
+        if (ok[k]) atomicAdd(&cnt[w][(key[k] >> shift) & 255u], 1u);
+    __syncthreads();
+    {
+        uint32_t run = hist[((size_t)i * blocks + b) * 256 + tid];
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+            const uint32_t c = cnt[ww][tid];
+            cnt[ww][tid] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int k = 0; k < kSortIpt; ++k) {
+        const uint32_t dg = (key[k] >> shift) & 255u;
+        const uint64_t peers = match_bits<8>(dg, ok[k]);
+        if (ok[k]) {
+            const uint32_t basev = cnt[w][dg];
+            const uint32_t pos = basev + (uint32_t)__popcll(peers & lt);
+            if (lane == __ffsll((unsigned long long)peers) - 1) cnt[w][dg] = basev + (uint32_t)__popcll(peers);
+            if (pos < n) {      // guard: offsets are consistent by construction
+                kout[seg + pos] = key[k];
+                vout[seg + pos] = val[k];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t stream)
+{
+    if (s.n == 0 || c.n_img == 0) return hipSuccess;
+    const uint64_t n = (uint64_t)s.n;
+    const dim3 grid((unsigned)c.sort_blocks, (unsigned)c.n_img);
+    // pass 0: dense keys (index order) -> compacted, digit 0
+    hipLaunchKernelGGL(k_sort_hist<true>, grid, dim3(256), 0, stream, c.keyz, c.vis_count, n, 0, c.sort_hist,
+                       c.sort_blocks);
+    hipLaunchKernelGGL(k_sort_scan<true>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
+                       c.vis_count, n);
+    hipLaunchKernelGGL(k_sort_scatter<true>, grid, dim3(256), 0, stream, c.keyz, (const uint32_t*)nullptr, c.sk[0],
+                       c.sv[0], c.vis_count, n, 0, c.sort_hist, c.sort_blocks);
+    int src = 0;
+    for (int pass = 1; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_sort_hist<false>, grid, dim3(256), 0, stream, c.sk[src], c.vis_count, n, shift,
+                           c.sort_hist, c.sort_blocks);
+        hipLaunchKernelGGL(k_sort_scan<false>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
+                           c.vis_count, n);
+        hipLaunchKernelGGL(k_sort_scatter<false>, grid, dim3(256), 0, stream, c.sk[src], c.sv[src], c.sk[src ^ 1],
+                           c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks);
+        src ^= 1;
+    }
+    // pass 0 wrote buffer 0; passes 1..3 alternate, so the sorted result is in buffer 1
+    return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -1,0 +1,289 @@
+"""Thin ctypes binding of libgsr (include/gsr.h).
+
+Argument marshalling only: every step of rendering runs in the HIP library.
+Device memory and streams come from PyTorch.  Importing this module does not
+load the library; the first use does, and fails loudly when the in-tree
+libgsr.so is missing (build it with ``python -m paper_2604_25459_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsr.so")
+
+GSR_OK = 0
+GSR_E_INVALID = -1
+GSR_E_OOM = -2
+GSR_E_DEVICE = -3
+GSR_E_NOT_FOUND = -4
+GSR_E_BUSY = -5
+GSR_E_REJECTED = -6
+GSR_E_OVERFLOW = -7
+GSR_E_TIMEOUT = -8
+
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+MEM_HOST, MEM_DEVICE = 0, 1
+
+
+class Options(C.Structure):
+    _fields_ = [("tile_size", C.c_int), ("images_per_thread", C.c_int), ("chunk_bytes", C.c_int64),
+                ("cutoff", C.c_float), ("profile", C.c_int), ("reserved", C.c_int * 7)]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int), ("storage", C.c_int), ("mem_kind", C.c_int),
+                ("n_bodies", C.c_int), ("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacities", C.c_void_p), ("sh", C.c_void_p), ("body_offsets", C.c_void_p)]
+
+
+class CameraDesc(C.Structure):
+    _fields_ = [("width", C.c_int), ("height", C.c_int), ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float),
+                ("cy", C.c_float), ("near_plane", C.c_float)]
+
+
+class RenderDesc(C.Structure):
+    _fields_ = [("scene_id", C.c_uint64), ("n_envs", C.c_int), ("n_cams", C.c_int), ("cams", C.c_void_p),
+                ("viewmats", C.c_void_p), ("body_poses", C.c_void_p), ("bg", C.c_float * 3),
+                ("out_rgb", C.c_void_p), ("out_depth", C.c_void_p), ("out_alpha", C.c_void_p)]
+
+
+class BinsOut(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("keys", C.c_void_p), ("values", C.c_void_p), ("ranges", C.c_void_p),
+                ("ranges_capacity", C.c_int64), ("n_pairs", C.c_int64), ("n_visible", C.c_int64),
+                ("tiles_x", C.c_int32), ("tiles_y", C.c_int32), ("tile_base", C.c_int64)]
+
+
+class ProjOut(C.Structure):
+    _fields_ = [("n", C.c_int64), ("zkey", C.c_void_p), ("rect", C.c_void_p), ("rec", C.c_void_p)]
+
+
+# name -> (restype, argtypes); every entry point declared in include/gsr.h
+SIGNATURES = {
+    "gsr_create": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p]),
+    "gsr_destroy": (C.c_int, [C.c_void_p]),
+    "gsr_scene_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_scene_destroy": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "gsr_scene_info": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_render": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_render_plain": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_debug_bins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "gsr_debug_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "gsr_stage_times": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "gsr_last_error": (C.c_char_p, []),
+    "gsr_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class GsrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libgsr error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load the in-tree libgsr.so (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_2604_25459_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != GSR_OK:
+        raise GsrError(rc, load().gsr_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+@dataclass
+class Camera:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    near: float = 0.01
+
+
+class Renderer:
+    """One libgsr context on a device."""
+
+    def __init__(self, device: int = 0, tile_size: int = 16, images_per_thread: int = 4, chunk_bytes: int = 0,
+                 cutoff: float = 0.0, profile: bool = False):
+        lib = load()
+        opt = Options(tile_size=tile_size, images_per_thread=images_per_thread, chunk_bytes=chunk_bytes,
+                      cutoff=cutoff, profile=int(profile))
+        h = C.c_void_p()
+        _check(lib.gsr_create(device, C.byref(opt), C.byref(h)))
+        self._h = h
+        self.device = device
+        self.tile_size = tile_size
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gsr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    STAGES = ("project", "depth_sort", "tile_count", "tile_scatter", "raster")
+
+    def stage_times(self, reset: bool = True):
+        """Device ms per stage accumulated since the last reset (profile=True)."""
+        ms = np.zeros(8, np.float64)
+        _check(load().gsr_stage_times(self._h, ms.ctypes.data, 8, int(reset)))
+        out = dict(zip(self.STAGES, ms[:5].tolist()))
+        out["raster_launches"] = int(ms[5])
+        out["renders"] = int(ms[6])
+        return out
+
+    # ---------------------------------------------------------- scenes
+    def add_scene(self, means, scales, quats, opacities, sh, sh_degree: int, body_offsets, storage: str = "f32") -> int:
+        """Host numpy float32 arrays (or CUDA tensors, all on one side)."""
+        import torch
+        dev = isinstance(means, torch.Tensor) and means.is_cuda
+        if not dev:
+            conv = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+            means, scales, quats, opacities, sh = map(conv, (means, scales, quats, opacities, sh))
+        off = np.ascontiguousarray(body_offsets, dtype=np.int64)
+        d = SceneDesc(n=int(means.shape[0]), sh_degree=int(sh_degree), storage=STORAGE[storage],
+                      mem_kind=MEM_DEVICE if dev else MEM_HOST, n_bodies=int(off.shape[0]) - 1,
+                      means=_ptr(means), scales=_ptr(scales), quats=_ptr(quats), opacities=_ptr(opacities),
+                      sh=_ptr(sh), body_offsets=off.ctypes.data)
+        sid = C.c_uint64()
+        _check(load().gsr_scene_create(self._h, C.byref(d), C.byref(sid)))
+        return int(sid.value)
+
+    def add_synth_scene(self, scene, storage: str = "f32") -> int:
+        return self.add_scene(scene.means, scene.scales, scene.quats, scene.opacities, scene.sh, scene.sh_degree,
+                              scene.body_offsets, storage)
+
+    def remove_scene(self, sid: int):
+        _check(load().gsr_scene_destroy(self._h, sid))
+
+    def scene_info(self, sid: int):
+        n, b, by = C.c_int64(), C.c_int(), C.c_int64()
+        _check(load().gsr_scene_info(self._h, sid, C.byref(n), C.byref(b), C.byref(by)))
+        return int(n.value), int(b.value), int(by.value)
+
+    # ---------------------------------------------------------- rendering
+    @staticmethod
+    def _cams(cams: Sequence) -> C.Array:
+        arr = (CameraDesc * len(cams))()
+        for k, c in enumerate(cams):
+            arr[k] = CameraDesc(width=int(c.width), height=int(c.height), fx=c.fx, fy=c.fy, cx=c.cx, cy=c.cy,
+                                near_plane=c.near)
+        return arr
+
+    def _desc(self, sid, cams, viewmats, poses, bg, rgb=None, depth=None, alpha=None):
+        carr = self._cams(cams)
+        d = RenderDesc(scene_id=sid, n_envs=int(viewmats.shape[1]), n_cams=len(cams), cams=C.addressof(carr),
+                       viewmats=_ptr(viewmats), body_poses=_ptr(poses) if poses is not None and poses.numel() else None,
+                       out_rgb=_ptr(rgb), out_depth=_ptr(depth), out_alpha=_ptr(alpha))
+        d.bg[0], d.bg[1], d.bg[2] = [float(x) for x in bg]
+        return d, carr
+
+    def alloc_outputs(self, cams, n_envs: int, alpha: bool = False):
+        import torch
+        npix = sum(n_envs * c.width * c.height for c in cams)
+        dev = torch.device("cuda", self.device)
+        rgb = torch.empty(npix * 3, dtype=torch.float32, device=dev)
+        depth = torch.empty(npix, dtype=torch.float32, device=dev)
+        a = torch.empty(npix, dtype=torch.float32, device=dev) if alpha else None
+        return rgb, depth, a
+
+    @staticmethod
+    def split(cams, n_envs: int, rgb, depth, alpha=None):
+        """Per camera slot views: rgb [E, H, W, 3], depth [E, H, W]."""
+        out, base = [], 0
+        for c in cams:
+            n = n_envs * c.width * c.height
+            r = rgb[3 * base:3 * (base + n)].view(n_envs, c.height, c.width, 3)
+            dd = depth[base:base + n].view(n_envs, c.height, c.width)
+            aa = alpha[base:base + n].view(n_envs, c.height, c.width) if alpha is not None else None
+            out.append((r, dd, aa))
+            base += n
+        return out
+
+    def render_into(self, sid, cams, viewmats, poses, rgb, depth, alpha=None, bg=(0.0, 0.0, 0.0), plain=False,
+                    stream=None):
+        """viewmats: CUDA float32 [C, E, 3, 4]; poses: CUDA float32 [E, B, 7]."""
+        import torch
+        d, carr = self._desc(sid, cams, viewmats, poses, bg, rgb, depth, alpha)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        fn = load().gsr_render_plain if plain else load().gsr_render
+        _check(fn(self._h, C.byref(d), C.c_void_p(st)))
+        del carr
+
+    def render(self, sid, cams, viewmats, poses, bg=(0.0, 0.0, 0.0), alpha=False, plain=False, stream=None):
+        E = int(viewmats.shape[1])
+        rgb, depth, a = self.alloc_outputs(cams, E, alpha)
+        self.render_into(sid, cams, viewmats, poses, rgb, depth, a, bg, plain, stream)
+        return self.split(cams, E, rgb, depth, a)
+
+    # ---------------------------------------------------------- debug
+    def debug_bins(self, sid, cams, viewmats, poses, image: int, capacity: int = 1 << 22):
+        d, carr = self._desc(sid, cams, viewmats, poses, (0, 0, 0))
+        for _ in range(2):
+            keys = np.empty(capacity, np.uint64)
+            vals = np.empty(capacity, np.uint32)
+            cam = cams[image // int(viewmats.shape[1])]
+            T = ((cam.width + self.tile_size - 1) // self.tile_size) * ((cam.height + self.tile_size - 1) // self.tile_size)
+            ranges = np.empty((T, 2), np.uint32)
+            o = BinsOut(capacity=capacity, keys=keys.ctypes.data, values=vals.ctypes.data, ranges=ranges.ctypes.data,
+                        ranges_capacity=T)
+            rc = load().gsr_debug_bins(self._h, C.byref(d), int(image), C.byref(o))
+            if rc == GSR_E_INVALID and o.n_pairs > capacity:
+                capacity = int(o.n_pairs)
+                continue
+            _check(rc)
+            n = int(o.n_pairs)
+            return dict(keys=keys[:n].copy(), values=vals[:n].copy(), ranges=ranges.astype(np.int64),
+                        n_visible=int(o.n_visible), tiles_x=int(o.tiles_x), tiles_y=int(o.tiles_y),
+                        tile_base=int(o.tile_base))
+        raise GsrError(GSR_E_INVALID, "debug_bins capacity retry failed")
+
+    def debug_project(self, sid, cams, viewmats, poses, image: int, n: int):
+        d, carr = self._desc(sid, cams, viewmats, poses, (0, 0, 0))
+        z = np.empty(n, np.uint32)
+        rect = np.empty((n, 4), np.int32)
+        rec = np.empty((n, 12), np.float32)
+        o = ProjOut(n=n, zkey=z.ctypes.data, rect=rect.ctypes.data, rec=rec.ctypes.data)
+        _check(load().gsr_debug_project(self._h, C.byref(d), int(image), C.byref(o)))
+        return dict(zkey=z, rect=rect, rec=rec)
+
+
+def batch_tensors(batch, device: int = 0):
+    """CUDA tensors (viewmats [C,E,3,4], poses [E,B,7]) and camera list of a synth.Batch."""
+    import torch
+    dev = torch.device("cuda", device)
+    vm = torch.from_numpy(np.ascontiguousarray(batch.viewmats, np.float32)).to(dev)
+    poses = torch.from_numpy(np.ascontiguousarray(batch.poses, np.float32)).to(dev)
+    cams = [Camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.near) for c in batch.cams]
+    return cams, vm, poses

@@ -275,6 +275,12 @@ def make_config(cfg: int, n_envs: int | None = None, step: int = 0):
     return scene, batch
 
 
+def make_poses(cfg: int, step: int, n_envs: int, n_bodies: int) -> np.ndarray:
+    """Body poses of workload ``cfg`` at ``step`` (the same draws make_config
+    uses for that step), without regenerating the scene."""
+    return random_poses(_rng(config_seed(cfg), _S_POSE, step), n_envs, n_bodies)
+
+
 # --------------------------------------------------------------------------
 # serving stream (workload 4)
 # --------------------------------------------------------------------------

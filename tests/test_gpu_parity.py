@@ -1,0 +1,278 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact: cull set, depth-key bits, tile rectangles, sort keys, tile lists
+and ranges (float32 binning specification).  Within tolerance: pixels
+(max-abs 1e-3 RGB, 1e-3 relative depth beyond 1 m) against the float64
+oracle, where a pixel may match any admissible result of a threshold decision
+taken within rounding distance of its boundary."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import attrs64, bin_ref, render_ref
+from oracle.spec32 import project32
+from oracle.storage import decoded_attrs
+from paper_2604_25459_amd import synth
+from tests.parity import compare, psnr
+from tests.scenes import one_camera, scene_from
+
+pytestmark = pytest.mark.gpu
+
+LOG2E = 1.4426950408889634
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def R():
+    _torch()
+    from paper_2604_25459_amd import gsr
+    r = gsr.Renderer(0)
+    yield r
+    r.close()
+
+
+def _upload(R, scene, storage="f32"):
+    return R.add_synth_scene(scene, storage)
+
+
+def _render(R, sid, batch, plain=False):
+    from paper_2604_25459_amd import gsr
+    cams, vm, poses = gsr.batch_tensors(batch)
+    return R.render(sid, cams, vm, poses, bg=tuple(batch.bg), alpha=True, plain=plain)
+
+
+def _img(got, c, e):
+    """Image (c, e) of a render result as numpy (rgb, depth, alpha)."""
+    r, d, a = got[c]
+    return r[e].cpu().numpy(), d[e].cpu().numpy(), a[e].cpu().numpy()
+
+
+def _same(x, y):
+    import torch
+    assert torch.equal(x, y)
+
+
+def _check_bins(R, sid, scene, batch, c, e, attrs=None):
+    from paper_2604_25459_amd import gsr
+    cams, vm, poses = gsr.batch_tensors(batch)
+    image = batch.image_index(c, e)
+    got = R.debug_bins(sid, cams, vm, poses, image)
+    ref = bin_ref(scene, batch, c, e, R.tile_size, attrs=attrs)
+    assert got["n_visible"] == int(ref.visible.sum())
+    assert got["tile_base"] == ref.tile_base
+    np.testing.assert_array_equal(got["keys"], ref.keys)
+    np.testing.assert_array_equal(got["values"], ref.values)
+    np.testing.assert_array_equal(got["ranges"], ref.ranges)
+    return ref
+
+
+def _check_image(got, ref, label, rgb_tol=1e-3):
+    rgb, depth, alpha = got
+    res = compare(rgb, depth, ref, rgb_tol=rgb_tol)
+    print(f"[{label}] {res}", flush=True)
+    assert res["ok"], (label, res)
+    assert res["n_unresolved"] <= max(2, res["n_pix"] // 20000)
+    np.testing.assert_allclose(alpha, ref.alpha, atol=2e-3)
+    return res
+
+
+# ------------------------------------------------------------------ projection
+def test_project_cfg0_matches_spec(R):
+    scene, batch = synth.make_config(0)
+    sid = _upload(R, scene)
+    from paper_2604_25459_amd import gsr
+    cams, vm, poses = gsr.batch_tensors(batch)
+    got = R.debug_project(sid, cams, vm, poses, 0, scene.n)
+    p = project32(scene, batch, 0, 0, R.tile_size)
+    vis = p["visible"]
+    np.testing.assert_array_equal(got["zkey"] != 0xFFFFFFFF, vis)
+    np.testing.assert_array_equal(got["zkey"][vis], p["zbits"][vis])
+    np.testing.assert_array_equal(got["rect"][vis], p["rect"][vis])
+    rec = got["rec"][vis]
+    # u, v and the radius follow the binary32 specification exactly
+    np.testing.assert_array_equal(rec[:, 0], p["u"][vis])
+    np.testing.assert_array_equal(rec[:, 1], p["v"][vis])
+    np.testing.assert_array_equal(rec[:, 7], p["radius"][vis])
+    np.testing.assert_array_equal(rec[:, 6].view(np.uint32), p["zbits"][vis])
+    con = p["conic"][vis].astype(np.float64)
+    np.testing.assert_allclose(rec[:, 2], -0.5 * LOG2E * con[:, 0], rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(rec[:, 3], -LOG2E * con[:, 1], rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(rec[:, 4], -0.5 * LOG2E * con[:, 2], rtol=1e-6, atol=1e-9)
+    at = attrs64(scene, batch)
+    np.testing.assert_allclose(rec[:, 8:11], at["rgb"][vis], atol=2e-6)
+    np.testing.assert_allclose(rec[:, 5], np.log2(scene.opacities[vis].astype(np.float64)), atol=2e-6)
+    R.remove_scene(sid)
+
+
+# ------------------------------------------------------------------ config 0
+def test_cfg0_bins_and_pixels(R):
+    scene, batch = synth.make_config(0)
+    sid = _upload(R, scene)
+    _check_bins(R, sid, scene, batch, 0, 0)
+    got = _render(R, sid, batch)
+    ref = render_ref(scene, batch, 0, 0, R.tile_size)
+    _check_image(_img(got, 0, 0), ref, "cfg0")
+    # the plain per-image path gives the same bits
+    plain = _render(R, sid, batch, plain=True)
+    _same(plain[0][0], got[0][0])
+    _same(plain[0][1], got[0][1])
+    R.remove_scene(sid)
+
+
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.2, 0.3, 0.4)])
+def test_ragged_100x75_random_scene(R, bg):
+    rng = np.random.default_rng(3)
+    n = 3000
+    means = rng.uniform([-1.2, -0.9, 1.0], [1.2, 0.9, 4.0], (n, 3))
+    scales = np.exp(rng.normal(math.log(0.04), 0.6, (n, 3)))
+    sh = np.concatenate([rng.uniform(0, 1, (n, 1, 3)), rng.normal(0, 0.1, (n, 15, 3))], axis=1)
+    scene = scene_from(means, scales, rng.standard_normal((n, 4)), 1 / (1 + np.exp(-rng.standard_normal(n))), sh, 3)
+    batch = one_camera(100, 75, 70.0, bg=bg)
+    sid = _upload(R, scene)
+    _check_bins(R, sid, scene, batch, 0, 0)
+    got = _render(R, sid, batch)
+    ref = render_ref(scene, batch, 0, 0, R.tile_size)
+    _check_image(_img(got, 0, 0), ref, f"ragged bg={bg}")
+    R.remove_scene(sid)
+
+
+# ------------------------------------------------------------------ batched configs (sampled envs)
+def test_cfg1_all_envs_batched(R):
+    scene, batch = synth.make_config(1)
+    sid = _upload(R, scene)
+    got = _render(R, sid, batch)
+    for e in (0, 17, 63):
+        _check_bins(R, sid, scene, batch, 0, e)
+        ref = render_ref(scene, batch, 0, e, R.tile_size)
+        _check_image(_img(got, 0, e), ref, f"cfg1 env {e}")
+    R.remove_scene(sid)
+
+
+def test_cfg1_batch_independence_and_plain(R):
+    scene, batch = synth.make_config(1, n_envs=8)
+    sid = _upload(R, scene)
+    full = _render(R, sid, batch)[0]
+    plain = _render(R, sid, batch, plain=True)[0]
+    _same(full[0], plain[0])
+    _same(full[1], plain[1])
+    alone = _render(R, sid, batch.subset([5]))[0]
+    _same(alone[0][0], full[0][5])
+    _same(alone[1][0], full[1][5])
+    again = _render(R, sid, batch)[0]
+    _same(again[0], full[0])      # deterministic
+    _same(again[1], full[1])
+    R.remove_scene(sid)
+
+
+def test_cfg2_full_batch_sampled(R):
+    scene, batch = synth.make_config(2)
+    sid = _upload(R, scene)
+    got = _render(R, sid, batch)
+    assert tuple(got[0][0].shape) == (2048, 480, 640, 3)
+    for e in (0, 1337):
+        _check_bins(R, sid, scene, batch, 0, e)
+        ref = render_ref(scene, batch, 0, e, R.tile_size)
+        _check_image(_img(got, 0, e), ref, f"cfg2 env {e}")
+    R.remove_scene(sid)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_half_storage_cfg1(R, storage):
+    scene, batch = synth.make_config(1, n_envs=4)
+    sid = _upload(R, scene, storage)
+    at = decoded_attrs(scene, storage)
+    got = _render(R, sid, batch)
+    for e in (0, 3):
+        _check_bins(R, sid, scene, batch, 0, e, attrs=at)
+        ref = render_ref(scene, batch, 0, e, R.tile_size, attrs=at)
+        img = _img(got, 0, e)
+        _check_image(img, ref, f"cfg1 {storage} env {e} (decoded attributes)")
+        full = render_ref(scene, batch, 0, e, R.tile_size, variants=False)
+        print(f"[cfg1 {storage} env {e} vs float32 attributes] max-abs {np.abs(img[0] - full.rgb).max():.4g} "
+              f"mean-abs {np.abs(img[0] - full.rgb).mean():.4g} PSNR {psnr(img[0], full.rgb):.2f} dB", flush=True)
+    R.remove_scene(sid)
+
+
+def test_cfg3_uneven_two_slots(R):
+    scene, batch = synth.make_config(3, n_envs=16)
+    sid = _upload(R, scene, "bf16")
+    at = decoded_attrs(scene, "bf16")
+    got = _render(R, sid, batch)
+    assert tuple(got[0][0].shape) == (16, 128, 128, 3) and tuple(got[1][0].shape) == (16, 480, 640, 3)
+    for c, e in ((0, 3), (1, 3), (1, 15)):
+        _check_bins(R, sid, scene, batch, c, e, attrs=at)
+        ref = render_ref(scene, batch, c, e, R.tile_size, attrs=at)
+        _check_image(_img(got, c, e), ref, f"cfg3 slot {c} env {e}")
+    R.remove_scene(sid)
+
+
+# ------------------------------------------------------------------ invariances and edge cases
+def test_tile_size_invariance():
+    _torch()
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(0)
+    outs = {}
+    for ts in (8, 16, 32):
+        r = gsr.Renderer(0, tile_size=ts)
+        sid = r.add_synth_scene(scene)
+        if ts != 16:
+            cams, vm, poses = gsr.batch_tensors(batch)
+            got = r.debug_bins(sid, cams, vm, poses, 0)
+            ref = bin_ref(scene, batch, 0, 0, ts)
+            np.testing.assert_array_equal(got["keys"], ref.keys)
+            np.testing.assert_array_equal(got["values"], ref.values)
+        outs[ts] = _img(_render(r, sid, batch), 0, 0)
+        r.close()
+    for ts in (8, 32):
+        np.testing.assert_array_equal(outs[ts][0], outs[16][0])
+        np.testing.assert_array_equal(outs[ts][1], outs[16][1])
+
+
+def test_empty_and_degenerate_scenes(R):
+    bg = (0.1, 0.6, 0.3)
+    batch = one_camera(40, 30, 30.0, bg=bg)
+    for label, scene in (("empty", scene_from(np.zeros((0, 3)), np.zeros((0, 3)), degree=0)),
+                         ("behind", scene_from([[0, 0, -1.0], [0.1, 0, -0.5], [0, 0, 0.005]], [0.3] * 3, degree=0)),
+                         ("transparent", scene_from([[0, 0, 2.0]], [0.3] * 3, opac=[0.5 / 255], degree=0))):
+        sid = _upload(R, scene)
+        rgb, depth, alpha = _img(_render(R, sid, batch), 0, 0)
+        np.testing.assert_array_equal(rgb, np.broadcast_to(np.float32(bg), (30, 40, 3)), err_msg=label)
+        assert (depth == 0).all() and (alpha == 0).all(), label
+        R.remove_scene(sid)
+
+
+@pytest.mark.parametrize("degree", [0, 1, 2, 3])
+def test_sh_degrees(R, degree):
+    scene, batch = synth.make_config(1, n_envs=1)
+    K = (degree + 1) ** 2
+    sub = np.arange(0, scene.n, 7)
+    keep = [int(np.searchsorted(sub, o)) for o in scene.body_offsets]
+    s = scene_from(scene.means[sub], scene.scales[sub], scene.quats[sub], scene.opacities[sub],
+                   scene.sh[sub][:, :K], degree=degree, body_offsets=keep)
+    sid = _upload(R, s)
+    got = _render(R, sid, batch)
+    ref = render_ref(s, batch, 0, 0, R.tile_size)
+    _check_image(_img(got, 0, 0), ref, f"degree {degree}")
+    R.remove_scene(sid)
+
+
+def test_invalid_render_arguments(R):
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(0)
+    sid = _upload(R, scene)
+    cams, vm, poses = gsr.batch_tensors(batch)
+    with pytest.raises(gsr.GsrError) as ei:
+        R.render(sid + 1000, cams, vm, poses)
+    assert ei.value.code == gsr.GSR_E_NOT_FOUND
+    bad = [gsr.Camera(0, 96, 100.0, 100.0, 64.0, 48.0)]
+    with pytest.raises(gsr.GsrError) as ei:
+        R.render(sid, bad, vm, poses)
+    assert ei.value.code == gsr.GSR_E_INVALID
+    R.remove_scene(sid)
