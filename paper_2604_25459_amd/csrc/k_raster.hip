@@ -3,30 +3,39 @@
 //
 // One workgroup per (image, tile) of the whole chunk, images of all camera
 // slots in one launch.  The tile's depth-sorted Gaussian list is staged into
-// LDS in batches of 256 records (each thread fetches one record); every
-// thread then composites its pixels against the batch, reading records by LDS
-// broadcast.  Per pixel and Gaussian:
-//     log2(alpha) = A dx^2 + B dx dy + C dy^2 + log2(o)   (conic pre-scaled)
-//     alpha < 1/255            -> skip
-//     alpha = min(0.99, alpha); T' = T (1 - alpha)
+// LDS in batches of 256 records (double-buffered: the next batch is fetched
+// into registers while the current one is composited).  Per pixel and
+// Gaussian, with the conic pre-scaled so that log2(alpha) = p:
+//     p = A dx^2 + B dx dy + C dy^2 + log2(o)
+//     p < log2(1/255)          -> skip
+//     alpha = min(0.99, 2^p); T' = T (1 - alpha)
 //     T' < 1e-4                -> stop before adding
 //     C += rgb alpha T, D += z alpha T, T = T'
-// A wave skips a Gaussian outright when its conservative square (mean +- r,
-// r = ceil(3.33 sqrt(lambda_max))) misses the wave's pixel block; no pixel
-// there can reach alpha >= 1/255.  The workgroup stops when every pixel has
-// terminated (block-wide count at each batch boundary).
+//
+// Wave-level culling ("ballot" step): for each batch every lane takes one
+// Gaussian and bounds p over the wave's pixel-centre rectangle from above (p is
+// concave: the maximum is at the mean if it lies inside, else on an edge,
+// where the 1D maximiser is clamped).  Gaussians whose bound stays below
+// log2(1/255) - kCullMargin cannot reach alpha >= 1/255 at any pixel of the
+// block; the ballot of the survivors is walked bit by bit, so each wave only
+// evaluates Gaussians that touch its pixels.  kCullMargin absorbs binary32
+// rounding of the per-pixel evaluation, so culling never removes a Gaussian a
+// pixel would have accepted and results do not depend on the tiling.
 #include "gsr_internal.h"
 
 namespace gsr {
 namespace {
 
 constexpr int kBatch = 256;
+constexpr float kLogAlphaMin = -7.99435343685886f;   // log2(1/255)
+constexpr float kCullMargin = 0.05f;                  // in log2(alpha) units
 
 // Pixel layout: TS <= 16: one pixel per thread, waves own 8x8 blocks.
 // TS == 32: 256 threads x 4 pixels, wave w owns rows [8w, 8w + 8) (32 x 8).
 template <int TS>
 struct Layout {
     static constexpr int kThreads = TS <= 16 ? TS * TS : 256;
+    static constexpr int kWaves = kThreads / 64;
     static constexpr int kPpt = TS <= 16 ? 1 : 4;
     static constexpr int kWaveW = TS <= 16 ? 8 : 32;
     static constexpr int kWaveH = 8;
@@ -43,13 +52,42 @@ struct Layout {
     }
 };
 
+// Upper bound of p = A x^2 + B x y + C y^2 + lo over [X0, X1] x [Y0, Y1]
+// (coordinates relative to the mean; A, C < 0).
+__device__ __forceinline__ float max_logalpha_rect(float A, float B, float C, float lo, float X0, float X1, float Y0,
+                                                   float Y1)
+{
+    if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return lo;
+    const float ky = -B / (2.0f * C);     // argmax over y for fixed x is ky * x
+    const float kx = -B / (2.0f * A);
+    float best = -INFINITY;
+    {
+        const float y = fminf(fmaxf(ky * X0, Y0), Y1);
+        best = fmaxf(best, fmaf(X0, fmaf(A, X0, B * y), C * y * y));
+    }
+    {
+        const float y = fminf(fmaxf(ky * X1, Y0), Y1);
+        best = fmaxf(best, fmaf(X1, fmaf(A, X1, B * y), C * y * y));
+    }
+    {
+        const float x = fminf(fmaxf(kx * Y0, X0), X1);
+        best = fmaxf(best, fmaf(Y0, fmaf(C, Y0, B * x), A * x * x));
+    }
+    {
+        const float x = fminf(fmaxf(kx * Y1, X0), X1);
+        best = fmaxf(best, fmaf(Y1, fmaf(C, Y1, B * x), A * x * x));
+    }
+    return best + lo;
+}
+
 template <int TS>
 __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, ChunkDev c, RasterParams p)
 {
     using L = Layout<TS>;
     constexpr int NT = L::kThreads;
     constexpr int PPT = L::kPpt;
-    __shared__ float4 sA[kBatch], sB[kBatch], sC[kBatch];
+    constexpr int PER_THREAD = kBatch / NT;     // records each thread stages per batch
+    __shared__ float4 sA[2][kBatch], sB[2][kBatch], sC[2][kBatch];
 
     const uint32_t bid = blockIdx.x;
     int sgi = 0;
@@ -69,7 +107,7 @@ __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, Chu
     const int w = tid >> 6, lane = __lane_id();
     int ox, oy;
     L::wave_origin(w, &ox, &oy);
-    // pixel-centre extent of the wave's block (for the conservative skip)
+    // pixel-centre rectangle of the wave's block
     const float wx0 = (float)(tx * TS + ox) + 0.5f;
     const float wx1 = wx0 + (float)(L::kWaveW - 1);
     const float wy0 = (float)(ty * TS + oy) + 0.5f;
@@ -78,7 +116,7 @@ __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, Chu
     float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
     bool live[PPT];
     int pxi[PPT], pyi[PPT];
-    int n_live = 0;
+    bool any_live = false;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         int lx, ly;
@@ -90,63 +128,89 @@ __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, Chu
         py[k] = (float)pyi[k] + 0.5f;
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = D[k] = 0.0f;
-        n_live += live[k] ? 1 : 0;
+        any_live = any_live || live[k];
     }
 
     const uint32_t* R = c.tile_range + ((size_t)i * c.t_max + t) * 2;
     const uint32_t start = R[0], end = R[1];
     const uint32_t* list = c.pairs + c.pair_base[i];
     const float4* rec = c.rec + (size_t)i * (size_t)s.n * 3;
-    const float kLogAlphaMin = -7.99435343685886f;   // log2(1/255)
+    const uint32_t n = (uint32_t)s.n;
 
-    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
-        for (int k = tid; k < kBatch; k += NT) {
-            const uint32_t e = b0 + (uint32_t)k;
+    // register staging of the next batch
+    float4 ra[PER_THREAD], rb[PER_THREAD], rc[PER_THREAD];
+    auto fetch = [&](uint32_t b0) {
+#pragma unroll
+        for (int q = 0; q < PER_THREAD; ++q) {
+            const uint32_t e = b0 + (uint32_t)(q * NT + tid);
             if (e < end) {
                 uint32_t g = list[e];
-                if (g >= (uint32_t)s.n) g = 0;      // guard: list entries are valid indices by construction
-                sA[k] = rec[3 * (size_t)g];
-                sB[k] = rec[3 * (size_t)g + 1];
-                sC[k] = rec[3 * (size_t)g + 2];
+                if (g >= n) g = 0;      // guard: list entries are valid indices by construction
+                ra[q] = rec[3 * (size_t)g];
+                rb[q] = rec[3 * (size_t)g + 1];
+                rc[q] = rec[3 * (size_t)g + 2];
             }
         }
+    };
+    if (start < end) fetch(start);
+    int buf = 0;
+    bool wave_live = __ballot(any_live) != 0ull;
+
+    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+#pragma unroll
+        for (int q = 0; q < PER_THREAD; ++q) {
+            sA[buf][q * NT + tid] = ra[q];
+            sB[buf][q * NT + tid] = rb[q];
+            sC[buf][q * NT + tid] = rc[q];
+        }
         __syncthreads();
+        if (b0 + kBatch < end) fetch(b0 + kBatch);
         const int cnt = (int)min((uint32_t)kBatch, end - b0);
-        if (n_live > 0) {
-            for (int j = 0; j < cnt; ++j) {
-                const float4 a = sA[j];
-                const float4 bq = sB[j];
-                const float r = bq.w;
-                if (a.x + r < wx0 || a.x - r > wx1 || a.y + r < wy0 || a.y - r > wy1) continue;
-                bool any = false;
+        for (int sub = 0; sub < cnt && wave_live; sub += 64) {
+            // ballot: which of these 64 Gaussians can touch this wave's block
+            const int jl = sub + lane;
+            bool keep = false;
+            if (jl < cnt) {
+                const float4 a = sA[buf][jl];
+                const float4 bq = sB[buf][jl];
+                const float m = max_logalpha_rect(a.z, a.w, bq.x, bq.y, wx0 - a.x, wx1 - a.x, wy0 - a.y, wy1 - a.y);
+                keep = m >= kLogAlphaMin - kCullMargin;
+            }
+            uint64_t mask = __ballot(keep);
+            while (mask) {
+                const int j = sub + (int)__builtin_ctzll(mask);
+                mask &= mask - 1ull;
+                const float4 a = sA[buf][j];
+                const float4 bq = sB[buf][j];
+                const float4 col = sC[buf][j];
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    if (!live[k]) continue;
                     const float dx = px[k] - a.x;
                     const float dy = py[k] - a.y;
                     const float pw = fmaf(dx, fmaf(a.z, dx, a.w * dy), fmaf(bq.x * dy, dy, bq.y));
-                    if (pw < kLogAlphaMin) continue;
                     const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(pw));
-                    const float Tn = T[k] * (1.0f - alpha);
-                    if (Tn < 1e-4f) {
-                        live[k] = false;
-                        --n_live;
-                        continue;
-                    }
-                    any = true;
-                    const float4 col = sC[j];
-                    const float wgt = alpha * T[k];
+                    const bool take = live[k] && pw >= kLogAlphaMin;
+                    const float Tn = fmaf(-T[k], alpha, T[k]);
+                    const bool stop = take && Tn < 1e-4f;
+                    const float wgt = (take && !stop) ? alpha * T[k] : 0.0f;
                     C0[k] = fmaf(col.x, wgt, C0[k]);
                     C1[k] = fmaf(col.y, wgt, C1[k]);
                     C2[k] = fmaf(col.z, wgt, C2[k]);
                     D[k] = fmaf(bq.z, wgt, D[k]);
-                    T[k] = Tn;
+                    T[k] = (take && !stop) ? Tn : T[k];
+                    live[k] = live[k] && !stop;
                 }
-                (void)any;
-                if (n_live == 0) break;
+                bool lv = false;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) lv = lv || live[k];
+                if (__ballot(lv) == 0ull) {
+                    wave_live = false;
+                    break;
+                }
             }
         }
-        if (__syncthreads_count(n_live > 0 ? 1 : 0) == 0) break;
+        buf ^= 1;
+        if (__syncthreads_count(wave_live && lane == 0 ? 1 : 0) == 0) break;
     }
 
 #pragma unroll
