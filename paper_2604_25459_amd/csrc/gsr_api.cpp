@@ -100,9 +100,9 @@ struct SceneRes {
 };
 
 struct Workspace {
-    DevBuf img, xform, keyz, rect, rec, sk0, sk1, sv0, sv1, sort_hist, vis_count, tile_hist, tile_range,
-        pair_count, pair_base, pairs, debug;
-    uint64_t* h_total = nullptr;   // pinned
+    DevBuf img, xform, keyz, rect, srect, rec, sk0, sk1, sv0, sv1, sort_hist, vis_count, tile_hist, tile_range,
+        pair_count, pair_base, pairs, row_hist, row_range, row_count, row_base, rows, debug;
+    uint64_t* h_total = nullptr;   // pinned: [0] pairs, [1] row entries of the current chunk
     ImageInfo* h_img = nullptr;    // pinned staging for image descriptions
     size_t h_img_cap = 0;
     hipEvent_t ev_total = nullptr, ev_done = nullptr;
@@ -110,8 +110,9 @@ struct Workspace {
     bool used = false;
     ~Workspace()
     {
-        for (DevBuf* b : {&img, &xform, &keyz, &rect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &vis_count,
-                          &tile_hist, &tile_range, &pair_count, &pair_base, &pairs, &debug})
+        for (DevBuf* b : {&img, &xform, &keyz, &rect, &srect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &vis_count,
+                          &tile_hist, &tile_range, &pair_count, &pair_base, &pairs, &row_hist, &row_range,
+                          &row_count, &row_base, &rows, &debug})
             b->release();
         if (h_total) (void)hipHostFree(h_total);
         if (h_img) (void)hipHostFree(h_img);
@@ -235,16 +236,17 @@ std::vector<ImageInfo> plan_images(const gsr_render_desc* d, int ts)
 struct ChunkPlan {
     int chunk;          // images per chunk
     int t_max;          // max tiles of any image
+    int tx_max, ty_max; // max tile columns / rows of any image
     int sort_blocks, tile_blocks;
 };
 
 size_t per_image_bytes(const SceneRes* sc, int t_max, int sort_blocks, int tile_blocks)
 {
     const size_t n = (size_t)sc->dev.n;
-    size_t b = n * (4 + 8 + 48 + 16);                                  // keyz, rect, records, sort buffers
+    size_t b = n * (4 + 16 + 48 + 16);                                 // keyz, rect + sorted rect, records, sort buffers
     b += (size_t)(sc->dev.n_bodies + 1) * 64;                          // transforms
     b += (size_t)sort_blocks * 256 * 4 + (size_t)tile_blocks * t_max * 4 + (size_t)t_max * 8 + 32;
-    b += n * 8 * 4;                                                    // pair estimate: ~8 tiles per Gaussian
+    b += n * 8 * 4 + n * 3 * 8;                                        // pair / row-entry estimates
     return b;
 }
 
@@ -252,7 +254,13 @@ ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<
 {
     ChunkPlan p{};
     p.t_max = 1;
-    for (const ImageInfo& im : imgs) p.t_max = std::max(p.t_max, im.tiles_x * im.tiles_y);
+    p.tx_max = 1;
+    p.ty_max = 1;
+    for (const ImageInfo& im : imgs) {
+        p.t_max = std::max(p.t_max, im.tiles_x * im.tiles_y);
+        p.tx_max = std::max(p.tx_max, im.tiles_x);
+        p.ty_max = std::max(p.ty_max, im.tiles_y);
+    }
     const int64_t n = sc->dev.n;
     p.sort_blocks = (int)std::max<int64_t>(1, (n + gsr::kSortItems - 1) / gsr::kSortItems);
     p.tile_blocks = (int)std::max<int64_t>(1, (n + gsr::kTileGauss - 1) / gsr::kTileGauss);
@@ -277,6 +285,7 @@ hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& 
     ENS(xform, I * (sc->dev.n_bodies + 1) * 64);
     ENS(keyz, I * n * 4);
     ENS(rect, I * n * 8);
+    ENS(srect, I * n * 8);
     ENS(rec, I * n * 48);
     ENS(sk0, I * n * 4);
     ENS(sk1, I * n * 4);
@@ -288,6 +297,10 @@ hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& 
     ENS(tile_range, I * (size_t)p.t_max * 8);
     ENS(pair_count, I * 4);
     ENS(pair_base, (I + 1) * 8);
+    ENS(row_hist, I * p.tile_blocks * (size_t)p.ty_max * 4);
+    ENS(row_range, I * (size_t)p.ty_max * 8);
+    ENS(row_count, I * 4);
+    ENS(row_base, (I + 1) * 8);
 #undef ENS
     if (!ws.h_total) {
         if ((e = hipHostMalloc((void**)&ws.h_total, 64, hipHostMallocDefault)) != hipSuccess) return e;
@@ -326,15 +339,22 @@ gsr::ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, 
     gsr::ChunkDev c{};
     c.n = (uint64_t)sc->dev.n;
     c.n_img = n_img;
-    int t_max = 1;
-    for (int k = 0; k < n_img; ++k) t_max = std::max(t_max, imgs[i0 + k].tiles_x * imgs[i0 + k].tiles_y);
+    int t_max = 1, tx_max = 1, ty_max = 1;
+    for (int k = 0; k < n_img; ++k) {
+        t_max = std::max(t_max, imgs[i0 + k].tiles_x * imgs[i0 + k].tiles_y);
+        tx_max = std::max(tx_max, imgs[i0 + k].tiles_x);
+        ty_max = std::max(ty_max, imgs[i0 + k].tiles_y);
+    }
     c.t_max = t_max;
+    c.tx_max = tx_max;
+    c.ty_max = ty_max;
     c.sort_blocks = p.sort_blocks;
     c.tile_blocks = p.tile_blocks;
     c.img = ws.img.as<ImageInfo>() + i0;
     c.xform = ws.xform.as<float>();
     c.keyz = ws.keyz.as<uint32_t>();
     c.rect = ws.rect.as<uint2>();
+    c.srect = ws.srect.as<uint2>();
     c.rec = ws.rec.as<float4>();
     c.sk[0] = ws.sk0.as<uint32_t>();
     c.sk[1] = ws.sk1.as<uint32_t>();
@@ -347,6 +367,11 @@ gsr::ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, 
     c.pair_count = ws.pair_count.as<uint32_t>();
     c.pair_base = ws.pair_base.as<uint64_t>();
     c.pairs = ws.pairs.as<uint32_t>();
+    c.row_hist = ws.row_hist.as<uint32_t>();
+    c.row_range = ws.row_range.as<uint32_t>();
+    c.row_count = ws.row_count.as<uint32_t>();
+    c.row_base = ws.row_base.as<uint64_t>();
+    c.rows = ws.rows.as<uint2>();
     return c;
 }
 
@@ -375,15 +400,22 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const gsr_render_desc* 
     HIP_TRY(gsr::launch_tile_count(s, c, st));
     if (prof) HIP_TRY(hipEventRecord(ev.e[3], st));
     HIP_TRY(hipMemcpyAsync(ws.h_total, c.pair_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ws.h_total + 1, c.row_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(ws.ev_total, st));
     HIP_TRY(hipEventSynchronize(ws.ev_total));
-    const uint64_t total = *ws.h_total;
+    const uint64_t total = ws.h_total[0];
+    const uint64_t row_total = ws.h_total[1];
     *pairs_total = total;
+    // everything enqueued before ev_total has completed, including earlier chunks: growing is safe
     if (ws.pairs.bytes < total * 4) {
-        // everything enqueued before ev_total has completed, including earlier chunks
         const size_t want = std::max<size_t>(total * 4, (size_t)((double)ws.pairs.bytes * 1.5));
         HIP_TRY(ws.pairs.ensure(std::max<size_t>(want + (total * 4) / 8, 1 << 20)));
         c.pairs = ws.pairs.as<uint32_t>();
+    }
+    if (ws.rows.bytes < row_total * 8) {
+        const size_t want = std::max<size_t>(row_total * 8, (size_t)((double)ws.rows.bytes * 1.5));
+        HIP_TRY(ws.rows.ensure(std::max<size_t>(want + (row_total * 8) / 8, 1 << 20)));
+        c.rows = ws.rows.as<uint2>();
     }
     HIP_TRY(gsr::launch_tile_scatter(s, c, st));
     if (mode == Mode::kBins) return GSR_OK;

@@ -69,14 +69,22 @@ struct ChunkDev {
     uint2* rect;               // [n_img][n] (x0 | x1 << 16, y0 | y1 << 16)
     float4* rec;               // [n_img][n][3] raster records
     uint32_t* sk[2];           // depth-sort keys, ping-pong [n_img][n]
-    uint32_t* sv[2];           // depth-sort values (Gaussian ids)
+    uint32_t* sv[2];           // depth-sort values (Gaussian ids); sorted result in sv[1]
+    uint2* srect;              // [n_img][n] tile rectangle of the j-th depth-ordered Gaussian
     uint32_t* sort_hist;       // [n_img][sort_blocks][256]
     uint32_t* vis_count;       // [n_img] visible Gaussians V_i
-    uint32_t* tile_hist;       // [n_img][tile_blocks][t_max] counts, then offsets
+    uint32_t* tile_hist;       // [n_img][tile_blocks][t_max] per-block tile counts
     uint32_t* tile_range;      // [n_img][t_max][2] local [start, end)
     uint32_t* pair_count;      // [n_img] P_i
     uint64_t* pair_base;       // [n_img + 1] exclusive prefix of P_i (last = total)
     uint32_t* pairs;           // [total pairs] Gaussian id per (tile, depth)-sorted entry
+    int ty_max;                // largest tile-row count of an image in the chunk
+    int tx_max;                // largest tile-column count
+    uint32_t* row_hist;        // [n_img][tile_blocks][ty_max] per-block row counts, then offsets
+    uint32_t* row_range;       // [n_img][ty_max][2] local [start, end) of each tile-row list
+    uint32_t* row_count;       // [n_img] R_i (entries of all row lists)
+    uint64_t* row_base;        // [n_img + 1] exclusive prefix of R_i
+    uint2* rows;               // [total row entries] (Gaussian id, x0 | x1 << 16) per (row, depth)-sorted entry
 };
 
 // Depth sort geometry.
@@ -93,7 +101,9 @@ hipError_t launch_compose(const SceneDev& s, const ChunkDev& c, const float* vie
 hipError_t launch_project(const SceneDev& s, const ChunkDev& c, int ts, float cutoff, int img_per_thread,
                           hipStream_t stream);
 hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
+// Tile and tile-row histograms, ranges, image bases (before the host reads the totals).
 hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
+// Stable two-level scatter: depth-ordered Gaussians -> tile-row lists -> tile lists.
 hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
 struct RasterParams {
     int ts;

@@ -108,11 +108,14 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
     }
 }
 
-template <bool FIRST>
+// LAST: also gathers each Gaussian's tile rectangle into depth order (once,
+// so later stages read rectangles contiguously).
+template <bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                       const uint32_t* __restrict__ counts, uint64_t n, int shift,
-                                                      const uint32_t* __restrict__ hist, int blocks)
+                                                      const uint32_t* __restrict__ hist, int blocks,
+                                                      const uint2* __restrict__ rect, uint2* __restrict__ srect)
 {
     __shared__ uint32_t cnt[4][256];
     const int i = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
@@ -165,6 +168,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
             if (pos < n) {      // guard: offsets are consistent by construction
                 kout[seg + pos] = key[k];
                 vout[seg + pos] = val[k];
+                if (LAST && val[k] < n) srect[seg + pos] = rect[seg + val[k]];
             }
         }
     }
@@ -182,8 +186,8 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
                        c.sort_blocks);
     hipLaunchKernelGGL(k_sort_scan<true>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
                        c.vis_count, n);
-    hipLaunchKernelGGL(k_sort_scatter<true>, grid, dim3(256), 0, stream, c.keyz, (const uint32_t*)nullptr, c.sk[0],
-                       c.sv[0], c.vis_count, n, 0, c.sort_hist, c.sort_blocks);
+    hipLaunchKernelGGL((k_sort_scatter<true, false>), grid, dim3(256), 0, stream, c.keyz, (const uint32_t*)nullptr,
+                       c.sk[0], c.sv[0], c.vis_count, n, 0, c.sort_hist, c.sort_blocks, c.rect, c.srect);
     int src = 0;
     for (int pass = 1; pass < 4; ++pass) {
         const int shift = 8 * pass;
@@ -191,8 +195,14 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
                            c.sort_hist, c.sort_blocks);
         hipLaunchKernelGGL(k_sort_scan<false>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
                            c.vis_count, n);
-        hipLaunchKernelGGL(k_sort_scatter<false>, grid, dim3(256), 0, stream, c.sk[src], c.sv[src], c.sk[src ^ 1],
-                           c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks);
+        if (pass == 3)
+            hipLaunchKernelGGL((k_sort_scatter<false, true>), grid, dim3(256), 0, stream, c.sk[src], c.sv[src],
+                               c.sk[src ^ 1], c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks, c.rect,
+                               c.srect);
+        else
+            hipLaunchKernelGGL((k_sort_scatter<false, false>), grid, dim3(256), 0, stream, c.sk[src], c.sv[src],
+                               c.sk[src ^ 1], c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks,
+                               c.rect, c.srect);
         src ^= 1;
     }
     // pass 0 wrote buffer 0; passes 1..3 alternate, so the sorted result is in buffer 1

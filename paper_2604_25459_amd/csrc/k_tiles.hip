@@ -3,19 +3,32 @@
 //
 // After the depth sort, every image's visible Gaussians are in ascending
 // (depth bits, index) order.  Expanding each Gaussian into its touched tiles
-// (row-major inside its rectangle) in that order yields the (tile, depth)
-// pairs already sorted on the low 32 key bits; a stable counting sort by tile
-// then gives exactly the order of the full 64-bit key sort with ties kept in
-// index order.  The expansion is never written out: each kernel re-expands its
-// Gaussians in LDS ("load-balanced" over one wave), so memory traffic per pair
-// is one 4-byte id write.
+// in that order yields the (tile, depth) pairs already sorted on the low 32
+// key bits; a stable counting sort by tile then gives exactly the order of the
+// full 64-bit key sort, ties kept in index order.
 //
-// Kernels (one wave per block, kTileGauss Gaussians per block):
-//   k_tile_hist    per-block tile histogram (LDS atomics)
-//   k_tile_scan    per image: tile totals, tile ranges, per-block offsets
-//   k_image_scan   pair base of every image in the chunk
-//   k_tile_scatter stable scatter of Gaussian ids into tile lists; ranks of
-//                  equal tiles inside a 64-pair window come from a ballot match
+// The counting sort runs in two stable levels so that every block writes to
+// few output streams (a block of depth-consecutive Gaussians touches every
+// tile of the image; scattering straight into ~10^3 tile lists leaves as many
+// partially written cache lines open per block):
+//   level 1  depth-ordered Gaussians -> one list per tile row (a Gaussian
+//            appears in each row its rectangle spans), blocks of kTileGauss
+//            Gaussians, one output stream per tile row;
+//   level 2  one block per (image, tile row) walks its row list in order and
+//            expands each entry into the tiles of that row, one output stream
+//            per tile of the row.
+// The last depth-sort pass leaves every rectangle in depth order and row-list
+// entries carry their x-range, so no stage gathers rectangles by id.
+// Expansions are never written out: each kernel re-expands in LDS, balanced
+// over one wave.  Ranks of equal buckets inside a 64-entry window come from a
+// ballot match; a per-bucket cursor in LDS carries the rank across windows.
+//
+// Kernels:
+//   k_tile_hist       per-block tile and tile-row histograms (LDS atomics)
+//   k_tile_scan       per image: tile ranges, row ranges, per-block row offsets
+//   k_image_scan      pair and row-entry bases of every image of the chunk
+//   k_row_scatter     level 1
+//   k_rowtile_scatter level 2
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -38,61 +51,74 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
     return x;
 }
 
-// LDS staging of one 64-Gaussian group of a block.
-struct Group {
-    uint32_t excl[64];   // exclusive prefix of pair counts
-    uint32_t x0[64], nx[64], y0[64];
-    uint32_t g[64];
-};
-
-// Loads Gaussians [jb, jb + 64) n [.., j1) of image i into `grp`; returns the
-// number of pairs of the group.
-__device__ __forceinline__ uint32_t load_group(const ChunkDev& c, uint64_t n, int i, uint32_t jb, uint32_t j1,
-                                               Group& grp)
+// Lanes holding the same `key` (low `bits` bits) among lanes with `active`.
+__device__ __forceinline__ uint64_t match_key(uint32_t key, bool active, int bits)
 {
-    const int lane = __lane_id();
-    const uint32_t j = jb + lane;
-    const bool ok = j < j1;
-    uint32_t g = 0, cnt = 0, x0 = 0, nx = 1, y0 = 0;
-    if (ok) g = c.sv[1][(size_t)i * n + j];
-    if (ok && g < n) {      // guard: sorted ids are valid indices by construction
-        const uint2 r = c.rect[(size_t)i * n + g];
-        x0 = r.x & 0xFFFFu;
-        nx = (r.x >> 16) - x0;
-        y0 = r.y & 0xFFFFu;
-        cnt = nx * ((r.y >> 16) - y0);
+    uint64_t peers = __ballot(active);
+    for (int b = 0; b < bits; ++b) {
+        const bool v = (key >> b) & 1u;
+        const uint64_t m = __ballot(v);
+        peers &= v ? m : ~m;
     }
-    const uint32_t inc = wave_incl_scan(cnt);
-    grp.excl[lane] = inc - cnt;
-    grp.x0[lane] = x0;
-    grp.nx[lane] = nx;
-    grp.y0[lane] = y0;
-    grp.g[lane] = g;
-    return __shfl(inc, 63, 64);
+    return peers;
 }
 
-// Owner (group slot) and tile of pair p of the current group.
-__device__ __forceinline__ uint32_t pair_tile(const Group& grp, uint32_t p, int tiles_x, uint32_t* owner)
+// LDS staging of one group of 64 items and their expansion counts.
+struct Group {
+    uint32_t excl[64];   // exclusive prefix of the counts (counts are >= 1 for valid items)
+    uint32_t a[64];      // first bucket (x0 or y0)
+    uint32_t w[64];      // rectangle width (2D expansion)
+    uint32_t b[64];      // first row (2D expansion)
+    uint32_t g[64];      // Gaussian id
+};
+
+// Item owning expansion slot p: largest k with excl[k] <= p.
+__device__ __forceinline__ uint32_t owner(const Group& grp, uint32_t p)
 {
     int lo = 0;
 #pragma unroll
     for (int step = 32; step > 0; step >>= 1)
-        if (grp.excl[lo + step] <= p) lo += step;     // largest k with excl[k] <= p (counts are >= 1)
-    const uint32_t s = p - grp.excl[lo];
-    const uint32_t nx = grp.nx[lo];
-    uint32_t row = (uint32_t)((float)s * __builtin_amdgcn_rcpf((float)nx));
-    if (row * nx > s) --row;
-    else if ((row + 1) * nx <= s) ++row;
-    const uint32_t col = s - row * nx;
-    *owner = (uint32_t)lo;
-    return (grp.y0[lo] + row) * (uint32_t)tiles_x + grp.x0[lo] + col;
+        if (grp.excl[lo + step] <= p) lo += step;
+    return (uint32_t)lo;
 }
 
+// Publish a group: counts -> exclusive prefix; returns the group's total.
+__device__ __forceinline__ uint32_t publish(Group& grp, uint32_t cnt, uint32_t a, uint32_t w, uint32_t b, uint32_t g)
+{
+    const int lane = __lane_id();
+    const uint32_t inc = wave_incl_scan(cnt);
+    grp.excl[lane] = inc - cnt;
+    grp.a[lane] = a;
+    grp.w[lane] = w;
+    grp.b[lane] = b;
+    grp.g[lane] = g;
+    return __shfl(inc, 63, 64);
+}
+
+// Depth-ordered Gaussian j of image i: id and tile rectangle (x0, x1, y0, y1).
+__device__ __forceinline__ bool sorted_rect(const ChunkDev& c, uint64_t n, int i, uint32_t j, uint32_t j1, uint32_t* g,
+                                            uint32_t* x0, uint32_t* x1, uint32_t* y0, uint32_t* y1)
+{
+    *g = 0;
+    *x0 = *x1 = *y0 = *y1 = 0;
+    if (j >= j1) return false;
+    *g = c.sv[1][(size_t)i * n + j];
+    if (*g >= n) return false;      // guard: sorted ids are valid indices by construction
+    const uint2 r = c.srect[(size_t)i * n + j];
+    *x0 = r.x & 0xFFFFu;
+    *x1 = r.x >> 16;
+    *y0 = r.y & 0xFFFFu;
+    *y1 = r.y >> 16;
+    return *x1 > *x0 && *y1 > *y0;
+}
+
+// ------------------------------------------------------------------ counts
 __global__ __launch_bounds__(64) void k_tile_hist(ChunkDev c, uint64_t n)
 {
     extern __shared__ uint32_t lds[];
     Group& grp = *reinterpret_cast<Group*>(lds);
     uint32_t* hist = lds + sizeof(Group) / 4;
+    uint32_t* rhist = hist + c.t_max;
     const int i = blockIdx.y, b = blockIdx.x, lane = __lane_id();
     const uint32_t V = c.n ? c.vis_count[i] : 0u;
     const uint32_t j0 = (uint32_t)b * kTileGauss;
@@ -101,25 +127,39 @@ __global__ __launch_bounds__(64) void k_tile_hist(ChunkDev c, uint64_t n)
     const ImageInfo im = c.img[i];
     const int T = im.tiles_x * im.tiles_y;
     for (int t = lane; t < T; t += 64) hist[t] = 0;
+    for (int y = lane; y < im.tiles_y; y += 64) rhist[y] = 0;
     __syncthreads();
     for (uint32_t jb = j0; jb < j1; jb += 64) {
-        const uint32_t total = load_group(c, n, i, jb, j1, grp);
+        uint32_t g, x0, x1, y0, y1;
+        const bool ok = sorted_rect(c, n, i, jb + lane, j1, &g, &x0, &x1, &y0, &y1);
+        const uint32_t nx = ok ? x1 - x0 : 1;
+        const uint32_t total = publish(grp, ok ? nx * (y1 - y0) : 0, x0, nx, y0, g);
         __syncthreads();
         for (uint32_t p0 = 0; p0 < total; p0 += 64) {
             const uint32_t p = p0 + lane;
             if (p < total) {
-                uint32_t k;
-                const uint32_t t = pair_tile(grp, p, im.tiles_x, &k);
+                const uint32_t k = owner(grp, p);
+                const uint32_t s = p - grp.excl[k];
+                const uint32_t w = grp.w[k];
+                uint32_t row = (uint32_t)((float)s * __builtin_amdgcn_rcpf((float)w));
+                if (row * w > s) --row;
+                else if ((row + 1) * w <= s) ++row;
+                const uint32_t col = s - row * w;
+                const uint32_t ty = grp.b[k] + row;
+                const uint32_t t = ty * (uint32_t)im.tiles_x + grp.a[k] + col;
                 if (t < (uint32_t)T) atomicAdd(&hist[t], 1u);
+                if (col == 0 && ty < (uint32_t)im.tiles_y) atomicAdd(&rhist[ty], 1u);
             }
         }
         __syncthreads();
     }
     uint32_t* out = c.tile_hist + ((size_t)i * c.tile_blocks + b) * c.t_max;
     for (int t = lane; t < T; t += 64) out[t] = hist[t];
+    uint32_t* rout = c.row_hist + ((size_t)i * c.tile_blocks + b) * c.ty_max;
+    for (int y = lane; y < im.tiles_y; y += 64) rout[y] = rhist[y];
 }
 
-__device__ __forceinline__ uint32_t block_excl_scan256_t(uint32_t v, uint32_t* total, uint32_t* lds8)
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* total, uint32_t* lds8)
 {
     const int lane = __lane_id();
     const int w = threadIdx.x >> 6;
@@ -138,74 +178,96 @@ __device__ __forceinline__ uint32_t block_excl_scan256_t(uint32_t v, uint32_t* t
     return pre + x - v;
 }
 
-// One block of 256 threads per image.
-__global__ __launch_bounds__(256) void k_tile_scan(ChunkDev c)
+// Per image (256 threads): bins summed over the image's blocks, exclusive scan
+// over bins -> [start, end) per bin; optionally per-block offsets in place.
+__device__ uint32_t scan_bins(uint32_t* H, int nb, int stride, int nbins, uint32_t* range, bool block_offsets,
+                              uint32_t* lds8)
 {
-    __shared__ uint32_t lds8[8];
-    const int i = blockIdx.x, tid = threadIdx.x;
-    const uint32_t V = c.n ? c.vis_count[i] : 0u;
-    const int nb = (int)((V + kTileGauss - 1) / kTileGauss);
-    const ImageInfo im = c.img[i];
-    const int T = im.tiles_x * im.tiles_y;
-    uint32_t* H = c.tile_hist + (size_t)i * c.tile_blocks * c.t_max;
-    uint32_t* R = c.tile_range + (size_t)i * c.t_max * 2;
+    const int tid = threadIdx.x;
     uint32_t run = 0;
-    for (int t0 = 0; t0 < T; t0 += 256) {
+    for (int t0 = 0; t0 < nbins; t0 += 256) {
         const int t = t0 + tid;
         uint32_t tot = 0;
-        if (t < T)
-            for (int b = 0; b < nb; ++b) tot += H[(size_t)b * c.t_max + t];
+        if (t < nbins)
+            for (int b = 0; b < nb; ++b) tot += H[(size_t)b * stride + t];
         uint32_t chunk_total;
-        const uint32_t start = run + block_excl_scan256_t(tot, &chunk_total, lds8);
-        if (t < T) {
-            R[2 * t] = start;
-            R[2 * t + 1] = start + tot;
-            uint32_t o = start;
-            for (int b = 0; b < nb; ++b) {
-                const uint32_t v = H[(size_t)b * c.t_max + t];
-                H[(size_t)b * c.t_max + t] = o;
-                o += v;
+        const uint32_t start = run + block_excl_scan256(tot, &chunk_total, lds8);
+        if (t < nbins) {
+            range[2 * t] = start;
+            range[2 * t + 1] = start + tot;
+            if (block_offsets) {
+                uint32_t o = start;
+                for (int b = 0; b < nb; ++b) {
+                    const uint32_t v = H[(size_t)b * stride + t];
+                    H[(size_t)b * stride + t] = o;
+                    o += v;
+                }
             }
         }
         run += chunk_total;
     }
-    if (tid == 0) c.pair_count[i] = run;
+    return run;
 }
 
-// Single block: pair_base[i] = sum of P over images before i; pair_base[n_img] = total.
+__global__ __launch_bounds__(256) void k_tile_scan(ChunkDev c)
+{
+    __shared__ uint32_t lds8[8];
+    const int i = blockIdx.x;
+    const uint32_t V = c.n ? c.vis_count[i] : 0u;
+    const int nb = (int)((V + kTileGauss - 1) / kTileGauss);
+    const ImageInfo im = c.img[i];
+    const uint32_t P = scan_bins(c.tile_hist + (size_t)i * c.tile_blocks * c.t_max, nb, c.t_max,
+                                 im.tiles_x * im.tiles_y, c.tile_range + (size_t)i * c.t_max * 2, false, lds8);
+    const uint32_t Rn = scan_bins(c.row_hist + (size_t)i * c.tile_blocks * c.ty_max, nb, c.ty_max, im.tiles_y,
+                                  c.row_range + (size_t)i * c.ty_max * 2, true, lds8);
+    if (threadIdx.x == 0) {
+        c.pair_count[i] = P;
+        c.row_count[i] = Rn;
+    }
+}
+
+// Single block: exclusive prefixes of P_i and R_i over the chunk's images.
 __global__ __launch_bounds__(256) void k_image_scan(ChunkDev c)
 {
-    __shared__ uint64_t part[256];
+    __shared__ uint64_t part[2][256];
     const int tid = threadIdx.x;
     const int per = (c.n_img + 255) / 256;
-    uint64_t s = 0;
-    for (int k = 0; k < per; ++k) {
-        const int i = tid * per + k;
-        if (i < c.n_img) s += c.pair_count[i];
-    }
-    part[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-        uint64_t run = 0;
-        for (int k = 0; k < 256; ++k) {
-            const uint64_t v = part[k];
-            part[k] = run;
-            run += v;
-        }
-        c.pair_base[c.n_img] = run;
-    }
-    __syncthreads();
-    uint64_t run = part[tid];
+    uint64_t sp = 0, sr = 0;
     for (int k = 0; k < per; ++k) {
         const int i = tid * per + k;
         if (i < c.n_img) {
-            c.pair_base[i] = run;
-            run += c.pair_count[i];
+            sp += c.pair_count[i];
+            sr += c.row_count[i];
+        }
+    }
+    part[0][tid] = sp;
+    part[1][tid] = sr;
+    __syncthreads();
+    if (tid < 2) {
+        uint64_t run = 0;
+        for (int k = 0; k < 256; ++k) {
+            const uint64_t v = part[tid][k];
+            part[tid][k] = run;
+            run += v;
+        }
+        if (tid == 0) c.pair_base[c.n_img] = run;
+        else c.row_base[c.n_img] = run;
+    }
+    __syncthreads();
+    uint64_t rp = part[0][tid], rr = part[1][tid];
+    for (int k = 0; k < per; ++k) {
+        const int i = tid * per + k;
+        if (i < c.n_img) {
+            c.pair_base[i] = rp;
+            c.row_base[i] = rr;
+            rp += c.pair_count[i];
+            rr += c.row_count[i];
         }
     }
 }
 
-__global__ __launch_bounds__(64) void k_tile_scatter(ChunkDev c, uint64_t n, int tile_bits)
+// ------------------------------------------------------------------ level 1
+__global__ __launch_bounds__(64) void k_row_scatter(ChunkDev c, uint64_t n, int row_bits)
 {
     extern __shared__ uint32_t lds[];
     Group& grp = *reinterpret_cast<Group*>(lds);
@@ -216,32 +278,85 @@ __global__ __launch_bounds__(64) void k_tile_scatter(ChunkDev c, uint64_t n, int
     if (j0 >= V) return;
     const uint32_t j1 = min(j0 + (uint32_t)kTileGauss, V);
     const ImageInfo im = c.img[i];
-    const int T = im.tiles_x * im.tiles_y;
-    const uint32_t* off = c.tile_hist + ((size_t)i * c.tile_blocks + b) * c.t_max;
-    for (int t = lane; t < T; t += 64) cursor[t] = off[t];
-    uint32_t* out = c.pairs + c.pair_base[i];
-    const uint32_t P = c.pair_count[i];
+    const uint32_t TY = (uint32_t)im.tiles_y;
+    const uint32_t* off = c.row_hist + ((size_t)i * c.tile_blocks + b) * c.ty_max;
+    for (uint32_t y = lane; y < TY; y += 64) cursor[y] = off[y];
+    uint2* out = c.rows + c.row_base[i];
+    const uint32_t Rn = c.row_count[i];
     const uint64_t lt = lanemask_lt64();
     __syncthreads();
     for (uint32_t jb = j0; jb < j1; jb += 64) {
-        const uint32_t total = load_group(c, n, i, jb, j1, grp);
+        uint32_t g, x0, x1, y0, y1;
+        const bool okg = sorted_rect(c, n, i, jb + lane, j1, &g, &x0, &x1, &y0, &y1);
+        const uint32_t total = publish(grp, okg ? y1 - y0 : 0, y0, x0 | (x1 << 16), 0, g);
         __syncthreads();
         for (uint32_t p0 = 0; p0 < total; p0 += 64) {
             const uint32_t p = p0 + lane;
             bool ok = p < total;
-            uint32_t k = 0, t = 0;
-            if (ok) t = pair_tile(grp, p, im.tiles_x, &k);
-            ok = ok && t < (uint32_t)T;
-            uint64_t peers = __ballot(ok);
-            for (int bit = 0; bit < tile_bits; ++bit) {
-                const bool v = (t >> bit) & 1u;
-                const uint64_t m = __ballot(v);
-                peers &= v ? m : ~m;
-            }
+            uint32_t k = 0, y = 0;
             if (ok) {
-                const uint32_t basev = cursor[t];
+                k = owner(grp, p);
+                y = grp.a[k] + (p - grp.excl[k]);
+                ok = y < TY;
+            }
+            const uint64_t peers = match_key(y, ok, row_bits);
+            if (ok) {
+                const uint32_t basev = cursor[y];
                 const uint32_t pos = basev + (uint32_t)__popcll(peers & lt);
-                if (lane == __ffsll((unsigned long long)peers) - 1) cursor[t] = basev + (uint32_t)__popcll(peers);
+                if (lane == __ffsll((unsigned long long)peers) - 1) cursor[y] = basev + (uint32_t)__popcll(peers);
+                if (pos < Rn) out[pos] = make_uint2(grp.g[k], grp.w[k]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ level 2
+__global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, int col_bits)
+{
+    extern __shared__ uint32_t lds[];
+    Group& grp = *reinterpret_cast<Group*>(lds);
+    uint32_t* cursor = lds + sizeof(Group) / 4;
+    const int i = blockIdx.y, y = blockIdx.x, lane = __lane_id();
+    const ImageInfo im = c.img[i];
+    if (y >= im.tiles_y) return;
+    const uint32_t TX = (uint32_t)im.tiles_x;
+    const uint32_t* rr = c.row_range + ((size_t)i * c.ty_max + y) * 2;
+    const uint32_t r0 = rr[0], r1 = rr[1];
+    if (r0 >= r1) return;
+    const uint2* list = c.rows + c.row_base[i];
+    const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX) * 2;
+    for (uint32_t x = lane; x < TX; x += 64) cursor[x] = tr[2 * x];
+    uint32_t* out = c.pairs + c.pair_base[i];
+    const uint32_t P = c.pair_count[i];
+    const uint64_t lt = lanemask_lt64();
+    __syncthreads();
+    for (uint32_t e0 = r0; e0 < r1; e0 += 64) {
+        const uint32_t e = e0 + lane;
+        uint32_t g = 0, x0 = 0, cnt = 0;
+        if (e < r1) {
+            const uint2 ent = list[e];
+            g = ent.x;
+            x0 = ent.y & 0xFFFFu;
+            const uint32_t x1 = ent.y >> 16;
+            cnt = x1 > x0 ? x1 - x0 : 0;
+        }
+        const uint32_t total = publish(grp, cnt, x0, 0, 0, g);
+        __syncthreads();
+        for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+            const uint32_t p = p0 + lane;
+            bool ok = p < total;
+            uint32_t k = 0, x = 0;
+            if (ok) {
+                k = owner(grp, p);
+                x = grp.a[k] + (p - grp.excl[k]);
+                ok = x < TX;
+            }
+            const uint64_t peers = match_key(x, ok, col_bits);
+            if (ok) {
+                const uint32_t basev = cursor[x];
+                const uint32_t pos = basev + (uint32_t)__popcll(peers & lt);
+                if (lane == __ffsll((unsigned long long)peers) - 1) cursor[x] = basev + (uint32_t)__popcll(peers);
                 if (pos < P) out[pos] = grp.g[k];
             }
         }
@@ -264,17 +379,22 @@ __global__ __launch_bounds__(256) void k_debug_keys(ChunkDev c, int image, uint6
     }
 }
 
-}  // namespace
+int bits_for(int v)
+{
+    int b = 1;
+    while ((1 << b) < v) ++b;
+    return b;
+}
 
-static size_t tile_lds_bytes(const ChunkDev& c) { return sizeof(Group) + (size_t)c.t_max * 4; }
+}  // namespace
 
 hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t stream)
 {
     if (c.n_img == 0) return hipSuccess;
     const uint64_t n = (uint64_t)s.n;
     if (n > 0) {
-        hipLaunchKernelGGL(k_tile_hist, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(64),
-                           tile_lds_bytes(c), stream, c, n);
+        const size_t lds = sizeof(Group) + (size_t)(c.t_max + c.ty_max) * 4;
+        hipLaunchKernelGGL(k_tile_hist, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(64), lds, stream, c, n);
     }
     hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)c.n_img), dim3(256), 0, stream, c);
     hipLaunchKernelGGL(k_image_scan, dim3(1), dim3(256), 0, stream, c);
@@ -284,10 +404,11 @@ hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t s
 hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, hipStream_t stream)
 {
     if (c.n_img == 0 || s.n == 0) return hipSuccess;
-    int bits = 1;
-    while ((1 << bits) < c.t_max) ++bits;
-    hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(64),
-                       tile_lds_bytes(c), stream, c, (uint64_t)s.n, bits);
+    const uint64_t n = (uint64_t)s.n;
+    hipLaunchKernelGGL(k_row_scatter, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(64),
+                       sizeof(Group) + (size_t)c.ty_max * 4, stream, c, n, bits_for(c.ty_max));
+    hipLaunchKernelGGL(k_rowtile_scatter, dim3((unsigned)c.ty_max, (unsigned)c.n_img), dim3(64),
+                       sizeof(Group) + (size_t)c.tx_max * 4, stream, c, n, bits_for(c.tx_max));
     return hipGetLastError();
 }
 
