@@ -17,8 +17,10 @@
 // concave: the maximum is at the mean if it lies inside, else on an edge,
 // where the 1D maximiser is clamped).  Gaussians whose bound stays below
 // log2(1/255) - kCullMargin cannot reach alpha >= 1/255 at any pixel of the
-// block; the ballot of the survivors is walked bit by bit, so each wave only
-// evaluates Gaussians that touch its pixels.  kCullMargin absorbs binary32
+// block (narrowed to the bounding box of its still-live pixels); the ballot of
+// the survivors is walked bit by bit, so each wave only evaluates Gaussians
+// that touch its pixels, and skips the blending work when no live pixel
+// reaches the alpha threshold.  kCullMargin absorbs binary32
 // rounding of the per-pixel evaluation, so culling never removes a Gaussian a
 // pixel would have accepted and results do not depend on the tiling.
 #include "gsr_internal.h"
@@ -167,13 +169,26 @@ __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, Chu
         if (b0 + kBatch < end) fetch(b0 + kBatch);
         const int cnt = (int)min((uint32_t)kBatch, end - b0);
         for (int sub = 0; sub < cnt && wave_live; sub += 64) {
-            // ballot: which of these 64 Gaussians can touch this wave's block
+            // pixel-centre rectangle still to be shaded: the live pixels' bounding box
+            float lx0 = wx0, lx1 = wx1, ly0 = wy0, ly1 = wy1;
+            if (PPT == 1) {
+                const uint64_t M = __ballot(live[0]);             // lane = 8 * row + column
+                uint64_t cm = M | (M >> 32);
+                cm |= cm >> 16;
+                cm |= cm >> 8;
+                cm &= 0xFFull;
+                lx0 = wx0 + (float)__builtin_ctzll(cm);
+                lx1 = wx0 + (float)(63 - __builtin_clzll(cm));
+                ly0 = wy0 + (float)(__builtin_ctzll(M) >> 3);
+                ly1 = wy0 + (float)((63 - __builtin_clzll(M)) >> 3);
+            }
+            // ballot: which of these 64 Gaussians can touch the live pixels
             const int jl = sub + lane;
             bool keep = false;
             if (jl < cnt) {
                 const float4 a = sA[buf][jl];
                 const float4 bq = sB[buf][jl];
-                const float m = max_logalpha_rect(a.z, a.w, bq.x, bq.y, wx0 - a.x, wx1 - a.x, wy0 - a.y, wy1 - a.y);
+                const float m = max_logalpha_rect(a.z, a.w, bq.x, bq.y, lx0 - a.x, lx1 - a.x, ly0 - a.y, ly1 - a.y);
                 keep = m >= kLogAlphaMin - kCullMargin;
             }
             uint64_t mask = __ballot(keep);
@@ -182,14 +197,23 @@ __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, Chu
                 mask &= mask - 1ull;
                 const float4 a = sA[buf][j];
                 const float4 bq = sB[buf][j];
-                const float4 col = sC[buf][j];
+                float pw[PPT];
+                bool tk[PPT];
+                bool anyt = false;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     const float dx = px[k] - a.x;
                     const float dy = py[k] - a.y;
-                    const float pw = fmaf(dx, fmaf(a.z, dx, a.w * dy), fmaf(bq.x * dy, dy, bq.y));
-                    const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(pw));
-                    const bool take = live[k] && pw >= kLogAlphaMin;
+                    pw[k] = fmaf(dx, fmaf(a.z, dx, a.w * dy), fmaf(bq.x * dy, dy, bq.y));
+                    tk[k] = live[k] && pw[k] >= kLogAlphaMin;
+                    anyt = anyt || tk[k];
+                }
+                if (__ballot(anyt) == 0ull) continue;       // no live pixel of the wave reaches 1/255
+                const float4 col = sC[buf][j];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(pw[k]));
+                    const bool take = tk[k];
                     const float Tn = fmaf(-T[k], alpha, T[k]);
                     const bool stop = take && Tn < 1e-4f;
                     const float wgt = (take && !stop) ? alpha * T[k] : 0.0f;

@@ -31,6 +31,8 @@
 //   k_rowtile_scatter level 2
 #include "gsr_internal.h"
 
+#include <algorithm>
+
 namespace gsr {
 namespace {
 
@@ -312,21 +314,28 @@ __global__ __launch_bounds__(64) void k_row_scatter(ChunkDev c, uint64_t n, int 
 }
 
 // ------------------------------------------------------------------ level 2
-__global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, int col_bits)
+// Block (y * n_groups + cg, i): tile row y of image i, tile columns
+// [cg * ceil(TX / n_groups), ...) -- every column group walks the whole row
+// list and emits only its own columns' pairs, with its own cursors.
+__global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, int col_bits, int n_groups)
 {
     extern __shared__ uint32_t lds[];
     Group& grp = *reinterpret_cast<Group*>(lds);
     uint32_t* cursor = lds + sizeof(Group) / 4;
-    const int i = blockIdx.y, y = blockIdx.x, lane = __lane_id();
+    const int i = blockIdx.y, lane = __lane_id();
+    const int y = blockIdx.x / n_groups, cg = blockIdx.x - y * n_groups;
     const ImageInfo im = c.img[i];
     if (y >= im.tiles_y) return;
     const uint32_t TX = (uint32_t)im.tiles_x;
+    const uint32_t gw = (TX + n_groups - 1) / n_groups;
+    const uint32_t c0 = min(TX, (uint32_t)cg * gw), c1 = min(TX, c0 + gw);
+    if (c0 >= c1) return;
     const uint32_t* rr = c.row_range + ((size_t)i * c.ty_max + y) * 2;
     const uint32_t r0 = rr[0], r1 = rr[1];
     if (r0 >= r1) return;
     const uint2* list = c.rows + c.row_base[i];
     const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX) * 2;
-    for (uint32_t x = lane; x < TX; x += 64) cursor[x] = tr[2 * x];
+    for (uint32_t x = c0 + lane; x < c1; x += 64) cursor[x] = tr[2 * x];
     uint32_t* out = c.pairs + c.pair_base[i];
     const uint32_t P = c.pair_count[i];
     const uint64_t lt = lanemask_lt64();
@@ -337,8 +346,8 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
         if (e < r1) {
             const uint2 ent = list[e];
             g = ent.x;
-            x0 = ent.y & 0xFFFFu;
-            const uint32_t x1 = ent.y >> 16;
+            x0 = max(ent.y & 0xFFFFu, c0);
+            const uint32_t x1 = min(ent.y >> 16, c1);
             cnt = x1 > x0 ? x1 - x0 : 0;
         }
         const uint32_t total = publish(grp, cnt, x0, 0, 0, g);
@@ -350,7 +359,7 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
             if (ok) {
                 k = owner(grp, p);
                 x = grp.a[k] + (p - grp.excl[k]);
-                ok = x < TX;
+                ok = x < c1;
             }
             const uint64_t peers = match_key(x, ok, col_bits);
             if (ok) {
@@ -407,8 +416,9 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, hipStream_t
     const uint64_t n = (uint64_t)s.n;
     hipLaunchKernelGGL(k_row_scatter, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(64),
                        sizeof(Group) + (size_t)c.ty_max * 4, stream, c, n, bits_for(c.ty_max));
-    hipLaunchKernelGGL(k_rowtile_scatter, dim3((unsigned)c.ty_max, (unsigned)c.n_img), dim3(64),
-                       sizeof(Group) + (size_t)c.tx_max * 4, stream, c, n, bits_for(c.tx_max));
+    const int groups = 1;   // splitting a row into column groups re-reads the row list and measured slower
+    hipLaunchKernelGGL(k_rowtile_scatter, dim3((unsigned)(c.ty_max * groups), (unsigned)c.n_img), dim3(64),
+                       sizeof(Group) + (size_t)c.tx_max * 4, stream, c, n, bits_for(c.tx_max), groups);
     return hipGetLastError();
 }
 
