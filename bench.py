@@ -35,6 +35,89 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def run_serving(R, args):
+    """Replay the first `serve_seconds` of the seeded Poisson trace (200 req/s,
+    1-256 envs, 128x128 / 320x240 / 640x480, FP16 scenes of 50k-1M Gaussians
+    plus 4-16 bodies) in real time through the continuous-batching server.
+    Latency = submission to completion on the device."""
+    import threading
+    import numpy as np
+    import torch
+    from paper_2604_25459_amd import gsr, synth
+
+    dev = torch.device("cuda", 0)
+    trace = [r for r in synth.serving_trace() if r.arrival_s < args.serve_seconds]
+    K = max(1, min(args.serve_scenes, 32))
+    log(f"[serve] {len(trace)} requests over {args.serve_seconds:.0f} s, pool of {K} resident scenes (FP16)")
+    scenes = [synth.serving_pool_scene(k) for k in range(K)]
+    sids = [R.add_synth_scene(sc, "f16") for sc in scenes]
+    prepared = []
+    for idx, req in enumerate(trace):
+        sc = scenes[req.scene % K]
+        b = synth.serving_batch(req, sc, idx)
+        prepared.append((req, req.scene % K, b))
+    S = gsr.Server(R, n_streams=args.serve_streams)
+    # warm the server's workspaces (one request per resolution)
+    for w, h in synth.SERVE_RESOLUTIONS:
+        b = synth.serving_batch(synth.Request(0.0, 4, w, h, 0), scenes[0], 10**6 + w)
+        cams, vm, poses = gsr.batch_tensors(b)
+        rgb, depth, _ = R.alloc_outputs(cams, b.n_envs)
+        torch.cuda.synchronize()
+        S.wait(S.submit(sids[0], cams, vm, poses, rgb, depth))
+    base = S.stats()
+    tickets = []
+    lock = threading.Lock()
+    done_images = [0]
+    lat = []
+    t0 = time.perf_counter()
+
+    def producer():
+        for req, si, b in prepared:
+            now = time.perf_counter() - t0
+            if req.arrival_s > now:
+                time.sleep(req.arrival_s - now)
+            cams, vm, poses = gsr.batch_tensors(b)
+            rgb, depth, _ = R.alloc_outputs(cams, b.n_envs)
+            torch.cuda.current_stream(dev).synchronize()
+            t = S.submit(sids[si], cams, vm, poses, rgb, depth)
+            with lock:
+                tickets.append((t, b.n_envs * b.n_cams))
+        with lock:
+            tickets.append((None, 0))
+
+    th = threading.Thread(target=producer)
+    th.start()
+    k = 0
+    while True:
+        with lock:
+            item = tickets[k] if k < len(tickets) else False
+        if item is False:
+            time.sleep(0.0005)
+            continue
+        t, n_img = item
+        if t is None:
+            break
+        info = S.wait(t)
+        lat.append(info["t_complete_us"] - info["t_submit_us"])
+        done_images[0] += n_img
+        k += 1
+    wall = time.perf_counter() - t0
+    th.join()
+    st = S.stats()
+    S.close()
+    for sid in sids:
+        R.remove_scene(sid)
+    n = st["completed"] - base["completed"]
+    lat_ms = np.asarray(lat, np.float64) / 1000.0
+    out = {"requests": n, "arrival_rate_hz": 200.0, "trace_seconds": args.serve_seconds, "scenes": K,
+           "streams": args.serve_streams, "latency_p50_ms": float(np.percentile(lat_ms, 50)),
+           "latency_p99_ms": float(np.percentile(lat_ms, 99)), "latency_max_ms": float(lat_ms.max()),
+           "env_frames_per_s": done_images[0] / wall, "wall_s": wall,
+           "mean_batch_requests": st["mean_batch_requests"], "batches": st["batches"] - base["batches"]}
+    log(f"[serve] {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,6 +129,10 @@ def main():
     ap.add_argument("--plain-envs", type=int, default=64, help="envs timed on the plain per-env path (0 = skip)")
     ap.add_argument("--cpu-images", type=int, default=3, help="images rendered by the CPU oracle (0 = skip)")
     ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds of the Poisson serving trace replayed in real time (0 = skip)")
+    ap.add_argument("--serve-scenes", type=int, default=8, help="resident scenes in the serving pool (trace uses 32)")
+    ap.add_argument("--serve-streams", type=int, default=2)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -109,6 +196,8 @@ def main():
         plain = {"value": pe / psec, "unit": "env-frames/s", "envs_timed": pe}
         log(f"[bench] plain path {plain['value']:.1f} env-frames/s over {pe} envs")
 
+    serving = run_serving(R, args) if args.serve_seconds > 0 else None
+
     # oracle on the host cores, bounded sample of the same workload
     cpu = None
     evals_per_pixel = None
@@ -153,6 +242,7 @@ def main():
                    "resolution": [[c.width, c.height] for c in cams], "gaussians": scene.n,
                    "sh_degree": scene.sh_degree, "storage": args.storage, "tile": args.tile},
         "plain_path": plain,
+        "serving": serving,
         "stages_ms_per_step": {k: v / args.steps for k, v in st.items() if k in R.STAGES},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -25,8 +25,8 @@
  *   - pixel (x, y) has its centre at (x + 0.5, y + 0.5);
  *   - images are ordered camera-slot-major: image i = c * n_envs + e.
  *
- * Threading: a context may be used from several host threads; calls on one
- * context are serialised internally except gsr_submit / gsr_wait of a server.
+ * Threading: a context may be used from several host threads; render calls
+ * on different streams run concurrently, each with its own working memory.
  *
  * Errors: every call returns GSR_OK (0) or a negative GSR_E_* code.  Arguments
  * are validated before any device work is enqueued; on failure nothing is
@@ -177,6 +177,63 @@ int gsr_render_plain(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
  * pairs (n_pairs is still reported). */
 int gsr_debug_bins(gsr_ctx* ctx, const gsr_render_desc* desc, int image, gsr_bins_out* out);
 int gsr_debug_project(gsr_ctx* ctx, const gsr_render_desc* desc, int image, gsr_proj_out* out);
+
+/* ---- serving ---------------------------------------------------------
+ * A server renders requests from several producers (e.g. RL workers) as they
+ * arrive, with continuous batching: worker threads, each with its own device
+ * stream (default priority) and working memory, take the oldest pending
+ * request and merge later pending requests of the same scene into one batched
+ * launch (any resolutions, up to 8 image sizes and max_batch_images images);
+ * requests that arrive while batches run join the next batch a worker forms,
+ * and batches on different streams overlap on the device.  A request is
+ * admitted when its estimated working memory fits in memory_budget next to
+ * the requests in flight; it waits in the queue otherwise.  Results are
+ * identical to rendering the request alone: no per-image computation depends
+ * on the batch. */
+typedef struct {
+    int n_streams;          /* concurrent batches (worker threads and streams), 1..8; 0 = 2 */
+    int max_batch_images;   /* most images merged into one batch; 0 = 4096 */
+    int64_t memory_budget;  /* bytes of working memory for admitted requests in flight; 0 = 32 GiB */
+    int reserved[8];
+} gsr_server_cfg;
+
+typedef struct {
+    int status;             /* GSR_OK or the error code of the request's batch */
+    int n_images;           /* images of the request */
+    int64_t batch_id;       /* batch the request was rendered in */
+    int batch_requests;     /* requests merged into that batch */
+    int batch_images;       /* images of that batch */
+    int64_t t_submit_us;    /* steady-clock microseconds: submission, */
+    int64_t t_admit_us;     /* admission into a batch, */
+    int64_t t_start_us;     /* start of the batch's launches, */
+    int64_t t_complete_us;  /* completion of the batch on the device */
+} gsr_req_info;
+
+typedef struct {
+    int64_t submitted, completed, rejected, pending, batches, images;
+    int64_t in_flight_bytes, in_flight_bytes_max;
+    double latency_p50_us, latency_p99_us, latency_mean_us, latency_max_us;   /* completed requests */
+    double mean_batch_requests;
+} gsr_stats;
+
+/* Starts the worker threads.  `cfg` may be NULL.  The context must outlive the
+ * server. */
+int gsr_server_create(gsr_ctx* ctx, const gsr_server_cfg* cfg, gsr_server** out);
+/* Queues a render request; thread-safe, non-blocking.  The descriptor is
+ * validated (as gsr_render) and copied, including its camera array; its device
+ * buffers (viewmats, body_poses, outputs) must stay valid and untouched until
+ * gsr_wait reports the request complete.  GSR_E_REJECTED if the request alone
+ * exceeds memory_budget. */
+int gsr_submit(gsr_server* srv, const gsr_render_desc* desc, uint64_t* ticket);
+/* Waits for a request: timeout_us < 0 waits forever, 0 polls.  Returns the
+ * request's status (GSR_E_TIMEOUT if it is not complete yet); once a completed
+ * request has been reported its ticket is released (GSR_E_NOT_FOUND after). */
+int gsr_wait(gsr_server* srv, uint64_t ticket, int64_t timeout_us, gsr_req_info* info);
+/* Counters and latency percentiles (submission to completion) so far. */
+int gsr_server_stats(gsr_server* srv, gsr_stats* stats);
+/* Finishes every queued and running request, stops the workers, frees the
+ * server.  NULL is accepted. */
+int gsr_server_destroy(gsr_server* srv);
 
 /* Stage timers of a context created with profile = 1: device milliseconds
  * accumulated over the renders since the last reset, measured with HIP events

@@ -19,17 +19,21 @@ constexpr int kMaxShDegree = 3;
 // Attribute storage formats of a resident scene.
 enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
 
-// Per-image description inside one launch chunk (device resident).
+// Per-image description inside one launch (device resident).  Images of one
+// launch may come from several render requests: every image carries its own
+// input offsets and output pointers.
 struct ImageInfo {
     int width, height;
     int tiles_x, tiles_y;
     float fx, fy, cx, cy, near_plane;
-    int cam;              // camera slot c
-    int env;              // environment e
+    uint32_t key_tile_base;   // first global tile id of the image in its request (sort keys)
+    uint32_t vm_off;          // float offset of the image's world->camera [R | t] in the viewmat array
+    uint32_t pose_off;        // float offset of the image's env body poses [B][7] in the pose array
+    float bg[3];              // background colour of the image's request
     int pad0;
-    uint32_t key_tile_base;   // first global tile id of the image in the whole batch (sort keys)
-    uint32_t pad1;
-    uint64_t out_pixel;   // index of the image's first pixel in the caller's output (camera-slot-major)
+    float* out_rgb;           // first pixel of the image: [H][W][3]
+    float* out_depth;         // [H][W]
+    float* out_alpha;         // [H][W] or null
 };
 
 // Resident scene, device pointers.
@@ -97,7 +101,7 @@ constexpr int kTileGauss = 4096;
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `stream` and return hipGetLastError().
 hipError_t launch_compose(const SceneDev& s, const ChunkDev& c, const float* viewmats, const float* poses,
-                          int n_envs_total, hipStream_t stream);
+                          hipStream_t stream);
 hipError_t launch_project(const SceneDev& s, const ChunkDev& c, int ts, float cutoff, int img_per_thread,
                           hipStream_t stream);
 hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
@@ -110,10 +114,6 @@ struct RasterParams {
     int n_segs;
     RasterSeg segs[kMaxSegs];
     uint32_t n_blocks;
-    float bg[3];
-    float* out_rgb;
-    float* out_depth;
-    float* out_alpha;      // may be null
 };
 hipError_t launch_raster(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream);
 

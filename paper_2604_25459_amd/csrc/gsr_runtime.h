@@ -1,0 +1,119 @@
+// Host runtime internals shared by the C ABI (gsr_api.cpp) and the serving
+// loop (gsr_server.cpp): contexts, resident scenes, working-memory pools and
+// the launch sequence of the batched renderer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gsr.h"
+#include "gsr_internal.h"
+
+namespace gsr {
+
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define GSR_HIP_TRY(expr)                                       \
+    do {                                                        \
+        hipError_t _e = (expr);                                 \
+        if (_e != hipSuccess) return ::gsr::hip_fail(_e, #expr); \
+    } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need);
+    void release();
+    template <class T>
+    T* as() const
+    {
+        return static_cast<T*>(p);
+    }
+};
+
+struct SceneRes {
+    SceneDev dev{};
+    DevBuf pos, rot, scale, sh, body_off;
+    int64_t bytes = 0;
+    hipEvent_t last_use = nullptr;   // recorded after the last render that used the scene
+    bool used = false;
+    std::atomic<int> in_calls{0};     // render calls currently enqueuing work on this scene
+    ~SceneRes();
+};
+
+// Working memory of one render call at a time.
+struct Workspace {
+    DevBuf img, xform, keyz, rect, srect, rec, sk0, sk1, sv0, sv1, sort_hist, vis_count, tile_hist, tile_range,
+        pair_count, pair_base, pairs, row_hist, row_range, row_count, row_base, rows, debug, stage_vm, stage_pose;
+    uint64_t* h_total = nullptr;   // pinned: [0] pairs, [1] row entries of the current chunk
+    ImageInfo* h_img = nullptr;    // pinned staging for image descriptions
+    size_t h_img_cap = 0;
+    hipEvent_t ev_total = nullptr, ev_done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool used = false;      // ev_done has been recorded at least once
+    bool in_call = false;   // owned by a render call right now
+    ~Workspace();
+};
+
+// HIP events bracketing the pipeline stages of one chunk (profile option).
+struct StageEvents {
+    hipEvent_t e[6] = {};
+};
+
+// Images of one launch sequence (possibly from several requests), grouped so
+// that images of equal size are contiguous.
+struct RenderJob {
+    std::vector<ImageInfo> imgs;
+    const float* viewmats = nullptr;   // base of ImageInfo::vm_off
+    const float* poses = nullptr;      // base of ImageInfo::pose_off
+};
+
+enum class Mode { kRender, kBins, kProject };
+
+struct ChunkPlan {
+    int chunk;          // images per chunk
+    int t_max;          // max tiles of any image
+    int tx_max, ty_max; // max tile columns / rows of any image
+    int sort_blocks, tile_blocks;
+};
+
+// Validated per-request image list of a render descriptor (camera-slot-major).
+std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies);
+int validate_desc(const gsr_ctx* ctx, const gsr_render_desc* d, const SceneRes* sc, bool need_outputs);
+size_t image_bytes_estimate(const SceneRes* sc, int width, int height, int ts);
+ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain);
+hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, size_t n_images_total);
+
+// Enqueue the whole job on `st` (blocks once per chunk for its pair count).
+int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, hipStream_t st, bool plain);
+
+// Scene lookup that pins the scene against destruction; release_scene unpins.
+SceneRes* acquire_scene(gsr_ctx* ctx, uint64_t id);
+void release_scene(SceneRes* sc);
+// Records that the scene is used by work enqueued on `st` (GSR_E_BUSY on destroy until it completes).
+int mark_scene_use(gsr_ctx* ctx, SceneRes* sc, hipStream_t st);
+// A workspace no other call owns (caller holds ctx->mu).
+Workspace* acquire_workspace_locked(gsr_ctx* ctx, hipStream_t stream);
+
+}  // namespace gsr
+
+struct gsr_ctx {
+    int device = 0;
+    gsr_options opt{};
+    std::mutex mu;                                   // scenes, pool, timers
+    std::map<uint64_t, std::unique_ptr<gsr::SceneRes>> scenes;
+    uint64_t next_id = 1;
+    std::vector<std::unique_ptr<gsr::Workspace>> pool;
+    std::vector<gsr::StageEvents> pending;            // recorded, not yet read
+    double stage_ms[5] = {0, 0, 0, 0, 0};
+    double raster_launches = 0, renders = 0;
+    std::atomic<bool> poisoned{false};
+};

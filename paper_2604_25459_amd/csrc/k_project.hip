@@ -77,7 +77,7 @@ __device__ __forceinline__ void mat3_mul(const float A[9], const float B[9], flo
 // One thread per (image, body slot).  xform row: A (9, row-major), a (3),
 // camera centre expressed in the slot's local frame (3), unused (1).
 __global__ __launch_bounds__(256) void k_compose(SceneDev s, ChunkDev c, const float* __restrict__ viewmats,
-                                                 const float* __restrict__ poses, int n_envs_total)
+                                                 const float* __restrict__ poses)
 {
     const int slots = s.n_bodies + 1;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_compose(SceneDev s, ChunkDev c, const f
     const int i = idx / slots;
     const int slot = idx - i * slots;
     const ImageInfo im = c.img[i];
-    const float* vm = viewmats + ((size_t)im.cam * n_envs_total + im.env) * 12;
+    const float* vm = viewmats + im.vm_off;
     const float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
     const float tc[3] = {vm[3], vm[7], vm[11]};
     // camera centre in world: C = -R_c^T t_c (continuous quantity, colour only)
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_compose(SceneDev s, ChunkDev c, const f
         out[15] = 0.0f;
         return;
     }
-    const float* p = poses + ((size_t)im.env * s.n_bodies + (slot - 1)) * 7;
+    const float* p = poses + im.pose_off + (size_t)(slot - 1) * 7;
     float Rb[9], A[9];
     quat_rot(p[0], p[1], p[2], p[3], Rb);
     mat3_mul(Rc, Rb, A);
@@ -358,11 +358,10 @@ __global__ __launch_bounds__(256) void k_scene_convert(int64_t n, int64_t n_pad,
 }  // namespace
 
 hipError_t launch_compose(const SceneDev& s, const ChunkDev& c, const float* viewmats, const float* poses,
-                          int n_envs_total, hipStream_t stream)
+                          hipStream_t stream)
 {
     const int total = c.n_img * (s.n_bodies + 1);
-    hipLaunchKernelGGL(k_compose, dim3((total + 255) / 256), dim3(256), 0, stream, s, c, viewmats, poses,
-                       n_envs_total);
+    hipLaunchKernelGGL(k_compose, dim3((total + 255) / 256), dim3(256), 0, stream, s, c, viewmats, poses);
     return hipGetLastError();
 }
 

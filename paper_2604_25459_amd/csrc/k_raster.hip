@@ -240,12 +240,12 @@ __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, Chu
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         if (pxi[k] >= im.width || pyi[k] >= im.height) continue;
-        const size_t pix = im.out_pixel + (size_t)pyi[k] * im.width + pxi[k];
-        p.out_rgb[3 * pix + 0] = fmaf(T[k], p.bg[0], C0[k]);
-        p.out_rgb[3 * pix + 1] = fmaf(T[k], p.bg[1], C1[k]);
-        p.out_rgb[3 * pix + 2] = fmaf(T[k], p.bg[2], C2[k]);
-        p.out_depth[pix] = T[k] < 1.0f ? D[k] / (1.0f - T[k]) : 0.0f;
-        if (p.out_alpha) p.out_alpha[pix] = 1.0f - T[k];
+        const size_t pix = (size_t)pyi[k] * im.width + pxi[k];
+        im.out_rgb[3 * pix + 0] = fmaf(T[k], im.bg[0], C0[k]);
+        im.out_rgb[3 * pix + 1] = fmaf(T[k], im.bg[1], C1[k]);
+        im.out_rgb[3 * pix + 2] = fmaf(T[k], im.bg[2], C2[k]);
+        im.out_depth[pix] = T[k] < 1.0f ? D[k] / (1.0f - T[k]) : 0.0f;
+        if (im.out_alpha) im.out_alpha[pix] = 1.0f - T[k];
     }
 }
 

@@ -63,6 +63,24 @@ class ProjOut(C.Structure):
     _fields_ = [("n", C.c_int64), ("zkey", C.c_void_p), ("rect", C.c_void_p), ("rec", C.c_void_p)]
 
 
+class ServerCfg(C.Structure):
+    _fields_ = [("n_streams", C.c_int), ("max_batch_images", C.c_int), ("memory_budget", C.c_int64),
+                ("reserved", C.c_int * 8)]
+
+
+class ReqInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("n_images", C.c_int), ("batch_id", C.c_int64), ("batch_requests", C.c_int),
+                ("batch_images", C.c_int), ("t_submit_us", C.c_int64), ("t_admit_us", C.c_int64),
+                ("t_start_us", C.c_int64), ("t_complete_us", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64), ("pending", C.c_int64),
+                ("batches", C.c_int64), ("images", C.c_int64), ("in_flight_bytes", C.c_int64),
+                ("in_flight_bytes_max", C.c_int64), ("latency_p50_us", C.c_double), ("latency_p99_us", C.c_double),
+                ("latency_mean_us", C.c_double), ("latency_max_us", C.c_double), ("mean_batch_requests", C.c_double)]
+
+
 # name -> (restype, argtypes); every entry point declared in include/gsr.h
 SIGNATURES = {
     "gsr_create": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p]),
@@ -75,6 +93,11 @@ SIGNATURES = {
     "gsr_debug_bins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "gsr_debug_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "gsr_stage_times": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "gsr_server_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int64, C.c_void_p]),
+    "gsr_server_stats": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsr_server_destroy": (C.c_int, [C.c_void_p]),
     "gsr_last_error": (C.c_char_p, []),
     "gsr_version": (C.c_char_p, []),
 }
@@ -277,6 +300,50 @@ class Renderer:
         o = ProjOut(n=n, zkey=z.ctypes.data, rect=rect.ctypes.data, rec=rec.ctypes.data)
         _check(load().gsr_debug_project(self._h, C.byref(d), int(image), C.byref(o)))
         return dict(zkey=z, rect=rect, rec=rec)
+
+
+class Server:
+    """Continuous-batching request server on a Renderer's context."""
+
+    def __init__(self, renderer: Renderer, n_streams: int = 2, max_batch_images: int = 4096, memory_budget: int = 0):
+        cfg = ServerCfg(n_streams=n_streams, max_batch_images=max_batch_images, memory_budget=memory_budget)
+        h = C.c_void_p()
+        _check(load().gsr_server_create(renderer._h, C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._r = renderer
+        self._keep = {}
+
+    def submit(self, sid, cams, viewmats, poses, rgb, depth, alpha=None, bg=(0.0, 0.0, 0.0)) -> int:
+        d, carr = self._r._desc(sid, cams, viewmats, poses, bg, rgb, depth, alpha)
+        t = C.c_uint64()
+        _check(load().gsr_submit(self._h, C.byref(d), C.byref(t)))
+        self._keep[int(t.value)] = (viewmats, poses, rgb, depth, alpha)
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> dict:
+        info = ReqInfo()
+        rc = load().gsr_wait(self._h, C.c_uint64(ticket), C.c_int64(timeout_us), C.byref(info))
+        if rc != GSR_E_TIMEOUT:
+            self._keep.pop(ticket, None)
+        _check(rc)
+        return {k: getattr(info, k) for k, _ in ReqInfo._fields_}
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(load().gsr_server_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gsr_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def batch_tensors(batch, device: int = 0):

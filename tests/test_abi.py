@@ -49,6 +49,12 @@ def test_null_arguments_rejected():
     assert lib.gsr_debug_bins(None, None, 0, None) == gsr.GSR_E_INVALID
     assert lib.gsr_debug_project(None, None, 0, None) == gsr.GSR_E_INVALID
     assert lib.gsr_scene_info(None, 1, None, None, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_stage_times(None, None, 0, 0) == gsr.GSR_E_INVALID
+    assert lib.gsr_server_create(None, None, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_submit(None, None, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_wait(None, 1, 0, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_server_stats(None, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_server_destroy(None) == gsr.GSR_OK
     assert lib.gsr_destroy(None) == gsr.GSR_OK
 
 
@@ -78,3 +84,6 @@ def test_struct_layouts_match_header():
     assert C.sizeof(gsr.RenderDesc) == 8 + 4 + 4 + 8 * 3 + 12 + 4 + 8 * 3
     assert C.sizeof(gsr.BinsOut) == 8 * 5 + 8 + 8 + 4 + 4 + 8
     assert C.sizeof(gsr.ProjOut) == 8 * 4
+    assert C.sizeof(gsr.ServerCfg) == 4 + 4 + 8 + 32
+    assert C.sizeof(gsr.ReqInfo) == 4 + 4 + 8 + 4 + 4 + 8 * 4
+    assert C.sizeof(gsr.Stats) == 8 * 8 + 8 * 5
