@@ -133,6 +133,7 @@ def main():
                     help="seconds of the Poisson serving trace replayed in real time (0 = skip)")
     ap.add_argument("--serve-scenes", type=int, default=8, help="resident scenes in the serving pool (trace uses 32)")
     ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--no-autotune", action="store_true", help="skip the launch-parameter autotuner")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -158,6 +159,11 @@ def main():
     rgb, depth, _ = R.alloc_outputs(cams, E)
     stream = torch.cuda.current_stream(dev)
 
+    tuning = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tuning = R.autotune(sid, cams, vm, poses[0], rgb, depth)
+        log(f"[bench] autotuned in {time.perf_counter() - t0:.1f} s: {tuning}")
     log(f"[bench] warmup {args.warmup} steps of {E} envs x {C} cams")
     for s in range(args.warmup):
         R.render_into(sid, cams, vm, poses[s], rgb, depth, None, tuple(batch.bg))
@@ -240,7 +246,8 @@ def main():
         "dtype": args.storage if args.storage != "f32" else "f32", "data": "synthetic",
         "config": {"workload": synth.CONFIG_NAMES[args.config], "envs": E, "cams": C,
                    "resolution": [[c.width, c.height] for c in cams], "gaussians": scene.n,
-                   "sh_degree": scene.sh_degree, "storage": args.storage, "tile": args.tile},
+                   "sh_degree": scene.sh_degree, "storage": args.storage, "tile": args.tile,
+                   "tuning": tuning},
         "plain_path": plain,
         "serving": serving,
         "stages_ms_per_step": {k: v / args.steps for k, v in st.items() if k in R.STAGES},

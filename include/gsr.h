@@ -71,7 +71,9 @@ typedef struct {
     int64_t chunk_bytes;    /* device working-memory budget per render chunk; 0 = 24 GiB */
     float cutoff;           /* splat radius in standard deviations; 0 = 3.33 (conservative for alpha >= 1/255) */
     int profile;            /* 1 = record HIP events around every pipeline stage (see gsr_stage_times) */
-    int reserved[7];
+    int graphs;             /* 0 = capture the per-chunk stages of gsr_render into hipGraphs and replay them
+                               (default); -1 = launch every kernel eagerly */
+    int reserved[6];
 } gsr_options;
 
 /* A scene: static background plus Gaussian clusters bound to rigid bodies
@@ -234,6 +236,36 @@ int gsr_server_stats(gsr_server* srv, gsr_stats* stats);
 /* Finishes every queued and running request, stops the workers, frees the
  * server.  NULL is accepted. */
 int gsr_server_destroy(gsr_server* srv);
+
+/* ---- autotuning --------------------------------------------------------
+ * Launch parameters that change no pixel: tile side (8/16/32: pixels are
+ * bit-identical across tile sizes because every tile's list is a filter of
+ * one depth order and the radius is conservative), Gaussians staged in LDS
+ * per raster round, images per projection thread, persistent raster
+ * workgroups, images per memory chunk.  They are kept per shape class (scene,
+ * env count, camera sizes); gsr_render of a tuned class uses them.  Sort keys
+ * and tile lists reported by gsr_debug_bins always use the context's
+ * tile_size. */
+typedef struct {
+    int tile_size;          /* 8, 16, 32 */
+    int lds_batch;          /* 64/128/256 for 8x8 tiles, 256/512 otherwise */
+    int images_per_thread;  /* 1..16 */
+    int persistent;         /* 0 or 1 */
+    int chunk_images;       /* 0 = from chunk_bytes, else images per memory chunk */
+    float ms;               /* out: time of one render with these parameters (gsr_autotune) */
+    int reserved[4];
+} gsr_tuning;
+
+/* Times candidate parameters on `desc` (coordinate descent, each candidate one
+ * warm-up and two timed renders into desc's outputs on `stream`), stores the
+ * fastest for desc's shape class and returns it in `best`.  Synchronous. */
+int gsr_autotune(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream, gsr_tuning* best);
+/* Parameters a render of desc's shape class uses now; sets them (validated). */
+int gsr_tuning_get(gsr_ctx* ctx, const gsr_render_desc* desc, gsr_tuning* out);
+int gsr_tuning_set(gsr_ctx* ctx, const gsr_render_desc* desc, const gsr_tuning* t);
+/* Tuning cache as JSON lines (one shape class per line); load merges. */
+int gsr_tuning_save(gsr_ctx* ctx, const char* path);
+int gsr_tuning_load(gsr_ctx* ctx, const char* path);
 
 /* Stage timers of a context created with profile = 1: device milliseconds
  * accumulated over the renders since the last reset, measured with HIP events

@@ -10,6 +10,9 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <functional>
+#include <sstream>
 
 #include "gsr_runtime.h"
 
@@ -79,6 +82,10 @@ Workspace::~Workspace()
     if (h_img) (void)hipHostFree(h_img);
     if (ev_total) (void)hipEventDestroy(ev_total);
     if (ev_done) (void)hipEventDestroy(ev_done);
+    for (auto& kv : graphs)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    counter.release();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 
 // ------------------------------------------------------------------ planning
@@ -175,7 +182,8 @@ size_t image_bytes_estimate(const SceneRes* sc, int width, int height, int ts)
     return per_image_bytes(sc, tx * ty, ty, sb, tb);
 }
 
-ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain)
+ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain,
+                      int chunk_images)
 {
     ChunkPlan p{};
     p.t_max = p.tx_max = p.ty_max = 1;
@@ -191,7 +199,8 @@ ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<
         p.chunk = 1;
     } else {
         const size_t per = per_image_bytes(sc, p.t_max, p.ty_max, p.sort_blocks, p.tile_blocks);
-        const size_t c = std::max<size_t>(1, (size_t)ctx->opt.chunk_bytes / std::max<size_t>(per, 1));
+        size_t c = std::max<size_t>(1, (size_t)ctx->opt.chunk_bytes / std::max<size_t>(per, 1));
+        if (chunk_images > 0) c = std::min<size_t>(c, (size_t)chunk_images);
         p.chunk = (int)std::min<size_t>(c, imgs.size());
     }
     return p;
@@ -244,6 +253,28 @@ hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& 
     return hipSuccess;
 }
 
+std::string shape_key(const SceneRes* sc, const gsr_render_desc* d)
+{
+    std::string k = "n" + std::to_string(sc->dev.n) + "_b" + std::to_string(sc->dev.n_bodies) + "_d" +
+                    std::to_string(sc->dev.degree) + "_s" + std::to_string(sc->dev.storage) + "_e" +
+                    std::to_string(d->n_envs) + "_c";
+    for (int c = 0; c < d->n_cams; ++c)
+        k += (c ? "," : "") + std::to_string(d->cams[c].width) + "x" + std::to_string(d->cams[c].height);
+    return k;
+}
+
+Tuning tuning_for(gsr_ctx* ctx, const SceneRes* sc, const gsr_render_desc* d)
+{
+    Tuning t;
+    t.ts = ctx->opt.tile_size;
+    t.ipt = ctx->opt.images_per_thread;
+    t.batch = t.ts == 8 ? 64 : 256;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->tuned.find(shape_key(sc, d));
+    if (it != ctx->tuned.end()) t = it->second;
+    return t;
+}
+
 namespace {
 
 ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, int i0, int n_img,
@@ -288,29 +319,94 @@ ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, int i
     return c;
 }
 
+// One pipeline stage, launched eagerly or as a captured graph.  Graphs are
+// captured on the workspace's private stream (capture executes nothing) and
+// launched on the caller's stream; a graph is re-captured when anything its
+// launches depend on (buffers, sizes, parameters) changed.
+int run_stage(Workspace& ws, bool graph, int chunk_idx, int stage, const std::vector<uint64_t>& key, hipStream_t st,
+              const std::function<hipError_t(hipStream_t)>& fn)
+{
+    if (!graph) {
+        GSR_HIP_TRY(fn(st));
+        return GSR_OK;
+    }
+    StageGraph& g = ws.graphs[{chunk_idx, stage}];
+    if (!g.exec || g.key != key) {
+        if (g.exec) {
+            (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+        if (!ws.capture_stream) GSR_HIP_TRY(hipStreamCreateWithFlags(&ws.capture_stream, hipStreamNonBlocking));
+        GSR_HIP_TRY(hipStreamBeginCapture(ws.capture_stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t e = fn(ws.capture_stream);
+        hipGraph_t graph_ = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(ws.capture_stream, &graph_);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph_) (void)hipGraphDestroy(graph_);
+            return hip_fail(e != hipSuccess ? e : e2, "stage capture");
+        }
+        const hipError_t e3 = hipGraphInstantiate(&g.exec, graph_, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph_);
+        if (e3 != hipSuccess) {
+            g.exec = nullptr;
+            return hip_fail(e3, "hipGraphInstantiate");
+        }
+        g.key = key;
+    }
+    GSR_HIP_TRY(hipGraphLaunch(g.exec, st));
+    return GSR_OK;
+}
+
 // Enqueue the pipeline of images [i0, i0 + n_img) of `job` (image descriptions
 // already on the device).  `pairs_total` receives the chunk's pair count.
 int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, const ChunkPlan& plan, int i0,
-              int n_img, int ipt, hipStream_t st, Mode mode, uint64_t* pairs_total)
+              int n_img, int chunk_idx, hipStream_t st, Mode mode, bool graph, uint64_t* pairs_total)
 {
     ChunkDev c = chunk_view(ws, sc, plan, i0, n_img, job.imgs);
     const SceneDev& s = sc->dev;
+    const Tuning& tu = job.tune;
     const bool prof = ctx->opt.profile && mode == Mode::kRender;
     StageEvents ev;
     if (prof) {
         for (hipEvent_t& e : ev.e) GSR_HIP_TRY(hipEventCreate(&e));
         GSR_HIP_TRY(hipEventRecord(ev.e[0], st));
     }
-    GSR_HIP_TRY(launch_compose(s, c, job.viewmats, job.poses, st));
-    GSR_HIP_TRY(launch_project(s, c, ctx->opt.tile_size, ctx->opt.cutoff, ipt, st));
+    // everything the captured launches depend on
+    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)sc, (uint64_t)s.n, (uint64_t)(uintptr_t)c.img, (uint64_t)n_img,
+                                 (uint64_t)c.t_max, (uint64_t)c.tx_max, (uint64_t)c.ty_max, (uint64_t)c.sort_blocks,
+                                 (uint64_t)c.tile_blocks, (uint64_t)tu.ts, (uint64_t)tu.batch, (uint64_t)tu.ipt,
+                                 (uint64_t)tu.persistent, (uint64_t)(uintptr_t)job.viewmats,
+                                 (uint64_t)(uintptr_t)job.poses, (uint64_t)(uintptr_t)ws.h_total,
+                                 (uint64_t)ctx->opt.cutoff * 1000};
+    for (void* ptr : {(void*)c.xform, (void*)c.keyz, (void*)c.rect, (void*)c.srect, (void*)c.rec, (void*)c.sk[0],
+                      (void*)c.sk[1], (void*)c.sv[0], (void*)c.sv[1], (void*)c.sort_hist, (void*)c.vis_count,
+                      (void*)c.tile_hist, (void*)c.tile_range, (void*)c.pair_count, (void*)c.pair_base,
+                      (void*)c.row_hist, (void*)c.row_range, (void*)c.row_count, (void*)c.row_base})
+        key.push_back((uint64_t)(uintptr_t)ptr);
+    for (int k = 0; k < n_img; ++k)
+        key.push_back(((uint64_t)job.imgs[i0 + k].width << 32) | (uint64_t)job.imgs[i0 + k].height);
+
+    int rc = run_stage(ws, graph, chunk_idx, 0, key, st, [&](hipStream_t q) {
+        hipError_t e = launch_compose(s, c, job.viewmats, job.poses, q);
+        if (e == hipSuccess) e = launch_project(s, c, tu.ts, ctx->opt.cutoff, tu.ipt, q);
+        return e;
+    });
+    if (rc) return rc;
     if (mode == Mode::kProject) return GSR_OK;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[1], st));
-    GSR_HIP_TRY(launch_depth_sort(s, c, st));
+    rc = run_stage(ws, graph, chunk_idx, 1, key, st, [&](hipStream_t q) { return launch_depth_sort(s, c, q); });
+    if (rc) return rc;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[2], st));
-    GSR_HIP_TRY(launch_tile_count(s, c, st));
+    rc = run_stage(ws, graph, chunk_idx, 2, key, st, [&](hipStream_t q) {
+        hipError_t e = launch_tile_count(s, c, q);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws.h_total, c.pair_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, q);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws.h_total + 1, c.row_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, q);
+        return e;
+    });
+    if (rc) return rc;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[3], st));
-    GSR_HIP_TRY(hipMemcpyAsync(ws.h_total, c.pair_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    GSR_HIP_TRY(hipMemcpyAsync(ws.h_total + 1, c.row_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     GSR_HIP_TRY(hipEventRecord(ws.ev_total, st));
     GSR_HIP_TRY(hipEventSynchronize(ws.ev_total));
     const uint64_t total = ws.h_total[0];
@@ -320,19 +416,29 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     if (ws.pairs.bytes < total * 4) {
         const size_t want = std::max<size_t>(total * 4, (size_t)((double)ws.pairs.bytes * 1.5));
         GSR_HIP_TRY(ws.pairs.ensure(std::max<size_t>(want + (total * 4) / 8, 1 << 20)));
-        c.pairs = ws.pairs.as<uint32_t>();
     }
     if (ws.rows.bytes < row_total * 8) {
         const size_t want = std::max<size_t>(row_total * 8, (size_t)((double)ws.rows.bytes * 1.5));
         GSR_HIP_TRY(ws.rows.ensure(std::max<size_t>(want + (row_total * 8) / 8, 1 << 20)));
-        c.rows = ws.rows.as<uint2>();
     }
-    GSR_HIP_TRY(launch_tile_scatter(s, c, st));
+    c.pairs = ws.pairs.as<uint32_t>();
+    c.rows = ws.rows.as<uint2>();
+    key.push_back((uint64_t)(uintptr_t)c.pairs);
+    key.push_back((uint64_t)(uintptr_t)c.rows);
+    rc = run_stage(ws, graph, chunk_idx, 3, key, st, [&](hipStream_t q) { return launch_tile_scatter(s, c, q); });
+    if (rc) return rc;
     if (mode == Mode::kBins) return GSR_OK;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[4], st));
 
     RasterParams rp{};
-    rp.ts = ctx->opt.tile_size;
+    rp.ts = tu.ts;
+    rp.batch = tu.batch;
+    rp.persistent = tu.persistent;
+    rp.persistent_blocks = ctx->cu_count * (tu.ts == 8 ? 16 : 4);
+    if (tu.persistent) {
+        GSR_HIP_TRY(ws.counter.ensure(256));
+        rp.counter = ws.counter.as<uint32_t>();
+    }
     uint32_t blocks = 0;
     const std::vector<ImageInfo>& imgs = job.imgs;
     for (int k = 0; k < n_img;) {
@@ -349,7 +455,9 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
         k = m;
     }
     rp.n_blocks = blocks;
-    GSR_HIP_TRY(launch_raster(s, c, rp, st));
+    key.push_back((uint64_t)(uintptr_t)rp.counter);
+    rc = run_stage(ws, graph, chunk_idx, 4, key, st, [&](hipStream_t q) { return launch_raster(s, c, rp, q); });
+    if (rc) return rc;
     if (prof) {
         GSR_HIP_TRY(hipEventRecord(ev.e[5], st));
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -370,20 +478,35 @@ Workspace* acquire_workspace_locked(gsr_ctx* ctx, hipStream_t stream)
     return ctx->pool.back().get();
 }
 
-int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, hipStream_t st, bool plain)
+int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_in, hipStream_t st, bool plain,
+               bool graphs)
 {
-    if (job.imgs.empty()) return GSR_OK;
-    const ChunkPlan plan = plan_chunks(ctx, sc, job.imgs, plain);
+    if (job_in.imgs.empty()) return GSR_OK;
+    RenderJob job = job_in;
+    const ChunkPlan plan = plan_chunks(ctx, sc, job.imgs, plain, job.tune.chunk_images);
     // buffers may be reallocated: earlier work on this workspace must be finished
     if (ws.used) GSR_HIP_TRY(hipEventSynchronize(ws.ev_done));
     GSR_HIP_TRY(ensure_workspace(ws, sc, plan, job.imgs.size()));
+    // per-step inputs staged at fixed addresses, so captured graphs replay across steps
+    if (job.viewmats != ws.stage_vm.as<float>()) {
+        GSR_HIP_TRY(ws.stage_vm.ensure(std::max<size_t>(job.viewmat_floats, 1) * 4));
+        GSR_HIP_TRY(hipMemcpyAsync(ws.stage_vm.p, job.viewmats, job.viewmat_floats * 4, hipMemcpyDeviceToDevice, st));
+        job.viewmats = ws.stage_vm.as<float>();
+    }
+    if (job.pose_floats && job.poses != ws.stage_pose.as<float>()) {
+        GSR_HIP_TRY(ws.stage_pose.ensure(job.pose_floats * 4));
+        GSR_HIP_TRY(hipMemcpyAsync(ws.stage_pose.p, job.poses, job.pose_floats * 4, hipMemcpyDeviceToDevice, st));
+        job.poses = ws.stage_pose.as<float>();
+    }
     std::memcpy(ws.h_img, job.imgs.data(), job.imgs.size() * sizeof(ImageInfo));
     GSR_HIP_TRY(hipMemcpyAsync(ws.img.p, ws.h_img, job.imgs.size() * sizeof(ImageInfo), hipMemcpyHostToDevice, st));
-    const int ipt = plain ? 1 : ctx->opt.images_per_thread;
-    for (int i0 = 0; i0 < (int)job.imgs.size(); i0 += plan.chunk) {
+    if (plain) job.tune.ipt = 1;
+    const bool use_graphs = graphs && !plain && ctx->opt.graphs >= 0;
+    int chunk_idx = 0;
+    for (int i0 = 0; i0 < (int)job.imgs.size(); i0 += plan.chunk, ++chunk_idx) {
         const int n_img = std::min<int>(plan.chunk, (int)job.imgs.size() - i0);
         uint64_t total = 0;
-        const int rc = run_chunk(ctx, ws, sc, job, plan, i0, n_img, ipt, st, Mode::kRender, &total);
+        const int rc = run_chunk(ctx, ws, sc, job, plan, i0, n_img, chunk_idx, st, Mode::kRender, use_graphs, &total);
         if (rc) {
             if (rc == GSR_E_DEVICE) ctx->poisoned = true;
             return rc;
@@ -421,7 +544,7 @@ using namespace gsr;
 
 namespace {
 
-int render_impl(gsr_ctx* ctx, const gsr_render_desc* d, void* stream, bool plain)
+int render_impl(gsr_ctx* ctx, const gsr_render_desc* d, void* stream, bool plain, const Tuning* force = nullptr)
 {
     if (!ctx) return fail(GSR_E_INVALID, "ctx is NULL");
     if (!d) return fail(GSR_E_INVALID, "render desc is NULL");
@@ -444,10 +567,13 @@ int render_impl(gsr_ctx* ctx, const gsr_render_desc* d, void* stream, bool plain
     if (e != hipSuccess) rc = hip_fail(e, "hipSetDevice");
     if (!rc) {
         RenderJob job;
-        job.imgs = images_of(d, ctx->opt.tile_size, sc->dev.n_bodies);
+        job.tune = force ? *force : tuning_for(ctx, sc, d);
+        job.imgs = images_of(d, job.tune.ts, sc->dev.n_bodies);
         job.viewmats = d->viewmats;
         job.poses = d->body_poses;
-        rc = render_job(ctx, *ws, sc, job, st, plain);
+        job.viewmat_floats = (size_t)d->n_cams * d->n_envs * 12;
+        job.pose_floats = (size_t)d->n_envs * sc->dev.n_bodies * 7;
+        rc = render_job(ctx, *ws, sc, job, st, plain, true);
     }
     if (!rc) rc = mark_scene_use(ctx, sc, st);
     {
@@ -477,6 +603,9 @@ int debug_run(gsr_ctx* ctx, const gsr_render_desc* d, int image, Mode mode, Scen
         ws->in_call = true;
     }
     *ws_out = ws;
+    job->tune.ts = ctx->opt.tile_size;
+    job->tune.batch = ctx->opt.tile_size == 8 ? 64 : 256;
+    job->tune.ipt = 1;
     job->imgs = images_of(d, ctx->opt.tile_size, sc->dev.n_bodies);
     job->viewmats = d->viewmats;
     job->poses = d->body_poses;
@@ -484,7 +613,7 @@ int debug_run(gsr_ctx* ctx, const gsr_render_desc* d, int image, Mode mode, Scen
     GSR_HIP_TRY(ensure_workspace(*ws, sc, *plan, job->imgs.size()));
     std::memcpy(ws->h_img, job->imgs.data(), job->imgs.size() * sizeof(ImageInfo));
     GSR_HIP_TRY(hipMemcpy(ws->img.p, ws->h_img, job->imgs.size() * sizeof(ImageInfo), hipMemcpyHostToDevice));
-    rc = run_chunk(ctx, *ws, sc, *job, *plan, image, 1, 1, nullptr, mode, total);
+    rc = run_chunk(ctx, *ws, sc, *job, *plan, image, 1, 0, nullptr, mode, false, total);
     if (rc) return rc;
     GSR_HIP_TRY(hipDeviceSynchronize());
     return GSR_OK;
@@ -534,6 +663,7 @@ GSR_EXPORT int gsr_create(int device, const gsr_options* opt, gsr_ctx** out)
     if (!ctx) return fail(GSR_E_OOM, "context allocation failed");
     ctx->device = device;
     ctx->opt = o;
+    ctx->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     *out = ctx;
     return GSR_OK;
 }
@@ -778,4 +908,222 @@ GSR_EXPORT int gsr_debug_project(gsr_ctx* ctx, const gsr_render_desc* d, int ima
         rc = fail(GSR_E_DEVICE, "copy of records failed");
     debug_finish(ctx, sc, ws);
     return rc;
+}
+
+// ============================================================== autotuning
+
+namespace {
+
+bool tuning_valid(const gsr_ctx* ctx, const gsr_render_desc* d, const Tuning& t, std::string* why)
+{
+    if (t.ts != 8 && t.ts != 16 && t.ts != 32) return *why = "tile_size must be 8, 16 or 32", false;
+    if (t.ts == 8 ? (t.batch != 64 && t.batch != 128 && t.batch != 256) : (t.batch != 256 && t.batch != 512))
+        return *why = "lds_batch must be 64/128/256 for 8-pixel tiles, 256/512 otherwise", false;
+    if (t.ipt < 1 || t.ipt > 16) return *why = "images_per_thread must be in 1..16", false;
+    if (t.persistent != 0 && t.persistent != 1) return *why = "persistent must be 0 or 1", false;
+    if (t.chunk_images < 0) return *why = "chunk_images must be >= 0", false;
+    for (int c = 0; c < d->n_cams; ++c) {
+        const int64_t tiles = (int64_t)((d->cams[c].width + t.ts - 1) / t.ts) * ((d->cams[c].height + t.ts - 1) / t.ts);
+        if (tiles > 15000) return *why = "more than 15000 tiles per image for this tile size", false;
+    }
+    (void)ctx;
+    return true;
+}
+
+Tuning from_public(const gsr_tuning* t)
+{
+    Tuning r;
+    r.ts = t->tile_size;
+    r.batch = t->lds_batch;
+    r.ipt = t->images_per_thread;
+    r.persistent = t->persistent;
+    r.chunk_images = t->chunk_images;
+    r.ms = t->ms;
+    return r;
+}
+
+void to_public(const Tuning& t, gsr_tuning* o)
+{
+    std::memset(o, 0, sizeof *o);
+    o->tile_size = t.ts;
+    o->lds_batch = t.batch;
+    o->images_per_thread = t.ipt;
+    o->persistent = t.persistent;
+    o->chunk_images = t.chunk_images;
+    o->ms = t.ms;
+}
+
+}  // namespace
+
+GSR_EXPORT int gsr_tuning_get(gsr_ctx* ctx, const gsr_render_desc* d, gsr_tuning* out)
+{
+    if (!ctx || !d || !out) return fail(GSR_E_INVALID, "ctx / desc / out is NULL");
+    SceneRes* sc = acquire_scene(ctx, d->scene_id);
+    if (!sc) return fail(GSR_E_NOT_FOUND, "unknown scene id");
+    int rc = validate_desc(ctx, d, sc, false);
+    if (!rc) to_public(tuning_for(ctx, sc, d), out);
+    release_scene(sc);
+    return rc;
+}
+
+GSR_EXPORT int gsr_tuning_set(gsr_ctx* ctx, const gsr_render_desc* d, const gsr_tuning* t)
+{
+    if (!ctx || !d || !t) return fail(GSR_E_INVALID, "ctx / desc / tuning is NULL");
+    SceneRes* sc = acquire_scene(ctx, d->scene_id);
+    if (!sc) return fail(GSR_E_NOT_FOUND, "unknown scene id");
+    int rc = validate_desc(ctx, d, sc, false);
+    std::string why;
+    const Tuning tu = from_public(t);
+    if (!rc && !tuning_valid(ctx, d, tu, &why)) rc = fail(GSR_E_INVALID, why);
+    if (!rc) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->tuned[shape_key(sc, d)] = tu;
+    }
+    release_scene(sc);
+    return rc;
+}
+
+GSR_EXPORT int gsr_autotune(gsr_ctx* ctx, const gsr_render_desc* d, void* stream, gsr_tuning* best)
+{
+    if (!ctx || !d) return fail(GSR_E_INVALID, "ctx / desc is NULL");
+    SceneRes* sc = acquire_scene(ctx, d->scene_id);
+    if (!sc) return fail(GSR_E_NOT_FOUND, "unknown scene id");
+    int rc = validate_desc(ctx, d, sc, true);
+    const std::string key = rc ? std::string() : shape_key(sc, d);
+    Tuning cur = rc ? Tuning() : tuning_for(ctx, sc, d);
+    release_scene(sc);
+    if (rc) return rc;
+    GSR_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    GSR_HIP_TRY(hipEventCreate(&e0));
+    GSR_HIP_TRY(hipEventCreate(&e1));
+    auto time_of = [&](const Tuning& t, double* ms) -> int {
+        int r = render_impl(ctx, d, stream, false, &t);     // warm-up (captures graphs, grows buffers)
+        if (r) return r;
+        if (hipEventRecord(e0, st) != hipSuccess) return fail(GSR_E_DEVICE, "event record");
+        for (int k = 0; k < 2 && !r; ++k) r = render_impl(ctx, d, stream, false, &t);
+        if (r) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return fail(GSR_E_DEVICE, "event sync");
+        float f = 0.0f;
+        if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return fail(GSR_E_DEVICE, "event time");
+        *ms = f / 2.0;
+        return GSR_OK;
+    };
+    double best_ms = 0.0;
+    rc = time_of(cur, &best_ms);
+    std::string why;
+    auto consider = [&](Tuning t) {
+        if (rc || !tuning_valid(ctx, d, t, &why)) return;
+        double ms = 0.0;
+        const int r = time_of(t, &ms);
+        if (r == GSR_E_OOM || r == GSR_E_INVALID) return;   // candidate does not fit: skip it
+        if (r) {
+            rc = r;
+            return;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            cur = t;
+        }
+    };
+    for (int ts : {8, 16, 32}) {
+        if (ts == cur.ts) continue;
+        Tuning t = cur;
+        t.ts = ts;
+        t.batch = ts == 8 ? 64 : 256;
+        consider(t);
+    }
+    for (int b : {64, 128, 256, 512}) {
+        if (b == cur.batch) continue;
+        Tuning t = cur;
+        t.batch = b;
+        consider(t);
+    }
+    for (int ipt : {1, 2, 4, 8}) {
+        if (ipt == cur.ipt) continue;
+        Tuning t = cur;
+        t.ipt = ipt;
+        consider(t);
+    }
+    {
+        Tuning t = cur;
+        t.persistent = 1 - cur.persistent;
+        consider(t);
+    }
+    for (int ch : {0, 64, 256}) {
+        if (ch == cur.chunk_images) continue;
+        Tuning t = cur;
+        t.chunk_images = ch;
+        consider(t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    cur.ms = (float)best_ms;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->tuned[key] = cur;
+    }
+    if (best) to_public(cur, best);
+    return GSR_OK;
+}
+
+GSR_EXPORT int gsr_tuning_save(gsr_ctx* ctx, const char* path)
+{
+    if (!ctx || !path) return fail(GSR_E_INVALID, "ctx / path is NULL");
+    std::ofstream f(path);
+    if (!f) return fail(GSR_E_INVALID, std::string("cannot write ") + path);
+    f.precision(9);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (const auto& kv : ctx->tuned) {
+        const Tuning& t = kv.second;
+        f << "{\"key\": \"" << kv.first << "\", \"tile_size\": " << t.ts << ", \"lds_batch\": " << t.batch
+          << ", \"images_per_thread\": " << t.ipt << ", \"persistent\": " << t.persistent
+          << ", \"chunk_images\": " << t.chunk_images << ", \"ms\": " << t.ms << "}\n";
+    }
+    return f ? GSR_OK : fail(GSR_E_INVALID, "write failed");
+}
+
+GSR_EXPORT int gsr_tuning_load(gsr_ctx* ctx, const char* path)
+{
+    if (!ctx || !path) return fail(GSR_E_INVALID, "ctx / path is NULL");
+    std::ifstream f(path);
+    if (!f) return fail(GSR_E_NOT_FOUND, std::string("cannot read ") + path);
+    std::string line;
+    std::map<std::string, Tuning> got;
+    auto num = [](const std::string& l, const char* name, double* v) {
+        const std::string pat = std::string("\"") + name + "\":";
+        const size_t p = l.find(pat);
+        if (p == std::string::npos) return false;
+        *v = std::strtod(l.c_str() + p + pat.size(), nullptr);
+        return true;
+    };
+    while (std::getline(f, line)) {
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        const std::string kp = "\"key\": \"";
+        const size_t a = line.find(kp);
+        const size_t b = a == std::string::npos ? a : line.find('"', a + kp.size());
+        double ts, ba, ipt, pe, ch, ms;
+        if (a == std::string::npos || b == std::string::npos || !num(line, "tile_size", &ts) ||
+            !num(line, "lds_batch", &ba) || !num(line, "images_per_thread", &ipt) || !num(line, "persistent", &pe) ||
+            !num(line, "chunk_images", &ch) || !num(line, "ms", &ms))
+            return fail(GSR_E_INVALID, "malformed tuning line: " + line);
+        Tuning t;
+        t.ts = (int)ts;
+        t.batch = (int)ba;
+        t.ipt = (int)ipt;
+        t.persistent = (int)pe;
+        t.chunk_images = (int)ch;
+        t.ms = (float)ms;
+        if ((t.ts != 8 && t.ts != 16 && t.ts != 32) || t.ipt < 1 || t.ipt > 16 || (t.persistent != 0 && t.persistent != 1) ||
+            t.chunk_images < 0 ||
+            (t.ts == 8 ? (t.batch != 64 && t.batch != 128 && t.batch != 256) : (t.batch != 256 && t.batch != 512)))
+            return fail(GSR_E_INVALID, "invalid tuning values: " + line);
+        got[line.substr(a + kp.size(), b - a - kp.size())] = t;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (const auto& kv : got) ctx->tuned[kv.first] = kv.second;
+    return GSR_OK;
 }

@@ -110,7 +110,11 @@ hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t s
 // Stable two-level scatter: depth-ordered Gaussians -> tile-row lists -> tile lists.
 hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
 struct RasterParams {
-    int ts;
+    int ts;                  // tile side: 8, 16 or 32
+    int batch;               // records staged in LDS per round
+    int persistent;          // 1: persistent workgroups pulling tiles from `counter`
+    int persistent_blocks;   // workgroups of the persistent launch
+    uint32_t* counter;       // device tile counter (persistent launch)
     int n_segs;
     RasterSeg segs[kMaxSegs];
     uint32_t n_blocks;

@@ -49,6 +49,27 @@ struct SceneRes {
     ~SceneRes();
 };
 
+// HIP events bracketing the pipeline stages of one chunk (profile option).
+struct StageEvents {
+    hipEvent_t e[6] = {};
+};
+
+// Launch parameters of one shape class (none of them changes a pixel).
+struct Tuning {
+    int ts = 16;            // tile side
+    int batch = 256;        // raster LDS batch
+    int ipt = 4;            // images per projection thread
+    int persistent = 0;     // persistent raster workgroups
+    int chunk_images = 0;   // images per memory chunk (0 = from the memory budget)
+    float ms = 0.0f;        // measured step time when tuned
+};
+
+// Captured launch sequence of one pipeline stage of one chunk.
+struct StageGraph {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+};
+
 // Working memory of one render call at a time.
 struct Workspace {
     DevBuf img, xform, keyz, rect, srect, rec, sk0, sk1, sv0, sv1, sort_hist, vis_count, tile_hist, tile_range,
@@ -60,12 +81,10 @@ struct Workspace {
     hipStream_t last_stream = nullptr;
     bool used = false;      // ev_done has been recorded at least once
     bool in_call = false;   // owned by a render call right now
+    DevBuf counter;         // persistent raster tile counter
+    hipStream_t capture_stream = nullptr;          // graphs are captured here, launched on the caller's stream
+    std::map<std::pair<int, int>, StageGraph> graphs;   // (chunk index, stage) -> executable graph
     ~Workspace();
-};
-
-// HIP events bracketing the pipeline stages of one chunk (profile option).
-struct StageEvents {
-    hipEvent_t e[6] = {};
 };
 
 // Images of one launch sequence (possibly from several requests), grouped so
@@ -74,6 +93,9 @@ struct RenderJob {
     std::vector<ImageInfo> imgs;
     const float* viewmats = nullptr;   // base of ImageInfo::vm_off
     const float* poses = nullptr;      // base of ImageInfo::pose_off
+    size_t viewmat_floats = 0;         // extent of the arrays above (staged into the workspace)
+    size_t pose_floats = 0;
+    Tuning tune;
 };
 
 enum class Mode { kRender, kBins, kProject };
@@ -89,11 +111,18 @@ struct ChunkPlan {
 std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies);
 int validate_desc(const gsr_ctx* ctx, const gsr_render_desc* d, const SceneRes* sc, bool need_outputs);
 size_t image_bytes_estimate(const SceneRes* sc, int width, int height, int ts);
-ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain);
+ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain,
+                      int chunk_images = 0);
+// Shape-class key of a render descriptor (scene, envs, camera sizes).
+std::string shape_key(const SceneRes* sc, const gsr_render_desc* d);
+// Tuning a render of `d` uses: the tuned entry of its shape class or the context defaults.
+Tuning tuning_for(gsr_ctx* ctx, const SceneRes* sc, const gsr_render_desc* d);
 hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, size_t n_images_total);
 
-// Enqueue the whole job on `st` (blocks once per chunk for its pair count).
-int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, hipStream_t st, bool plain);
+// Enqueue the whole job on `st` (blocks once per chunk for its pair count);
+// `graphs` allows replaying captured stage graphs (batched path only).
+int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, hipStream_t st, bool plain,
+               bool graphs);
 
 // Scene lookup that pins the scene against destruction; release_scene unpins.
 SceneRes* acquire_scene(gsr_ctx* ctx, uint64_t id);
@@ -116,4 +145,6 @@ struct gsr_ctx {
     double stage_ms[5] = {0, 0, 0, 0, 0};
     double raster_launches = 0, renders = 0;
     std::atomic<bool> poisoned{false};
+    std::map<std::string, gsr::Tuning> tuned;         // shape class -> launch parameters
+    int cu_count = 256;
 };

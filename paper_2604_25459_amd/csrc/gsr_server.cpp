@@ -109,11 +109,17 @@ int render_batch(gsr_server* srv, Workspace& ws, hipStream_t st, const std::vect
         job.viewmats = ws.stage_vm.as<float>();
         job.poses = ws.stage_pose.as<float>();
     }
+    job.viewmat_floats = vm_at;
+    job.pose_floats = pose_at;
+    job.tune.ts = ctx->opt.tile_size;
+    job.tune.batch = ctx->opt.tile_size == 8 ? 64 : 256;
+    job.tune.ipt = ctx->opt.images_per_thread;
     // images of equal size contiguous (one raster segment each)
     std::stable_sort(job.imgs.begin(), job.imgs.end(), [](const ImageInfo& a, const ImageInfo& b) {
         return a.width != b.width ? a.width < b.width : a.height < b.height;
     });
-    int rc = render_job(ctx, ws, sc, job, st, false);
+    // batches change composition from one to the next: launched eagerly, not captured
+    int rc = render_job(ctx, ws, sc, job, st, false, false);
     if (!rc) rc = mark_scene_use(ctx, sc, st);
     if (!rc) GSR_HIP_TRY(hipStreamSynchronize(st));
     return rc;

@@ -25,10 +25,11 @@
 // pixel would have accepted and results do not depend on the tiling.
 #include "gsr_internal.h"
 
+#include <algorithm>
+
 namespace gsr {
 namespace {
 
-constexpr int kBatch = 256;
 constexpr float kLogAlphaMin = -7.99435343685886f;   // log2(1/255)
 constexpr float kCullMargin = 0.05f;                  // in log2(alpha) units
 
@@ -82,16 +83,25 @@ __device__ __forceinline__ float max_logalpha_rect(float A, float B, float C, fl
     return best + lo;
 }
 
-template <int TS>
-__global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, ChunkDev c, RasterParams p)
+template <int TS, int kBatch>
+struct RasterLds {
+    float4 a[2][kBatch], b[2][kBatch], c[2][kBatch];
+};
+
+// Composites tile `bid` of the chunk (block id in segment order).
+template <int TS, int kBatch>
+__device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c, const RasterParams& p, uint32_t bid,
+                                            RasterLds<TS, kBatch>& L_)
 {
     using L = Layout<TS>;
     constexpr int NT = L::kThreads;
     constexpr int PPT = L::kPpt;
     constexpr int PER_THREAD = kBatch / NT;     // records each thread stages per batch
-    __shared__ float4 sA[2][kBatch], sB[2][kBatch], sC[2][kBatch];
+    static_assert(PER_THREAD >= 1 && kBatch % 64 == 0, "batch must be a multiple of 64 and >= the block size");
+    auto& sA = L_.a;
+    auto& sB = L_.b;
+    auto& sC = L_.c;
 
-    const uint32_t bid = blockIdx.x;
     int sgi = 0;
 #pragma unroll
     for (int k = 1; k < kMaxSegs; ++k)
@@ -249,17 +259,76 @@ __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, Chu
     }
 }
 
+// One workgroup per tile.
+template <int TS, int kBatch>
+__global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, ChunkDev c, RasterParams p)
+{
+    __shared__ RasterLds<TS, kBatch> lds;
+    raster_tile<TS, kBatch>(s, c, p, blockIdx.x, lds);
+}
+
+// Persistent workgroups: each takes tiles from a global counter (zeroed by
+// k_zero_counter before the launch) until every tile is done; tiles are taken
+// in image order, so concurrently shaded tiles share their images' records in
+// cache.  Every workgroup exits once the counter passes n_blocks.
+template <int TS, int kBatch>
+__global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster_persistent(SceneDev s, ChunkDev c, RasterParams p,
+                                                                            uint32_t* counter)
+{
+    __shared__ RasterLds<TS, kBatch> lds;
+    __shared__ uint32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t bid = next;
+        __syncthreads();
+        if (bid >= p.n_blocks) break;
+        raster_tile<TS, kBatch>(s, c, p, bid, lds);
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_counter(uint32_t* counter) { *counter = 0u; }
+
+template <int TS, int kBatch>
+hipError_t launch_ts(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream)
+{
+    constexpr int NT = Layout<TS>::kThreads;
+    if (p.persistent && p.counter) {
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, stream, p.counter);
+        const uint32_t grid = std::min<uint32_t>(p.n_blocks, (uint32_t)p.persistent_blocks);
+        hipLaunchKernelGGL((k_raster_persistent<TS, kBatch>), dim3(grid), dim3(NT), 0, stream, s, c, p, p.counter);
+    } else {
+        hipLaunchKernelGGL((k_raster<TS, kBatch>), dim3(p.n_blocks), dim3(NT), 0, stream, s, c, p);
+    }
+    return hipGetLastError();
+}
+
+// LDS batch sizes: 64 / 128 / 256 records for 8x8 tiles (one wave), 256 / 512
+// for the 256-thread layouts (a batch holds at least one record per thread).
+template <int TS>
+hipError_t launch_batch(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream)
+{
+    if constexpr (TS == 8) {
+        if (p.batch == 64) return launch_ts<TS, 64>(s, c, p, stream);
+        if (p.batch == 128) return launch_ts<TS, 128>(s, c, p, stream);
+        return launch_ts<TS, 256>(s, c, p, stream);
+    } else {
+        if (p.batch == 512) return launch_ts<TS, 512>(s, c, p, stream);
+        return launch_ts<TS, 256>(s, c, p, stream);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_raster(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream)
 {
     if (p.n_blocks == 0) return hipSuccess;
     switch (p.ts) {
-    case 8: hipLaunchKernelGGL(k_raster<8>, dim3(p.n_blocks), dim3(Layout<8>::kThreads), 0, stream, s, c, p); break;
-    case 32: hipLaunchKernelGGL(k_raster<32>, dim3(p.n_blocks), dim3(Layout<32>::kThreads), 0, stream, s, c, p); break;
-    default: hipLaunchKernelGGL(k_raster<16>, dim3(p.n_blocks), dim3(Layout<16>::kThreads), 0, stream, s, c, p); break;
+    case 8: return launch_batch<8>(s, c, p, stream);
+    case 32: return launch_batch<32>(s, c, p, stream);
+    default: return launch_batch<16>(s, c, p, stream);
     }
-    return hipGetLastError();
 }
 
 }  // namespace gsr

@@ -33,7 +33,12 @@ MEM_HOST, MEM_DEVICE = 0, 1
 
 class Options(C.Structure):
     _fields_ = [("tile_size", C.c_int), ("images_per_thread", C.c_int), ("chunk_bytes", C.c_int64),
-                ("cutoff", C.c_float), ("profile", C.c_int), ("reserved", C.c_int * 7)]
+                ("cutoff", C.c_float), ("profile", C.c_int), ("graphs", C.c_int), ("reserved", C.c_int * 6)]
+
+
+class TuningDesc(C.Structure):
+    _fields_ = [("tile_size", C.c_int), ("lds_batch", C.c_int), ("images_per_thread", C.c_int),
+                ("persistent", C.c_int), ("chunk_images", C.c_int), ("ms", C.c_float), ("reserved", C.c_int * 4)]
 
 
 class SceneDesc(C.Structure):
@@ -93,6 +98,11 @@ SIGNATURES = {
     "gsr_debug_bins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "gsr_debug_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "gsr_stage_times": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "gsr_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_tuning_get": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_tuning_set": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_tuning_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "gsr_tuning_load": (C.c_int, [C.c_void_p, C.c_char_p]),
     "gsr_server_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int64, C.c_void_p]),
@@ -154,10 +164,10 @@ class Renderer:
     """One libgsr context on a device."""
 
     def __init__(self, device: int = 0, tile_size: int = 16, images_per_thread: int = 4, chunk_bytes: int = 0,
-                 cutoff: float = 0.0, profile: bool = False):
+                 cutoff: float = 0.0, profile: bool = False, graphs: bool = True):
         lib = load()
         opt = Options(tile_size=tile_size, images_per_thread=images_per_thread, chunk_bytes=chunk_bytes,
-                      cutoff=cutoff, profile=int(profile))
+                      cutoff=cutoff, profile=int(profile), graphs=0 if graphs else -1)
         h = C.c_void_p()
         _check(lib.gsr_create(device, C.byref(opt), C.byref(h)))
         self._h = h
@@ -269,6 +279,36 @@ class Renderer:
         rgb, depth, a = self.alloc_outputs(cams, E, alpha)
         self.render_into(sid, cams, viewmats, poses, rgb, depth, a, bg, plain, stream)
         return self.split(cams, E, rgb, depth, a)
+
+    # ---------------------------------------------------------- tuning
+    TUNING_KEYS = ("tile_size", "lds_batch", "images_per_thread", "persistent", "chunk_images", "ms")
+
+    def autotune(self, sid, cams, viewmats, poses, rgb, depth, alpha=None, stream=None) -> dict:
+        import torch
+        d, carr = self._desc(sid, cams, viewmats, poses, (0, 0, 0), rgb, depth, alpha)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        t = TuningDesc()
+        _check(load().gsr_autotune(self._h, C.byref(d), C.c_void_p(st), C.byref(t)))
+        return {k: getattr(t, k) for k in self.TUNING_KEYS}
+
+    def tuning(self, sid, cams, viewmats, poses) -> dict:
+        d, carr = self._desc(sid, cams, viewmats, poses, (0, 0, 0))
+        t = TuningDesc()
+        _check(load().gsr_tuning_get(self._h, C.byref(d), C.byref(t)))
+        return {k: getattr(t, k) for k in self.TUNING_KEYS}
+
+    def set_tuning(self, sid, cams, viewmats, poses, **kw):
+        d, carr = self._desc(sid, cams, viewmats, poses, (0, 0, 0))
+        cur = self.tuning(sid, cams, viewmats, poses)
+        cur.update(kw)
+        t = TuningDesc(**{k: cur[k] for k in self.TUNING_KEYS})
+        _check(load().gsr_tuning_set(self._h, C.byref(d), C.byref(t)))
+
+    def save_tuning(self, path: str):
+        _check(load().gsr_tuning_save(self._h, path.encode()))
+
+    def load_tuning(self, path: str):
+        _check(load().gsr_tuning_load(self._h, path.encode()))
 
     # ---------------------------------------------------------- debug
     def debug_bins(self, sid, cams, viewmats, poses, image: int, capacity: int = 1 << 22):

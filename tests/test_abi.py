@@ -55,6 +55,11 @@ def test_null_arguments_rejected():
     assert lib.gsr_wait(None, 1, 0, None) == gsr.GSR_E_INVALID
     assert lib.gsr_server_stats(None, None) == gsr.GSR_E_INVALID
     assert lib.gsr_server_destroy(None) == gsr.GSR_OK
+    assert lib.gsr_autotune(None, None, None, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_tuning_get(None, None, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_tuning_set(None, None, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_tuning_save(None, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_tuning_load(None, None) == gsr.GSR_E_INVALID
     assert lib.gsr_destroy(None) == gsr.GSR_OK
 
 
@@ -78,7 +83,8 @@ def test_create_without_gpu_reports_device_error():
 
 def test_struct_layouts_match_header():
     # sizes computed from the C declarations (LP64): a mismatch would corrupt every call
-    assert C.sizeof(gsr.Options) == 4 + 4 + 8 + 4 + 4 + 28 + 4
+    assert C.sizeof(gsr.Options) == 4 + 4 + 8 + 4 + 4 + 4 + 24 + 4
+    assert C.sizeof(gsr.TuningDesc) == 6 * 4 + 16
     assert C.sizeof(gsr.SceneDesc) == 8 + 4 * 4 + 8 * 6
     assert C.sizeof(gsr.CameraDesc) == 7 * 4
     assert C.sizeof(gsr.RenderDesc) == 8 + 4 + 4 + 8 * 3 + 12 + 4 + 8 * 3

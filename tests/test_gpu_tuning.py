@@ -1,0 +1,86 @@
+"""hipGraph replay and autotuned launch parameters change no pixel: every
+replay and every parameter set gives the bits of the eager default render."""
+import numpy as np
+import pytest
+
+from paper_2604_25459_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_graph_replays_match_eager():
+    torch = _torch()
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(1, n_envs=8)
+    Rg = gsr.Renderer(0)                  # graphs on (default)
+    Re = gsr.Renderer(0, graphs=False)
+    sg, se = Rg.add_synth_scene(scene), Re.add_synth_scene(scene)
+    cams, vm, _ = gsr.batch_tensors(batch)
+    dev = vm.device
+    for step in range(4):                 # new poses every step: one capture, then replays
+        poses = torch.from_numpy(synth.make_poses(1, step, 8, scene.n_bodies)).to(dev)
+        eager = Re.render(se, cams, vm, poses, alpha=True)
+        torch.cuda.synchronize()
+        replay = Rg.render(sg, cams, vm, poses, alpha=True)
+        torch.cuda.synchronize()
+        for a, b in zip(eager[0], replay[0]):
+            assert torch.equal(a, b), f"step {step}"
+    Rg.close()
+    Re.close()
+
+
+@pytest.mark.parametrize("params", [dict(tile_size=8, lds_batch=64), dict(tile_size=8, lds_batch=256),
+                                    dict(tile_size=32, lds_batch=512), dict(lds_batch=512, images_per_thread=1),
+                                    dict(images_per_thread=8, persistent=1), dict(persistent=1, chunk_images=3)])
+def test_tuning_changes_no_pixel(params):
+    torch = _torch()
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(3, n_envs=5)       # two camera slots of different sizes
+    R = gsr.Renderer(0)
+    sid = R.add_synth_scene(scene, "bf16")
+    cams, vm, poses = gsr.batch_tensors(batch)
+    ref = R.render(sid, cams, vm, poses, alpha=True)
+    R.set_tuning(sid, cams, vm, poses, **params)
+    got = R.tuning(sid, cams, vm, poses)
+    for k, v in params.items():
+        assert got[k] == v
+    for _ in range(2):
+        out = R.render(sid, cams, vm, poses, alpha=True)
+        for slot_ref, slot_out in zip(ref, out):
+            for a, b in zip(slot_ref, slot_out):
+                assert torch.equal(a, b), params
+    R.close()
+
+
+def test_autotune_and_cache_roundtrip(tmp_path):
+    torch = _torch()
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(1, n_envs=16)
+    R = gsr.Renderer(0)
+    sid = R.add_synth_scene(scene)
+    cams, vm, poses = gsr.batch_tensors(batch)
+    ref = R.render(sid, cams, vm, poses)
+    rgb, depth, _ = R.alloc_outputs(cams, 16)
+    best = R.autotune(sid, cams, vm, poses, rgb, depth)
+    print("autotuned", best, flush=True)
+    assert best["tile_size"] in (8, 16, 32) and best["ms"] > 0
+    assert R.tuning(sid, cams, vm, poses) == best
+    out = R.render(sid, cams, vm, poses)
+    assert torch.equal(out[0][0], ref[0][0]) and torch.equal(out[0][1], ref[0][1])
+    path = str(tmp_path / "tune.jsonl")
+    R.save_tuning(path)
+    R2 = gsr.Renderer(0)
+    sid2 = R2.add_synth_scene(scene)
+    R2.load_tuning(path)
+    loaded = R2.tuning(sid2, cams, vm, poses)
+    assert {k: v for k, v in loaded.items() if k != "ms"} == {k: v for k, v in best.items() if k != "ms"}
+    assert loaded["ms"] == pytest.approx(best["ms"], rel=1e-6)
+    R2.close()
+    R.close()
