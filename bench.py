@@ -13,6 +13,8 @@ on the same GPU, per-stage device times, the roofline of the dominant kernel
 and the CPU oracle's rate on a bounded sample.
 """
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +31,72 @@ FP32_PEAK_TFLOPS = 157.3
 # weight 1, four accumulations 8).
 FLOPS_EVAL = 11
 FLOPS_ACCEPT = 11
+# Sources that fix what the rasteriser reads and writes: a counter summary
+# taken on other sources gives no traffic figure.
+RASTER_SOURCES = ("paper_2604_25459_amd/csrc/k_raster.hip",)
+PMC_SUMMARY = "profiles/k_raster_cfg2_2048env_640x480_f32_pmc.json"
+CALIB_BYTES = 1 << 30
+
+
+def raster_source_hash():
+    h = hashlib.sha256()
+    for rel in RASTER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _pmc_rows(path, counter):
+    with open(path, newline="") as f:
+        rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def pmc_summary(fetch_csv, write_csv, out_path, command):
+    """Condense two counter runs of the same bench command (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch) into HBM bytes per rasteriser launch.  Each
+    counter is scaled by what it reads for the calibration copy (the first
+    device-to-device copy kernel, 1 GiB read and 1 GiB written)."""
+    out = {"command": command, "source_sha256": raster_source_hash(), "sources": list(RASTER_SOURCES)}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _pmc_rows(path, counter)
+        calib = next(r for r in rows if "copyBuffer" in r["Kernel_Name"])
+        kib = float(calib["Counter_Value"])
+        factor = (CALIB_BYTES / 1024.0) / kib
+        if not 0.25 <= factor <= 4.0:
+            raise SystemExit(f"{counter}: calibration copy read {kib} KiB, not near 1 GiB")
+        rast = [float(r["Counter_Value"]) for r in rows if "k_raster" in r["Kernel_Name"]]
+        if not rast:
+            raise SystemExit(f"{counter}: no rasteriser dispatch in {path}")
+        key = counter.split("_")[0].lower()
+        out[f"{key}_calibration_kib"] = kib
+        out[f"{key}_factor"] = factor
+        out[f"{key}_kib_per_dispatch"] = sum(rast) / len(rast)
+        out[f"{key}_dispatches"] = len(rast)
+        out[f"{key}_bytes_per_launch"] = sum(rast) / len(rast) * 1024.0 * factor
+    out["traffic_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
+def measured_traffic(tuning):
+    """HBM bytes per rasteriser launch from the committed counter summary, or
+    None when it was taken on other sources or other launch parameters."""
+    path = os.path.join(ROOT, PMC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        s = json.load(f)
+    if s.get("source_sha256") != raster_source_hash():
+        return None
+    if tuning is not None and s.get("tuning") is not None:
+        strip = lambda t: {k: v for k, v in t.items() if k != "ms"}
+        if strip(s["tuning"]) != strip(tuning):
+            return None
+    return s["traffic_bytes_per_launch"]
 
 
 def log(msg):
@@ -134,7 +202,27 @@ def main():
     ap.add_argument("--serve-scenes", type=int, default=8, help="resident scenes in the serving pool (trace uses 32)")
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true", help="skip the launch-parameter autotuner")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first copy 1 GiB device to device (calibrates the memory counters)")
+    ap.add_argument("--no-count", action="store_true", help="skip the counting renders of the roofline")
+    ap.add_argument("--no-graphs", action="store_true", help="launch every stage eagerly (no graph replay)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the counter summary of two rocprofv3 --pmc runs of this bench and exit")
+    ap.add_argument("--pmc-out", default=os.path.join(ROOT, PMC_SUMMARY))
+    ap.add_argument("--pmc-command", default="", help="command line recorded in the counter summary")
+    ap.add_argument("--pmc-tuning", default="", help="JSON of the launch parameters the counted run used")
     args = ap.parse_args()
+
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_out, args.pmc_command)
+        if args.pmc_tuning:
+            with open(args.pmc_out) as f:
+                s = json.load(f)
+            s["tuning"] = json.loads(args.pmc_tuning)
+            with open(args.pmc_out, "w") as f:
+                json.dump(s, f, indent=1)
+                f.write("\n")
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build renders on one GPU only; run with --gpus 1 (multi-GPU sharding is "
@@ -146,10 +234,19 @@ def main():
 
     from paper_2604_25459_amd import gsr, synth
 
+    if args.calibration_copy:
+        x = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)                       # device-to-device copy kernel: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del x, y
+        log("[bench] calibration: 1 GiB device-to-device copy done")
+
     log(f"[bench] config {args.config}: generating workload")
     scene, batch = synth.make_config(args.config, n_envs=args.envs or None)
     E, C = batch.n_envs, batch.n_cams
-    R = gsr.Renderer(0, tile_size=args.tile, profile=True)
+    R = gsr.Renderer(0, tile_size=args.tile, profile=True, graphs=not args.no_graphs)
     sid = R.add_synth_scene(scene, args.storage)
     cams, vm, _ = gsr.batch_tensors(batch)
     dev = torch.device("cuda", 0)
@@ -206,38 +303,65 @@ def main():
 
     # oracle on the host cores, bounded sample of the same workload
     cpu = None
-    evals_per_pixel = None
     if args.cpu_images:
-        from oracle import render_ref
+        from oracle import oracle_threads, render_ref
         b0 = synth.make_config(args.config, n_envs=args.envs or None, step=args.warmup)[1]
-        cores = len(os.sched_getaffinity(0))
+        cores = oracle_threads()
         t0 = time.perf_counter()
-        visited, accepted_est, npx = 0, 0, 0
         for k in range(args.cpu_images):
-            e = (k * 997) % E
-            ref = render_ref(scene, b0, 0, e, args.tile, variants=False)
-            visited += int(ref.visited.sum())
-            npx += ref.visited.size
+            render_ref(scene, b0, 0, (k * 997) % E, args.tile, variants=False)
         csec = time.perf_counter() - t0
         cpu = {"value": args.cpu_images / csec, "unit": "env-frames/s", "cores": cores, "kind": "oracle",
-               "sample": f"{args.cpu_images} envs of step {args.warmup} (float32 binning spec + float64 compositing)"}
-        evals_per_pixel = visited / max(npx, 1)
-        log(f"[bench] oracle {cpu['value']:.3f} env-frames/s on {cores} cores; {evals_per_pixel:.1f} list entries "
-            f"visited per pixel")
+               "sample": f"{args.cpu_images} envs of step {args.warmup} (float32 binning spec on one thread + "
+                         f"float64 compositing on {cores} OpenMP threads)"}
+        log(f"[bench] oracle {cpu['value']:.3f} env-frames/s on {cores} cores")
 
-    # roofline of the dominant kernel (the rasteriser, bound by vector ALU work)
-    pixels_per_step = sum(E * c.width * c.height for c in cams)
-    raster_ms = st["raster"] / max(st["raster_launches"], 1)
+    # roofline of the dominant kernel (the rasteriser, bound by vector ALU
+    # work): exact per-pixel work of every timed step, from counting renders
+    # of the same poses with the same launch parameters (untimed)
     roof = None
-    if evals_per_pixel is not None and raster_ms > 0:
+    raster_ms = st["raster"] / max(st["raster_launches"], 1)
+    if not args.no_count and raster_ms > 0:
+        npx = rgb.numel() // 3
+        work = torch.empty(npx * 2, dtype=torch.int32, device=dev)
+        visits = accepts = 0
+        for s in range(args.steps):
+            R.render_into(sid, cams, vm, poses[args.warmup + s], rgb, depth, None, tuple(batch.bg), work=work)
+            w = work.view(npx, 2)
+            visits += int(w[:, 0].sum(dtype=torch.int64))
+            accepts += int(w[:, 1].sum(dtype=torch.int64))
+        torch.cuda.synchronize()
+        R.stage_times(reset=True)
+        del work
+        flops_step = (visits * FLOPS_EVAL + accepts * FLOPS_ACCEPT) / args.steps
         launches_per_step = st["raster_launches"] / args.steps
-        evals_per_launch = evals_per_pixel * pixels_per_step / launches_per_step
-        flops = evals_per_launch * (FLOPS_EVAL + FLOPS_ACCEPT * 0.5)
-        achieved = flops / (raster_ms * 1e-3) / 1e12
+        flops_launch = flops_step / launches_per_step
+        achieved = flops_launch / (raster_ms * 1e-3) / 1e12
+        traffic = measured_traffic(tuning)
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                "kernel": "k_raster", "avg_ms": raster_ms,
-                "units": "list entries visited up to each pixel's termination, estimated from the oracle sample"}
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": "k_raster", "avg_ms": raster_ms, "launches_per_step": launches_per_step,
+                "flop_per_launch": flops_launch,
+                "visits_per_pixel": visits / (npx * args.steps), "accepts_per_pixel": accepts / (npx * args.steps),
+                "units": "list entries up to each pixel's termination x 11 flop + blended Gaussians x 11 flop"}
+        log(f"[bench] raster {roof['visits_per_pixel']:.1f} visits, {roof['accepts_per_pixel']:.1f} blends per "
+            f"pixel; {achieved:.2f} TFLOP/s algorithmic over {raster_ms:.2f} ms per launch")
+
+    # whole-path algorithmic HBM bytes per env-frame with the measured V and P
+    # per image: V (R + 8) + P (12 + 24 + 4 + R) + W H 16 + scene / E, R = 40 B
+    n_img_step = E * C
+    V = st["visible"] / max(st["renders"], 1) / n_img_step
+    P = st["pairs"] / max(st["renders"], 1) / n_img_step
+    px_env = sum(c.width * c.height for c in cams)
+    scene_bytes = R.scene_info(sid)[2]
+    b_alg = C * (V * 48 + P * 80) + px_env * 16 + scene_bytes / E
+    path = {"visible_per_image": V, "pairs_per_image": P, "pairs_per_step": P * n_img_step,
+            "alg_bytes_per_env_frame": b_alg,
+            "alg_hbm_frac": b_alg * value / (HBM_PEAK_GBS * 1e9)}
+    props = torch.cuda.get_device_properties(dev)
+    host = {"gpu": props.name, "arch": getattr(props, "gcnArchName", ""),
+            "host_cores": len(os.sched_getaffinity(0)), "nproc": os.cpu_count()}
 
     out = {
         "metric": "env-frames/s at 640x480 x 2048 envs vs plain path; p50/p99 request latency",
@@ -251,6 +375,8 @@ def main():
         "plain_path": plain,
         "serving": serving,
         "stages_ms_per_step": {k: v / args.steps for k, v in st.items() if k in R.STAGES},
+        "path": path,
+        "host": host,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

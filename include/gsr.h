@@ -113,6 +113,9 @@ typedef struct {
     float* out_rgb;               /* device; slot c is a contiguous [E][H_c][W_c][3] block, slots in order */
     float* out_depth;             /* device; slot c is [E][H_c][W_c]; normalised expected depth, 0 where empty */
     float* out_alpha;             /* device, optional (NULL): 1 - final transmittance, same layout as depth */
+    uint32_t* out_work;           /* device, optional (NULL): per pixel two counts, [..][H_c][W_c][2]: list entries
+                                     visited up to and including the one that stopped the pixel (else the tile's
+                                     list length), and Gaussians blended -- the algorithmic work of compositing */
 } gsr_render_desc;
 
 /* Materialised binning of one image (for parity checks). */
@@ -271,8 +274,10 @@ int gsr_tuning_load(gsr_ctx* ctx, const char* path);
  * accumulated over the renders since the last reset, measured with HIP events
  * recorded on the render stream.  ms[0] compose + project, ms[1] depth sort,
  * ms[2] tile count, ms[3] tile scatter, ms[4] raster, ms[5] launches of the
- * raster kernel, ms[6] renders timed.  `n` is the capacity of `ms` (>= 7).
- * Waits for the timed work to finish.  reset = 1 clears the accumulators. */
+ * raster kernel, ms[6] renders timed; if n >= 10 also the totals over the
+ * timed renders of ms[7] visible Gaussians, ms[8] (tile, Gaussian) pairs,
+ * ms[9] tile-row list entries.  `n` is the capacity of `ms` (>= 7).  Waits
+ * for the timed work to finish.  reset = 1 clears the accumulators. */
 int gsr_stage_times(gsr_ctx* ctx, double* ms, int n, int reset);
 
 /* Description of the last error on this host thread ("" if none). */

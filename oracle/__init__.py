@@ -23,5 +23,5 @@ Gaussian clusters with their rigid bodies, "Rigid-Link Gaussian Kinematics"):
 """
 from .spec32 import bin_ref, quat_to_rot32  # noqa: F401
 from .attrs64 import attrs64  # noqa: F401
-from .render import render_ref, composite64  # noqa: F401
+from .render import render_ref, composite64, oracle_threads  # noqa: F401
 from .brute import brute_ref  # noqa: F401

@@ -27,6 +27,9 @@
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     const double *u, *v, *ca, *cb, *cc, *op, *rgb, *z;
@@ -94,6 +97,16 @@ static void run_pixel(const uint32_t *list, int64_t n, double px, double py, con
  * met more flagged decisions than max_flags), visited [H][W] (list entries
  * visited up to termination).  Returns 0.
  */
+/* Threads the compositing loop runs on (OpenMP's default team size). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int oracle_composite(int W, int H, int ts, int tiles_x, const int64_t *ranges, const uint32_t *values,
                      const double *u, const double *v, const double *ca, const double *cb, const double *cc,
                      const double *op, const double *rgb, const double *z, const double *bg,

@@ -53,8 +53,14 @@ def _load():
         lib.oracle_composite.argtypes = ([ctypes.c_int] * 4 + [P, P] + [P] * 9 + [ctypes.c_double, ctypes.c_int]
                                          + [P] * 7)
         lib.oracle_composite.restype = ctypes.c_int
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def oracle_threads() -> int:
+    """Threads the float64 compositing runs on (the float32 binning is one thread)."""
+    return int(_load().oracle_threads())
 
 
 def _ptr(a: Optional[np.ndarray]):

@@ -115,7 +115,8 @@ int validate_desc(const gsr_ctx* ctx, const gsr_render_desc* d, const SceneRes* 
         return fail(GSR_E_INVALID, "pose / viewmat arrays too large");
     if (need_outputs) {
         if (!d->out_rgb || !d->out_depth) return fail(GSR_E_INVALID, "out_rgb / out_depth is NULL");
-        if (((uintptr_t)d->out_rgb & 3) || ((uintptr_t)d->out_depth & 3) || ((uintptr_t)d->out_alpha & 3))
+        if (((uintptr_t)d->out_rgb & 3) || ((uintptr_t)d->out_depth & 3) || ((uintptr_t)d->out_alpha & 3) ||
+            ((uintptr_t)d->out_work & 3))
             return fail(GSR_E_INVALID, "outputs must be 4-byte aligned");
     }
     return GSR_OK;
@@ -151,6 +152,7 @@ std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies)
                 im.out_rgb = d->out_rgb + 3 * pixel_base;
                 im.out_depth = d->out_depth + pixel_base;
                 im.out_alpha = d->out_alpha ? d->out_alpha + pixel_base : nullptr;
+                im.out_work = d->out_work ? d->out_work + 2 * pixel_base : nullptr;
             }
             tile_base += (uint64_t)tx * ty;
             pixel_base += (uint64_t)cam.width * cam.height;
@@ -228,7 +230,7 @@ hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& 
     ENS(tile_hist, I * p.tile_blocks * (size_t)p.t_max * 4);
     ENS(tile_range, I * (size_t)p.t_max * 8);
     ENS(pair_count, I * 4);
-    ENS(pair_base, (I + 1) * 8);
+    ENS(pair_base, (I + 2) * 8);
     ENS(row_hist, I * p.tile_blocks * (size_t)p.ty_max * 4);
     ENS(row_range, I * (size_t)p.ty_max * 8);
     ENS(row_count, I * 4);
@@ -403,6 +405,8 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
             e = hipMemcpyAsync(ws.h_total, c.pair_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, q);
         if (e == hipSuccess)
             e = hipMemcpyAsync(ws.h_total + 1, c.row_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, q);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws.h_total + 2, c.pair_base + n_img + 1, sizeof(uint64_t), hipMemcpyDeviceToHost, q);
         return e;
     });
     if (rc) return rc;
@@ -412,6 +416,12 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     const uint64_t total = ws.h_total[0];
     const uint64_t row_total = ws.h_total[1];
     *pairs_total = total;
+    if (prof) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->count_pairs += (double)total;
+        ctx->count_rows += (double)row_total;
+        ctx->count_visible += (double)ws.h_total[2];
+    }
     // everything enqueued before ev_total has completed, including earlier chunks: growing is safe
     if (ws.pairs.bytes < total * 4) {
         const size_t want = std::max<size_t>(total * 4, (size_t)((double)ws.pairs.bytes * 1.5));
@@ -434,6 +444,8 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     rp.ts = tu.ts;
     rp.batch = tu.batch;
     rp.persistent = tu.persistent;
+    rp.count_work = 0;
+    for (int k = 0; k < n_img; ++k) rp.count_work |= job.imgs[i0 + k].out_work != nullptr;
     rp.persistent_blocks = ctx->cu_count * (tu.ts == 8 ? 16 : 4);
     if (tu.persistent) {
         GSR_HIP_TRY(ws.counter.ensure(256));
@@ -456,6 +468,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     }
     rp.n_blocks = blocks;
     key.push_back((uint64_t)(uintptr_t)rp.counter);
+    key.push_back((uint64_t)rp.count_work);
     rc = run_stage(ws, graph, chunk_idx, 4, key, st, [&](hipStream_t q) { return launch_raster(s, c, rp, q); });
     if (rc) return rc;
     if (prof) {
@@ -808,10 +821,16 @@ GSR_EXPORT int gsr_stage_times(gsr_ctx* ctx, double* ms, int n, int reset)
     for (int k = 0; k < 5; ++k) ms[k] = ctx->stage_ms[k];
     ms[5] = ctx->raster_launches;
     ms[6] = ctx->renders;
+    if (n >= 10) {
+        ms[7] = ctx->count_visible;
+        ms[8] = ctx->count_pairs;
+        ms[9] = ctx->count_rows;
+    }
     if (reset) {
         for (double& v : ctx->stage_ms) v = 0.0;
         ctx->raster_launches = 0;
         ctx->renders = 0;
+        ctx->count_visible = ctx->count_pairs = ctx->count_rows = 0;
     }
     return GSR_OK;
 }
@@ -1041,7 +1060,7 @@ GSR_EXPORT int gsr_autotune(gsr_ctx* ctx, const gsr_render_desc* d, void* stream
         t.batch = b;
         consider(t);
     }
-    for (int ipt : {1, 2, 4, 8}) {
+    for (int ipt : {1, 2, 4, 8, 16}) {
         if (ipt == cur.ipt) continue;
         Tuning t = cur;
         t.ipt = ipt;

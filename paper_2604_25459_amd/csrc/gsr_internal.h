@@ -34,6 +34,7 @@ struct ImageInfo {
     float* out_rgb;           // first pixel of the image: [H][W][3]
     float* out_depth;         // [H][W]
     float* out_alpha;         // [H][W] or null
+    uint32_t* out_work;       // [H][W][2] (visited entries, blended Gaussians) or null
 };
 
 // Resident scene, device pointers.
@@ -80,7 +81,7 @@ struct ChunkDev {
     uint32_t* tile_hist;       // [n_img][tile_blocks][t_max] per-block tile counts
     uint32_t* tile_range;      // [n_img][t_max][2] local [start, end)
     uint32_t* pair_count;      // [n_img] P_i
-    uint64_t* pair_base;       // [n_img + 1] exclusive prefix of P_i (last = total)
+    uint64_t* pair_base;       // [n_img + 2] exclusive prefix of P_i, total pairs, total visible
     uint32_t* pairs;           // [total pairs] Gaussian id per (tile, depth)-sorted entry
     int ty_max;                // largest tile-row count of an image in the chunk
     int tx_max;                // largest tile-column count
@@ -113,8 +114,9 @@ struct RasterParams {
     int ts;                  // tile side: 8, 16 or 32
     int batch;               // records staged in LDS per round
     int persistent;          // 1: persistent workgroups pulling tiles from `counter`
+    int count_work;          // 1: images carry out_work (counting instantiation)
     int persistent_blocks;   // workgroups of the persistent launch
-    uint32_t* counter;       // device tile counter (persistent launch)
+    uint32_t* counter;       // device tile counters, one per XCD (persistent launch)
     int n_segs;
     RasterSeg segs[kMaxSegs];
     uint32_t n_blocks;
@@ -129,5 +131,18 @@ hipError_t launch_scene_convert(int storage, int64_t n, int64_t n_pad, int degre
 // Debug: 64-bit keys of one image from its sorted pairs.
 hipError_t launch_debug_keys(const ChunkDev& c, int image, uint64_t n, const uint32_t* pairs, uint64_t n_pairs,
                              uint64_t* keys_out, hipStream_t stream);
+
+// Workgroups of a launch are handed to the chip's 8 XCDs round-robin by
+// linear id, and each XCD has its own L2.  xcd_remap renumbers linear id b of
+// a G-workgroup launch so that each XCD runs one contiguous range of logical
+// ids: neighbouring work (the tiles or blocks of one image) then shares one
+// L2 instead of being fetched into all eight.  A bijection of [0, G).
+constexpr int kXcds = 8;
+
+__host__ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t G)
+{
+    const uint32_t q = G / kXcds, r = G % kXcds, x = b % kXcds, k = b / kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
 
 }  // namespace gsr

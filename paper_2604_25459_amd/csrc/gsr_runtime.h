@@ -74,7 +74,7 @@ struct StageGraph {
 struct Workspace {
     DevBuf img, xform, keyz, rect, srect, rec, sk0, sk1, sv0, sv1, sort_hist, vis_count, tile_hist, tile_range,
         pair_count, pair_base, pairs, row_hist, row_range, row_count, row_base, rows, debug, stage_vm, stage_pose;
-    uint64_t* h_total = nullptr;   // pinned: [0] pairs, [1] row entries of the current chunk
+    uint64_t* h_total = nullptr;   // pinned: [0] pairs, [1] row entries, [2] visible Gaussians of the current chunk
     ImageInfo* h_img = nullptr;    // pinned staging for image descriptions
     size_t h_img_cap = 0;
     hipEvent_t ev_total = nullptr, ev_done = nullptr;
@@ -144,6 +144,7 @@ struct gsr_ctx {
     std::vector<gsr::StageEvents> pending;            // recorded, not yet read
     double stage_ms[5] = {0, 0, 0, 0, 0};
     double raster_launches = 0, renders = 0;
+    double count_visible = 0, count_pairs = 0, count_rows = 0;   // profiled renders
     std::atomic<bool> poisoned{false};
     std::map<std::string, gsr::Tuning> tuned;         // shape class -> launch parameters
     int cu_count = 256;

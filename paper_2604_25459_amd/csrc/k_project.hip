@@ -167,13 +167,17 @@ __device__ __forceinline__ void sh_rgb(const float* f, float x, float y, float z
 
 // ---------------------------------------------------------------- project
 // Grid: x = Gaussian blocks of 256, y = groups of `ipt` images.  A thread loads
-// its Gaussian once and projects it into each image of its group.
+// its Gaussian once and projects it into each image of its group.  Blocks are
+// renumbered so that one XCD runs every image group of a run of Gaussian
+// blocks back to back: the scene is fetched into each L2 about once.
 template <int ST, int DEG>
 __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts, float cutoff, int ipt)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
+    const int64_t g = (int64_t)bx * 256 + threadIdx.x;
     if (g >= s.n) return;
-    const int i_begin = blockIdx.y * ipt;
+    const int i_begin = (int)by * ipt;
 
     int slot = 0;
     if (s.n_bodies > 0 && g >= s.body_off[0]) {

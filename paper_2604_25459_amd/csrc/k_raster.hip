@@ -32,6 +32,12 @@ namespace {
 
 constexpr float kLogAlphaMin = -7.99435343685886f;   // log2(1/255)
 constexpr float kCullMargin = 0.05f;                  // in log2(alpha) units
+// x coordinate given to a pixel once it has stopped (or lies outside the
+// image): p evaluates to -inf there for every Gaussian (|A| is at least the
+// dilation's share, so A dx^2 overflows), so the pixel never takes another
+// Gaussian and needs no separate liveness flag in the per-Gaussian loop.
+constexpr float kDead = 1.0e30f;
+constexpr float kDeadTest = 1.0e29f;
 
 // Pixel layout: TS <= 16: one pixel per thread, waves own 8x8 blocks.
 // TS == 32: 256 threads x 4 pixels, wave w owns rows [8w, 8w + 8) (32 x 8).
@@ -61,8 +67,12 @@ __device__ __forceinline__ float max_logalpha_rect(float A, float B, float C, fl
                                                    float Y1)
 {
     if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return lo;
-    const float ky = -B / (2.0f * C);     // argmax over y for fixed x is ky * x
-    const float kx = -B / (2.0f * A);
+    // argmax over y for fixed x is ky * x (and over x for fixed y, kx * y).  An
+    // approximate reciprocal moves the evaluated point along the edge by a
+    // relative 1e-7, which lowers the bound by a second-order amount only:
+    // the point stays on the edge, so the value is still attained there.
+    const float ky = -B * __builtin_amdgcn_rcpf(2.0f * C);
+    const float kx = -B * __builtin_amdgcn_rcpf(2.0f * A);
     float best = -INFINITY;
     {
         const float y = fminf(fmaxf(ky * X0, Y0), Y1);
@@ -89,7 +99,7 @@ struct RasterLds {
 };
 
 // Composites tile `bid` of the chunk (block id in segment order).
-template <int TS, int kBatch>
+template <int TS, int kBatch, bool COUNT>
 __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c, const RasterParams& p, uint32_t bid,
                                             RasterLds<TS, kBatch>& L_)
 {
@@ -126,7 +136,7 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
     const float wy1 = wy0 + (float)(L::kWaveH - 1);
 
     float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
-    bool live[PPT];
+    uint32_t stop_at[PPT], blended[PPT];     // work counters (COUNT only)
     int pxi[PPT], pyi[PPT];
     bool any_live = false;
 #pragma unroll
@@ -135,12 +145,14 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         L::pixel(lane, k, &lx, &ly);
         pxi[k] = tx * TS + ox + lx;
         pyi[k] = ty * TS + oy + ly;
-        live[k] = pxi[k] < im.width && pyi[k] < im.height;
-        px[k] = (float)pxi[k] + 0.5f;
+        const bool inside = pxi[k] < im.width && pyi[k] < im.height;
+        px[k] = inside ? (float)pxi[k] + 0.5f : kDead;
         py[k] = (float)pyi[k] + 0.5f;
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = D[k] = 0.0f;
-        any_live = any_live || live[k];
+        stop_at[k] = 0xFFFFFFFFu;
+        blended[k] = 0u;
+        any_live = any_live || inside;
     }
 
     const uint32_t* R = c.tile_range + ((size_t)i * c.t_max + t) * 2;
@@ -182,7 +194,7 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             // pixel-centre rectangle still to be shaded: the live pixels' bounding box
             float lx0 = wx0, lx1 = wx1, ly0 = wy0, ly1 = wy1;
             if (PPT == 1) {
-                const uint64_t M = __ballot(live[0]);             // lane = 8 * row + column
+                const uint64_t M = __ballot(px[0] < kDeadTest);  // lane = 8 * row + column
                 uint64_t cm = M | (M >> 32);
                 cm |= cm >> 16;
                 cm |= cm >> 8;
@@ -208,40 +220,41 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
                 const float4 a = sA[buf][j];
                 const float4 bq = sB[buf][j];
                 float pw[PPT];
-                bool tk[PPT];
                 bool anyt = false;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     const float dx = px[k] - a.x;
                     const float dy = py[k] - a.y;
                     pw[k] = fmaf(dx, fmaf(a.z, dx, a.w * dy), fmaf(bq.x * dy, dy, bq.y));
-                    tk[k] = live[k] && pw[k] >= kLogAlphaMin;
-                    anyt = anyt || tk[k];
+                    anyt = anyt || pw[k] >= kLogAlphaMin;
                 }
                 if (__ballot(anyt) == 0ull) continue;       // no live pixel of the wave reaches 1/255
                 const float4 col = sC[buf][j];
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
+                    const bool take = pw[k] >= kLogAlphaMin;
                     const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(pw[k]));
-                    const bool take = tk[k];
                     const float Tn = fmaf(-T[k], alpha, T[k]);
                     const bool stop = take && Tn < 1e-4f;
-                    const float wgt = (take && !stop) ? alpha * T[k] : 0.0f;
+                    const bool add = take && !stop;
+                    const float wgt = add ? alpha * T[k] : 0.0f;
                     C0[k] = fmaf(col.x, wgt, C0[k]);
                     C1[k] = fmaf(col.y, wgt, C1[k]);
                     C2[k] = fmaf(col.z, wgt, C2[k]);
                     D[k] = fmaf(bq.z, wgt, D[k]);
-                    T[k] = (take && !stop) ? Tn : T[k];
-                    live[k] = live[k] && !stop;
-                }
-                bool lv = false;
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) lv = lv || live[k];
-                if (__ballot(lv) == 0ull) {
-                    wave_live = false;
-                    break;
+                    T[k] = add ? Tn : T[k];
+                    px[k] = stop ? kDead : px[k];
+                    if (COUNT) {
+                        blended[k] += add ? 1u : 0u;
+                        if (stop) stop_at[k] = b0 - start + (uint32_t)j + 1u;
+                    }
                 }
             }
+            // the wave stops once none of its pixels is live (checked per 64 candidates)
+            bool lv = false;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) lv = lv || px[k] < kDeadTest;
+            if (__ballot(lv) == 0ull) wave_live = false;
         }
         buf ^= 1;
         if (__syncthreads_count(wave_live && lane == 0 ? 1 : 0) == 0) break;
@@ -256,52 +269,73 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         im.out_rgb[3 * pix + 2] = fmaf(T[k], im.bg[2], C2[k]);
         im.out_depth[pix] = T[k] < 1.0f ? D[k] / (1.0f - T[k]) : 0.0f;
         if (im.out_alpha) im.out_alpha[pix] = 1.0f - T[k];
+        if (COUNT && im.out_work) {
+            im.out_work[2 * pix] = stop_at[k] != 0xFFFFFFFFu ? stop_at[k] : end - start;
+            im.out_work[2 * pix + 1] = blended[k];
+        }
     }
 }
 
 // One workgroup per tile.
-template <int TS, int kBatch>
+template <int TS, int kBatch, bool COUNT>
 __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, ChunkDev c, RasterParams p)
 {
     __shared__ RasterLds<TS, kBatch> lds;
-    raster_tile<TS, kBatch>(s, c, p, blockIdx.x, lds);
+    raster_tile<TS, kBatch, COUNT>(s, c, p, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
-// Persistent workgroups: each takes tiles from a global counter (zeroed by
-// k_zero_counter before the launch) until every tile is done; tiles are taken
-// in image order, so concurrently shaded tiles share their images' records in
-// cache.  Every workgroup exits once the counter passes n_blocks.
-template <int TS, int kBatch>
+// Persistent workgroups.  The tiles are split into one contiguous range per
+// XCD that has workgroups (min(8, grid) of them); the workgroups of an XCD take
+// that range's tiles in image order from the XCD's own counter (zeroed by
+// k_zero_counter before the launch), so concurrently shaded tiles share their
+// images' records in that XCD's L2.  Every workgroup exits once its counter
+// passes its range.
+template <int TS, int kBatch, bool COUNT>
 __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster_persistent(SceneDev s, ChunkDev c, RasterParams p,
                                                                             uint32_t* counter)
 {
     __shared__ RasterLds<TS, kBatch> lds;
     __shared__ uint32_t next;
+    const uint32_t parts = gridDim.x < (uint32_t)kXcds ? gridDim.x : (uint32_t)kXcds;
+    const uint32_t x = blockIdx.x % (uint32_t)kXcds;       // < parts
+    const uint32_t q = p.n_blocks / parts, r = p.n_blocks % parts;
+    const uint32_t first = x * q + (x < r ? x : r), count = q + (x < r ? 1u : 0u);
     for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) next = atomicAdd(&counter[x], 1u);
         __syncthreads();
-        const uint32_t bid = next;
+        const uint32_t k = next;
         __syncthreads();
-        if (bid >= p.n_blocks) break;
-        raster_tile<TS, kBatch>(s, c, p, bid, lds);
+        if (k >= count) break;
+        raster_tile<TS, kBatch, COUNT>(s, c, p, first + k, lds);
         __syncthreads();
     }
 }
 
-__global__ void k_zero_counter(uint32_t* counter) { *counter = 0u; }
+// Clears the per-XCD tile counters (a kernel, so that it can sit in a graph).
+__global__ void k_zero_counter(uint32_t* counter)
+{
+    if (threadIdx.x < (uint32_t)kXcds) counter[threadIdx.x] = 0u;
+}
+
+template <int TS, int kBatch, bool COUNT>
+hipError_t launch_tsc(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream)
+{
+    constexpr int NT = Layout<TS>::kThreads;
+    if (p.persistent && p.counter) {
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, p.counter);
+        const uint32_t grid = std::min<uint32_t>(p.n_blocks, (uint32_t)p.persistent_blocks);
+        hipLaunchKernelGGL((k_raster_persistent<TS, kBatch, COUNT>), dim3(grid), dim3(NT), 0, stream, s, c, p,
+                           p.counter);
+    } else {
+        hipLaunchKernelGGL((k_raster<TS, kBatch, COUNT>), dim3(p.n_blocks), dim3(NT), 0, stream, s, c, p);
+    }
+    return hipGetLastError();
+}
 
 template <int TS, int kBatch>
 hipError_t launch_ts(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream)
 {
-    constexpr int NT = Layout<TS>::kThreads;
-    if (p.persistent && p.counter) {
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, stream, p.counter);
-        const uint32_t grid = std::min<uint32_t>(p.n_blocks, (uint32_t)p.persistent_blocks);
-        hipLaunchKernelGGL((k_raster_persistent<TS, kBatch>), dim3(grid), dim3(NT), 0, stream, s, c, p, p.counter);
-    } else {
-        hipLaunchKernelGGL((k_raster<TS, kBatch>), dim3(p.n_blocks), dim3(NT), 0, stream, s, c, p);
-    }
-    return hipGetLastError();
+    return p.count_work ? launch_tsc<TS, kBatch, true>(s, c, p, stream) : launch_tsc<TS, kBatch, false>(s, c, p, stream);
 }
 
 // LDS batch sizes: 64 / 128 / 256 records for 8x8 tiles (one wave), 256 / 512

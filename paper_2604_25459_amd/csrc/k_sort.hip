@@ -66,7 +66,8 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ 
                                                    uint64_t n, int shift, uint32_t* __restrict__ hist, int blocks)
 {
     __shared__ uint32_t h[256];
-    const int i = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), tid = threadIdx.x;
     const uint64_t cnt = FIRST ? n : counts[i];
     const uint64_t base = (uint64_t)b * kSortItems;
     if (base >= cnt) return;            // block-uniform: no barrier skipped by part of the block
@@ -118,7 +119,8 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
                                                       const uint2* __restrict__ rect, uint2* __restrict__ srect)
 {
     __shared__ uint32_t cnt[4][256];
-    const int i = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), tid = threadIdx.x;
     const int w = tid >> 6, lane = __lane_id();
     const uint64_t count = FIRST ? n : counts[i];
     const uint64_t base = (uint64_t)b * kSortItems;

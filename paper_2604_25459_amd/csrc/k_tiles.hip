@@ -121,7 +121,8 @@ __global__ __launch_bounds__(64) void k_tile_hist(ChunkDev c, uint64_t n)
     Group& grp = *reinterpret_cast<Group*>(lds);
     uint32_t* hist = lds + sizeof(Group) / 4;
     uint32_t* rhist = hist + c.t_max;
-    const int i = blockIdx.y, b = blockIdx.x, lane = __lane_id();
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
     const uint32_t V = c.n ? c.vis_count[i] : 0u;
     const uint32_t j0 = (uint32_t)b * kTileGauss;
     if (j0 >= V) return;
@@ -228,24 +229,28 @@ __global__ __launch_bounds__(256) void k_tile_scan(ChunkDev c)
     }
 }
 
-// Single block: exclusive prefixes of P_i and R_i over the chunk's images.
+// Single block: exclusive prefixes of P_i and R_i over the chunk's images;
+// pair_base[n_img] = total pairs, row_base[n_img] = total row entries,
+// pair_base[n_img + 1] = total visible Gaussians of the chunk.
 __global__ __launch_bounds__(256) void k_image_scan(ChunkDev c)
 {
-    __shared__ uint64_t part[2][256];
+    __shared__ uint64_t part[3][256];
     const int tid = threadIdx.x;
     const int per = (c.n_img + 255) / 256;
-    uint64_t sp = 0, sr = 0;
+    uint64_t sp = 0, sr = 0, sv = 0;
     for (int k = 0; k < per; ++k) {
         const int i = tid * per + k;
         if (i < c.n_img) {
             sp += c.pair_count[i];
             sr += c.row_count[i];
+            sv += c.n ? c.vis_count[i] : 0u;
         }
     }
     part[0][tid] = sp;
     part[1][tid] = sr;
+    part[2][tid] = sv;
     __syncthreads();
-    if (tid < 2) {
+    if (tid < 3) {
         uint64_t run = 0;
         for (int k = 0; k < 256; ++k) {
             const uint64_t v = part[tid][k];
@@ -253,7 +258,8 @@ __global__ __launch_bounds__(256) void k_image_scan(ChunkDev c)
             run += v;
         }
         if (tid == 0) c.pair_base[c.n_img] = run;
-        else c.row_base[c.n_img] = run;
+        else if (tid == 1) c.row_base[c.n_img] = run;
+        else c.pair_base[c.n_img + 1] = run;
     }
     __syncthreads();
     uint64_t rp = part[0][tid], rr = part[1][tid];
@@ -274,7 +280,8 @@ __global__ __launch_bounds__(64) void k_row_scatter(ChunkDev c, uint64_t n, int 
     extern __shared__ uint32_t lds[];
     Group& grp = *reinterpret_cast<Group*>(lds);
     uint32_t* cursor = lds + sizeof(Group) / 4;
-    const int i = blockIdx.y, b = blockIdx.x, lane = __lane_id();
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
     const uint32_t V = c.n ? c.vis_count[i] : 0u;
     const uint32_t j0 = (uint32_t)b * kTileGauss;
     if (j0 >= V) return;
@@ -322,8 +329,9 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
     extern __shared__ uint32_t lds[];
     Group& grp = *reinterpret_cast<Group*>(lds);
     uint32_t* cursor = lds + sizeof(Group) / 4;
-    const int i = blockIdx.y, lane = __lane_id();
-    const int y = blockIdx.x / n_groups, cg = blockIdx.x - y * n_groups;
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
+    const int y = bx / n_groups, cg = bx - y * n_groups;
     const ImageInfo im = c.img[i];
     if (y >= im.tiles_y) return;
     const uint32_t TX = (uint32_t)im.tiles_x;

@@ -55,7 +55,8 @@ class CameraDesc(C.Structure):
 class RenderDesc(C.Structure):
     _fields_ = [("scene_id", C.c_uint64), ("n_envs", C.c_int), ("n_cams", C.c_int), ("cams", C.c_void_p),
                 ("viewmats", C.c_void_p), ("body_poses", C.c_void_p), ("bg", C.c_float * 3),
-                ("out_rgb", C.c_void_p), ("out_depth", C.c_void_p), ("out_alpha", C.c_void_p)]
+                ("out_rgb", C.c_void_p), ("out_depth", C.c_void_p), ("out_alpha", C.c_void_p),
+                ("out_work", C.c_void_p)]
 
 
 class BinsOut(C.Structure):
@@ -189,11 +190,14 @@ class Renderer:
 
     def stage_times(self, reset: bool = True):
         """Device ms per stage accumulated since the last reset (profile=True)."""
-        ms = np.zeros(8, np.float64)
-        _check(load().gsr_stage_times(self._h, ms.ctypes.data, 8, int(reset)))
+        ms = np.zeros(10, np.float64)
+        _check(load().gsr_stage_times(self._h, ms.ctypes.data, 10, int(reset)))
         out = dict(zip(self.STAGES, ms[:5].tolist()))
         out["raster_launches"] = int(ms[5])
         out["renders"] = int(ms[6])
+        out["visible"] = int(ms[7])
+        out["pairs"] = int(ms[8])
+        out["row_entries"] = int(ms[9])
         return out
 
     # ---------------------------------------------------------- scenes
@@ -234,11 +238,11 @@ class Renderer:
                                 near_plane=c.near)
         return arr
 
-    def _desc(self, sid, cams, viewmats, poses, bg, rgb=None, depth=None, alpha=None):
+    def _desc(self, sid, cams, viewmats, poses, bg, rgb=None, depth=None, alpha=None, work=None):
         carr = self._cams(cams)
         d = RenderDesc(scene_id=sid, n_envs=int(viewmats.shape[1]), n_cams=len(cams), cams=C.addressof(carr),
                        viewmats=_ptr(viewmats), body_poses=_ptr(poses) if poses is not None and poses.numel() else None,
-                       out_rgb=_ptr(rgb), out_depth=_ptr(depth), out_alpha=_ptr(alpha))
+                       out_rgb=_ptr(rgb), out_depth=_ptr(depth), out_alpha=_ptr(alpha), out_work=_ptr(work))
         d.bg[0], d.bg[1], d.bg[2] = [float(x) for x in bg]
         return d, carr
 
@@ -265,10 +269,11 @@ class Renderer:
         return out
 
     def render_into(self, sid, cams, viewmats, poses, rgb, depth, alpha=None, bg=(0.0, 0.0, 0.0), plain=False,
-                    stream=None):
-        """viewmats: CUDA float32 [C, E, 3, 4]; poses: CUDA float32 [E, B, 7]."""
+                    stream=None, work=None):
+        """viewmats: CUDA float32 [C, E, 3, 4]; poses: CUDA float32 [E, B, 7]; work: optional CUDA int32
+        [pixels * 2] receiving (visited list entries, blended Gaussians) per pixel."""
         import torch
-        d, carr = self._desc(sid, cams, viewmats, poses, bg, rgb, depth, alpha)
+        d, carr = self._desc(sid, cams, viewmats, poses, bg, rgb, depth, alpha, work)
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         fn = load().gsr_render_plain if plain else load().gsr_render
         _check(fn(self._h, C.byref(d), C.c_void_p(st)))

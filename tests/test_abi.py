@@ -87,7 +87,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(gsr.TuningDesc) == 6 * 4 + 16
     assert C.sizeof(gsr.SceneDesc) == 8 + 4 * 4 + 8 * 6
     assert C.sizeof(gsr.CameraDesc) == 7 * 4
-    assert C.sizeof(gsr.RenderDesc) == 8 + 4 + 4 + 8 * 3 + 12 + 4 + 8 * 3
+    assert C.sizeof(gsr.RenderDesc) == 8 + 4 + 4 + 8 * 3 + 12 + 4 + 8 * 4
     assert C.sizeof(gsr.BinsOut) == 8 * 5 + 8 + 8 + 4 + 4 + 8
     assert C.sizeof(gsr.ProjOut) == 8 * 4
     assert C.sizeof(gsr.ServerCfg) == 4 + 4 + 8 + 32

@@ -126,6 +126,30 @@ def test_cfg0_bins_and_pixels(R):
     R.remove_scene(sid)
 
 
+def test_work_counts_match_oracle(R):
+    """Per-pixel list entries visited up to termination equal the oracle's count
+    (pixels whose decisions are within rounding of a threshold excepted)."""
+    import torch
+    from paper_2604_25459_amd import gsr
+    for cfg, e in ((0, 0), (1, 5)):
+        scene, batch = synth.make_config(cfg, n_envs=e + 1)
+        sid = _upload(R, scene)
+        cams, vm, poses = gsr.batch_tensors(batch)
+        rgb, depth, _ = R.alloc_outputs(cams, batch.n_envs)
+        work = torch.zeros(rgb.numel() // 3 * 2, dtype=torch.int32, device=rgb.device)
+        R.render_into(sid, cams, vm, poses, rgb, depth, work=work)
+        cam = batch.cams[0]
+        npx = cam.width * cam.height
+        w = work.view(-1, 2)[e * npx:(e + 1) * npx].cpu().numpy().reshape(cam.height, cam.width, 2)
+        ref = render_ref(scene, batch, 0, e, R.tile_size, variants=False)
+        ok = ref.nflag == 0
+        np.testing.assert_array_equal(w[..., 0][ok], ref.visited[ok])
+        assert (w[..., 1] <= w[..., 0]).all()
+        plain = R.render(sid, cams, vm, poses)          # counting changes no pixel
+        assert torch.equal(plain[0][0].reshape(-1), rgb)
+        R.remove_scene(sid)
+
+
 @pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.2, 0.3, 0.4)])
 def test_ragged_100x75_random_scene(R, bg):
     rng = np.random.default_rng(3)
