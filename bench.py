@@ -205,6 +205,7 @@ def main():
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first copy 1 GiB device to device (calibrates the memory counters)")
     ap.add_argument("--no-count", action="store_true", help="skip the counting renders of the roofline")
+    ap.add_argument("--obs-steps", type=int, default=3, help="steps timed with the u8 observation epilogue (0 = skip)")
     ap.add_argument("--no-graphs", action="store_true", help="launch every stage eagerly (no graph replay)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary of two rocprofv3 --pmc runs of this bench and exit")
@@ -279,6 +280,32 @@ def main():
     value = E * args.steps / sec
     ms_per_step = 1000.0 * sec / args.steps
     log(f"[bench] {value:.1f} env-frames/s, {ms_per_step:.2f} ms/step, stages {st}")
+
+    # policy-ready observations: same workload, u8 pixels with per-image exposure /
+    # contrast / brightness randomisation fused into the rasteriser, no float colour
+    observation = None
+    if args.obs_steps:
+        g = torch.Generator().manual_seed(7)
+        n_img = E * C
+        gain = (2.0 ** (torch.rand(n_img, generator=g) - 0.5)).to(dev)
+        contrast = (0.8 + 0.4 * torch.rand(n_img, generator=g)).to(dev)
+        bright = (0.1 * torch.rand(n_img, generator=g) - 0.05).to(dev)
+        obs_out = torch.empty(rgb.numel(), dtype=torch.uint8, device=dev)
+        obs = gsr.Observation("u8", obs_out, gain, contrast, bright)
+        R.render_into(sid, cams, vm, poses[args.warmup], None, depth, None, tuple(batch.bg), obs=obs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.obs_steps):
+            R.render_into(sid, cams, vm, poses[args.warmup + s % args.steps], None, depth, None, tuple(batch.bg),
+                          obs=obs)
+        torch.cuda.synchronize()
+        osec = time.perf_counter() - t0
+        R.stage_times(reset=True)
+        observation = {"value": E * args.obs_steps / osec, "unit": "env-frames/s", "format": "u8",
+                       "steps": args.obs_steps, "randomisation": "gain 2^U[-0.5,0.5], contrast U[0.8,1.2], "
+                                                                  "brightness U[-0.05,0.05] per image"}
+        del obs_out
+        log(f"[bench] observation path (u8 + randomisation) {observation['value']:.1f} env-frames/s")
 
     # plain per-env path on a subset (same GPU, same kernels, one image per launch chain)
     plain = None
@@ -373,6 +400,7 @@ def main():
                    "sh_degree": scene.sh_degree, "storage": args.storage, "tile": args.tile,
                    "tuning": tuning},
         "plain_path": plain,
+        "observation_path": observation,
         "serving": serving,
         "stages_ms_per_step": {k: v / args.steps for k, v in st.items() if k in R.STAGES},
         "path": path,

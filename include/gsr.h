@@ -58,6 +58,9 @@ extern "C" {
 #define GSR_STORAGE_F16 1    /* scales, rotations, opacity and SH as IEEE half; means stay float32 */
 #define GSR_STORAGE_BF16 2   /* same with bfloat16 */
 
+#define GSR_OBS_U8 1         /* observation bytes: round(255 x), [..][H][W][3] uint8 */
+#define GSR_OBS_F16 2        /* observation halves: x rounded to nearest even, [..][H][W][3] */
+
 #define GSR_MEM_HOST 0       /* scene arrays are host pointers */
 #define GSR_MEM_DEVICE 1     /* scene arrays are device pointers on the context's device */
 
@@ -94,12 +97,47 @@ typedef struct {
 } gsr_scene_desc;
 
 /* One camera slot.  Every environment has one camera per slot; slots may
- * differ in resolution and intrinsics. */
+ * differ in resolution and intrinsics.
+ *
+ * Body-attached cameras (a wrist camera riding on a robot link): with
+ * attach_body = b >= 0 the slot's viewmats are body-b -> camera transforms
+ * [R_o | t_o] (one per env, so a per-env offset also carries camera-pose
+ * randomisation), and the world -> camera transform is composed on the
+ * device from the env's pose (q_b, t_b) of body b:
+ *     R_c = R_o R(q_b)^T,  t_c = t_o - R_c t_b
+ * in binary32, each product and sum rounded separately, sums left to right
+ * (so tile lists stay bit-exact).  attach_body = -1: viewmats are
+ * world -> camera as given. */
 typedef struct {
     int width, height;            /* pixels, 1..8192 */
     float fx, fy, cx, cy;         /* pinhole intrinsics in pixels */
     float near_plane;             /* Gaussians with camera depth <= near_plane are culled; > 0 */
+    int attach_body;              /* -1, or the body (0..B-1) the camera rides on */
 } gsr_camera;
+
+/* Fused observation epilogue (image-level appearance randomisation and a
+ * compact pixel format for a policy network, applied as each tile's pixels
+ * are written; the domain randomisation of brightness, contrast and exposure
+ * of the paper's sim-to-real manipulation experiment, Sec. "Vision-Centric
+ * Manipulation Learning").  Per image
+ * (camera slot c, env e), with the parameter arrays indexed [c][e] and each
+ * optional (NULL = identity), on every channel of the composited colour rgb,
+ * each step rounded to binary32:
+ *     x = rgb * gain;  x = x - 0.5;  x = x * contrast;  x = x + 0.5;
+ *     x = x + brightness;  x = min(max(x, 0), 1)
+ * then GSR_OBS_U8 stores floor(x * 255 + 0.5) as a byte and GSR_OBS_F16 the
+ * half nearest to x (ties to even).  `gain` is a linear exposure factor
+ * (2^EV).  `out` has the layout of out_rgb with 1 (U8) or 2 (F16) bytes per
+ * channel and is caller-owned device memory.  out_rgb may be NULL when an
+ * observation is requested (only the observation and depth are written). */
+typedef struct {
+    int format;                   /* GSR_OBS_U8 or GSR_OBS_F16 */
+    int reserved0;
+    const float* gain;            /* device [C][E] or NULL (1) */
+    const float* contrast;        /* device [C][E] or NULL (1) */
+    const float* brightness;      /* device [C][E] or NULL (0) */
+    void* out;                    /* device; u8 or half, [..][H_c][W_c][3] like out_rgb; 2-byte aligned for F16 */
+} gsr_observation;
 
 /* One render call: n_envs environments x n_cams camera slots. */
 typedef struct {
@@ -116,6 +154,7 @@ typedef struct {
     uint32_t* out_work;           /* device, optional (NULL): per pixel two counts, [..][H_c][W_c][2]: list entries
                                      visited up to and including the one that stopped the pixel (else the tile's
                                      list length), and Gaussians blended -- the algorithmic work of compositing */
+    const gsr_observation* obs;   /* host, optional (NULL): fused observation epilogue */
 } gsr_render_desc;
 
 /* Materialised binning of one image (for parity checks). */
@@ -256,7 +295,9 @@ typedef struct {
     int persistent;         /* 0 or 1 */
     int chunk_images;       /* 0 = from chunk_bytes, else images per memory chunk */
     float ms;               /* out: time of one render with these parameters (gsr_autotune) */
-    int reserved[4];
+    int bin_schedule;       /* tile lists from tile-row lists: 0 stable scatter (one wave per row),
+                               1 gather (one lane per tile column); identical lists */
+    int reserved[3];
 } gsr_tuning;
 
 /* Times candidate parameters on `desc` (coordinate descent, each candidate one

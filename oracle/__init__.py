@@ -20,8 +20,11 @@ Gaussian clusters with their rigid bodies, "Rigid-Link Gaussian Kinematics"):
   threshold decision lies within rounding distance of its boundary.
 * ``brute.brute_ref``  -- every Gaussian at every pixel in (depth, index)
   order; for tiny scenes only.
+* ``observe``          -- the observation epilogue (exposure gain, contrast,
+  brightness, clamp, u8 / f16 pixels) applied to oracle colours.
 """
 from .spec32 import bin_ref, quat_to_rot32  # noqa: F401
 from .attrs64 import attrs64  # noqa: F401
 from .render import render_ref, composite64, oracle_threads  # noqa: F401
 from .brute import brute_ref  # noqa: F401
+from .observe import observe64, observe32, observe_codes, quantise_u8  # noqa: F401

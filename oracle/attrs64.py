@@ -46,6 +46,22 @@ def quat_to_rot64(q: np.ndarray) -> np.ndarray:
     return R
 
 
+def viewmat64(batch, c: int, e: int):
+    """World->camera (W, w) of image (c, e) in float64.  A camera slot attached
+    to body k carries body->camera offsets (R_o, t_o): a world point p is
+    first taken into the body frame, R_k^T (p - t_k), then into the camera,
+    so W = R_o R_k^T and w = t_o - W t_k."""
+    vm = np.asarray(batch.viewmats[c, e], np.float64)
+    Ro, to = vm[:, :3], vm[:, 3]
+    k = int(getattr(batch.cams[c], "attach_body", -1))
+    if k < 0:
+        return Ro, to
+    pose = np.asarray(batch.poses[e, k], np.float64)
+    Rk = quat_to_rot64(pose[None, 0:4])[0]
+    W = Ro @ Rk.T
+    return W, to - W @ pose[4:7]
+
+
 def attrs64(scene, batch, c: int = 0, e: int = 0, attrs: Dict[str, np.ndarray] | None = None) -> Dict[str, np.ndarray]:
     """Float64 projection of every Gaussian into image (c, e).
 
@@ -73,8 +89,7 @@ def attrs64(scene, batch, c: int = 0, e: int = 0, attrs: Dict[str, np.ndarray] |
         Rb[m] = Rbody[body[m]]
         tb[m] = pose[body[m], 4:7]
 
-    vm = np.asarray(batch.viewmats[c, e], np.float64)
-    Wc, wt = vm[:, :3], vm[:, 3]
+    Wc, wt = viewmat64(batch, c, e)
 
     mu_world = np.einsum("nij,nj->ni", Rb, mu) + tb
     t = mu_world @ Wc.T + wt

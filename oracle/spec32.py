@@ -21,6 +21,9 @@ Readings where the paper is silent (also listed in the design notes):
   the half field of view; the projected mean is not clamped;
 * conservative radius r = ceil(3.33 * sqrt(lambda_max)); 3.33 >= sqrt(2 ln 255)
   so no pixel outside the square can reach alpha >= 1/255;
+* the tile rectangle uses the tighter of that square and the axis-aligned box
+  of the opacity-aware ellipse q <= 2 ln(255 o) (bounded per opacity bucket,
+  QMAX below), which is still conservative;
 * the determinant uses the Lagrange identity (no cancellation).
 """
 from __future__ import annotations
@@ -37,6 +40,15 @@ DILATE_SQ = F(0.09)
 EIG_FLOOR = F(0.1)
 GUARD = F(1.3)
 ALPHA_MIN = F(1.0) / F(255.0)
+
+# Opacity-aware splat extent.  alpha >= 1/255 needs q <= 2 ln(255 o), q the
+# Mahalanobis form of the dilated 2D covariance.  Opacities fall in buckets
+# (2^-(k+1), 2^-k], k = 0..7 (k = 8 and beyond are culled by o >= 1/255), and
+# QMAX[k] is 1.01 * 2 ln(255 * 2^-k) rounded up to binary32: a bound for the
+# whole bucket with 1 % to spare for binary32 rounding of the extents below.
+QMAX = np.array([float.fromhex(h) for h in (
+    "0x1.662ff2p+3", "0x1.3961dcp+3", "0x1.0c93c4p+3", "0x1.bf8b5cp+2",
+    "0x1.65ef2ep+2", "0x1.0c5300p+2", "0x1.656da6p+1", "0x1.646a94p+0")], F)
 
 
 def quat_to_rot32(q: np.ndarray) -> np.ndarray:
@@ -96,12 +108,31 @@ def tile_bases(batch, ts: int) -> np.ndarray:
     return np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
 
 
+def viewmat32(batch, c: int, e: int):
+    """World->camera (R_c, t_c) of image (c, e) in the float32 spec.  A camera
+    slot attached to body k carries body->camera offsets [R_o | t_o] instead;
+    then R_c = R_o R(q_k)^T (matmul32 with the transposed body rotation) and
+    t_c = t_o - R_c t_k, the product summed left to right before the one
+    subtraction (the camera rides rigidly on the body: its world pose is the
+    body's pose followed by the offset)."""
+    vm = np.asarray(batch.viewmats[c, e], F)
+    Ro, to = vm[:, :3], vm[:, 3]
+    k = int(getattr(batch.cams[c], "attach_body", -1))
+    if k < 0:
+        return Ro, to
+    pose = np.asarray(batch.poses[e, k], F)
+    Rk = quat_to_rot32(pose[0:4])
+    Rc = matmul32(Ro, np.ascontiguousarray(Rk.T))
+    tk = pose[4:7]
+    Rt = np.array([(Rc[i, 0] * tk[0] + Rc[i, 1] * tk[1]) + Rc[i, 2] * tk[2] for i in range(3)], F)
+    return Rc, (to - Rt).astype(F)
+
+
 def compose32(batch, scene, c: int, e: int):
     """Per-body camera-from-body transforms (A, a) for image (c, e); slot 0 is
     the static background (A = R_c, a = t_c), slot b+1 is body b:
     A = R_c R(q_b), a = R_c t_b + t_c."""
-    vm = np.asarray(batch.viewmats[c, e], F)
-    Rc, tc = vm[:, :3], vm[:, 3]
+    Rc, tc = viewmat32(batch, c, e)
     B = scene.n_bodies
     As = np.empty((B + 1, 3, 3), F)
     as_ = np.empty((B + 1, 3), F)
@@ -187,12 +218,20 @@ def project32(scene, batch, c: int, e: int, ts: int = 16, cutoff: float = 3.33,
         r = np.ceil(F(cutoff) * np.sqrt(lam))
         u = (fx * tx) / tz + cx
         v = (fy * ty) / tz + cy
+        # axis-aligned half-extents of the ellipse q <= QMAX[bucket of o]
+        # (sqrt(Q Sigma_xx), sqrt(Q Sigma_yy)), never beyond the radius
+        k = np.zeros(N, np.int64)
+        for j in range(1, 8):
+            k += (opac <= F(2.0 ** -j)).astype(np.int64)
+        Q = QMAX[k]
+        rx = np.minimum(r, np.sqrt(Q * ca))
+        ry = np.minimum(r, np.sqrt(Q * cc))
         tsf = F(ts)
         TX, TY = image_tiles(cam.width, cam.height, ts)
-        x0 = np.clip(np.floor((u - r) / tsf), F(0), F(TX))
-        x1 = np.clip(np.floor((u + r) / tsf) + ONE, F(0), F(TX))
-        y0 = np.clip(np.floor((v - r) / tsf), F(0), F(TY))
-        y1 = np.clip(np.floor((v + r) / tsf) + ONE, F(0), F(TY))
+        x0 = np.clip(np.floor((u - rx) / tsf), F(0), F(TX))
+        x1 = np.clip(np.floor((u + rx) / tsf) + ONE, F(0), F(TX))
+        y0 = np.clip(np.floor((v - ry) / tsf), F(0), F(TY))
+        y1 = np.clip(np.floor((v + ry) / tsf) + ONE, F(0), F(TY))
         finite_t = np.isfinite(tx) & np.isfinite(ty) & np.isfinite(tz)
         vis = finite_t & (tz > F(cam.near)) & (opac >= ALPHA_MIN) & np.isfinite(det) & (det > F(0))
         vis &= np.isfinite(r) & np.isfinite(u) & np.isfinite(v)

@@ -113,11 +113,27 @@ int validate_desc(const gsr_ctx* ctx, const gsr_render_desc* d, const SceneRes* 
     if ((int64_t)d->n_envs * std::max(sc->dev.n_bodies, 1) * 7 > 0xFFFFFFFFLL ||
         (int64_t)d->n_envs * d->n_cams * 12 > 0xFFFFFFFFLL)
         return fail(GSR_E_INVALID, "pose / viewmat arrays too large");
+    for (int c = 0; c < d->n_cams; ++c) {
+        const int ab = d->cams[c].attach_body;
+        if (ab < -1 || ab >= sc->dev.n_bodies)
+            return fail(GSR_E_INVALID, "attach_body must be -1 or a body of the scene (0..B-1)");
+    }
     if (need_outputs) {
-        if (!d->out_rgb || !d->out_depth) return fail(GSR_E_INVALID, "out_rgb / out_depth is NULL");
+        if (!d->out_depth) return fail(GSR_E_INVALID, "out_depth is NULL");
+        if (!d->out_rgb && !d->obs) return fail(GSR_E_INVALID, "out_rgb is NULL and no observation is requested");
         if (((uintptr_t)d->out_rgb & 3) || ((uintptr_t)d->out_depth & 3) || ((uintptr_t)d->out_alpha & 3) ||
             ((uintptr_t)d->out_work & 3))
             return fail(GSR_E_INVALID, "outputs must be 4-byte aligned");
+        if (d->obs) {
+            const gsr_observation* o = d->obs;
+            if (o->format != GSR_OBS_U8 && o->format != GSR_OBS_F16)
+                return fail(GSR_E_INVALID, "observation format must be GSR_OBS_U8 or GSR_OBS_F16");
+            if (!o->out) return fail(GSR_E_INVALID, "observation output is NULL");
+            if (o->format == GSR_OBS_F16 && ((uintptr_t)o->out & 1))
+                return fail(GSR_E_INVALID, "half observation output must be 2-byte aligned");
+            if (((uintptr_t)o->gain & 3) || ((uintptr_t)o->contrast & 3) || ((uintptr_t)o->brightness & 3))
+                return fail(GSR_E_INVALID, "observation parameters must be 4-byte aligned");
+        }
     }
     return GSR_OK;
 }
@@ -148,11 +164,22 @@ std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies)
             im.bg[0] = d->bg[0];
             im.bg[1] = d->bg[1];
             im.bg[2] = d->bg[2];
-            if (d->out_rgb) {
-                im.out_rgb = d->out_rgb + 3 * pixel_base;
+            im.attach_body = cam.attach_body;
+            if (d->out_depth) {
+                im.out_rgb = d->out_rgb ? d->out_rgb + 3 * pixel_base : nullptr;
                 im.out_depth = d->out_depth + pixel_base;
                 im.out_alpha = d->out_alpha ? d->out_alpha + pixel_base : nullptr;
                 im.out_work = d->out_work ? d->out_work + 2 * pixel_base : nullptr;
+                if (d->obs) {
+                    const gsr_observation* o = d->obs;
+                    const size_t bpc = o->format == GSR_OBS_F16 ? 2 : 1;
+                    im.out_obs = (char*)o->out + 3 * pixel_base * bpc;
+                    im.obs_gain = o->gain;
+                    im.obs_contrast = o->contrast;
+                    im.obs_bright = o->brightness;
+                    im.obs_fmt = o->format;
+                    im.obs_idx = (uint32_t)((size_t)c * E + e);
+                }
             }
             tile_base += (uint64_t)tx * ty;
             pixel_base += (uint64_t)cam.width * cam.height;
@@ -379,7 +406,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
                                  (uint64_t)c.tile_blocks, (uint64_t)tu.ts, (uint64_t)tu.batch, (uint64_t)tu.ipt,
                                  (uint64_t)tu.persistent, (uint64_t)(uintptr_t)job.viewmats,
                                  (uint64_t)(uintptr_t)job.poses, (uint64_t)(uintptr_t)ws.h_total,
-                                 (uint64_t)ctx->opt.cutoff * 1000};
+                                 (uint64_t)(ctx->opt.cutoff * 1.0e6f), (uint64_t)tu.bin};
     for (void* ptr : {(void*)c.xform, (void*)c.keyz, (void*)c.rect, (void*)c.srect, (void*)c.rec, (void*)c.sk[0],
                       (void*)c.sk[1], (void*)c.sv[0], (void*)c.sv[1], (void*)c.sort_hist, (void*)c.vis_count,
                       (void*)c.tile_hist, (void*)c.tile_range, (void*)c.pair_count, (void*)c.pair_base,
@@ -435,7 +462,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     c.rows = ws.rows.as<uint2>();
     key.push_back((uint64_t)(uintptr_t)c.pairs);
     key.push_back((uint64_t)(uintptr_t)c.rows);
-    rc = run_stage(ws, graph, chunk_idx, 3, key, st, [&](hipStream_t q) { return launch_tile_scatter(s, c, q); });
+    rc = run_stage(ws, graph, chunk_idx, 3, key, st, [&](hipStream_t q) { return launch_tile_scatter(s, c, tu.bin, q); });
     if (rc) return rc;
     if (mode == Mode::kBins) return GSR_OK;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[4], st));
@@ -941,6 +968,7 @@ bool tuning_valid(const gsr_ctx* ctx, const gsr_render_desc* d, const Tuning& t,
     if (t.ipt < 1 || t.ipt > 16) return *why = "images_per_thread must be in 1..16", false;
     if (t.persistent != 0 && t.persistent != 1) return *why = "persistent must be 0 or 1", false;
     if (t.chunk_images < 0) return *why = "chunk_images must be >= 0", false;
+    if (t.bin != 0 && t.bin != 1) return *why = "bin_schedule must be 0 or 1", false;
     for (int c = 0; c < d->n_cams; ++c) {
         const int64_t tiles = (int64_t)((d->cams[c].width + t.ts - 1) / t.ts) * ((d->cams[c].height + t.ts - 1) / t.ts);
         if (tiles > 15000) return *why = "more than 15000 tiles per image for this tile size", false;
@@ -957,6 +985,7 @@ Tuning from_public(const gsr_tuning* t)
     r.ipt = t->images_per_thread;
     r.persistent = t->persistent;
     r.chunk_images = t->chunk_images;
+    r.bin = t->bin_schedule;
     r.ms = t->ms;
     return r;
 }
@@ -969,6 +998,7 @@ void to_public(const Tuning& t, gsr_tuning* o)
     o->images_per_thread = t.ipt;
     o->persistent = t.persistent;
     o->chunk_images = t.chunk_images;
+    o->bin_schedule = t.bin;
     o->ms = t.ms;
 }
 
@@ -1071,6 +1101,11 @@ GSR_EXPORT int gsr_autotune(gsr_ctx* ctx, const gsr_render_desc* d, void* stream
         t.persistent = 1 - cur.persistent;
         consider(t);
     }
+    {
+        Tuning t = cur;
+        t.bin = 1 - cur.bin;
+        consider(t);
+    }
     for (int ch : {0, 64, 256}) {
         if (ch == cur.chunk_images) continue;
         Tuning t = cur;
@@ -1100,7 +1135,8 @@ GSR_EXPORT int gsr_tuning_save(gsr_ctx* ctx, const char* path)
         const Tuning& t = kv.second;
         f << "{\"key\": \"" << kv.first << "\", \"tile_size\": " << t.ts << ", \"lds_batch\": " << t.batch
           << ", \"images_per_thread\": " << t.ipt << ", \"persistent\": " << t.persistent
-          << ", \"chunk_images\": " << t.chunk_images << ", \"ms\": " << t.ms << "}\n";
+          << ", \"chunk_images\": " << t.chunk_images << ", \"bin_schedule\": " << t.bin << ", \"ms\": " << t.ms
+          << "}\n";
     }
     return f ? GSR_OK : fail(GSR_E_INVALID, "write failed");
 }
@@ -1124,7 +1160,7 @@ GSR_EXPORT int gsr_tuning_load(gsr_ctx* ctx, const char* path)
         const std::string kp = "\"key\": \"";
         const size_t a = line.find(kp);
         const size_t b = a == std::string::npos ? a : line.find('"', a + kp.size());
-        double ts, ba, ipt, pe, ch, ms;
+        double ts, ba, ipt, pe, ch, ms, bs = 1;
         if (a == std::string::npos || b == std::string::npos || !num(line, "tile_size", &ts) ||
             !num(line, "lds_batch", &ba) || !num(line, "images_per_thread", &ipt) || !num(line, "persistent", &pe) ||
             !num(line, "chunk_images", &ch) || !num(line, "ms", &ms))
@@ -1135,9 +1171,11 @@ GSR_EXPORT int gsr_tuning_load(gsr_ctx* ctx, const char* path)
         t.ipt = (int)ipt;
         t.persistent = (int)pe;
         t.chunk_images = (int)ch;
+        (void)num(line, "bin_schedule", &bs);     // optional: older caches predate it
+        t.bin = (int)bs;
         t.ms = (float)ms;
         if ((t.ts != 8 && t.ts != 16 && t.ts != 32) || t.ipt < 1 || t.ipt > 16 || (t.persistent != 0 && t.persistent != 1) ||
-            t.chunk_images < 0 ||
+            t.chunk_images < 0 || (t.bin != 0 && t.bin != 1) ||
             (t.ts == 8 ? (t.batch != 64 && t.batch != 128 && t.batch != 256) : (t.batch != 256 && t.batch != 512)))
             return fail(GSR_E_INVALID, "invalid tuning values: " + line);
         got[line.substr(a + kp.size(), b - a - kp.size())] = t;

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gsr.h"
+
 namespace gsr {
 
 constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;  // depth-key slot of a culled Gaussian
@@ -30,11 +32,17 @@ struct ImageInfo {
     uint32_t vm_off;          // float offset of the image's world->camera [R | t] in the viewmat array
     uint32_t pose_off;        // float offset of the image's env body poses [B][7] in the pose array
     float bg[3];              // background colour of the image's request
-    int pad0;
-    float* out_rgb;           // first pixel of the image: [H][W][3]
+    int attach_body;          // -1: viewmat is world->camera; b: viewmat is body-b->camera
+    float* out_rgb;           // first pixel of the image: [H][W][3] or null
     float* out_depth;         // [H][W]
     float* out_alpha;         // [H][W] or null
     uint32_t* out_work;       // [H][W][2] (visited entries, blended Gaussians) or null
+    void* out_obs;            // observation epilogue output [H][W][3] (u8 or half) or null
+    const float* obs_gain;    // per-image parameters (indexed by obs_idx) or null
+    const float* obs_contrast;
+    const float* obs_bright;
+    int obs_fmt;              // GSR_OBS_U8 / GSR_OBS_F16
+    uint32_t obs_idx;         // c * E + e within the image's request
 };
 
 // Resident scene, device pointers.
@@ -109,7 +117,9 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
 // Tile and tile-row histograms, ranges, image bases (before the host reads the totals).
 hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
 // Stable two-level scatter: depth-ordered Gaussians -> tile-row lists -> tile lists.
-hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
+// schedule 0: level 2 as a stable scatter (one wave per tile row); 1: as a
+// gather (one lane per tile column).  Both give identical tile lists.
+hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedule, hipStream_t stream);
 struct RasterParams {
     int ts;                  // tile side: 8, 16 or 32
     int batch;               // records staged in LDS per round

@@ -36,6 +36,7 @@ struct Request {
     uint64_t ticket = 0;
     gsr_render_desc desc{};
     std::vector<gsr_camera> cams;
+    gsr_observation obs{};
     SceneRes* scene = nullptr;
     int n_images = 0;
     int64_t bytes = 0;
@@ -247,6 +248,10 @@ GSR_EXPORT int gsr_submit(gsr_server* srv, const gsr_render_desc* d, uint64_t* t
     r->desc = *d;
     r->cams.assign(d->cams, d->cams + d->n_cams);
     r->desc.cams = r->cams.data();
+    if (d->obs) {
+        r->obs = *d->obs;
+        r->desc.obs = &r->obs;
+    }
     r->scene = sc;
     r->n_images = d->n_envs * d->n_cams;
     for (const gsr_camera& c : r->cams)

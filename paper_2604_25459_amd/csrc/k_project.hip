@@ -10,7 +10,11 @@
 // The binning quantities are computed in the library's binary32
 // specification: one rounding per operation (this file is compiled with
 // -ffp-contract=off), sums left to right, correctly rounded division and
-// square root, constants as float literals.
+// square root, constants as float literals.  The tile rectangle is the tighter
+// of the conservative radius square and the axis-aligned box of the ellipse
+// on which alpha falls to 1/255 for the Gaussian's opacity (per opacity
+// bucket, with a 1 % margin), so no pixel that could take the Gaussian is
+// left out of its tiles.
 #include "gsr_internal.h"
 
 #include <hip/hip_fp16.h>
@@ -86,8 +90,25 @@ __global__ __launch_bounds__(256) void k_compose(SceneDev s, ChunkDev c, const f
     const int slot = idx - i * slots;
     const ImageInfo im = c.img[i];
     const float* vm = viewmats + im.vm_off;
-    const float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
-    const float tc[3] = {vm[3], vm[7], vm[11]};
+    float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
+    float tc[3] = {vm[3], vm[7], vm[11]};
+    if (im.attach_body >= 0) {
+        // camera rides on a body: the viewmat is body->camera [R_o | t_o];
+        // world->camera = R_o R_k^T, t_o - (R_o R_k^T) t_k (k = attach_body)
+        const float* pk = poses + im.pose_off + (size_t)im.attach_body * 7;
+        float Rk[9], RkT[9], Ro[9];
+        quat_rot(pk[0], pk[1], pk[2], pk[3], Rk);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) RkT[3 * r + q] = Rk[3 * q + r];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Ro[k] = Rc[k];
+        mat3_mul(Ro, RkT, Rc);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            tc[r] = tc[r] - ((Rc[3 * r + 0] * pk[4] + Rc[3 * r + 1] * pk[5]) + Rc[3 * r + 2] * pk[6]);
+    }
     // camera centre in world: C = -R_c^T t_c (continuous quantity, colour only)
     const float Cw[3] = {-(Rc[0] * tc[0] + Rc[3] * tc[1] + Rc[6] * tc[2]),
                          -(Rc[1] * tc[0] + Rc[4] * tc[1] + Rc[7] * tc[2]),
@@ -231,6 +252,17 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
     const float op = pm.w;
     const float alpha_min = 1.0f / 255.0f;
     const float tsf = (float)ts;
+    // Opacity-aware extent: alpha >= 1/255 needs q <= 2 ln(255 o).  For o in
+    // (2^-(k+1), 2^-k] the bound 1.01 * 2 ln(255 * 2^-k), rounded up to
+    // binary32, holds with 1 % to spare for the rounding of the extents.
+    int kq = 0;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) kq += op <= __uint_as_float((uint32_t)(127 - j) << 23) ? 1 : 0;
+    constexpr float kQmax[8] = {0x1.662ff2p+3f, 0x1.3961dcp+3f, 0x1.0c93c4p+3f, 0x1.bf8b5cp+2f,
+                                0x1.65ef2ep+2f, 0x1.0c5300p+2f, 0x1.656da6p+1f, 0x1.646a94p+0f};
+    float qmax = kQmax[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) qmax = kq == j ? kQmax[j] : qmax;
 
     for (int ii = 0; ii < ipt; ++ii) {
         const int i = i_begin + ii;
@@ -282,10 +314,13 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
         const float r = ceilf(cutoff * sqrtf(lam));
         const float u = (fx * tx) / tz + im.cx;
         const float v = (fy * ty) / tz + im.cy;
-        const float x0 = fminf(fmaxf(floorf((u - r) / tsf), 0.0f), (float)im.tiles_x);
-        const float x1 = fminf(fmaxf(floorf((u + r) / tsf) + 1.0f, 0.0f), (float)im.tiles_x);
-        const float y0 = fminf(fmaxf(floorf((v - r) / tsf), 0.0f), (float)im.tiles_y);
-        const float y1 = fminf(fmaxf(floorf((v + r) / tsf) + 1.0f, 0.0f), (float)im.tiles_y);
+        // tighter of the radius square and the box of the ellipse q <= qmax
+        const float rx = fminf(r, sqrtf(qmax * ca));
+        const float ry = fminf(r, sqrtf(qmax * cc));
+        const float x0 = fminf(fmaxf(floorf((u - rx) / tsf), 0.0f), (float)im.tiles_x);
+        const float x1 = fminf(fmaxf(floorf((u + rx) / tsf) + 1.0f, 0.0f), (float)im.tiles_x);
+        const float y0 = fminf(fmaxf(floorf((v - ry) / tsf), 0.0f), (float)im.tiles_y);
+        const float y1 = fminf(fmaxf(floorf((v + ry) / tsf) + 1.0f, 0.0f), (float)im.tiles_y);
 
         bool vis = isfinite(tx) && isfinite(ty) && isfinite(tz) && tz > im.near_plane && op >= alpha_min &&
                    isfinite(det) && det > 0.0f && isfinite(r) && isfinite(u) && isfinite(v);

@@ -23,7 +23,14 @@
 // reaches the alpha threshold.  kCullMargin absorbs binary32
 // rounding of the per-pixel evaluation, so culling never removes a Gaussian a
 // pixel would have accepted and results do not depend on the tiling.
+//
+// Output: rgb = C + T bg, depth = D / (1 - T) (0 where nothing was added),
+// optional alpha = 1 - T, optional work counts, and optionally the fused
+// observation epilogue (gain, contrast about 0.5, brightness, clamp to
+// [0, 1], then bytes or halves) on the colour before it leaves registers.
 #include "gsr_internal.h"
+
+#include <hip/hip_fp16.h>
 
 #include <algorithm>
 
@@ -260,13 +267,41 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         if (__syncthreads_count(wave_live && lane == 0 ? 1 : 0) == 0) break;
     }
 
+    // observation epilogue parameters of this image (identity when absent)
+    float gain = 1.0f, contrast = 1.0f, bright = 0.0f;
+    if (im.out_obs) {
+        if (im.obs_gain) gain = im.obs_gain[im.obs_idx];
+        if (im.obs_contrast) contrast = im.obs_contrast[im.obs_idx];
+        if (im.obs_bright) bright = im.obs_bright[im.obs_idx];
+    }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         if (pxi[k] >= im.width || pyi[k] >= im.height) continue;
         const size_t pix = (size_t)pyi[k] * im.width + pxi[k];
-        im.out_rgb[3 * pix + 0] = fmaf(T[k], im.bg[0], C0[k]);
-        im.out_rgb[3 * pix + 1] = fmaf(T[k], im.bg[1], C1[k]);
-        im.out_rgb[3 * pix + 2] = fmaf(T[k], im.bg[2], C2[k]);
+        const float rgb[3] = {fmaf(T[k], im.bg[0], C0[k]), fmaf(T[k], im.bg[1], C1[k]), fmaf(T[k], im.bg[2], C2[k])};
+        if (im.out_rgb) {
+            im.out_rgb[3 * pix + 0] = rgb[0];
+            im.out_rgb[3 * pix + 1] = rgb[1];
+            im.out_rgb[3 * pix + 2] = rgb[2];
+        }
+        if (im.out_obs) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                // each step rounded on its own (no contraction in this file)
+                float x = rgb[ch] * gain;
+                x = x - 0.5f;
+                x = x * contrast;
+                x = x + 0.5f;
+                x = x + bright;
+                x = fminf(fmaxf(x, 0.0f), 1.0f);
+                if (im.obs_fmt == GSR_OBS_U8) {
+                    const float q = floorf(x * 255.0f + 0.5f);
+                    static_cast<uint8_t*>(im.out_obs)[3 * pix + ch] = (uint8_t)q;
+                } else {
+                    static_cast<__half*>(im.out_obs)[3 * pix + ch] = __float2half_rn(x);
+                }
+            }
+        }
         im.out_depth[pix] = T[k] < 1.0f ? D[k] / (1.0f - T[k]) : 0.0f;
         if (im.out_alpha) im.out_alpha[pix] = 1.0f - T[k];
         if (COUNT && im.out_work) {

@@ -381,6 +381,64 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
     }
 }
 
+// ------------------------------------------------------------ level 2, gather
+// One wave per (image, tile row, 64 tile columns), lane = tile column.  The
+// wave walks its row list in order, 64 entries at a time staged in LDS and
+// read back as broadcasts, and each lane whose column lies in an entry's
+// x-range appends the Gaussian to its own tile list, starting at the tile's
+// range start.  Per tile the appends follow the row list's (depth, index)
+// order, so the lists equal those of the stable scatter above; no ranks or
+// cursors are shared between lanes, at the price of testing every entry of
+// the row against every column.
+__global__ __launch_bounds__(64) void k_rowtile_gather(ChunkDev c, int n_cc)
+{
+    __shared__ uint64_t ent_s[64];      // (x0 | x1 << 16) << 32 | Gaussian
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
+    const int y = bx / n_cc, cc = bx - y * n_cc;
+    const ImageInfo im = c.img[i];
+    const uint32_t TX = (uint32_t)im.tiles_x;
+    if (y >= im.tiles_y || (uint32_t)cc * 64u >= TX) return;
+    const uint32_t* rr = c.row_range + ((size_t)i * c.ty_max + y) * 2;
+    const uint32_t r0 = rr[0], r1 = rr[1];
+    if (r0 >= r1) return;
+    const uint2* list = c.rows + c.row_base[i];
+    uint32_t* out = c.pairs + c.pair_base[i];
+    const uint32_t tx = (uint32_t)cc * 64u + (uint32_t)lane;
+    uint32_t cur = 0, lim = 0;
+    if (tx < TX) {
+        const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX + tx) * 2;
+        cur = tr[0];
+        lim = tr[1];
+    }
+    // entries past r1 are staged as empty ranges (x0 = x1 = 0) and never match
+    auto load = [&](uint32_t e) -> uint64_t {
+        if (e >= r1) return 0ull;
+        const uint2 v = list[e];
+        return ((uint64_t)v.y << 32) | v.x;
+    };
+    uint64_t next = load(r0 + lane);
+    for (uint32_t e0 = r0; e0 < r1; e0 += 64) {
+        ent_s[lane] = next;
+        __syncthreads();
+        next = load(e0 + 64 + lane);
+        for (int jb = 0; jb < 64; jb += 16) {
+            uint64_t E[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) E[k] = ent_s[jb + k];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t xr = (uint32_t)(E[k] >> 32);
+                const uint32_t x0 = xr & 0xFFFFu, w = (xr >> 16) - x0;
+                const bool in = tx - x0 < w;      // unsigned: x0 <= tx < x1; x1 <= TX
+                if (in && cur < lim) out[cur] = (uint32_t)E[k];
+                cur += in ? 1u : 0u;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Keys of one image: key = (global tile << 32) | depth bits of the Gaussian.
 __global__ __launch_bounds__(256) void k_debug_keys(ChunkDev c, int image, uint64_t n, const uint32_t* pairs,
                                                     uint64_t* keys)
@@ -418,15 +476,21 @@ hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, hipStream_t stream)
+hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedule, hipStream_t stream)
 {
     if (c.n_img == 0 || s.n == 0) return hipSuccess;
     const uint64_t n = (uint64_t)s.n;
     hipLaunchKernelGGL(k_row_scatter, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(64),
                        sizeof(Group) + (size_t)c.ty_max * 4, stream, c, n, bits_for(c.ty_max));
-    const int groups = 1;   // splitting a row into column groups re-reads the row list and measured slower
-    hipLaunchKernelGGL(k_rowtile_scatter, dim3((unsigned)(c.ty_max * groups), (unsigned)c.n_img), dim3(64),
-                       sizeof(Group) + (size_t)c.tx_max * 4, stream, c, n, bits_for(c.tx_max), groups);
+    if (schedule == 1) {
+        const int n_cc = (c.tx_max + 63) / 64;
+        hipLaunchKernelGGL(k_rowtile_gather, dim3((unsigned)(c.ty_max * n_cc), (unsigned)c.n_img), dim3(64), 0,
+                           stream, c, n_cc);
+    } else {
+        const int groups = 1;   // splitting a row into column groups re-reads the row list and measured slower
+        hipLaunchKernelGGL(k_rowtile_scatter, dim3((unsigned)(c.ty_max * groups), (unsigned)c.n_img), dim3(64),
+                           sizeof(Group) + (size_t)c.tx_max * 4, stream, c, n, bits_for(c.tx_max), groups);
+    }
     return hipGetLastError();
 }
 

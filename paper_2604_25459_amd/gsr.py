@@ -28,6 +28,7 @@ GSR_E_OVERFLOW = -7
 GSR_E_TIMEOUT = -8
 
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+OBS_FORMAT = {"u8": 1, "f16": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
 
 
@@ -38,7 +39,8 @@ class Options(C.Structure):
 
 class TuningDesc(C.Structure):
     _fields_ = [("tile_size", C.c_int), ("lds_batch", C.c_int), ("images_per_thread", C.c_int),
-                ("persistent", C.c_int), ("chunk_images", C.c_int), ("ms", C.c_float), ("reserved", C.c_int * 4)]
+                ("persistent", C.c_int), ("chunk_images", C.c_int), ("ms", C.c_float),
+                ("bin_schedule", C.c_int), ("reserved", C.c_int * 3)]
 
 
 class SceneDesc(C.Structure):
@@ -49,14 +51,19 @@ class SceneDesc(C.Structure):
 
 class CameraDesc(C.Structure):
     _fields_ = [("width", C.c_int), ("height", C.c_int), ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float),
-                ("cy", C.c_float), ("near_plane", C.c_float)]
+                ("cy", C.c_float), ("near_plane", C.c_float), ("attach_body", C.c_int)]
+
+
+class ObsDesc(C.Structure):
+    _fields_ = [("format", C.c_int), ("reserved0", C.c_int), ("gain", C.c_void_p), ("contrast", C.c_void_p),
+                ("brightness", C.c_void_p), ("out", C.c_void_p)]
 
 
 class RenderDesc(C.Structure):
     _fields_ = [("scene_id", C.c_uint64), ("n_envs", C.c_int), ("n_cams", C.c_int), ("cams", C.c_void_p),
                 ("viewmats", C.c_void_p), ("body_poses", C.c_void_p), ("bg", C.c_float * 3),
                 ("out_rgb", C.c_void_p), ("out_depth", C.c_void_p), ("out_alpha", C.c_void_p),
-                ("out_work", C.c_void_p)]
+                ("out_work", C.c_void_p), ("obs", C.c_void_p)]
 
 
 class BinsOut(C.Structure):
@@ -159,6 +166,19 @@ class Camera:
     cx: float
     cy: float
     near: float = 0.01
+    attach_body: int = -1     # >= 0: the slot's viewmats are body -> camera offsets of that body
+
+
+@dataclass
+class Observation:
+    """Fused observation epilogue request: ``out`` receives u8 or f16 pixels
+    ([pixels * 3], the layout of rgb); gain / contrast / brightness are
+    optional CUDA float32 tensors [C * E]."""
+    format: str
+    out: object
+    gain: object = None
+    contrast: object = None
+    brightness: object = None
 
 
 class Renderer:
@@ -235,16 +255,22 @@ class Renderer:
         arr = (CameraDesc * len(cams))()
         for k, c in enumerate(cams):
             arr[k] = CameraDesc(width=int(c.width), height=int(c.height), fx=c.fx, fy=c.fy, cx=c.cx, cy=c.cy,
-                                near_plane=c.near)
+                                near_plane=c.near, attach_body=int(getattr(c, "attach_body", -1)))
         return arr
 
-    def _desc(self, sid, cams, viewmats, poses, bg, rgb=None, depth=None, alpha=None, work=None):
+    def _desc(self, sid, cams, viewmats, poses, bg, rgb=None, depth=None, alpha=None, work=None, obs=None):
         carr = self._cams(cams)
         d = RenderDesc(scene_id=sid, n_envs=int(viewmats.shape[1]), n_cams=len(cams), cams=C.addressof(carr),
                        viewmats=_ptr(viewmats), body_poses=_ptr(poses) if poses is not None and poses.numel() else None,
                        out_rgb=_ptr(rgb), out_depth=_ptr(depth), out_alpha=_ptr(alpha), out_work=_ptr(work))
         d.bg[0], d.bg[1], d.bg[2] = [float(x) for x in bg]
-        return d, carr
+        keep = [carr]
+        if obs is not None:
+            od = ObsDesc(format=OBS_FORMAT[obs.format], gain=_ptr(obs.gain), contrast=_ptr(obs.contrast),
+                         brightness=_ptr(obs.brightness), out=_ptr(obs.out))
+            d.obs = C.addressof(od)
+            keep.append(od)
+        return d, keep
 
     def alloc_outputs(self, cams, n_envs: int, alpha: bool = False):
         import torch
@@ -269,11 +295,12 @@ class Renderer:
         return out
 
     def render_into(self, sid, cams, viewmats, poses, rgb, depth, alpha=None, bg=(0.0, 0.0, 0.0), plain=False,
-                    stream=None, work=None):
+                    stream=None, work=None, obs=None):
         """viewmats: CUDA float32 [C, E, 3, 4]; poses: CUDA float32 [E, B, 7]; work: optional CUDA int32
-        [pixels * 2] receiving (visited list entries, blended Gaussians) per pixel."""
+        [pixels * 2] receiving (visited list entries, blended Gaussians) per pixel; obs: optional
+        Observation (rgb may then be None)."""
         import torch
-        d, carr = self._desc(sid, cams, viewmats, poses, bg, rgb, depth, alpha, work)
+        d, carr = self._desc(sid, cams, viewmats, poses, bg, rgb, depth, alpha, work, obs)
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         fn = load().gsr_render_plain if plain else load().gsr_render
         _check(fn(self._h, C.byref(d), C.c_void_p(st)))
@@ -286,7 +313,7 @@ class Renderer:
         return self.split(cams, E, rgb, depth, a)
 
     # ---------------------------------------------------------- tuning
-    TUNING_KEYS = ("tile_size", "lds_batch", "images_per_thread", "persistent", "chunk_images", "ms")
+    TUNING_KEYS = ("tile_size", "lds_batch", "images_per_thread", "persistent", "chunk_images", "bin_schedule", "ms")
 
     def autotune(self, sid, cams, viewmats, poses, rgb, depth, alpha=None, stream=None) -> dict:
         import torch
@@ -358,11 +385,11 @@ class Server:
         self._r = renderer
         self._keep = {}
 
-    def submit(self, sid, cams, viewmats, poses, rgb, depth, alpha=None, bg=(0.0, 0.0, 0.0)) -> int:
-        d, carr = self._r._desc(sid, cams, viewmats, poses, bg, rgb, depth, alpha)
+    def submit(self, sid, cams, viewmats, poses, rgb, depth, alpha=None, bg=(0.0, 0.0, 0.0), obs=None) -> int:
+        d, carr = self._r._desc(sid, cams, viewmats, poses, bg, rgb, depth, alpha, obs=obs)
         t = C.c_uint64()
         _check(load().gsr_submit(self._h, C.byref(d), C.byref(t)))
-        self._keep[int(t.value)] = (viewmats, poses, rgb, depth, alpha)
+        self._keep[int(t.value)] = (viewmats, poses, rgb, depth, alpha, obs)
         return int(t.value)
 
     def wait(self, ticket: int, timeout_us: int = -1) -> dict:
@@ -397,5 +424,6 @@ def batch_tensors(batch, device: int = 0):
     dev = torch.device("cuda", device)
     vm = torch.from_numpy(np.ascontiguousarray(batch.viewmats, np.float32)).to(dev)
     poses = torch.from_numpy(np.ascontiguousarray(batch.poses, np.float32)).to(dev)
-    cams = [Camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.near) for c in batch.cams]
+    cams = [Camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.near, getattr(c, "attach_body", -1))
+            for c in batch.cams]
     return cams, vm, poses

@@ -76,6 +76,7 @@ class Camera:
     cx: float
     cy: float
     near: float = 0.01
+    attach_body: int = -1     # >= 0: viewmats of this slot are body -> camera offsets
 
 
 @dataclass

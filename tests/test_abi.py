@@ -81,15 +81,33 @@ def test_create_without_gpu_reports_device_error():
     assert lib.gsr_create(0, None, C.byref(h)) == gsr.GSR_E_DEVICE
 
 
+def _c_layout(structs):
+    """sizeof and field offsets of header structs as gcc lays them out."""
+    import subprocess
+    import tempfile
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gsr.h"', "int main(void) {"]
+    for cname, fields in structs:
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(src, "w") as f:
+            f.write("\n".join(lines))
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", exe, src])
+        out = subprocess.check_output([exe]).decode().split()
+    return dict(zip(out[0::2], (int(v) for v in out[1::2])))
+
+
 def test_struct_layouts_match_header():
-    # sizes computed from the C declarations (LP64): a mismatch would corrupt every call
-    assert C.sizeof(gsr.Options) == 4 + 4 + 8 + 4 + 4 + 4 + 24 + 4
-    assert C.sizeof(gsr.TuningDesc) == 6 * 4 + 16
-    assert C.sizeof(gsr.SceneDesc) == 8 + 4 * 4 + 8 * 6
-    assert C.sizeof(gsr.CameraDesc) == 7 * 4
-    assert C.sizeof(gsr.RenderDesc) == 8 + 4 + 4 + 8 * 3 + 12 + 4 + 8 * 4
-    assert C.sizeof(gsr.BinsOut) == 8 * 5 + 8 + 8 + 4 + 4 + 8
-    assert C.sizeof(gsr.ProjOut) == 8 * 4
-    assert C.sizeof(gsr.ServerCfg) == 4 + 4 + 8 + 32
-    assert C.sizeof(gsr.ReqInfo) == 4 + 4 + 8 + 4 + 4 + 8 * 4
-    assert C.sizeof(gsr.Stats) == 8 * 8 + 8 * 5
+    # every ctypes structure of the binding against gcc's layout of include/gsr.h
+    pairs = [(gsr.Options, "gsr_options"), (gsr.TuningDesc, "gsr_tuning"), (gsr.SceneDesc, "gsr_scene_desc"),
+             (gsr.CameraDesc, "gsr_camera"), (gsr.ObsDesc, "gsr_observation"), (gsr.RenderDesc, "gsr_render_desc"),
+             (gsr.BinsOut, "gsr_bins_out"), (gsr.ProjOut, "gsr_proj_out"), (gsr.ServerCfg, "gsr_server_cfg"),
+             (gsr.ReqInfo, "gsr_req_info"), (gsr.Stats, "gsr_stats")]
+    lay = _c_layout([(cn, [f for f, _ in py._fields_]) for py, cn in pairs])
+    for py, cn in pairs:
+        assert C.sizeof(py) == lay[cn], cn
+        for f, _ in py._fields_:
+            assert getattr(py, f).offset == lay[f"{cn}.{f}"], f"{cn}.{f}"
