@@ -195,7 +195,8 @@ size_t per_image_bytes(const SceneRes* sc, int t_max, int ty_max, int sort_block
     const size_t n = (size_t)sc->dev.n;
     size_t b = n * (4 + 16 + 48 + 16);                                 // key, rect + sorted rect, record, sort buffers
     b += (size_t)(sc->dev.n_bodies + 1) * 64;                          // transforms
-    b += (size_t)sort_blocks * 256 * 4 + (size_t)tile_blocks * (t_max + ty_max) * 4 + (size_t)(t_max + ty_max) * 8;
+    b += (size_t)sort_blocks * 256 * 4 + (size_t)tile_blocks * ty_max * 4 + (size_t)(t_max + ty_max) * 8;
+    b += (size_t)(t_max + 2 * ty_max + 1) * 4;                         // tile difference array (bound)
     b += n * 8 * 4 + n * 3 * 8 + sizeof(ImageInfo) + 64;               // pair / row-entry estimates
     return b;
 }
@@ -254,7 +255,7 @@ hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& 
     ENS(sv1, I * n * 4);
     ENS(sort_hist, I * p.sort_blocks * 256 * 4);
     ENS(vis_count, I * 4);
-    ENS(tile_hist, I * p.tile_blocks * (size_t)p.t_max * 4);
+    ENS(tile_hist, I * (size_t)(p.tx_max + 1) * (p.ty_max + 1) * 4);
     ENS(tile_range, I * (size_t)p.t_max * 8);
     ENS(pair_count, I * 4);
     ENS(pair_base, (I + 2) * 8);
@@ -335,7 +336,7 @@ ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, int i
     c.sv[1] = ws.sv1.as<uint32_t>();
     c.sort_hist = ws.sort_hist.as<uint32_t>();
     c.vis_count = ws.vis_count.as<uint32_t>();
-    c.tile_hist = ws.tile_hist.as<uint32_t>();
+    c.tile_hist = ws.tile_hist.as<int32_t>();
     c.tile_range = ws.tile_range.as<uint32_t>();
     c.pair_count = ws.pair_count.as<uint32_t>();
     c.pair_base = ws.pair_base.as<uint64_t>();

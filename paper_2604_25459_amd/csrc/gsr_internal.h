@@ -86,7 +86,7 @@ struct ChunkDev {
     uint2* srect;              // [n_img][n] tile rectangle of the j-th depth-ordered Gaussian
     uint32_t* sort_hist;       // [n_img][sort_blocks][256]
     uint32_t* vis_count;       // [n_img] visible Gaussians V_i
-    uint32_t* tile_hist;       // [n_img][tile_blocks][t_max] per-block tile counts
+    int32_t* tile_hist;       // [n_img][(tx_max + 1) (ty_max + 1)] 2D difference array of tile counts
     uint32_t* tile_range;      // [n_img][t_max][2] local [start, end)
     uint32_t* pair_count;      // [n_img] P_i
     uint64_t* pair_base;       // [n_img + 2] exclusive prefix of P_i, total pairs, total visible

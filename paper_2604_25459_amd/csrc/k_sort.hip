@@ -10,7 +10,9 @@
 // block are stable: each wave owns a contiguous quarter of the block's items,
 // walks it in order 64 items at a time, and ranks equal digits with a ballot
 // match (peers = lanes with the same digit) and a per-wave running counter in
-// LDS.
+// LDS.  The scatter first places the block's items in LDS in their stable
+// digit order, then writes them out in that order, so each digit's run of
+// the block leaves as consecutive addresses.
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -119,6 +121,8 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
                                                       const uint2* __restrict__ rect, uint2* __restrict__ srect)
 {
     __shared__ uint32_t cnt[4][256];
+    __shared__ uint32_t lstart[256], gbase[256], lds8[8];
+    __shared__ uint32_t skey[kSortItems], sval[kSortItems];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), tid = threadIdx.x;
     const int w = tid >> 6, lane = __lane_id();
@@ -148,14 +152,18 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
     for (int k = 0; k < kSortIpt; ++k)
         if (ok[k]) atomicAdd(&cnt[w][(key[k] >> shift) & 255u], 1u);
     __syncthreads();
+    // block-local layout: digit-major, and within a digit wave-major, each
+    // wave's items in order -- the stable order of the block's items
+    uint32_t n_items;
     {
-        uint32_t run = hist[((size_t)i * blocks + b) * 256 + tid];
-#pragma unroll
-        for (int ww = 0; ww < 4; ++ww) {
-            const uint32_t c = cnt[ww][tid];
-            cnt[ww][tid] = run;
-            run += c;
-        }
+        const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid], c3 = cnt[3][tid];
+        const uint32_t start = block_excl_scan256(c0 + c1 + c2 + c3, &n_items, lds8);
+        lstart[tid] = start;
+        gbase[tid] = hist[((size_t)i * blocks + b) * 256 + tid];
+        cnt[0][tid] = start;
+        cnt[1][tid] = start + c0;
+        cnt[2][tid] = start + c0 + c1;
+        cnt[3][tid] = start + c0 + c1 + c2;
     }
     __syncthreads();
     const uint64_t lt = lanemask_lt();
@@ -165,13 +173,25 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
         const uint64_t peers = match_bits<8>(dg, ok[k]);
         if (ok[k]) {
             const uint32_t basev = cnt[w][dg];
-            const uint32_t pos = basev + (uint32_t)__popcll(peers & lt);
+            const uint32_t lpos = basev + (uint32_t)__popcll(peers & lt);
             if (lane == __ffsll((unsigned long long)peers) - 1) cnt[w][dg] = basev + (uint32_t)__popcll(peers);
-            if (pos < n) {      // guard: offsets are consistent by construction
-                kout[seg + pos] = key[k];
-                vout[seg + pos] = val[k];
-                if (LAST && val[k] < n) srect[seg + pos] = rect[seg + val[k]];
+            if (lpos < (uint32_t)kSortItems) {     // guard: lpos < n_items <= kSortItems by construction
+                skey[lpos] = key[k];
+                sval[lpos] = val[k];
             }
+        }
+    }
+    __syncthreads();
+    // write out in block-local order: consecutive threads write consecutive
+    // addresses inside each digit's run
+    for (uint32_t t = (uint32_t)tid; t < n_items; t += 256u) {
+        const uint32_t k = skey[t], v = sval[t];
+        const uint32_t dg = (k >> shift) & 255u;
+        const uint32_t pos = gbase[dg] + (t - lstart[dg]);
+        if (pos < n) {      // guard: offsets are consistent by construction
+            kout[seg + pos] = k;
+            vout[seg + pos] = v;
+            if (LAST && v < n) srect[seg + pos] = rect[seg + v];
         }
     }
 }

@@ -24,7 +24,7 @@
 // ballot match; a per-bucket cursor in LDS carries the rank across windows.
 //
 // Kernels:
-//   k_tile_hist       per-block tile and tile-row histograms (LDS atomics)
+//   k_tile_hist       tile and tile-row counts as difference arrays (LDS atomics)
 //   k_tile_scan       per image: tile ranges, row ranges, per-block row offsets
 //   k_image_scan      pair and row-entry bases of every image of the chunk
 //   k_row_scatter     level 1
@@ -115,51 +115,63 @@ __device__ __forceinline__ bool sorted_rect(const ChunkDev& c, uint64_t n, int i
 }
 
 // ------------------------------------------------------------------ counts
-__global__ __launch_bounds__(64) void k_tile_hist(ChunkDev c, uint64_t n)
+// A Gaussian adds one to every tile of its rectangle [x0, x1) x [y0, y1) and
+// one to every tile row [y0, y1).  Both are written as difference arrays --
+// +1 at (x0, y0) and (x1, y1), -1 at (x1, y0) and (x0, y1); +1 at y0, -1 at
+// y1 -- and summed up by prefix sums in k_tile_scan: four atomics per
+// Gaussian instead of one per (tile, Gaussian) pair.  Tile counts are only
+// needed per image (the tile lists are written by rows), so the block's 2D
+// differences are added into the image's array; row counts are needed per
+// block (level-1 offsets), so each block writes its own.
+__global__ __launch_bounds__(256) void k_zero_diff(int32_t* __restrict__ d, uint64_t n)
 {
-    extern __shared__ uint32_t lds[];
-    Group& grp = *reinterpret_cast<Group*>(lds);
-    uint32_t* hist = lds + sizeof(Group) / 4;
-    uint32_t* rhist = hist + c.t_max;
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) d[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_tile_hist(ChunkDev c, uint64_t n)
+{
+    extern __shared__ int32_t lds_i[];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-    const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
+    const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), tid = threadIdx.x;
     const uint32_t V = c.n ? c.vis_count[i] : 0u;
     const uint32_t j0 = (uint32_t)b * kTileGauss;
-    if (j0 >= V) return;
+    if (j0 >= V) return;                // block-uniform
     const uint32_t j1 = min(j0 + (uint32_t)kTileGauss, V);
     const ImageInfo im = c.img[i];
-    const int T = im.tiles_x * im.tiles_y;
-    for (int t = lane; t < T; t += 64) hist[t] = 0;
-    for (int y = lane; y < im.tiles_y; y += 64) rhist[y] = 0;
+    const int P1 = im.tiles_x + 1, Q1 = im.tiles_y + 1;
+    const int D = P1 * Q1;
+    int32_t* diff = lds_i;              // [Q1][P1]
+    int32_t* rdiff = lds_i + D;         // [Q1]
+    for (int t = tid; t < D; t += 256) diff[t] = 0;
+    for (int y = tid; y < Q1; y += 256) rdiff[y] = 0;
     __syncthreads();
-    for (uint32_t jb = j0; jb < j1; jb += 64) {
+    for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += 256) {
         uint32_t g, x0, x1, y0, y1;
-        const bool ok = sorted_rect(c, n, i, jb + lane, j1, &g, &x0, &x1, &y0, &y1);
-        const uint32_t nx = ok ? x1 - x0 : 1;
-        const uint32_t total = publish(grp, ok ? nx * (y1 - y0) : 0, x0, nx, y0, g);
-        __syncthreads();
-        for (uint32_t p0 = 0; p0 < total; p0 += 64) {
-            const uint32_t p = p0 + lane;
-            if (p < total) {
-                const uint32_t k = owner(grp, p);
-                const uint32_t s = p - grp.excl[k];
-                const uint32_t w = grp.w[k];
-                uint32_t row = (uint32_t)((float)s * __builtin_amdgcn_rcpf((float)w));
-                if (row * w > s) --row;
-                else if ((row + 1) * w <= s) ++row;
-                const uint32_t col = s - row * w;
-                const uint32_t ty = grp.b[k] + row;
-                const uint32_t t = ty * (uint32_t)im.tiles_x + grp.a[k] + col;
-                if (t < (uint32_t)T) atomicAdd(&hist[t], 1u);
-                if (col == 0 && ty < (uint32_t)im.tiles_y) atomicAdd(&rhist[ty], 1u);
-            }
+        if (sorted_rect(c, n, i, j, j1, &g, &x0, &x1, &y0, &y1) && x1 <= (uint32_t)im.tiles_x &&
+            y1 <= (uint32_t)im.tiles_y) {
+            atomicAdd(&diff[y0 * P1 + x0], 1);
+            atomicAdd(&diff[y0 * P1 + x1], -1);
+            atomicAdd(&diff[y1 * P1 + x0], -1);
+            atomicAdd(&diff[y1 * P1 + x1], 1);
+            atomicAdd(&rdiff[y0], 1);
+            atomicAdd(&rdiff[y1], -1);
         }
-        __syncthreads();
     }
-    uint32_t* out = c.tile_hist + ((size_t)i * c.tile_blocks + b) * c.t_max;
-    for (int t = lane; t < T; t += 64) out[t] = hist[t];
-    uint32_t* rout = c.row_hist + ((size_t)i * c.tile_blocks + b) * c.ty_max;
-    for (int y = lane; y < im.tiles_y; y += 64) rout[y] = rhist[y];
+    __syncthreads();
+    int32_t* gd = c.tile_hist + (size_t)i * (size_t)(c.tx_max + 1) * (c.ty_max + 1);
+    for (int t = tid; t < D; t += 256) {
+        const int32_t v = diff[t];
+        if (v) atomicAdd(&gd[t], v);
+    }
+    if (tid == 0) {                     // per-block row counts: prefix of the row differences
+        uint32_t* rout = c.row_hist + ((size_t)i * c.tile_blocks + b) * c.ty_max;
+        int32_t run = 0;
+        for (int y = 0; y < im.tiles_y; ++y) {
+            run += rdiff[y];
+            rout[y] = (uint32_t)run;
+        }
+    }
 }
 
 __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* total, uint32_t* lds8)
@@ -219,8 +231,39 @@ __global__ __launch_bounds__(256) void k_tile_scan(ChunkDev c)
     const uint32_t V = c.n ? c.vis_count[i] : 0u;
     const int nb = (int)((V + kTileGauss - 1) / kTileGauss);
     const ImageInfo im = c.img[i];
-    const uint32_t P = scan_bins(c.tile_hist + (size_t)i * c.tile_blocks * c.t_max, nb, c.t_max,
-                                 im.tiles_x * im.tiles_y, c.tile_range + (size_t)i * c.t_max * 2, false, lds8);
+    const int TX = im.tiles_x, TY = im.tiles_y, P1 = TX + 1;
+    // 2D prefix of the image's difference array (rows, then columns) gives
+    // the tile counts, in place; then the tile ranges by a scan in tile order
+    int32_t* gd = c.tile_hist + (size_t)i * (size_t)(c.tx_max + 1) * (c.ty_max + 1);
+    for (int y = threadIdx.x; y < TY; y += 256) {
+        int32_t run = 0;
+        for (int x = 0; x < TX; ++x) {
+            run += gd[y * P1 + x];
+            gd[y * P1 + x] = run;
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < TX; x += 256) {
+        int32_t run = 0;
+        for (int y = 0; y < TY; ++y) {
+            run += gd[y * P1 + x];
+            gd[y * P1 + x] = run;
+        }
+    }
+    __syncthreads();
+    uint32_t* range = c.tile_range + (size_t)i * c.t_max * 2;
+    uint32_t P = 0;
+    for (int t0 = 0; t0 < TX * TY; t0 += 256) {
+        const int t = t0 + threadIdx.x;
+        const uint32_t cnt = t < TX * TY ? (uint32_t)gd[(t / TX) * P1 + (t % TX)] : 0u;
+        uint32_t chunk_total;
+        const uint32_t start = P + block_excl_scan256(cnt, &chunk_total, lds8);
+        if (t < TX * TY) {
+            range[2 * t] = start;
+            range[2 * t + 1] = start + cnt;
+        }
+        P += chunk_total;
+    }
     const uint32_t Rn = scan_bins(c.row_hist + (size_t)i * c.tile_blocks * c.ty_max, nb, c.ty_max, im.tiles_y,
                                   c.row_range + (size_t)i * c.ty_max * 2, true, lds8);
     if (threadIdx.x == 0) {
@@ -467,9 +510,12 @@ hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t s
 {
     if (c.n_img == 0) return hipSuccess;
     const uint64_t n = (uint64_t)s.n;
+    const uint64_t nd = (uint64_t)c.n_img * (uint64_t)(c.tx_max + 1) * (uint64_t)(c.ty_max + 1);
+    hipLaunchKernelGGL(k_zero_diff, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, stream, c.tile_hist, nd);
     if (n > 0) {
-        const size_t lds = sizeof(Group) + (size_t)(c.t_max + c.ty_max) * 4;
-        hipLaunchKernelGGL(k_tile_hist, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(64), lds, stream, c, n);
+        const size_t lds = (size_t)((c.tx_max + 1) * (c.ty_max + 1) + c.ty_max + 1) * 4;
+        hipLaunchKernelGGL(k_tile_hist, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(256), lds, stream, c,
+                           n);
     }
     hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)c.n_img), dim3(256), 0, stream, c);
     hipLaunchKernelGGL(k_image_scan, dim3(1), dim3(256), 0, stream, c);
