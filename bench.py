@@ -84,7 +84,7 @@ def pmc_summary(fetch_csv, write_csv, out_path, command):
 
 def measured_traffic(tuning):
     """HBM bytes per rasteriser launch from the committed counter summary, or
-    None when it was taken on other sources or other launch parameters."""
+    None when it was taken on other rasteriser sources or launch parameters."""
     path = os.path.join(ROOT, PMC_SUMMARY)
     if not os.path.exists(path):
         return None
@@ -93,8 +93,9 @@ def measured_traffic(tuning):
     if s.get("source_sha256") != raster_source_hash():
         return None
     if tuning is not None and s.get("tuning") is not None:
-        strip = lambda t: {k: v for k, v in t.items() if k != "ms"}
-        if strip(s["tuning"]) != strip(tuning):
+        # only the launch parameters of the rasteriser itself matter here
+        keys = ("tile_size", "lds_batch", "persistent")
+        if any(s["tuning"].get(k) != tuning.get(k) for k in keys):
             return None
     return s["traffic_bytes_per_launch"]
 
