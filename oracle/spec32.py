@@ -194,13 +194,14 @@ def project32(scene, batch, c: int, e: int, ts: int = 16, cutoff: float = 3.33,
         W, H = F(cam.width), F(cam.height)
         lx = GUARD * ((HALF * W) / fx)
         ly = GUARD * ((HALF * H) / fy)
-        xcl = np.minimum(lx, np.maximum(-lx, tx / tz)) * tz
-        ycl = np.minimum(ly, np.maximum(-ly, ty / tz)) * tz
-        tz2 = tz * tz
-        j00 = fx / tz
-        j02 = -((fx * xcl) / tz2)
-        j11 = fy / tz
-        j12 = -((fy * ycl) / tz2)
+        itz = ONE / tz                      # the one division by depth; products below
+        itz2 = itz * itz
+        xcl = np.minimum(lx, np.maximum(-lx, tx * itz)) * tz
+        ycl = np.minimum(ly, np.maximum(-ly, ty * itz)) * tz
+        j00 = fx * itz
+        j02 = -((fx * xcl) * itz2)
+        j11 = fy * itz
+        j12 = -((fy * ycl) * itz2)
         v1 = np.stack([j00 * M[:, 0, k] + j02 * M[:, 2, k] for k in range(3)], axis=1)
         v2 = np.stack([j11 * M[:, 1, k] + j12 * M[:, 2, k] for k in range(3)], axis=1)
         n1 = (v1[:, 0] * v1[:, 0] + v1[:, 1] * v1[:, 1]) + v1[:, 2] * v1[:, 2]
@@ -216,8 +217,8 @@ def project32(scene, batch, c: int, e: int, ts: int = 16, cutoff: float = 3.33,
         h = HALF * (ca - cc)
         lam = m + np.sqrt(np.maximum(EIG_FLOOR, h * h + cb * cb))
         r = np.ceil(F(cutoff) * np.sqrt(lam))
-        u = (fx * tx) / tz + cx
-        v = (fy * ty) / tz + cy
+        u = (fx * tx) * itz + cx
+        v = (fy * ty) * itz + cy
         # axis-aligned half-extents of the ellipse q <= QMAX[bucket of o]
         # (sqrt(Q Sigma_xx), sqrt(Q Sigma_yy)), never beyond the radius
         k = np.zeros(N, np.int64)

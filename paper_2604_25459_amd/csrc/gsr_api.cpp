@@ -158,6 +158,9 @@ std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies)
             im.cx = cam.cx;
             im.cy = cam.cy;
             im.near_plane = cam.near_plane;
+            // binary32, one rounding per operation (this file is built without contraction)
+            im.guard_x = 1.3f * ((0.5f * (float)cam.width) / cam.fx);
+            im.guard_y = 1.3f * ((0.5f * (float)cam.height) / cam.fy);
             im.key_tile_base = (uint32_t)tile_base;
             im.vm_off = (uint32_t)(((size_t)c * E + e) * 12);
             im.pose_off = (uint32_t)((size_t)e * n_bodies * 7);

@@ -28,6 +28,7 @@ struct ImageInfo {
     int width, height;
     int tiles_x, tiles_y;
     float fx, fy, cx, cy, near_plane;
+    float guard_x, guard_y;   // Jacobian clamp of x/z, y/z: 1.3 * ((0.5 W) / fx), same in y (binary32)
     uint32_t key_tile_base;   // first global tile id of the image in its request (sort keys)
     uint32_t vm_off;          // float offset of the image's world->camera [R | t] in the viewmat array
     uint32_t pose_off;        // float offset of the image's env body poses [B][7] in the pose array
@@ -117,8 +118,9 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
 // Tile and tile-row histograms, ranges, image bases (before the host reads the totals).
 hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
 // Stable two-level scatter: depth-ordered Gaussians -> tile-row lists -> tile lists.
-// schedule 0: level 2 as a stable scatter (one wave per tile row); 1: as a
-// gather (one lane per tile column).  Both give identical tile lists.
+// schedule 0: level 2 as a stable scatter (one wave per tile row, ballot
+// ranks); 1: by a bit transpose (one lane per tile column appends the window
+// entries that cover it).  Both give identical tile lists.
 hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedule, hipStream_t stream);
 struct RasterParams {
     int ts;                  // tile side: 8, 16 or 32

@@ -251,7 +251,8 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
     const float mu[3] = {pm.x, pm.y, pm.z};
     const float op = pm.w;
     const float alpha_min = 1.0f / 255.0f;
-    const float tsf = (float)ts;
+    const float inv_ts = 1.0f / (float)ts;      // tile sides are powers of two: the scaling is exact
+    const float log2o = log2f(op);
     // Opacity-aware extent: alpha >= 1/255 needs q <= 2 ln(255 o).  For o in
     // (2^-(k+1), 2^-k] the bound 1.01 * 2 ln(255 * 2^-k), rounded up to
     // binary32, holds with 1 % to spare for the rounding of the extents.
@@ -284,15 +285,15 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
             for (int k = 0; k < 3; ++k) M[3 * r + k] = M[3 * r + k] * sc[k];
 
         const float fx = im.fx, fy = im.fy;
-        const float lx = 1.3f * ((0.5f * (float)im.width) / fx);
-        const float ly = 1.3f * ((0.5f * (float)im.height) / fy);
-        const float xcl = fminf(lx, fmaxf(-lx, tx / tz)) * tz;
-        const float ycl = fminf(ly, fmaxf(-ly, ty / tz)) * tz;
-        const float tz2 = tz * tz;
-        const float j00 = fx / tz;
-        const float j02 = -((fx * xcl) / tz2);
-        const float j11 = fy / tz;
-        const float j12 = -((fy * ycl) / tz2);
+        const float lx = im.guard_x, ly = im.guard_y;
+        const float itz = 1.0f / tz;            // the one division by depth; products below
+        const float itz2 = itz * itz;
+        const float xcl = fminf(lx, fmaxf(-lx, tx * itz)) * tz;
+        const float ycl = fminf(ly, fmaxf(-ly, ty * itz)) * tz;
+        const float j00 = fx * itz;
+        const float j02 = -((fx * xcl) * itz2);
+        const float j11 = fy * itz;
+        const float j12 = -((fy * ycl) * itz2);
         float v1[3], v2[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -312,15 +313,15 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
         const float h = 0.5f * (ca - cc);
         const float lam = m + sqrtf(fmaxf(0.1f, h * h + cb * cb));
         const float r = ceilf(cutoff * sqrtf(lam));
-        const float u = (fx * tx) / tz + im.cx;
-        const float v = (fy * ty) / tz + im.cy;
+        const float u = (fx * tx) * itz + im.cx;
+        const float v = (fy * ty) * itz + im.cy;
         // tighter of the radius square and the box of the ellipse q <= qmax
         const float rx = fminf(r, sqrtf(qmax * ca));
         const float ry = fminf(r, sqrtf(qmax * cc));
-        const float x0 = fminf(fmaxf(floorf((u - rx) / tsf), 0.0f), (float)im.tiles_x);
-        const float x1 = fminf(fmaxf(floorf((u + rx) / tsf) + 1.0f, 0.0f), (float)im.tiles_x);
-        const float y0 = fminf(fmaxf(floorf((v - ry) / tsf), 0.0f), (float)im.tiles_y);
-        const float y1 = fminf(fmaxf(floorf((v + ry) / tsf) + 1.0f, 0.0f), (float)im.tiles_y);
+        const float x0 = fminf(fmaxf(floorf((u - rx) * inv_ts), 0.0f), (float)im.tiles_x);
+        const float x1 = fminf(fmaxf(floorf((u + rx) * inv_ts) + 1.0f, 0.0f), (float)im.tiles_x);
+        const float y0 = fminf(fmaxf(floorf((v - ry) * inv_ts), 0.0f), (float)im.tiles_y);
+        const float y1 = fminf(fmaxf(floorf((v + ry) * inv_ts) + 1.0f, 0.0f), (float)im.tiles_y);
 
         bool vis = isfinite(tx) && isfinite(ty) && isfinite(tz) && tz > im.near_plane && op >= alpha_min &&
                    isfinite(det) && det > 0.0f && isfinite(r) && isfinite(u) && isfinite(v);
@@ -334,18 +335,20 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
         c.rect[o] = make_uint2((uint32_t)ix0 | ((uint32_t)ix1 << 16), (uint32_t)iy0 | ((uint32_t)iy1 << 16));
 
         // Raster record: conic pre-scaled so that log2(alpha) = p + log2(o)
-        // with p = A dx^2 + B dx dy + C dy^2.
-        const float ica = cc / det, icb = -cb / det, icc = ca / det;
+        // with p = A dx^2 + B dx dy + C dy^2.  Continuous quantities only
+        // (no binning decision depends on them): hardware reciprocals.
+        const float idet = __builtin_amdgcn_rcpf(det);
+        const float ica = cc * idet, icb = -cb * idet, icc = ca * idet;
         constexpr float kLog2e = 1.4426950408889634f;
         float rgb[3];
         {
             float dx = mu[0] - X[12], dy = mu[1] - X[13], dz = mu[2] - X[14];
-            const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            const float inv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
             sh_rgb<DEG>(f, dx * inv, dy * inv, dz * inv, rgb);
         }
         float4* rec = c.rec + 3 * o;
         rec[0] = make_float4(u, v, -0.5f * kLog2e * ica, -kLog2e * icb);
-        rec[1] = make_float4(-0.5f * kLog2e * icc, log2f(op), tz, r);
+        rec[1] = make_float4(-0.5f * kLog2e * icc, log2o, tz, r);
         rec[2] = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
     }
 }

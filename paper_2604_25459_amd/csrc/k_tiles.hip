@@ -424,60 +424,127 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
     }
 }
 
-// ------------------------------------------------------------ level 2, gather
-// One wave per (image, tile row, 64 tile columns), lane = tile column.  The
-// wave walks its row list in order, 64 entries at a time staged in LDS and
-// read back as broadcasts, and each lane whose column lies in an entry's
-// x-range appends the Gaussian to its own tile list, starting at the tile's
-// range start.  Per tile the appends follow the row list's (depth, index)
-// order, so the lists equal those of the stable scatter above; no ranks or
-// cursors are shared between lanes, at the price of testing every entry of
-// the row against every column.
-__global__ __launch_bounds__(64) void k_rowtile_gather(ChunkDev c, int n_cc)
+// ------------------------------------------------------ level 2, bit transpose
+// One wave per (image, tile row, 64 tile columns).  The row list is read 64
+// entries at a time (lane = entry, in list order).  Each lane turns its
+// entry's x-range into a 64-bit mask over the wave's columns; a 64 x 64 bit
+// transpose across the lanes (six butterfly stages of lane exchanges) then
+// leaves in lane x the set of window entries that cover column x, in list
+// order.  Lane x's entries go to its own tile list, after the tile's earlier
+// entries, so every tile list keeps the row list's (depth, index) order: the
+// same lists as the stable scatter, with no ranks or per-column ballots.
+__device__ __forceinline__ uint64_t transpose_bits64(uint64_t w)
 {
-    __shared__ uint64_t ent_s[64];      // (x0 | x1 << 16) << 32 | Gaussian
+    const int lane = __lane_id();
+    uint64_t m = 0x00000000FFFFFFFFull;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)w, s, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(w >> 32), s, 64);
+        const uint64_t v = ((uint64_t)hi << 32) | lo;
+        if ((lane & s) == 0) w = (w & m) | ((v & m) << s);
+        else w = (w & ~m) | ((v & ~m) >> s);
+        m ^= m << (s >> 1);         // next stage's mask: bits whose index has bit (s/2) clear
+    }
+    return w;
+}
+
+// Windows of kWin entries (kWin / 64 transposes); their pairs are staged in
+// LDS tile by tile and written out by consecutive lanes, so each tile's run
+// of the window leaves as consecutive addresses.  A window with more than
+// kStage pairs (rows of very wide splats) is written lane by lane instead.
+constexpr int kWin = 128;
+constexpr int kStage = 2048;
+
+__global__ __launch_bounds__(64) void k_rowtile_transpose(ChunkDev c, int n_cc)
+{
+    __shared__ uint32_t gs[kWin];
+    __shared__ uint32_t st_g[kStage];
+    __shared__ uint8_t st_x[kStage];
+    __shared__ uint32_t off_l[64], cur_l[64], lim_l[64];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
     const int y = bx / n_cc, cc = bx - y * n_cc;
     const ImageInfo im = c.img[i];
     const uint32_t TX = (uint32_t)im.tiles_x;
-    if (y >= im.tiles_y || (uint32_t)cc * 64u >= TX) return;
+    const uint32_t base = (uint32_t)cc * 64u;
+    if (y >= im.tiles_y || base >= TX) return;
     const uint32_t* rr = c.row_range + ((size_t)i * c.ty_max + y) * 2;
     const uint32_t r0 = rr[0], r1 = rr[1];
     if (r0 >= r1) return;
     const uint2* list = c.rows + c.row_base[i];
     uint32_t* out = c.pairs + c.pair_base[i];
-    const uint32_t tx = (uint32_t)cc * 64u + (uint32_t)lane;
+    const uint32_t tx = base + (uint32_t)lane;
     uint32_t cur = 0, lim = 0;
     if (tx < TX) {
         const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX + tx) * 2;
         cur = tr[0];
         lim = tr[1];
     }
-    // entries past r1 are staged as empty ranges (x0 = x1 = 0) and never match
-    auto load = [&](uint32_t e) -> uint64_t {
-        if (e >= r1) return 0ull;
-        const uint2 v = list[e];
-        return ((uint64_t)v.y << 32) | v.x;
+    lim_l[lane] = lim;
+    // entries past r1 are empty ranges and cover no column
+    auto load = [&](uint32_t e) { return e < r1 ? list[e] : make_uint2(0u, 0u); };
+    auto cover_of = [&](uint2 en) {
+        const uint32_t x0 = en.y & 0xFFFFu, x1 = en.y >> 16;
+        const uint32_t lo = min(max(x0, base) - base, 64u), hi = min(max(x1, base) - base, 64u);
+        const uint64_t below_hi = hi >= 64u ? ~0ull : ((1ull << hi) - 1ull);
+        const uint64_t below_lo = lo >= 64u ? ~0ull : ((1ull << lo) - 1ull);
+        return below_hi & ~below_lo;
     };
-    uint64_t next = load(r0 + lane);
-    for (uint32_t e0 = r0; e0 < r1; e0 += 64) {
-        ent_s[lane] = next;
+    uint2 next[kWin / 64];
+#pragma unroll
+    for (int w = 0; w < kWin / 64; ++w) next[w] = load(r0 + 64u * w + lane);
+    for (uint32_t e0 = r0; e0 < r1; e0 += kWin) {
+        uint64_t mine[kWin / 64];
+        uint32_t n = 0;
+#pragma unroll
+        for (int w = 0; w < kWin / 64; ++w) {
+            const uint2 en = next[w];
+            next[w] = load(e0 + kWin + 64u * w + lane);
+            gs[64 * w + lane] = en.x;
+            mine[w] = transpose_bits64(cover_of(en));      // window entries covering column tx
+            n += (uint32_t)__popcll(mine[w]);
+        }
+        const uint32_t incl = wave_incl_scan(n);
+        const uint32_t total = __shfl(incl, 63, 64);
+        const uint32_t off = incl - n;
         __syncthreads();
-        next = load(e0 + 64 + lane);
-        for (int jb = 0; jb < 64; jb += 16) {
-            uint64_t E[16];
+        if (total <= (uint32_t)kStage) {
+            // stage tile by tile (lane x owns [off, off + n)), then write out
+            off_l[lane] = off;
+            cur_l[lane] = cur;
+            uint32_t k = off;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) E[k] = ent_s[jb + k];
+            for (int w = 0; w < kWin / 64; ++w) {
+                uint64_t m = mine[w];
+                while (m) {
+                    const int e = __builtin_ctzll(m);
+                    m &= m - 1ull;
+                    st_g[k] = gs[64 * w + e];
+                    st_x[k] = (uint8_t)lane;
+                    ++k;
+                }
+            }
+            __syncthreads();
+            for (uint32_t t = (uint32_t)lane; t < total; t += 64u) {
+                const uint32_t x = st_x[t];
+                const uint32_t pos = cur_l[x] + (t - off_l[x]);
+                if (pos < lim_l[x]) out[pos] = st_g[t];
+            }
+        } else {
+            uint32_t cw = cur;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const uint32_t xr = (uint32_t)(E[k] >> 32);
-                const uint32_t x0 = xr & 0xFFFFu, w = (xr >> 16) - x0;
-                const bool in = tx - x0 < w;      // unsigned: x0 <= tx < x1; x1 <= TX
-                if (in && cur < lim) out[cur] = (uint32_t)E[k];
-                cur += in ? 1u : 0u;
+            for (int w = 0; w < kWin / 64; ++w) {
+                uint64_t m = mine[w];
+                while (m) {
+                    const int e = __builtin_ctzll(m);
+                    m &= m - 1ull;
+                    if (cw < lim) out[cw] = gs[64 * w + e];
+                    ++cw;
+                }
             }
         }
+        cur += n;
         __syncthreads();
     }
 }
@@ -530,7 +597,7 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
                        sizeof(Group) + (size_t)c.ty_max * 4, stream, c, n, bits_for(c.ty_max));
     if (schedule == 1) {
         const int n_cc = (c.tx_max + 63) / 64;
-        hipLaunchKernelGGL(k_rowtile_gather, dim3((unsigned)(c.ty_max * n_cc), (unsigned)c.n_img), dim3(64), 0,
+        hipLaunchKernelGGL(k_rowtile_transpose, dim3((unsigned)(c.ty_max * n_cc), (unsigned)c.n_img), dim3(64), 0,
                            stream, c, n_cc);
     } else {
         const int groups = 1;   // splitting a row into column groups re-reads the row list and measured slower

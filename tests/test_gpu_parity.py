@@ -79,7 +79,10 @@ def _check_image(got, ref, label, rgb_tol=1e-3):
     print(f"[{label}] {res}", flush=True)
     assert res["ok"], (label, res)
     assert res["n_unresolved"] <= max(2, res["n_pix"] // 20000)
-    np.testing.assert_allclose(alpha, ref.alpha, atol=2e-3)
+    # alpha of the primary result; a pixel with a flagged threshold decision may
+    # take the other admissible branch (its colour was checked against all of them)
+    calm = ref.nflag == 0
+    np.testing.assert_allclose(alpha[calm], ref.alpha[calm], atol=2e-3)
     return res
 
 
