@@ -215,6 +215,56 @@ int gsr_scene_info(gsr_ctx* ctx, uint64_t scene_id, int64_t* n, int* n_bodies, i
 int gsr_render(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
 int gsr_render_plain(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
 
+/* ---- batch LiDAR -----------------------------------------------------
+ * Ray casting of the same resident Gaussians, posed with the same rigid-body
+ * kinematics, for rotating and solid-state LiDARs (the paper's batch LiDAR
+ * module, Sec. "User Interface and Ecosystem Design", and its LiDAR feature
+ * table; dynamic objects and self-occlusion come from the posed scene).
+ *
+ * Sensor frame: x forward, y left, z up.  A LiDAR slot is a grid of rays,
+ * H beams (rows) x W columns: ray (r, c) has azimuth az0 + (c + 0.5) az_step
+ * and elevation elevations[r] (radians), direction
+ * (cos el cos az, cos el sin az, sin el).  A rotating LiDAR spans a full
+ * turn (W az_step = 2 pi); a solid-state one a sector.  Non-repetitive scan
+ * patterns are not supported.
+ *
+ * Per ray and Gaussian (posed mean m, rotation R, scales S, opacity o in the
+ * sensor frame), the Gaussian's response along the ray x(t) = t d peaks at
+ * t* = argmin_t q(t), q(t) = |S^-1 R^T (t d - m)|^2; it contributes
+ * alpha = min(0.99, o exp(-q(t*)/2)) at range t* if t* > near_range.
+ * Contributions are composited front to back in the order of the Gaussians'
+ * centre distances |m| (binary32 bits, ties by index) with the image model's
+ * rules (skip alpha < 1/255, stop before adding when T(1 - alpha) < 1e-4):
+ *     range = sum t* alpha T / (1 - T)  (0 where nothing was added),
+ *     hit   = 1 - T  (the return probability).
+ * Rays are binned into TS x TS tiles of the grid by conservative angular
+ * bounds of each Gaussian's alpha >= 1/255 ellipsoid, so the result equals
+ * casting every ray against every Gaussian. */
+typedef struct {
+    int width, height;            /* W columns, H beams; 1..8192 each */
+    float az0, az_step;           /* radians; az_step > 0, W az_step <= 2 pi */
+    const float* elevations;      /* host [H], radians, strictly ascending, within (-pi/2, pi/2) */
+    float near_range;             /* returns at t* <= near_range are ignored; > 0 */
+    int attach_body;              /* -1: viewmats are world -> sensor; b: body-b -> sensor (as for cameras) */
+} gsr_lidar;
+
+typedef struct {
+    uint64_t scene_id;
+    int n_envs;                   /* E >= 1 */
+    int n_lidars;                 /* L, 1..8 */
+    const gsr_lidar* lidars;      /* host, [L] */
+    const float* viewmats;        /* device, [L][E][3][4] world -> sensor (or body -> sensor when attached) */
+    const float* body_poses;      /* device, [E][B][7]; may be NULL when B = 0 */
+    float* out_range;             /* device; slot l is a contiguous [E][H_l][W_l] block, slots in order */
+    float* out_hit;               /* device, optional (NULL): 1 - T, same layout */
+} gsr_lidar_desc;
+
+/* Asynchronous on `stream` like gsr_render (one host wait per memory chunk).
+ * Inputs and outputs are caller-owned and must stay valid until the stream
+ * passes this call.  GSR_E_INVALID on bad sizes, angles or null pointers,
+ * before any device work. */
+int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* desc, void* stream);
+
 /* Binning and projection of image `image` (camera-slot-major index) of
  * `desc`, copied to host arrays.  Synchronous.  Output pointers of `desc` are
  * not used.  GSR_E_INVALID if out->capacity is smaller than the number of

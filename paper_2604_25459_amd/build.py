@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "libgsr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["k_project.hip", "k_sort.hip", "k_tiles.hip", "k_raster.hip", "gsr_api.cpp", "gsr_server.cpp"]
+SOURCES = ["k_project.hip", "k_sort.hip", "k_tiles.hip", "k_raster.hip", "k_lidar.hip", "gsr_api.cpp",
+           "gsr_server.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -8,6 +8,7 @@
 //   [host reads the chunk's pair and row-entry totals, grows buffers] ->
 //   two-level tile scatter -> raster (all images of the chunk, any sizes).
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -76,10 +77,11 @@ Workspace::~Workspace()
 {
     for (DevBuf* b : {&img, &xform, &keyz, &rect, &srect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &vis_count,
                       &tile_hist, &tile_range, &pair_count, &pair_base, &pairs, &row_hist, &row_range, &row_count,
-                      &row_base, &rows, &debug, &stage_vm, &stage_pose})
+                      &row_base, &rows, &debug, &stage_vm, &stage_pose, &stage_elev})
         b->release();
     if (h_total) (void)hipHostFree(h_total);
     if (h_img) (void)hipHostFree(h_img);
+    if (h_elev) (void)hipHostFree(h_elev);
     if (ev_total) (void)hipEventDestroy(ev_total);
     if (ev_done) (void)hipEventDestroy(ev_done);
     for (auto& kv : graphs)
@@ -193,10 +195,11 @@ std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies)
 
 namespace {
 
-size_t per_image_bytes(const SceneRes* sc, int t_max, int ty_max, int sort_blocks, int tile_blocks)
+size_t per_image_bytes(const SceneRes* sc, int t_max, int ty_max, int sort_blocks, int tile_blocks,
+                       size_t rec_bytes = 48)
 {
     const size_t n = (size_t)sc->dev.n;
-    size_t b = n * (4 + 16 + 48 + 16);                                 // key, rect + sorted rect, record, sort buffers
+    size_t b = n * (4 + 16 + rec_bytes + 16);                          // key, rect + sorted rect, record, sort buffers
     b += (size_t)(sc->dev.n_bodies + 1) * 64;                          // transforms
     b += (size_t)sort_blocks * 256 * 4 + (size_t)tile_blocks * ty_max * 4 + (size_t)(t_max + ty_max) * 8;
     b += (size_t)(t_max + 2 * ty_max + 1) * 4;                         // tile difference array (bound)
@@ -216,7 +219,7 @@ size_t image_bytes_estimate(const SceneRes* sc, int width, int height, int ts)
 }
 
 ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain,
-                      int chunk_images)
+                      int chunk_images, size_t rec_bytes)
 {
     ChunkPlan p{};
     p.t_max = p.tx_max = p.ty_max = 1;
@@ -231,7 +234,7 @@ ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<
     if (plain) {
         p.chunk = 1;
     } else {
-        const size_t per = per_image_bytes(sc, p.t_max, p.ty_max, p.sort_blocks, p.tile_blocks);
+        const size_t per = per_image_bytes(sc, p.t_max, p.ty_max, p.sort_blocks, p.tile_blocks, rec_bytes);
         size_t c = std::max<size_t>(1, (size_t)ctx->opt.chunk_bytes / std::max<size_t>(per, 1));
         if (chunk_images > 0) c = std::min<size_t>(c, (size_t)chunk_images);
         p.chunk = (int)std::min<size_t>(c, imgs.size());
@@ -239,7 +242,8 @@ ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<
     return p;
 }
 
-hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, size_t n_images_total)
+hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, size_t n_images_total,
+                            size_t rec_bytes)
 {
     const size_t n = (size_t)std::max<int64_t>(sc->dev.n, 1);
     const size_t I = (size_t)p.chunk;
@@ -251,7 +255,7 @@ hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& 
     ENS(keyz, I * n * 4);
     ENS(rect, I * n * 8);
     ENS(srect, I * n * 8);
-    ENS(rec, I * n * 48);
+    ENS(rec, I * n * rec_bytes);
     ENS(sk0, I * n * 4);
     ENS(sk1, I * n * 4);
     ENS(sv0, I * n * 4);
@@ -421,7 +425,9 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
 
     int rc = run_stage(ws, graph, chunk_idx, 0, key, st, [&](hipStream_t q) {
         hipError_t e = launch_compose(s, c, job.viewmats, job.poses, q);
-        if (e == hipSuccess) e = launch_project(s, c, tu.ts, ctx->opt.cutoff, tu.ipt, q);
+        if (e == hipSuccess)
+            e = job.lidar ? launch_project_lidar(s, c, tu.ts, tu.ipt, q)
+                          : launch_project(s, c, tu.ts, ctx->opt.cutoff, tu.ipt, q);
         return e;
     });
     if (rc) return rc;
@@ -500,7 +506,12 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     rp.n_blocks = blocks;
     key.push_back((uint64_t)(uintptr_t)rp.counter);
     key.push_back((uint64_t)rp.count_work);
-    rc = run_stage(ws, graph, chunk_idx, 4, key, st, [&](hipStream_t q) { return launch_raster(s, c, rp, q); });
+    if (job.lidar) {
+        rc = run_stage(ws, graph, chunk_idx, 4, key, st,
+                       [&](hipStream_t q) { return launch_raster_lidar(s, c, rp, q); });
+    } else {
+        rc = run_stage(ws, graph, chunk_idx, 4, key, st, [&](hipStream_t q) { return launch_raster(s, c, rp, q); });
+    }
     if (rc) return rc;
     if (prof) {
         GSR_HIP_TRY(hipEventRecord(ev.e[5], st));
@@ -527,10 +538,11 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
 {
     if (job_in.imgs.empty()) return GSR_OK;
     RenderJob job = job_in;
-    const ChunkPlan plan = plan_chunks(ctx, sc, job.imgs, plain, job.tune.chunk_images);
+    const size_t rec_bytes = job.lidar ? 64 : 48;
+    const ChunkPlan plan = plan_chunks(ctx, sc, job.imgs, plain, job.tune.chunk_images, rec_bytes);
     // buffers may be reallocated: earlier work on this workspace must be finished
     if (ws.used) GSR_HIP_TRY(hipEventSynchronize(ws.ev_done));
-    GSR_HIP_TRY(ensure_workspace(ws, sc, plan, job.imgs.size()));
+    GSR_HIP_TRY(ensure_workspace(ws, sc, plan, job.imgs.size(), rec_bytes));
     // per-step inputs staged at fixed addresses, so captured graphs replay across steps
     if (job.viewmats != ws.stage_vm.as<float>()) {
         GSR_HIP_TRY(ws.stage_vm.ensure(std::max<size_t>(job.viewmat_floats, 1) * 4));
@@ -874,6 +886,139 @@ GSR_EXPORT int gsr_render(gsr_ctx* ctx, const gsr_render_desc* desc, void* strea
 GSR_EXPORT int gsr_render_plain(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream)
 {
     return render_impl(ctx, desc, stream, true);
+}
+
+// ------------------------------------------------------------------ LiDAR
+
+namespace {
+
+int validate_lidar(const gsr_ctx* ctx, const gsr_lidar_desc* d, const SceneRes* sc)
+{
+    if (d->n_envs < 1) return fail(GSR_E_INVALID, "n_envs must be >= 1");
+    if (d->n_lidars < 1 || d->n_lidars > kMaxCams) return fail(GSR_E_INVALID, "n_lidars must be in 1..8");
+    if (!d->lidars) return fail(GSR_E_INVALID, "lidars is NULL");
+    if (!d->viewmats) return fail(GSR_E_INVALID, "viewmats is NULL");
+    if (sc->dev.n_bodies > 0 && !d->body_poses) return fail(GSR_E_INVALID, "body_poses is NULL but the scene has bodies");
+    if (!d->out_range) return fail(GSR_E_INVALID, "out_range is NULL");
+    if (((uintptr_t)d->viewmats & 3) || ((uintptr_t)d->body_poses & 3) || ((uintptr_t)d->out_range & 3) ||
+        ((uintptr_t)d->out_hit & 3))
+        return fail(GSR_E_INVALID, "arrays must be 4-byte aligned");
+    const int ts = ctx->opt.tile_size;
+    if (ts > 16) return fail(GSR_E_INVALID, "LiDAR ray tiles need a context tile size of 8 or 16");
+    const double two_pi = 6.283185307179586;
+    for (int l = 0; l < d->n_lidars; ++l) {
+        const gsr_lidar& L = d->lidars[l];
+        if (L.width < 1 || L.height < 1 || L.width > 8192 || L.height > 8192)
+            return fail(GSR_E_INVALID, "LiDAR grid size must be in 1..8192");
+        if (!(L.az_step > 0.0f) || !std::isfinite(L.az0) || (double)L.width * L.az_step > two_pi * (1.0 + 1e-6))
+            return fail(GSR_E_INVALID, "az_step must be > 0 with width * az_step <= 2 pi");
+        if (!L.elevations) return fail(GSR_E_INVALID, "elevations is NULL");
+        for (int r = 0; r < L.height; ++r) {
+            const float e = L.elevations[r];
+            if (!(e > -1.5707963f && e < 1.5707963f)) return fail(GSR_E_INVALID, "elevations must lie in (-pi/2, pi/2)");
+            if (r > 0 && !(e > L.elevations[r - 1])) return fail(GSR_E_INVALID, "elevations must ascend strictly");
+        }
+        if (!(L.near_range > 0.0f)) return fail(GSR_E_INVALID, "near_range must be > 0");
+        if (L.attach_body < -1 || L.attach_body >= sc->dev.n_bodies)
+            return fail(GSR_E_INVALID, "attach_body must be -1 or a body of the scene (0..B-1)");
+        const int64_t tiles = (int64_t)((L.width + ts - 1) / ts) * ((L.height + ts - 1) / ts);
+        if (tiles > 15000) return fail(GSR_E_INVALID, "more than 15000 tiles per LiDAR grid for this tile size");
+    }
+    if ((int64_t)d->n_envs * d->n_lidars > (1 << 24)) return fail(GSR_E_INVALID, "more than 2^24 scans in one call");
+    return GSR_OK;
+}
+
+}  // namespace
+
+GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* stream)
+{
+    if (!ctx) return fail(GSR_E_INVALID, "ctx is NULL");
+    if (!d) return fail(GSR_E_INVALID, "LiDAR desc is NULL");
+    if (ctx->poisoned) return fail(GSR_E_DEVICE, "context poisoned by an earlier device fault");
+    SceneRes* sc = acquire_scene(ctx, d->scene_id);
+    if (!sc) return fail(GSR_E_NOT_FOUND, "unknown scene id");
+    int rc = validate_lidar(ctx, d, sc);
+    if (rc) {
+        release_scene(sc);
+        return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Workspace* ws;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ws = acquire_workspace_locked(ctx, st);
+        ws->in_call = true;
+    }
+    auto body = [&]() -> int {
+        GSR_HIP_TRY(hipSetDevice(ctx->device));
+        // beam elevations of every slot, staged in pinned memory and copied to
+        // the device (earlier work on this workspace must be done with them)
+        if (ws->used) GSR_HIP_TRY(hipEventSynchronize(ws->ev_done));
+        size_t n_elev = 0;
+        for (int l = 0; l < d->n_lidars; ++l) n_elev += (size_t)d->lidars[l].height;
+        if (ws->h_elev_cap < n_elev) {
+            if (ws->h_elev) (void)hipHostFree(ws->h_elev);
+            ws->h_elev = nullptr;
+            ws->h_elev_cap = 0;
+            GSR_HIP_TRY(hipHostMalloc((void**)&ws->h_elev, n_elev * sizeof(float), hipHostMallocDefault));
+            ws->h_elev_cap = n_elev;
+        }
+        GSR_HIP_TRY(ws->stage_elev.ensure(n_elev * sizeof(float)));
+        RenderJob job;
+        job.lidar = true;
+        job.tune.ts = ctx->opt.tile_size;
+        job.tune.batch = 256;
+        job.tune.ipt = ctx->opt.images_per_thread;
+        const int E = d->n_envs, B = sc->dev.n_bodies, ts = job.tune.ts;
+        job.imgs.resize((size_t)E * d->n_lidars);
+        uint64_t tile_base = 0, ray_base = 0;
+        size_t eo = 0;
+        for (int l = 0; l < d->n_lidars; ++l) {
+            const gsr_lidar& L = d->lidars[l];
+            std::memcpy(ws->h_elev + eo, L.elevations, (size_t)L.height * sizeof(float));
+            const int tx = (L.width + ts - 1) / ts, ty = (L.height + ts - 1) / ts;
+            for (int e = 0; e < E; ++e) {
+                ImageInfo& im = job.imgs[(size_t)l * E + e];
+                std::memset(&im, 0, sizeof im);
+                im.kind = 1;
+                im.width = L.width;
+                im.height = L.height;
+                im.tiles_x = tx;
+                im.tiles_y = ty;
+                im.near_plane = L.near_range;
+                im.az0 = L.az0;
+                im.az_step = L.az_step;
+                im.elev = ws->stage_elev.as<float>() + eo;
+                im.attach_body = L.attach_body;
+                im.key_tile_base = (uint32_t)tile_base;
+                im.vm_off = (uint32_t)(((size_t)l * E + e) * 12);
+                im.pose_off = (uint32_t)((size_t)e * B * 7);
+                im.out_depth = d->out_range + ray_base;
+                im.out_alpha = d->out_hit ? d->out_hit + ray_base : nullptr;
+                tile_base += (uint64_t)tx * ty;
+                ray_base += (uint64_t)L.width * L.height;
+            }
+            eo += (size_t)L.height;
+        }
+        GSR_HIP_TRY(hipMemcpyAsync(ws->stage_elev.p, ws->h_elev, n_elev * sizeof(float), hipMemcpyHostToDevice, st));
+        // grids of equal size contiguous (one raster segment each)
+        std::stable_sort(job.imgs.begin(), job.imgs.end(), [](const ImageInfo& a, const ImageInfo& b) {
+            return a.width != b.width ? a.width < b.width : a.height < b.height;
+        });
+        job.viewmats = d->viewmats;
+        job.poses = d->body_poses;
+        job.viewmat_floats = (size_t)d->n_lidars * E * 12;
+        job.pose_floats = (size_t)E * B * 7;
+        return render_job(ctx, *ws, sc, job, st, false, false);
+    };
+    rc = body();
+    if (!rc) rc = mark_scene_use(ctx, sc, st);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ws->in_call = false;
+    }
+    release_scene(sc);
+    return rc;
 }
 
 GSR_EXPORT int gsr_debug_bins(gsr_ctx* ctx, const gsr_render_desc* d, int image, gsr_bins_out* out)

@@ -44,6 +44,10 @@ struct ImageInfo {
     const float* obs_bright;
     int obs_fmt;              // GSR_OBS_U8 / GSR_OBS_F16
     uint32_t obs_idx;         // c * E + e within the image's request
+    // LiDAR images (kind 1): width x height ray grid, range -> out_depth, hit -> out_alpha
+    int kind;                 // 0 camera, 1 LiDAR
+    float az0, az_step;       // ray azimuths az0 + (c + 0.5) az_step
+    const float* elev;        // device [height] beam elevations, ascending
 };
 
 // Resident scene, device pointers.
@@ -81,7 +85,7 @@ struct ChunkDev {
     float* xform;              // [n_img][n_bodies + 1][16]
     uint32_t* keyz;            // [n_img][n] depth bits or kInvalidKey
     uint2* rect;               // [n_img][n] (x0 | x1 << 16, y0 | y1 << 16)
-    float4* rec;               // [n_img][n][3] raster records
+    float4* rec;               // [n_img][n][3] raster records ([..][4] for LiDAR)
     uint32_t* sk[2];           // depth-sort keys, ping-pong [n_img][n]
     uint32_t* sv[2];           // depth-sort values (Gaussian ids); sorted result in sv[1]
     uint2* srect;              // [n_img][n] tile rectangle of the j-th depth-ordered Gaussian
@@ -117,6 +121,10 @@ hipError_t launch_project(const SceneDev& s, const ChunkDev& c, int ts, float cu
 hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
 // Tile and tile-row histograms, ranges, image bases (before the host reads the totals).
 hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
+// LiDAR: projection into the ray grid (keys = centre distance, conservative
+// angular tile rectangles, 64-byte whitening records) and per-ray compositing.
+hipError_t launch_project_lidar(const SceneDev& s, const ChunkDev& c, int ts, int ipt, hipStream_t stream);
+
 // Stable two-level scatter: depth-ordered Gaussians -> tile-row lists -> tile lists.
 // schedule 0: level 2 as a stable scatter (one wave per tile row, ballot
 // ranks); 1: by a bit transpose (one lane per tile column appends the window
@@ -133,6 +141,7 @@ struct RasterParams {
     RasterSeg segs[kMaxSegs];
     uint32_t n_blocks;
 };
+hipError_t launch_raster_lidar(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream);
 hipError_t launch_raster(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream);
 
 // Scene upload: convert caller float32 attributes to resident storage.

@@ -74,10 +74,13 @@ struct StageGraph {
 // Working memory of one render call at a time.
 struct Workspace {
     DevBuf img, xform, keyz, rect, srect, rec, sk0, sk1, sv0, sv1, sort_hist, vis_count, tile_hist, tile_range,
-        pair_count, pair_base, pairs, row_hist, row_range, row_count, row_base, rows, debug, stage_vm, stage_pose;
+        pair_count, pair_base, pairs, row_hist, row_range, row_count, row_base, rows, debug, stage_vm, stage_pose,
+        stage_elev;
     uint64_t* h_total = nullptr;   // pinned: [0] pairs, [1] row entries, [2] visible Gaussians of the current chunk
     ImageInfo* h_img = nullptr;    // pinned staging for image descriptions
     size_t h_img_cap = 0;
+    float* h_elev = nullptr;       // pinned staging for LiDAR beam elevations
+    size_t h_elev_cap = 0;
     hipEvent_t ev_total = nullptr, ev_done = nullptr;
     hipStream_t last_stream = nullptr;
     bool used = false;      // ev_done has been recorded at least once
@@ -97,6 +100,7 @@ struct RenderJob {
     size_t viewmat_floats = 0;         // extent of the arrays above (staged into the workspace)
     size_t pose_floats = 0;
     Tuning tune;
+    bool lidar = false;                // LiDAR ray grids instead of camera images
 };
 
 enum class Mode { kRender, kBins, kProject };
@@ -113,12 +117,13 @@ std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies)
 int validate_desc(const gsr_ctx* ctx, const gsr_render_desc* d, const SceneRes* sc, bool need_outputs);
 size_t image_bytes_estimate(const SceneRes* sc, int width, int height, int ts);
 ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain,
-                      int chunk_images = 0);
+                      int chunk_images = 0, size_t rec_bytes = 48);
 // Shape-class key of a render descriptor (scene, envs, camera sizes).
 std::string shape_key(const SceneRes* sc, const gsr_render_desc* d);
 // Tuning a render of `d` uses: the tuned entry of its shape class or the context defaults.
 Tuning tuning_for(gsr_ctx* ctx, const SceneRes* sc, const gsr_render_desc* d);
-hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, size_t n_images_total);
+hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, size_t n_images_total,
+                            size_t rec_bytes = 48);
 
 // Enqueue the whole job on `st` (blocks once per chunk for its pair count);
 // `graphs` allows replaying captured stage graphs (batched path only).

@@ -1,0 +1,283 @@
+// Batch LiDAR: ray casting of the resident, rigidly posed Gaussians for grids
+// of rays (rotating or solid-state sensors), through the same sort and tile
+// binning as the cameras.
+//
+// Projection (one thread per Gaussian, a group of scans per thread):
+//   * pose into the sensor frame with the binary32 specification of the
+//     camera path (t = A mu + a);
+//   * key = bits of the centre distance |t| (binary32, sqrt correctly
+//     rounded), so the compositing order is (distance, index);
+//   * tile rectangle: rows and columns of rays whose direction lies in the
+//     cone of the sphere of radius sqrt(Qmax) * max scale around t (Qmax the
+//     opacity bucket bound of the camera path), widened by a relative 1e-4 and
+//     an absolute 2e-6 rad against the rounding of the trigonometric
+//     functions; a cone across the seam of a full turn takes the hull of its
+//     two column ranges, a sensor inside the sphere takes the whole grid;
+//   * record: whitening W = S^-1 R^T (R, S the Gaussian's rotation in the
+//     sensor frame and its scales), the centre t, log2 o and W t.
+// Raster (one workgroup per tile of rays, one ray per thread): for each
+// listed Gaussian, d' = W d, t* = (d' . W t) / |d'|^2 (the peak of the
+// Gaussian along the ray), q = |W (t - t* d)|^2 (the offset taken in metres
+// first, so that no large whitened terms cancel), log2 alpha = log2 o - q/2
+// log2 e; then the compositing rules of the camera path with the range t* in
+// place of the depth.
+#include "gsr_device.h"
+
+#include <algorithm>
+
+namespace gsr {
+namespace {
+
+constexpr float kLidarLogAlphaMin = -7.99435343685886f;   // log2(1/255)
+constexpr float kHalfPi = 1.5707963267948966f;
+constexpr float kTwoPi = 6.283185307179586f;
+
+// First index r in [0, H) with v[r] >= x (strict = false) or v[r] > x
+// (strict = true), v ascending; H if none.
+__device__ __forceinline__ int first_at_least(const float* v, int H, float x, bool strict)
+{
+    int lo = 0, hi = H;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const bool below = strict ? v[mid] <= x : v[mid] < x;
+        if (below) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Columns c in [0, W) whose ray azimuth az0 + (c + 0.5) step lies in
+// [a0, a1] (radians, a1 - a0 < 2 pi); returns an empty range when none.
+__device__ __forceinline__ void column_range(float a0, float a1, float az0, float step, int W, int* c0, int* c1)
+{
+    const float lo = (a0 - az0) / step - 0.5f;
+    const float hi = (a1 - az0) / step - 0.5f;
+    int x0 = (int)ceilf(fmaxf(lo, -1.0f));
+    int x1 = (int)floorf(fminf(hi, (float)W)) + 1;
+    x0 = max(x0, 0);
+    x1 = min(x1, W);
+    *c0 = x0;
+    *c1 = x1;
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, int ts, int ipt)
+{
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
+    const int64_t g = (int64_t)bx * 256 + threadIdx.x;
+    if (g >= s.n) return;
+    const int i_begin = (int)by * ipt;
+    const int slot = body_slot(s, g);
+    const float4 pm = s.pos[g];
+    float q[4], sc[3];
+    load_rot_scale<ST>(s, g, q, sc);
+    float Rg[9];
+    quat_rot(q[0], q[1], q[2], q[3], Rg);
+    const float mu[3] = {pm.x, pm.y, pm.z};
+    const float op = pm.w;
+    const float log2o = log2f(op);
+    const float rho = sqrtf(opacity_qmax(op)) * fmaxf(sc[0], fmaxf(sc[1], sc[2]));
+    const float isc[3] = {1.0f / sc[0], 1.0f / sc[1], 1.0f / sc[2]};
+
+    for (int ii = 0; ii < ipt; ++ii) {
+        const int i = i_begin + ii;
+        if (i >= c.n_img) break;
+        const ImageInfo im = c.img[i];
+        const float* X = c.xform + ((size_t)i * (s.n_bodies + 1) + slot) * 16;
+        float A[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) A[k] = X[k];
+        const float tx = ((A[0] * mu[0] + A[1] * mu[1]) + A[2] * mu[2]) + X[9];
+        const float ty = ((A[3] * mu[0] + A[4] * mu[1]) + A[5] * mu[2]) + X[10];
+        const float tz = ((A[6] * mu[0] + A[7] * mu[1]) + A[8] * mu[2]) + X[11];
+        const float D = sqrtf((tx * tx + ty * ty) + tz * tz);
+        const size_t o = (size_t)i * (size_t)s.n + (size_t)g;
+        const bool ok = isfinite(tx) && isfinite(ty) && isfinite(tz) && op >= 1.0f / 255.0f && D > 0.0f &&
+                        isfinite(D) && sc[0] > 0.0f && sc[1] > 0.0f && sc[2] > 0.0f;
+        int r0 = 0, r1 = 0, c0 = 0, c1 = 0;
+        if (ok) {
+            if (D <= rho * 1.001f + 1e-6f) {            // the sensor may sit inside: every ray
+                r0 = 0;
+                r1 = im.height;
+                c0 = 0;
+                c1 = im.width;
+            } else {
+                const float ang = asinf(rho / D) * 1.0001f + 2e-6f;
+                const float el = asinf(fminf(1.0f, fmaxf(-1.0f, tz / D)));
+                r0 = first_at_least(im.elev, im.height, el - ang, false);   // rows with el - ang <= elev
+                r1 = first_at_least(im.elev, im.height, el + ang, true);    // ... <= el + ang
+                if (fabsf(el) + ang >= kHalfPi - 1e-4f) {
+                    c0 = 0;
+                    c1 = im.width;
+                } else {
+                    const float daz = asinf(fminf(1.0f, sinf(ang) / cosf(fabsf(el) + ang))) * 1.0001f + 2e-6f;
+                    const float th = atan2f(ty, tx);
+                    if (2.0f * daz >= kTwoPi - 1e-4f) {
+                        c0 = 0;
+                        c1 = im.width;
+                    } else {
+                        // the azimuth window, tested at its three 2 pi shifts; the hull of the hits
+                        int lo = im.width, hi = 0;
+#pragma unroll
+                        for (int k = -1; k <= 1; ++k) {
+                            int a, b;
+                            column_range(th - daz + (float)k * kTwoPi, th + daz + (float)k * kTwoPi, im.az0,
+                                         im.az_step, im.width, &a, &b);
+                            if (a < b) {
+                                lo = min(lo, a);
+                                hi = max(hi, b);
+                            }
+                        }
+                        c0 = lo;
+                        c1 = hi;
+                    }
+                }
+            }
+        }
+        const bool vis = ok && r1 > r0 && c1 > c0;
+        c.keyz[o] = vis ? __float_as_uint(D) : kInvalidKey;
+        if (!vis) continue;
+        const int x0 = c0 / ts, x1 = (c1 + ts - 1) / ts, y0 = r0 / ts, y1 = (r1 + ts - 1) / ts;
+        c.rect[o] = make_uint2((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16));
+        // whitening W = S^-1 (A Rg)^T: row k = (A Rg)[:, k] / s_k
+        float Rs[9];
+        mat3_mul(A, Rg, Rs);
+        float W[9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) W[3 * k + j] = Rs[3 * j + k] * isc[k];
+        const float w0 = (W[0] * tx + W[1] * ty) + W[2] * tz;
+        const float w1 = (W[3] * tx + W[4] * ty) + W[5] * tz;
+        const float w2 = (W[6] * tx + W[7] * ty) + W[8] * tz;
+        float4* rec = c.rec + 4 * o;
+        rec[0] = make_float4(W[0], W[1], W[2], tx);
+        rec[1] = make_float4(W[3], W[4], W[5], ty);
+        rec[2] = make_float4(W[6], W[7], W[8], tz);
+        rec[3] = make_float4(log2o, w0, w1, w2);
+    }
+}
+
+// One workgroup per TS x TS tile of rays; batches of kLBatch records in LDS.
+template <int TS>
+__global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c, RasterParams p)
+{
+    constexpr int NT = TS * TS;
+    constexpr int kLBatch = NT;
+    __shared__ float4 sr[4][kLBatch];
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    int sgi = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxSegs; ++k)
+        if (k < p.n_segs && bid >= p.segs[k].first_tile) sgi = k;
+    const RasterSeg seg = p.segs[sgi];
+    const uint32_t rel = bid - seg.first_tile;
+    const uint32_t io = rel / seg.tiles_per_image;
+    const uint32_t t = rel - io * seg.tiles_per_image;
+    const int i = (int)(seg.first_image + io);
+    const ImageInfo im = c.img[i];
+    const int tx = (int)(t % (uint32_t)im.tiles_x);
+    const int ty = (int)(t / (uint32_t)im.tiles_x);
+    const int tid = threadIdx.x;
+    const int col = tx * TS + (tid % TS), row = ty * TS + (tid / TS);
+    const bool inside = col < im.width && row < im.height;
+    float d[3] = {0.0f, 0.0f, 0.0f};
+    if (inside) {
+        const float az = im.az0 + ((float)col + 0.5f) * im.az_step;
+        const float el = im.elev[row];
+        float sa, ca, se, ce;
+        sincosf(az, &sa, &ca);
+        sincosf(el, &se, &ce);
+        d[0] = ce * ca;
+        d[1] = ce * sa;
+        d[2] = se;
+    }
+    bool live = inside;
+    float T = 1.0f, Rg = 0.0f;
+    const float near = im.near_plane;
+
+    const uint32_t* R = c.tile_range + ((size_t)i * c.t_max + t) * 2;
+    const uint32_t start = R[0], end = R[1];
+    const uint32_t* list = c.pairs + c.pair_base[i];
+    const float4* rec = c.rec + (size_t)i * (size_t)s.n * 4;
+    const uint32_t n = (uint32_t)s.n;
+    for (uint32_t b0 = start; b0 < end; b0 += kLBatch) {
+        __syncthreads();
+        const uint32_t e = b0 + (uint32_t)tid;
+        if (e < end) {
+            uint32_t g = list[e];
+            if (g >= n) g = 0;          // guard: list entries are valid indices by construction
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sr[k][tid] = rec[4 * (size_t)g + k];
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)kLBatch, end - b0);
+        if (live) {
+            for (int j = 0; j < cnt; ++j) {
+                const float4 m0 = sr[0][j], m1 = sr[1][j], m2 = sr[2][j], m3 = sr[3][j];
+                // d' = W d
+                const float dx = fmaf(m0.z, d[2], fmaf(m0.y, d[1], m0.x * d[0]));
+                const float dy = fmaf(m1.z, d[2], fmaf(m1.y, d[1], m1.x * d[0]));
+                const float dz = fmaf(m2.z, d[2], fmaf(m2.y, d[1], m2.x * d[0]));
+                const float aa = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const float bb = fmaf(dz, m3.w, fmaf(dy, m3.z, dx * m3.y));
+                const float tstar = bb * __builtin_amdgcn_rcpf(aa);
+                // offset of the centre from the ray's closest point, in metres, then whitened
+                const float px = fmaf(-tstar, d[0], m0.w);
+                const float py = fmaf(-tstar, d[1], m1.w);
+                const float pz = fmaf(-tstar, d[2], m2.w);
+                const float wx = fmaf(m0.z, pz, fmaf(m0.y, py, m0.x * px));
+                const float wy = fmaf(m1.z, pz, fmaf(m1.y, py, m1.x * px));
+                const float wz = fmaf(m2.z, pz, fmaf(m2.y, py, m2.x * px));
+                const float qq = fmaf(wz, wz, fmaf(wy, wy, wx * wx));
+                const float la = fmaf(-0.72134752044448170f, qq, m3.x);      // log2 o - q/2 log2 e
+                const bool take = tstar > near && la >= kLidarLogAlphaMin;
+                const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(la));
+                const float Tn = fmaf(-T, alpha, T);
+                const bool stop = take && Tn < 1e-4f;
+                const bool add = take && !stop;
+                Rg = add ? fmaf(tstar, alpha * T, Rg) : Rg;
+                T = add ? Tn : T;
+                if (stop) {
+                    live = false;
+                    break;
+                }
+            }
+        }
+        if (__syncthreads_count(live ? 1 : 0) == 0) break;
+    }
+    if (inside) {
+        const size_t pix = (size_t)row * im.width + col;
+        im.out_depth[pix] = T < 1.0f ? Rg / (1.0f - T) : 0.0f;
+        if (im.out_alpha) im.out_alpha[pix] = 1.0f - T;
+    }
+}
+
+template <int ST>
+hipError_t project_lidar_st(const SceneDev& s, const ChunkDev& c, int ts, int ipt, hipStream_t st)
+{
+    const dim3 grid((unsigned)((s.n + 255) / 256), (unsigned)((c.n_img + ipt - 1) / ipt));
+    hipLaunchKernelGGL((k_project_lidar<ST>), grid, dim3(256), 0, st, s, c, ts, ipt);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_project_lidar(const SceneDev& s, const ChunkDev& c, int ts, int ipt, hipStream_t stream)
+{
+    if (s.n == 0 || c.n_img == 0) return hipSuccess;
+    if (s.storage == kF16) return project_lidar_st<kF16>(s, c, ts, ipt, stream);
+    if (s.storage == kBF16) return project_lidar_st<kBF16>(s, c, ts, ipt, stream);
+    return project_lidar_st<kF32>(s, c, ts, ipt, stream);
+}
+
+hipError_t launch_raster_lidar(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream)
+{
+    if (p.n_blocks == 0) return hipSuccess;
+    if (p.ts == 8) hipLaunchKernelGGL((k_raster_lidar<8>), dim3(p.n_blocks), dim3(64), 0, stream, s, c, p);
+    else if (p.ts == 16) hipLaunchKernelGGL((k_raster_lidar<16>), dim3(p.n_blocks), dim3(256), 0, stream, s, c, p);
+    else return hipErrorInvalidValue;           // 32 x 32 ray tiles exceed the workgroup size
+    return hipGetLastError();
+}
+
+}  // namespace gsr

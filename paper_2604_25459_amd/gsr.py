@@ -66,6 +66,17 @@ class RenderDesc(C.Structure):
                 ("out_work", C.c_void_p), ("obs", C.c_void_p)]
 
 
+class LidarDesc(C.Structure):
+    _fields_ = [("width", C.c_int), ("height", C.c_int), ("az0", C.c_float), ("az_step", C.c_float),
+                ("elevations", C.c_void_p), ("near_range", C.c_float), ("attach_body", C.c_int)]
+
+
+class LidarRenderDesc(C.Structure):
+    _fields_ = [("scene_id", C.c_uint64), ("n_envs", C.c_int), ("n_lidars", C.c_int), ("lidars", C.c_void_p),
+                ("viewmats", C.c_void_p), ("body_poses", C.c_void_p), ("out_range", C.c_void_p),
+                ("out_hit", C.c_void_p)]
+
+
 class BinsOut(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("keys", C.c_void_p), ("values", C.c_void_p), ("ranges", C.c_void_p),
                 ("ranges_capacity", C.c_int64), ("n_pairs", C.c_int64), ("n_visible", C.c_int64),
@@ -103,6 +114,7 @@ SIGNATURES = {
     "gsr_scene_info": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_render": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_render_plain": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_render_lidar": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_debug_bins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "gsr_debug_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "gsr_stage_times": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
@@ -167,6 +179,20 @@ class Camera:
     cy: float
     near: float = 0.01
     attach_body: int = -1     # >= 0: the slot's viewmats are body -> camera offsets of that body
+
+
+@dataclass
+class Lidar:
+    """A ray grid: ``height`` beams at ``elevations`` (radians, ascending) x
+    ``width`` columns at azimuths az0 + (c + 0.5) az_step; sensor frame x
+    forward, y left, z up."""
+    width: int
+    height: int
+    az0: float
+    az_step: float
+    elevations: object          # sequence of height floats
+    near_range: float = 0.05
+    attach_body: int = -1
 
 
 @dataclass
@@ -311,6 +337,44 @@ class Renderer:
         rgb, depth, a = self.alloc_outputs(cams, E, alpha)
         self.render_into(sid, cams, viewmats, poses, rgb, depth, a, bg, plain, stream)
         return self.split(cams, E, rgb, depth, a)
+
+    # ---------------------------------------------------------- LiDAR
+    def render_lidar_into(self, sid, lidars, viewmats, poses, out_range, out_hit=None, stream=None):
+        """viewmats: CUDA float32 [L, E, 3, 4] world -> sensor (body -> sensor for attached slots);
+        out_range / out_hit: CUDA float32 [sum over slots of E * H * W]."""
+        import torch
+        keep = []
+        arr = (LidarDesc * len(lidars))()
+        for k, l in enumerate(lidars):
+            el = np.ascontiguousarray(np.asarray(l.elevations, np.float32))
+            keep.append(el)
+            arr[k] = LidarDesc(width=int(l.width), height=int(l.height), az0=float(l.az0), az_step=float(l.az_step),
+                               elevations=el.ctypes.data, near_range=float(l.near_range),
+                               attach_body=int(l.attach_body))
+        d = LidarRenderDesc(scene_id=sid, n_envs=int(viewmats.shape[1]), n_lidars=len(lidars),
+                            lidars=C.addressof(arr), viewmats=_ptr(viewmats),
+                            body_poses=_ptr(poses) if poses is not None and poses.numel() else None,
+                            out_range=_ptr(out_range), out_hit=_ptr(out_hit))
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(load().gsr_render_lidar(self._h, C.byref(d), C.c_void_p(st)))
+        del keep, arr
+
+    def render_lidar(self, sid, lidars, viewmats, poses, hit=True, stream=None):
+        """Per slot: (range [E, H, W], hit [E, H, W] or None)."""
+        import torch
+        E = int(viewmats.shape[1])
+        n = sum(E * l.width * l.height for l in lidars)
+        dev = torch.device("cuda", self.device)
+        rng = torch.empty(n, dtype=torch.float32, device=dev)
+        h = torch.empty(n, dtype=torch.float32, device=dev) if hit else None
+        self.render_lidar_into(sid, lidars, viewmats, poses, rng, h, stream)
+        out, base = [], 0
+        for l in lidars:
+            m = E * l.width * l.height
+            out.append((rng[base:base + m].view(E, l.height, l.width),
+                        h[base:base + m].view(E, l.height, l.width) if h is not None else None))
+            base += m
+        return out
 
     # ---------------------------------------------------------- tuning
     TUNING_KEYS = ("tile_size", "lds_batch", "images_per_thread", "persistent", "chunk_images", "bin_schedule", "ms")

@@ -214,6 +214,67 @@ def orbit_viewmats(rng: np.random.Generator, n: int, r_lo: float, r_hi: float,
 
 
 # --------------------------------------------------------------------------
+# LiDAR grids
+# --------------------------------------------------------------------------
+@dataclass
+class LidarSpec:
+    """A ray grid (sensor frame x forward, y left, z up): ``height`` beams at
+    ``elevations`` (radians, ascending) x ``width`` columns at azimuths
+    az0 + (c + 0.5) az_step."""
+    width: int
+    height: int
+    az0: float
+    az_step: float
+    elevations: np.ndarray
+    near_range: float = 0.05
+    attach_body: int = -1
+
+
+@dataclass
+class LidarBatch:
+    cams: List[LidarSpec]     # L LiDAR slots (named like camera slots, so posing code is shared)
+    viewmats: np.ndarray      # (L, E, 3, 4) float32 world -> sensor (body -> sensor when attached)
+    poses: np.ndarray         # (E, B, 7) float32
+
+    @property
+    def n_envs(self) -> int:
+        return int(self.viewmats.shape[1])
+
+
+def rotating_lidar(beams: int, columns: int, el_lo_deg: float, el_hi_deg: float, near: float = 0.05) -> LidarSpec:
+    """Full-turn LiDAR with evenly spaced beams (float64 angles rounded to float32)."""
+    el = np.radians(np.linspace(el_lo_deg, el_hi_deg, beams)).astype(np.float32)
+    return LidarSpec(width=columns, height=beams, az0=float(np.float32(-math.pi)),
+                     az_step=float(np.float32(2.0 * math.pi / columns)), elevations=el,
+                     near_range=float(np.float32(near)))
+
+
+def sector_lidar(beams: int, columns: int, az_deg: float, el_lo_deg: float, el_hi_deg: float,
+                 near: float = 0.05) -> LidarSpec:
+    """Solid-state LiDAR covering azimuths [-az/2, az/2] in front of the sensor."""
+    el = np.radians(np.linspace(el_lo_deg, el_hi_deg, beams)).astype(np.float32)
+    a = math.radians(az_deg)
+    return LidarSpec(width=columns, height=beams, az0=float(np.float32(-0.5 * a)),
+                     az_step=float(np.float32(a / columns)), elevations=el, near_range=float(np.float32(near)))
+
+
+def sensor_viewmats(rng: np.random.Generator, n: int, r_lo: float, r_hi: float, z: float = 0.0) -> np.ndarray:
+    """n level sensors at radius U[r_lo, r_hi] from the z axis, height z,
+    random heading.  World -> sensor [R^T | -R^T c], (n, 3, 4) float32."""
+    out = np.empty((n, 3, 4), np.float64)
+    ang = rng.uniform(0.0, 2.0 * math.pi, n)
+    rad = rng.uniform(r_lo, r_hi, n) if r_hi > r_lo else np.full(n, r_lo)
+    yaw = rng.uniform(-math.pi, math.pi, n)
+    for k in range(n):
+        c = np.array([rad[k] * math.cos(ang[k]), rad[k] * math.sin(ang[k]), z])
+        cy, sy = math.cos(yaw[k]), math.sin(yaw[k])
+        R = np.array([[cy, -sy, 0.0], [sy, cy, 0.0], [0.0, 0.0, 1.0]])       # sensor axes in world
+        out[k, :, :3] = R.T
+        out[k, :, 3] = -R.T @ c
+    return out.astype(np.float32)
+
+
+# --------------------------------------------------------------------------
 # the five workloads
 # --------------------------------------------------------------------------
 

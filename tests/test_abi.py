@@ -105,7 +105,8 @@ def test_struct_layouts_match_header():
     pairs = [(gsr.Options, "gsr_options"), (gsr.TuningDesc, "gsr_tuning"), (gsr.SceneDesc, "gsr_scene_desc"),
              (gsr.CameraDesc, "gsr_camera"), (gsr.ObsDesc, "gsr_observation"), (gsr.RenderDesc, "gsr_render_desc"),
              (gsr.BinsOut, "gsr_bins_out"), (gsr.ProjOut, "gsr_proj_out"), (gsr.ServerCfg, "gsr_server_cfg"),
-             (gsr.ReqInfo, "gsr_req_info"), (gsr.Stats, "gsr_stats")]
+             (gsr.ReqInfo, "gsr_req_info"), (gsr.Stats, "gsr_stats"), (gsr.LidarDesc, "gsr_lidar"),
+             (gsr.LidarRenderDesc, "gsr_lidar_desc")]
     lay = _c_layout([(cn, [f for f, _ in py._fields_]) for py, cn in pairs])
     for py, cn in pairs:
         assert C.sizeof(py) == lay[cn], cn

@@ -1,0 +1,133 @@
+"""GPU parity of the batch LiDAR: ranges and hit probabilities of a rotating
+and a body-mounted solid-state sensor against the float64 per-ray oracle
+(every ray against every Gaussian), plus the full-turn seam and invalid
+arguments."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lidar_ref
+from paper_2604_25459_amd import synth
+from tests.scenes import scene_from
+
+pytestmark = pytest.mark.gpu
+
+HIT_TOL = 1e-3
+RANGE_REL = 1e-3
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def R():
+    _torch()
+    from paper_2604_25459_amd import gsr
+    r = gsr.Renderer(0)
+    yield r
+    r.close()
+
+
+def _tensors(batch):
+    import torch
+    dev = torch.device("cuda", 0)
+    return (torch.from_numpy(np.ascontiguousarray(batch.viewmats, np.float32)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(batch.poses, np.float32)).to(dev))
+
+
+def _compare(got_range, got_hit, ref, label, min_hits=20):
+    ok = ~ref.flagged
+    e_hit = np.abs(got_hit - ref.hit)
+    e_rng = np.abs(got_range - ref.range) / np.maximum(1.0, ref.range)
+    print(f"[{label}] rays {ok.size} flagged {int((~ok).sum())} hits {int((ref.hit > 0).sum())} "
+          f"max hit err {e_hit[ok].max():.2e} max range rel err {e_rng[ok].max():.2e}", flush=True)
+    assert (~ok).mean() < 0.05
+    assert e_hit[ok].max() <= HIT_TOL
+    assert e_rng[ok].max() <= RANGE_REL
+    assert (ref.hit > 0.1).sum() >= min_hits   # the scans see something
+
+
+def test_lidar_rotating_and_mounted_match_oracle(R):
+    from paper_2604_25459_amd import gsr
+    scene = synth.make_scene(51, 4_000, 3, 800, sh_degree=0, half_box=3.0)
+    rng = np.random.default_rng(6)
+    E = 3
+    rot = synth.rotating_lidar(16, 128, -20, 20)
+    sec = synth.sector_lidar(8, 64, 70, -25, 15)
+    sec.attach_body = 1
+    # mounted sensor: 0.8 m behind body 1's origin, looking at it, heading jittered per env
+    off = np.zeros((E, 3, 4), np.float32)
+    for e in range(E):
+        yaw = rng.uniform(-0.3, 0.3)
+        Rm = np.array([[math.cos(yaw), -math.sin(yaw), 0], [math.sin(yaw), math.cos(yaw), 0], [0, 0, 1]])
+        c = np.array([-0.8, 0.0, 0.2])
+        off[e, :, :3] = Rm.T
+        off[e, :, 3] = -Rm.T @ c
+    vm = np.stack([synth.sensor_viewmats(rng, E, 0.5, 2.5, 0.1), off])
+    poses = synth.random_poses(rng, E, scene.n_bodies)
+    batch = synth.LidarBatch(cams=[rot, sec], viewmats=vm, poses=poses)
+    sid = R.add_synth_scene(scene)
+    vm_t, poses_t = _tensors(batch)
+    out = R.render_lidar(sid, [rot, sec], vm_t, poses_t)
+    for l, e in ((0, 0), (0, 2), (1, 1)):
+        ref = lidar_ref(scene, batch, l, e)
+        _compare(out[l][0][e].cpu().numpy(), out[l][1][e].cpu().numpy(), ref, f"lidar {l} env {e}")
+    # the same scans again: deterministic
+    again = R.render_lidar(sid, [rot, sec], vm_t, poses_t)
+    import torch
+    for (r0, h0), (r1, h1) in zip(out, again):
+        assert torch.equal(r0, r1) and torch.equal(h0, h1)
+    R.remove_scene(sid)
+
+
+def test_lidar_seam_and_near_sensor(R):
+    # a splat straddling the seam behind the sensor, and one that encloses the sensor
+    scene = scene_from([[-3.0, 0.0, 0.0], [0.05, 0.0, 0.0], [2.0, 1.0, 0.3]], [[0.3, 0.3, 0.3], [0.4, 0.4, 0.4],
+                                                                              [0.2, 0.05, 0.1]],
+                       opac=[0.8, 0.3, 0.9], degree=0)
+    lid = synth.rotating_lidar(8, 96, -30, 30, near=0.05)
+    vm = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1).astype(np.float32).reshape(1, 1, 3, 4)
+    batch = synth.LidarBatch(cams=[lid], viewmats=vm, poses=np.zeros((1, 0, 7), np.float32))
+    sid = R.add_synth_scene(scene)
+    vm_t, poses_t = _tensors(batch)
+    out = R.render_lidar(sid, [lid], vm_t, poses_t)
+    ref = lidar_ref(scene, batch, 0, 0)
+    _compare(out[0][0][0].cpu().numpy(), out[0][1][0].cpu().numpy(), ref, "seam", min_hits=5)
+    assert ref.hit[4, 0] > 0.3 and ref.hit[4, -1] > 0.3
+    R.remove_scene(sid)
+
+
+def test_lidar_invalid_arguments(R):
+    from paper_2604_25459_amd import gsr
+    scene = synth.make_scene(52, 500, 1, 100, sh_degree=0)
+    sid = R.add_synth_scene(scene)
+    rng = np.random.default_rng(1)
+    good = synth.rotating_lidar(4, 32, -10, 10)
+    vm = synth.sensor_viewmats(rng, 2, 1.0, 2.0)[None]
+    poses = synth.random_poses(rng, 2, 1)
+    vm_t, poses_t = _tensors(synth.LidarBatch(cams=[good], viewmats=vm, poses=poses))
+    bad_cases = []
+    b = synth.rotating_lidar(4, 32, -10, 10)
+    b.elevations = b.elevations[::-1].copy()           # descending
+    bad_cases.append(b)
+    b = synth.rotating_lidar(4, 32, -10, 10)
+    b.az_step = 1.0                                    # 32 rad > one turn
+    bad_cases.append(b)
+    b = synth.rotating_lidar(4, 32, -10, 10)
+    b.attach_body = 1                                  # the scene has one body
+    bad_cases.append(b)
+    b = synth.rotating_lidar(4, 32, -10, 10)
+    b.near_range = 0.0
+    bad_cases.append(b)
+    for bad in bad_cases:
+        with pytest.raises(gsr.GsrError) as ei:
+            R.render_lidar(sid, [bad], vm_t, poses_t)
+        assert ei.value.code == gsr.GSR_E_INVALID
+    R.render_lidar(sid, [good], vm_t, poses_t)         # and the good one still renders
+    _torch().cuda.synchronize()
+    R.remove_scene(sid)

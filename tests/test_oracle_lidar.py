@@ -1,0 +1,137 @@
+"""Pins of the batch-LiDAR oracle (CPU): closed forms for single and stacked
+Gaussians on a ray, the peak found by a dense line search (independent of the
+closed-form t*), rigid co-motion of a body-mounted sensor, and the seam of a
+full turn."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lidar_ref
+from oracle.lidar import ray_directions
+from paper_2604_25459_amd import synth
+from tests.scenes import quat_axis_angle, scene_from
+
+IDENT = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1).astype(np.float32)
+
+
+def _batch(lid, viewmat=IDENT, poses=None, n_bodies=0):
+    if poses is None:
+        poses = np.zeros((1, n_bodies, 7), np.float32)
+        poses[..., 0] = 1
+    return synth.LidarBatch(cams=[lid], viewmats=np.asarray(viewmat, np.float32).reshape(1, 1, 3, 4),
+                            poses=np.asarray(poses, np.float32).reshape(1, -1, 7))
+
+
+def _one_beam(el_deg=(0.0,), width=8):
+    """Beams at the given elevations, columns such that column width//2 looks along +x."""
+    step = 2 * math.pi / width
+    return synth.LidarSpec(width=width, height=len(el_deg), az0=float(np.float32(-math.pi)),
+                           az_step=float(np.float32(step)),
+                           elevations=np.radians(np.asarray(el_deg)).astype(np.float32), near_range=0.05)
+
+
+def test_isotropic_gaussian_on_the_ray():
+    # ray of column 4 (azimuth -pi + 4.5 step) straight at a Gaussian on it: q = 0, alpha = o
+    lid = _one_beam(width=8)
+    az = -math.pi + 4.5 * 2 * math.pi / 8
+    D, sigma, o = 3.0, 0.1, 0.7
+    mean = D * np.array([math.cos(az), math.sin(az), 0.0])
+    scene = scene_from([mean], [sigma] * 3, opac=o, degree=0)
+    ref = lidar_ref(scene, _batch(lid))
+    assert ref.hit[0, 4] == pytest.approx(o, abs=1e-6)
+    assert ref.range[0, 4] == pytest.approx(D, rel=1e-6)
+    assert ref.hit[0, 0] == 0.0 and ref.range[0, 0] == 0.0        # the opposite direction sees nothing
+
+
+@pytest.mark.parametrize("el_deg", [0.5, 1.0, 2.0])
+def test_offset_ray_closed_form(el_deg):
+    # Gaussian on +x at distance D, ray at elevation phi: closest approach h = D sin phi at t* = D cos phi
+    lid = synth.LidarSpec(width=4, height=1, az0=float(np.float32(-math.pi)), az_step=float(np.float32(math.pi / 2)),
+                          elevations=np.array([math.radians(el_deg)], np.float32), near_range=0.05)
+    # column 2 has azimuth -pi + 2.5 * pi/2 = pi/4; rotate the Gaussian onto that azimuth
+    az = -math.pi + 2.5 * math.pi / 2
+    D, sigma, o = 4.0, 0.08, 0.9
+    mean = D * np.array([math.cos(az), math.sin(az), 0.0])
+    scene = scene_from([mean], [sigma] * 3, opac=o, degree=0)
+    ref = lidar_ref(scene, _batch(lid))
+    phi = float(np.float32(math.radians(el_deg)))
+    h = D * math.sin(phi)
+    a = min(0.99, o * math.exp(-0.5 * h * h / sigma ** 2))
+    if a >= 1 / 255:
+        assert ref.hit[0, 2] == pytest.approx(a, rel=1e-5)
+        assert ref.range[0, 2] == pytest.approx(D * math.cos(phi), rel=1e-6)
+    else:
+        assert ref.hit[0, 2] == 0.0
+
+
+def test_two_gaussians_stacked_on_a_ray():
+    lid = _one_beam(width=8)
+    az = -math.pi + 4.5 * 2 * math.pi / 8
+    u = np.array([math.cos(az), math.sin(az), 0.0])
+    (D1, o1), (D2, o2) = (2.0, 0.6), (5.0, 0.5)
+    scene = scene_from([D2 * u, D1 * u], [0.1] * 3, opac=[o2, o1], degree=0)   # far one first in storage
+    ref = lidar_ref(scene, _batch(lid))
+    hit = 1 - (1 - o1) * (1 - o2)
+    assert ref.hit[0, 4] == pytest.approx(hit, abs=1e-6)
+    assert ref.range[0, 4] == pytest.approx((D1 * o1 + D2 * o2 * (1 - o1)) / hit, rel=1e-6)
+    np.testing.assert_array_equal(ref.order, [1, 0])                             # nearer centre first
+
+
+def test_peak_matches_dense_line_search():
+    """t* and q(t*) of the closed form against a dense search along the ray
+    for anisotropic, rotated Gaussians."""
+    rng = np.random.default_rng(3)
+    lid = synth.rotating_lidar(6, 24, -10, 10)
+    n = 5
+    means = rng.uniform([1.5, -1.5, -0.3], [3.0, 1.5, 0.3], (n, 3))
+    scales = np.exp(rng.normal(math.log(0.3), 0.5, (n, 3)))
+    q = rng.standard_normal((n, 4))
+    scene = scene_from(means, scales, q, opac=0.95, degree=0)
+    d = ray_directions(lid).reshape(-1, 3)
+    from oracle.attrs64 import quat_to_rot64
+    for g in range(n):
+        single = scene_from(means[g:g + 1], scales[g:g + 1], q[g:g + 1], opac=0.95, degree=0)
+        ref = lidar_ref(single, _batch(lid))
+        R = quat_to_rot64(np.asarray(single.quats, np.float64))[0]
+        S = np.asarray(single.scales, np.float64)[0]
+        m = np.asarray(single.means, np.float64)[0]
+        ts = np.linspace(0.05, 8.0, 200001)
+        for k in range(0, d.shape[0], 7):
+            x = ts[:, None] * d[k][None] - m[None]
+            qq = np.sum(((x @ R) / S) ** 2, axis=1)
+            j = int(np.argmin(qq))
+            a = min(0.99, 0.95 * math.exp(-0.5 * qq[j]))
+            r, c = divmod(k, lid.width)
+            if a >= 1 / 255 * 1.01:
+                assert ref.hit[r, c] == pytest.approx(a, rel=2e-3)
+                assert ref.range[r, c] == pytest.approx(ts[j], abs=1e-3)
+            elif a < 1 / 255 * 0.99:
+                assert ref.hit[r, c] == 0.0
+
+
+def test_body_mounted_sensor_co_moves():
+    rng = np.random.default_rng(9)
+    n = 200
+    means = rng.uniform(-0.25, 0.25, (n, 3)) + np.array([1.5, 0.0, 0.0])
+    scene = scene_from(means, np.exp(rng.normal(math.log(0.03), 0.3, (n, 3))), rng.standard_normal((n, 4)),
+                       1 / (1 + np.exp(-rng.standard_normal(n))), degree=0, body_offsets=[0, n])
+    lid = synth.sector_lidar(8, 32, 60, -10, 10)
+    lid.attach_body = 0
+    out = []
+    for ax, ang, t in (([1, 0, 0], 0.0, [0, 0, 0]), ([0.2, 0.5, -0.7], 1.3, [3.0, -2.0, 1.0])):
+        poses = np.array([[[*quat_axis_angle(ax, ang), *t]]], np.float32)
+        out.append(lidar_ref(scene, _batch(lid, IDENT, poses)))
+    np.testing.assert_allclose(out[0].hit, out[1].hit, atol=1e-5)
+    np.testing.assert_allclose(out[0].range, out[1].range, rtol=1e-5, atol=1e-6)
+
+
+def test_full_turn_seam():
+    # a Gaussian straight behind the sensor (azimuth pi) lies on the seam of the grid:
+    # the first and the last column both see it
+    lid = synth.rotating_lidar(1, 64, 0, 0)
+    lid.elevations = np.zeros(1, np.float32)
+    scene = scene_from([[-3.0, 0.0, 0.0]], [0.2] * 3, opac=0.8, degree=0)
+    ref = lidar_ref(scene, _batch(lid))
+    assert ref.hit[0, 0] > 0.5 and ref.hit[0, -1] > 0.5
+    assert ref.hit[0, 0] == pytest.approx(ref.hit[0, -1], rel=1e-6)
