@@ -207,6 +207,7 @@ def main():
                     help="first copy 1 GiB device to device (calibrates the memory counters)")
     ap.add_argument("--no-count", action="store_true", help="skip the counting renders of the roofline")
     ap.add_argument("--obs-steps", type=int, default=3, help="steps timed with the u8 observation epilogue (0 = skip)")
+    ap.add_argument("--lidar-steps", type=int, default=3, help="steps of the batch-LiDAR leg (0 = skip)")
     ap.add_argument("--no-graphs", action="store_true", help="launch every stage eagerly (no graph replay)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary of two rocprofv3 --pmc runs of this bench and exit")
@@ -308,6 +309,33 @@ def main():
         del obs_out
         log(f"[bench] observation path (u8 + randomisation) {observation['value']:.1f} env-frames/s")
 
+    # batch LiDAR on the same scene and poses: one rotating 32 x 1024 sensor per env
+    lidar = None
+    if args.lidar_steps:
+        lid = synth.rotating_lidar(32, 1024, -25.0, 15.0)
+        lrng = np.random.default_rng(11)
+        lvm = torch.from_numpy(synth.sensor_viewmats(lrng, E, 0.5, 3.0, 0.2)[None]).to(dev)
+        n_rays = E * lid.width * lid.height
+        l_range = torch.empty(n_rays, dtype=torch.float32, device=dev)
+        l_hit = torch.empty(n_rays, dtype=torch.float32, device=dev)
+        R.render_lidar_into(sid, [lid], lvm, poses[args.warmup], l_range, l_hit)
+        torch.cuda.synchronize()
+        R.stage_times(reset=True)
+        t0 = time.perf_counter()
+        for s in range(args.lidar_steps):
+            R.render_lidar_into(sid, [lid], lvm, poses[args.warmup + s % args.steps], l_range, l_hit)
+        torch.cuda.synchronize()
+        lsec = time.perf_counter() - t0
+        lst = R.stage_times(reset=True)
+        lidar = {"value": E * args.lidar_steps / lsec, "unit": "env-scans/s",
+                 "rays_per_s": n_rays * args.lidar_steps / lsec, "steps": args.lidar_steps,
+                 "sensor": "rotating, 32 beams [-25, 15] deg x 1024 columns", "envs": E,
+                 "ms_per_step": 1000.0 * lsec / args.lidar_steps,
+                 "stages_ms_per_step": {k: v / args.lidar_steps for k, v in lst.items() if k in R.STAGES},
+                 "hit_fraction": float((l_hit > 0.5).float().mean())}
+        del l_range, l_hit
+        log(f"[bench] LiDAR {lidar['value']:.1f} env-scans/s ({lidar['rays_per_s'] / 1e9:.2f} G rays/s)")
+
     # plain per-env path on a subset (same GPU, same kernels, one image per launch chain)
     plain = None
     if args.plain_envs:
@@ -402,6 +430,7 @@ def main():
                    "tuning": tuning},
         "plain_path": plain,
         "observation_path": observation,
+        "lidar": lidar,
         "serving": serving,
         "stages_ms_per_step": {k: v / args.steps for k, v in st.items() if k in R.STAGES},
         "path": path,

@@ -538,7 +538,7 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
 {
     if (job_in.imgs.empty()) return GSR_OK;
     RenderJob job = job_in;
-    const size_t rec_bytes = job.lidar ? 64 : 48;
+    const size_t rec_bytes = job.lidar ? 80 : 48;
     const ChunkPlan plan = plan_chunks(ctx, sc, job.imgs, plain, job.tune.chunk_images, rec_bytes);
     // buffers may be reallocated: earlier work on this workspace must be finished
     if (ws.used) GSR_HIP_TRY(hipEventSynchronize(ws.ev_done));

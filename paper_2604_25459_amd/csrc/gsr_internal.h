@@ -85,7 +85,7 @@ struct ChunkDev {
     float* xform;              // [n_img][n_bodies + 1][16]
     uint32_t* keyz;            // [n_img][n] depth bits or kInvalidKey
     uint2* rect;               // [n_img][n] (x0 | x1 << 16, y0 | y1 << 16)
-    float4* rec;               // [n_img][n][3] raster records ([..][4] for LiDAR)
+    float4* rec;               // [n_img][n][3] raster records ([..][5] for LiDAR)
     uint32_t* sk[2];           // depth-sort keys, ping-pong [n_img][n]
     uint32_t* sv[2];           // depth-sort values (Gaussian ids); sorted result in sv[1]
     uint2* srect;              // [n_img][n] tile rectangle of the j-th depth-ordered Gaussian
@@ -122,7 +122,7 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
 // Tile and tile-row histograms, ranges, image bases (before the host reads the totals).
 hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t stream);
 // LiDAR: projection into the ray grid (keys = centre distance, conservative
-// angular tile rectangles, 64-byte whitening records) and per-ray compositing.
+// angular tile rectangles, 80-byte whitening and cone records) and per-ray compositing.
 hipError_t launch_project_lidar(const SceneDev& s, const ChunkDev& c, int ts, int ipt, hipStream_t stream);
 
 // Stable two-level scatter: depth-ordered Gaussians -> tile-row lists -> tile lists.

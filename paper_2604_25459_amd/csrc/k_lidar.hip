@@ -14,7 +14,8 @@
 //     functions; a cone across the seam of a full turn takes the hull of its
 //     two column ranges, a sensor inside the sphere takes the whole grid;
 //   * record: whitening W = S^-1 R^T (R, S the Gaussian's rotation in the
-//     sensor frame and its scales), the centre t, log2 o and W t.
+//     sensor frame and its scales), the centre t, log2 o and W t, and the
+//     cone (centre direction, cosine of the half-angle) for wave culling.
 // Raster (one workgroup per tile of rays, one ray per thread): for each
 // listed Gaussian, d' = W d, t* = (d' . W t) / |d'|^2 (the peak of the
 // Gaussian along the ray), q = |W (t - t* d)|^2 (the offset taken in metres
@@ -31,6 +32,7 @@ namespace {
 constexpr float kLidarLogAlphaMin = -7.99435343685886f;   // log2(1/255)
 constexpr float kHalfPi = 1.5707963267948966f;
 constexpr float kTwoPi = 6.283185307179586f;
+constexpr int kLidarRec = 5;        // float4s per record: whitening rows + centre, log2 o + W t, cone
 
 // First index r in [0, H) with v[r] >= x (strict = false) or v[r] > x
 // (strict = true), v ascending; H if none.
@@ -95,6 +97,7 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
         const bool ok = isfinite(tx) && isfinite(ty) && isfinite(tz) && op >= 1.0f / 255.0f && D > 0.0f &&
                         isfinite(D) && sc[0] > 0.0f && sc[1] > 0.0f && sc[2] > 0.0f;
         int r0 = 0, r1 = 0, c0 = 0, c1 = 0;
+        float cone_c = -2.0f;                           // cosine of the cone half-angle; -2 = every direction
         if (ok) {
             if (D <= rho * 1.001f + 1e-6f) {            // the sensor may sit inside: every ray
                 r0 = 0;
@@ -103,6 +106,7 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
                 c1 = im.width;
             } else {
                 const float ang = asinf(rho / D) * 1.0001f + 2e-6f;
+                cone_c = cosf(ang);
                 const float el = asinf(fminf(1.0f, fmaxf(-1.0f, tz / D)));
                 r0 = first_at_least(im.elev, im.height, el - ang, false);   // rows with el - ang <= elev
                 r1 = first_at_least(im.elev, im.height, el + ang, true);    // ... <= el + ang
@@ -150,21 +154,28 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
         const float w0 = (W[0] * tx + W[1] * ty) + W[2] * tz;
         const float w1 = (W[3] * tx + W[4] * ty) + W[5] * tz;
         const float w2 = (W[6] * tx + W[7] * ty) + W[8] * tz;
-        float4* rec = c.rec + 4 * o;
+        float4* rec = c.rec + kLidarRec * o;
         rec[0] = make_float4(W[0], W[1], W[2], tx);
         rec[1] = make_float4(W[3], W[4], W[5], ty);
         rec[2] = make_float4(W[6], W[7], W[8], tz);
         rec[3] = make_float4(log2o, w0, w1, w2);
+        const float iD = 1.0f / D;
+        rec[4] = make_float4(tx * iD, ty * iD, tz * iD, cone_c);
     }
 }
 
 // One workgroup per TS x TS tile of rays; batches of kLBatch records in LDS.
+// Wave-level culling: each wave bounds its rays by a cone (axis = their
+// normalised mean direction, half-angle beta = the widest ray), and a
+// Gaussian survives when its own cone (half-angle alpha around its centre
+// direction, as used for the tile rectangle) comes within alpha + beta of
+// that axis; only survivors are evaluated, bit by bit of the wave's ballot.
 template <int TS>
 __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c, RasterParams p)
 {
     constexpr int NT = TS * TS;
     constexpr int kLBatch = NT;
-    __shared__ float4 sr[4][kLBatch];
+    __shared__ float4 sr[kLidarRec][kLBatch];
     const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
     int sgi = 0;
 #pragma unroll
@@ -178,7 +189,7 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
     const ImageInfo im = c.img[i];
     const int tx = (int)(t % (uint32_t)im.tiles_x);
     const int ty = (int)(t / (uint32_t)im.tiles_x);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = __lane_id();
     const int col = tx * TS + (tid % TS), row = ty * TS + (tid / TS);
     const bool inside = col < im.width && row < im.height;
     float d[3] = {0.0f, 0.0f, 0.0f};
@@ -192,15 +203,33 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
         d[1] = ce * sa;
         d[2] = se;
     }
+    // the wave's cone: axis w, cos / sin of its half-angle (culling off when wider than 90 degrees)
+    float w[3] = {d[0], d[1], d[2]};
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[k] += __shfl_xor(w[k], m, 64);
+    const float wn = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    bool cull = wn > 0.0f;
+    if (cull)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[k] /= wn;
+    float cb = inside ? d[0] * w[0] + d[1] * w[1] + d[2] * w[2] : 1.0f;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) cb = fminf(cb, __shfl_xor(cb, m, 64));
+    cb = cb - 1e-5f;                                  // rounding of the directions and of the axis
+    cull = cull && cb > 0.0f;
+    const float sb = sqrtf(fmaxf(0.0f, 1.0f - cb * cb));
+
     bool live = inside;
     float T = 1.0f, Rg = 0.0f;
     const float near = im.near_plane;
-
     const uint32_t* R = c.tile_range + ((size_t)i * c.t_max + t) * 2;
     const uint32_t start = R[0], end = R[1];
     const uint32_t* list = c.pairs + c.pair_base[i];
-    const float4* rec = c.rec + (size_t)i * (size_t)s.n * 4;
+    const float4* rec = c.rec + (size_t)i * (size_t)s.n * kLidarRec;
     const uint32_t n = (uint32_t)s.n;
+    bool wave_live = __ballot(live) != 0ull;
     for (uint32_t b0 = start; b0 < end; b0 += kLBatch) {
         __syncthreads();
         const uint32_t e = b0 + (uint32_t)tid;
@@ -208,12 +237,27 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
             uint32_t g = list[e];
             if (g >= n) g = 0;          // guard: list entries are valid indices by construction
 #pragma unroll
-            for (int k = 0; k < 4; ++k) sr[k][tid] = rec[4 * (size_t)g + k];
+            for (int k = 0; k < kLidarRec; ++k) sr[k][tid] = rec[kLidarRec * (size_t)g + k];
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)kLBatch, end - b0);
-        if (live) {
-            for (int j = 0; j < cnt; ++j) {
+        for (int sub = 0; sub < cnt && wave_live; sub += 64) {
+            const int jl = sub + lane;
+            bool keep = false;
+            if (jl < cnt) {
+                const float4 cn = sr[4][jl];
+                if (!cull || cn.w < -1.5f) {
+                    keep = true;
+                } else {
+                    const float sa = sqrtf(fmaxf(0.0f, 1.0f - cn.w * cn.w));
+                    keep = cn.x * w[0] + cn.y * w[1] + cn.z * w[2] >= cn.w * cb - sa * sb - 1e-6f;
+                }
+            }
+            uint64_t mask = __ballot(keep);
+            while (mask) {
+                const int j = sub + (int)__builtin_ctzll(mask);
+                mask &= mask - 1ull;
+                if (!live) continue;
                 const float4 m0 = sr[0][j], m1 = sr[1][j], m2 = sr[2][j], m3 = sr[3][j];
                 // d' = W d
                 const float dx = fmaf(m0.z, d[2], fmaf(m0.y, d[1], m0.x * d[0]));
@@ -238,13 +282,11 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
                 const bool add = take && !stop;
                 Rg = add ? fmaf(tstar, alpha * T, Rg) : Rg;
                 T = add ? Tn : T;
-                if (stop) {
-                    live = false;
-                    break;
-                }
+                live = live && !stop;
             }
+            if (__ballot(live) == 0ull) wave_live = false;
         }
-        if (__syncthreads_count(live ? 1 : 0) == 0) break;
+        if (__syncthreads_count(wave_live && lane == 0 ? 1 : 0) == 0) break;
     }
     if (inside) {
         const size_t pix = (size_t)row * im.width + col;
