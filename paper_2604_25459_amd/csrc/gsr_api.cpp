@@ -77,7 +77,7 @@ Workspace::~Workspace()
 {
     for (DevBuf* b : {&img, &xform, &keyz, &rect, &srect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &vis_count,
                       &tile_hist, &tile_range, &pair_count, &pair_base, &pairs, &row_hist, &row_range, &row_count,
-                      &row_base, &rows, &debug, &stage_vm, &stage_pose, &stage_elev})
+                      &row_base, &rows, &debug, &stage_vm, &stage_pose, &stage_elev, &seg_off})
         b->release();
     if (h_total) (void)hipHostFree(h_total);
     if (h_img) (void)hipHostFree(h_img);
@@ -470,9 +470,21 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     }
     c.pairs = ws.pairs.as<uint32_t>();
     c.rows = ws.rows.as<uint2>();
+    // long tile-row lists are split into segments of about 4096 entries (one wave each)
+    const uint64_t n_rows = (uint64_t)n_img * (uint64_t)c.ty_max;
+    const uint64_t per_row = n_rows ? row_total / n_rows : 0;
+    const int n_seg = (int)std::min<uint64_t>(32, std::max<uint64_t>(1, (per_row + 4095) / 4096));
+    uint32_t* seg_off = nullptr;
+    if (n_seg > 1 && tu.bin == 0) {
+        GSR_HIP_TRY(ws.seg_off.ensure(n_rows * (uint64_t)n_seg * (uint64_t)c.tx_max * 4));
+        seg_off = ws.seg_off.as<uint32_t>();
+    }
     key.push_back((uint64_t)(uintptr_t)c.pairs);
     key.push_back((uint64_t)(uintptr_t)c.rows);
-    rc = run_stage(ws, graph, chunk_idx, 3, key, st, [&](hipStream_t q) { return launch_tile_scatter(s, c, tu.bin, q); });
+    key.push_back((uint64_t)n_seg);
+    key.push_back((uint64_t)(uintptr_t)seg_off);
+    rc = run_stage(ws, graph, chunk_idx, 3, key, st,
+                   [&](hipStream_t q) { return launch_tile_scatter(s, c, tu.bin, n_seg, seg_off, q); });
     if (rc) return rc;
     if (mode == Mode::kBins) return GSR_OK;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[4], st));

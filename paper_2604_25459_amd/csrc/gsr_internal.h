@@ -129,7 +129,10 @@ hipError_t launch_project_lidar(const SceneDev& s, const ChunkDev& c, int ts, in
 // schedule 0: level 2 as a stable scatter (one wave per tile row, ballot
 // ranks); 1: by a bit transpose (one lane per tile column appends the window
 // entries that cover it).  Both give identical tile lists.
-hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedule, hipStream_t stream);
+// n_seg: segments per tile-row list for schedule 0 (seg_off: n_img * ty_max *
+// n_seg * tx_max words of scratch when n_seg > 1).
+hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedule, int n_seg, uint32_t* seg_off,
+                               hipStream_t stream);
 struct RasterParams {
     int ts;                  // tile side: 8, 16 or 32
     int batch;               // records staged in LDS per round

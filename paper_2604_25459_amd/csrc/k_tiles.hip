@@ -28,6 +28,8 @@
 //   k_tile_scan       per image: tile ranges, row ranges, per-block row offsets
 //   k_image_scan      pair and row-entry bases of every image of the chunk
 //   k_row_scatter     level 1
+//   k_rowseg_count    level 2, per-segment tile counts of long rows
+//   k_rowseg_scan     level 2, first output position of each segment per tile
 //   k_rowtile_scatter level 2
 #include "gsr_internal.h"
 
@@ -364,29 +366,101 @@ __global__ __launch_bounds__(64) void k_row_scatter(ChunkDev c, uint64_t n, int 
 }
 
 // ------------------------------------------------------------------ level 2
-// Block (y * n_groups + cg, i): tile row y of image i, tile columns
-// [cg * ceil(TX / n_groups), ...) -- every column group walks the whole row
-// list and emits only its own columns' pairs, with its own cursors.
-__global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, int col_bits, int n_groups)
+// A long tile-row list is cut into n_seg consecutive segments, one wave
+// each.  k_rowseg_count counts each segment's pairs per tile column (a
+// difference array over the columns: +1 at x0, -1 at x1 per entry);
+// k_rowseg_scan turns the counts, per tile, into each segment's first output
+// position (the tile's range start plus the pairs of the earlier segments),
+// so that the segments scatter independently and together keep every tile
+// list in row-list order.  With one segment the tile range starts are used
+// directly.
+__device__ __forceinline__ void segment_of(uint32_t r0, uint32_t r1, int sg, int n_seg, uint32_t* s0, uint32_t* s1)
+{
+    const uint64_t len = r1 - r0;
+    *s0 = r0 + (uint32_t)(len * (uint64_t)sg / (uint64_t)n_seg);
+    *s1 = r0 + (uint32_t)(len * (uint64_t)(sg + 1) / (uint64_t)n_seg);
+}
+
+__global__ __launch_bounds__(64) void k_rowseg_count(ChunkDev c, int n_seg, uint32_t* __restrict__ seg_off)
+{
+    extern __shared__ int32_t diff[];       // [TX + 1]
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
+    const int y = bx / n_seg, sg = bx - y * n_seg;
+    const ImageInfo im = c.img[i];
+    if (y >= im.tiles_y) return;
+    const int TX = im.tiles_x;
+    for (int x = lane; x <= TX; x += 64) diff[x] = 0;
+    __syncthreads();
+    const uint32_t* rr = c.row_range + ((size_t)i * c.ty_max + y) * 2;
+    uint32_t s0, s1;
+    segment_of(rr[0], rr[1], sg, n_seg, &s0, &s1);
+    const uint2* list = c.rows + c.row_base[i];
+    for (uint32_t e = s0 + (uint32_t)lane; e < s1; e += 64) {
+        const uint32_t xr = list[e].y;
+        const uint32_t x0 = min(xr & 0xFFFFu, (uint32_t)TX), x1 = min(xr >> 16, (uint32_t)TX);
+        if (x1 > x0) {
+            atomicAdd(&diff[x0], 1);
+            atomicAdd(&diff[x1], -1);
+        }
+    }
+    __syncthreads();
+    uint32_t* out = seg_off + (((size_t)i * c.ty_max + y) * n_seg + sg) * c.tx_max;
+    int32_t carry = 0;
+    for (int x0 = 0; x0 < TX; x0 += 64) {
+        const int x = x0 + lane;
+        const int32_t v = x < TX ? diff[x] : 0;
+        const int32_t inc = (int32_t)wave_incl_scan((uint32_t)v) + carry;
+        if (x < TX) out[x] = (uint32_t)inc;
+        carry = __shfl(inc, 63, 64);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_rowseg_scan(ChunkDev c, int n_seg, uint32_t* __restrict__ seg_off)
+{
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int i = (int)(L / gridDim.x), y = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
+    const ImageInfo im = c.img[i];
+    if (y >= im.tiles_y) return;
+    const int TX = im.tiles_x;
+    const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX) * 2;
+    uint32_t* base = seg_off + ((size_t)i * c.ty_max + y) * n_seg * c.tx_max;
+    for (int x = lane; x < TX; x += 64) {
+        uint32_t run = tr[2 * x];
+        for (int sg = 0; sg < n_seg; ++sg) {
+            uint32_t* q = base + (size_t)sg * c.tx_max + x;
+            const uint32_t v = *q;
+            *q = run;
+            run += v;
+        }
+    }
+}
+
+// Block (y * n_seg + sg, i): segment sg of tile row y of image i.
+__global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, int col_bits, int n_seg,
+                                                        const uint32_t* __restrict__ seg_off)
 {
     extern __shared__ uint32_t lds[];
     Group& grp = *reinterpret_cast<Group*>(lds);
     uint32_t* cursor = lds + sizeof(Group) / 4;
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
-    const int y = bx / n_groups, cg = bx - y * n_groups;
+    const int y = bx / n_seg, sg = bx - y * n_seg;
     const ImageInfo im = c.img[i];
     if (y >= im.tiles_y) return;
     const uint32_t TX = (uint32_t)im.tiles_x;
-    const uint32_t gw = (TX + n_groups - 1) / n_groups;
-    const uint32_t c0 = min(TX, (uint32_t)cg * gw), c1 = min(TX, c0 + gw);
-    if (c0 >= c1) return;
     const uint32_t* rr = c.row_range + ((size_t)i * c.ty_max + y) * 2;
-    const uint32_t r0 = rr[0], r1 = rr[1];
+    uint32_t r0, r1;
+    segment_of(rr[0], rr[1], sg, n_seg, &r0, &r1);
     if (r0 >= r1) return;
     const uint2* list = c.rows + c.row_base[i];
-    const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX) * 2;
-    for (uint32_t x = c0 + lane; x < c1; x += 64) cursor[x] = tr[2 * x];
+    if (n_seg == 1) {
+        const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX) * 2;
+        for (uint32_t x = lane; x < TX; x += 64) cursor[x] = tr[2 * x];
+    } else {
+        const uint32_t* so = seg_off + (((size_t)i * c.ty_max + y) * n_seg + sg) * c.tx_max;
+        for (uint32_t x = lane; x < TX; x += 64) cursor[x] = so[x];
+    }
     uint32_t* out = c.pairs + c.pair_base[i];
     const uint32_t P = c.pair_count[i];
     const uint64_t lt = lanemask_lt64();
@@ -397,8 +471,8 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
         if (e < r1) {
             const uint2 ent = list[e];
             g = ent.x;
-            x0 = max(ent.y & 0xFFFFu, c0);
-            const uint32_t x1 = min(ent.y >> 16, c1);
+            x0 = ent.y & 0xFFFFu;
+            const uint32_t x1 = min(ent.y >> 16, TX);
             cnt = x1 > x0 ? x1 - x0 : 0;
         }
         const uint32_t total = publish(grp, cnt, x0, 0, 0, g);
@@ -410,7 +484,7 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
             if (ok) {
                 k = owner(grp, p);
                 x = grp.a[k] + (p - grp.excl[k]);
-                ok = x < c1;
+                ok = x < TX;
             }
             const uint64_t peers = match_key(x, ok, col_bits);
             if (ok) {
@@ -589,7 +663,8 @@ hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedule, hipStream_t stream)
+hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedule, int n_seg, uint32_t* seg_off,
+                               hipStream_t stream)
 {
     if (c.n_img == 0 || s.n == 0) return hipSuccess;
     const uint64_t n = (uint64_t)s.n;
@@ -600,9 +675,15 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
         hipLaunchKernelGGL(k_rowtile_transpose, dim3((unsigned)(c.ty_max * n_cc), (unsigned)c.n_img), dim3(64), 0,
                            stream, c, n_cc);
     } else {
-        const int groups = 1;   // splitting a row into column groups re-reads the row list and measured slower
-        hipLaunchKernelGGL(k_rowtile_scatter, dim3((unsigned)(c.ty_max * groups), (unsigned)c.n_img), dim3(64),
-                           sizeof(Group) + (size_t)c.tx_max * 4, stream, c, n, bits_for(c.tx_max), groups);
+        if (n_seg < 1 || !seg_off) n_seg = 1;
+        const dim3 grid((unsigned)(c.ty_max * n_seg), (unsigned)c.n_img);
+        if (n_seg > 1) {
+            hipLaunchKernelGGL(k_rowseg_count, grid, dim3(64), (size_t)(c.tx_max + 1) * 4, stream, c, n_seg, seg_off);
+            hipLaunchKernelGGL(k_rowseg_scan, dim3((unsigned)c.ty_max, (unsigned)c.n_img), dim3(64), 0, stream, c,
+                               n_seg, seg_off);
+        }
+        hipLaunchKernelGGL(k_rowtile_scatter, grid, dim3(64), sizeof(Group) + (size_t)c.tx_max * 4, stream, c, n,
+                           bits_for(c.tx_max), n_seg, (const uint32_t*)seg_off);
     }
     return hipGetLastError();
 }
