@@ -303,3 +303,37 @@ def test_invalid_render_arguments(R):
         R.render(sid, bad, vm, poses)
     assert ei.value.code == gsr.GSR_E_INVALID
     R.remove_scene(sid)
+
+
+def test_large_image_near_the_tile_limit(R):
+    """1920 x 1080 (8160 tiles of 16, a ragged last tile row) with a dense
+    scene: tile ids, pair offsets and the raster grid at their largest test
+    sizes; tile lists bit-exact, pixels within tolerance."""
+    scene = synth.make_scene(61, 60_000, 2, 5_000, sh_degree=1, half_box=4.0)
+    rng = np.random.default_rng(12)
+    cam = synth.pinhole(1920, 1080, 70.0)
+    batch = synth.Batch(cams=[cam], viewmats=synth.orbit_viewmats(rng, 2, 3.0, 5.0)[None],
+                        poses=synth.random_poses(rng, 2, scene.n_bodies), bg=np.array([0.2, 0.3, 0.4], np.float32))
+    sid = _upload(R, scene)
+    got = _render(R, sid, batch)
+    ref = _check_bins(R, sid, scene, batch, 0, 1)
+    assert ref.ranges.shape[0] == 120 * 68
+    _check_image(_img(got, 0, 1), render_ref(scene, batch, 0, 1, R.tile_size), "1920x1080")
+    R.remove_scene(sid)
+
+
+def test_many_tiny_images_one_launch(R):
+    """4096 environments of 24 x 16 (two ragged tiles each): many images per
+    chunk and per raster segment; sampled images against the oracle."""
+    scene = synth.make_scene(62, 3_000, 2, 500, sh_degree=0, half_box=2.0)
+    rng = np.random.default_rng(13)
+    E = 4096
+    cam = synth.pinhole(24, 16, 60.0)
+    batch = synth.Batch(cams=[cam], viewmats=synth.orbit_viewmats(rng, E, 2.5, 4.0)[None],
+                        poses=synth.random_poses(rng, E, scene.n_bodies))
+    sid = _upload(R, scene)
+    got = _render(R, sid, batch)
+    for e in (0, 1, 2049, E - 1):
+        _check_image(_img(got, 0, e), render_ref(scene, batch, 0, e, R.tile_size), f"tiny env {e}")
+    _check_bins(R, sid, scene, batch, 0, E - 1)
+    R.remove_scene(sid)
