@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--no-count", action="store_true", help="skip the counting renders of the roofline")
     ap.add_argument("--obs-steps", type=int, default=3, help="steps timed with the u8 observation epilogue (0 = skip)")
     ap.add_argument("--lidar-steps", type=int, default=3, help="steps of the batch-LiDAR leg (0 = skip)")
+    ap.add_argument("--no-storage-check", dest="storage_check", action="store_false",
+                    help="skip the FP16/BF16 storage leg (throughput and per-image error)")
     ap.add_argument("--no-graphs", action="store_true", help="launch every stage eagerly (no graph replay)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary of two rocprofv3 --pmc runs of this bench and exit")
@@ -336,6 +338,45 @@ def main():
         del l_range, l_hit
         log(f"[bench] LiDAR {lidar['value']:.1f} env-scans/s ({lidar['rays_per_s'] / 1e9:.2f} G rays/s)")
 
+    # half-precision storage: throughput of the same step, and the per-image
+    # error of every image against the float32-storage render of the same
+    # step (storage error; both are checked against the oracle in the tests)
+    storage = None
+    if args.storage_check and args.storage == "f32":
+        storage = {}
+        ref_rgb = rgb.clone()                    # last timed step, float32 storage
+        last = poses[args.warmup + args.steps - 1]
+        for st_name in ("f16", "bf16"):
+            hsid = R.add_synth_scene(scene, st_name)
+            R.render_into(hsid, cams, vm, last, rgb, depth, None, tuple(batch.bg))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(args.steps):
+                R.render_into(hsid, cams, vm, poses[args.warmup + s], rgb, depth, None, tuple(batch.bg))
+            torch.cuda.synchronize()
+            hsec = time.perf_counter() - t0
+            R.stage_times(reset=True)
+            per_img = []
+            base = 0
+            for cam in cams:                     # per camera slot: [E, H*W*3]
+                n = E * cam.width * cam.height * 3
+                d = (rgb[base:base + n] - ref_rgb[base:base + n]).view(E, -1).double()
+                per_img.append((d.abs().amax(dim=1), d.abs().mean(dim=1), (d * d).mean(dim=1)))
+                base += n
+            mx = torch.cat([p[0] for p in per_img]).cpu().numpy()
+            ma = torch.cat([p[1] for p in per_img]).cpu().numpy()
+            mse = torch.cat([p[2] for p in per_img]).cpu().numpy()
+            psnr = 10.0 * np.log10(1.0 / np.maximum(mse, 1e-30))
+            storage[st_name] = {"value": E * args.steps / hsec, "unit": "env-frames/s",
+                                "scene_bytes": R.scene_info(hsid)[2],
+                                "error_vs_f32_storage_per_image": {
+                                    "images": int(mx.size), "max_abs_max": float(mx.max()),
+                                    "mean_abs_mean": float(ma.mean()), "psnr_db_min": float(psnr.min()),
+                                    "psnr_db_median": float(np.median(psnr))}}
+            R.remove_scene(hsid)
+            log(f"[bench] {st_name} storage: {storage[st_name]}")
+        del ref_rgb
+
     # plain per-env path on a subset (same GPU, same kernels, one image per launch chain)
     plain = None
     if args.plain_envs:
@@ -431,6 +472,7 @@ def main():
         "plain_path": plain,
         "observation_path": observation,
         "lidar": lidar,
+        "half_storage": storage,
         "serving": serving,
         "stages_ms_per_step": {k: v / args.steps for k, v in st.items() if k in R.STAGES},
         "path": path,
