@@ -339,9 +339,26 @@ __global__ __launch_bounds__(64) void k_row_scatter(ChunkDev c, uint64_t n, int 
     const uint32_t Rn = c.row_count[i];
     const uint64_t lt = lanemask_lt64();
     __syncthreads();
+    // the next group's ids and rectangles are fetched while this group is placed
+    const size_t seg = (size_t)i * n;
+    uint32_t g_next = 0;
+    uint2 r_next = make_uint2(0u, 0u);
+    if (j0 + lane < j1) {
+        g_next = c.sv[1][seg + j0 + lane];
+        r_next = c.srect[seg + j0 + lane];
+    }
     for (uint32_t jb = j0; jb < j1; jb += 64) {
-        uint32_t g, x0, x1, y0, y1;
-        const bool okg = sorted_rect(c, n, i, jb + lane, j1, &g, &x0, &x1, &y0, &y1);
+        uint32_t g = g_next;
+        const uint2 r = r_next;
+        const bool in_group = jb + lane < j1;
+        if (jb + 64 + lane < j1) {
+            g_next = c.sv[1][seg + jb + 64 + lane];
+            r_next = c.srect[seg + jb + 64 + lane];
+        }
+        const uint32_t x0 = r.x & 0xFFFFu, x1 = r.x >> 16, y0 = r.y & 0xFFFFu, y1 = r.y >> 16;
+        // guard: sorted ids are valid indices by construction
+        const bool okg = in_group && g < n && x1 > x0 && y1 > y0;
+        if (!okg) g = 0;
         const uint32_t total = publish(grp, okg ? y1 - y0 : 0, y0, x0 | (x1 << 16), 0, g);
         __syncthreads();
         for (uint32_t p0 = 0; p0 < total; p0 += 64) {
@@ -465,11 +482,14 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
     const uint32_t P = c.pair_count[i];
     const uint64_t lt = lanemask_lt64();
     __syncthreads();
+    // the next window of entries is fetched while this one is placed
+    uint2 nxt = r0 + (uint32_t)lane < r1 ? list[r0 + lane] : make_uint2(0u, 0u);
     for (uint32_t e0 = r0; e0 < r1; e0 += 64) {
-        const uint32_t e = e0 + lane;
+        const uint2 ent = nxt;
+        const bool valid = e0 + (uint32_t)lane < r1;
+        if (e0 + 64u + (uint32_t)lane < r1) nxt = list[e0 + 64u + lane];
         uint32_t g = 0, x0 = 0, cnt = 0;
-        if (e < r1) {
-            const uint2 ent = list[e];
+        if (valid) {
             g = ent.x;
             x0 = ent.y & 0xFFFFu;
             const uint32_t x1 = min(ent.y >> 16, TX);
