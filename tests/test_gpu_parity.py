@@ -337,3 +337,25 @@ def test_many_tiny_images_one_launch(R):
         _check_image(_img(got, 0, e), render_ref(scene, batch, 0, e, R.tile_size), f"tiny env {e}")
     _check_bins(R, sid, scene, batch, 0, E - 1)
     R.remove_scene(sid)
+
+
+def test_stage_totals_match_oracle_bins():
+    """The profiled renderer's totals of visible Gaussians and (tile,
+    Gaussian) pairs equal the sums of the oracle's binning over the images."""
+    _torch()
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(1, n_envs=6)
+    r = gsr.Renderer(0, profile=True)
+    sid = r.add_synth_scene(scene)
+    cams, vm, poses = gsr.batch_tensors(batch)
+    r.stage_times(reset=True)
+    r.render(sid, cams, vm, poses)
+    st = r.stage_times(reset=True)
+    vis = pairs = 0
+    for e in range(batch.n_envs):
+        b = bin_ref(scene, batch, 0, e, r.tile_size)
+        vis += int(b.visible.sum())
+        pairs += len(b.keys)
+    assert st["renders"] == 1
+    assert st["visible"] == vis and st["pairs"] == pairs
+    r.close()
