@@ -176,8 +176,8 @@ typedef struct {
     int64_t n;                    /* in: must equal the scene's Gaussian count */
     uint32_t* zkey;               /* [n] float32 bits of camera depth; 0xFFFFFFFF where culled */
     int32_t* rect;                /* [n][4] tile rectangle x0, x1, y0, y1 (half-open); unspecified where culled */
-    float* rec;                   /* [n][12] u, v, A, B, C, log2(o), z, r, R, G, B, 0 where
-                                     log2(alpha) = A dx^2 + B dx dy + C dy^2 + log2(o); unspecified where culled */
+    float* rec;                   /* [n][12] u, v, a1, b1, c1, log2(o), z, r, R, G, B, 0 where
+                                     log2(alpha) = log2(o) - (a1 dx + b1 dy)^2 - (c1 dy)^2; unspecified where culled */
 } gsr_proj_out;
 
 /* ---- context ---------------------------------------------------------
@@ -340,7 +340,7 @@ int gsr_server_destroy(gsr_server* srv);
  * tile_size. */
 typedef struct {
     int tile_size;          /* 8, 16, 32 */
-    int lds_batch;          /* 64/128/256 for 8x8 tiles, 256/512 otherwise */
+    int lds_batch;          /* 64/128/256 for 8x8 tiles, 64/128/256/512 otherwise */
     int images_per_thread;  /* 1..16 */
     int persistent;         /* 0 or 1 */
     int chunk_images;       /* 0 = from chunk_bytes, else images per memory chunk */

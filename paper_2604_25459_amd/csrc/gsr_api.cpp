@@ -305,7 +305,7 @@ Tuning tuning_for(gsr_ctx* ctx, const SceneRes* sc, const gsr_render_desc* d)
     Tuning t;
     t.ts = ctx->opt.tile_size;
     t.ipt = ctx->opt.images_per_thread;
-    t.batch = t.ts == 8 ? 64 : 256;
+    t.batch = 64;                       // 64-record LDS batches: 8 workgroups per CU
     std::lock_guard<std::mutex> lk(ctx->mu);
     auto it = ctx->tuned.find(shape_key(sc, d));
     if (it != ctx->tuned.end()) t = it->second;
@@ -672,7 +672,7 @@ int debug_run(gsr_ctx* ctx, const gsr_render_desc* d, int image, Mode mode, Scen
     }
     *ws_out = ws;
     job->tune.ts = ctx->opt.tile_size;
-    job->tune.batch = ctx->opt.tile_size == 8 ? 64 : 256;
+    job->tune.batch = 64;
     job->tune.ipt = 1;
     job->imgs = images_of(d, ctx->opt.tile_size, sc->dev.n_bodies);
     job->viewmats = d->viewmats;
@@ -1124,8 +1124,8 @@ namespace {
 bool tuning_valid(const gsr_ctx* ctx, const gsr_render_desc* d, const Tuning& t, std::string* why)
 {
     if (t.ts != 8 && t.ts != 16 && t.ts != 32) return *why = "tile_size must be 8, 16 or 32", false;
-    if (t.ts == 8 ? (t.batch != 64 && t.batch != 128 && t.batch != 256) : (t.batch != 256 && t.batch != 512))
-        return *why = "lds_batch must be 64/128/256 for 8-pixel tiles, 256/512 otherwise", false;
+    if (t.batch != 64 && t.batch != 128 && t.batch != 256 && (t.ts == 8 || t.batch != 512))
+        return *why = "lds_batch must be 64/128/256 for 8-pixel tiles, 64/128/256/512 otherwise", false;
     if (t.ipt < 1 || t.ipt > 16) return *why = "images_per_thread must be in 1..16", false;
     if (t.persistent != 0 && t.persistent != 1) return *why = "persistent must be 0 or 1", false;
     if (t.chunk_images < 0) return *why = "chunk_images must be >= 0", false;
@@ -1242,7 +1242,7 @@ GSR_EXPORT int gsr_autotune(gsr_ctx* ctx, const gsr_render_desc* d, void* stream
         if (ts == cur.ts) continue;
         Tuning t = cur;
         t.ts = ts;
-        t.batch = ts == 8 ? 64 : 256;
+        t.batch = 64;
         consider(t);
     }
     for (int b : {64, 128, 256, 512}) {
@@ -1337,7 +1337,7 @@ GSR_EXPORT int gsr_tuning_load(gsr_ctx* ctx, const char* path)
         t.ms = (float)ms;
         if ((t.ts != 8 && t.ts != 16 && t.ts != 32) || t.ipt < 1 || t.ipt > 16 || (t.persistent != 0 && t.persistent != 1) ||
             t.chunk_images < 0 || (t.bin != 0 && t.bin != 1) ||
-            (t.ts == 8 ? (t.batch != 64 && t.batch != 128 && t.batch != 256) : (t.batch != 256 && t.batch != 512)))
+            (t.batch != 64 && t.batch != 128 && t.batch != 256 && (t.ts == 8 || t.batch != 512)))
             return fail(GSR_E_INVALID, "invalid tuning values: " + line);
         got[line.substr(a + kp.size(), b - a - kp.size())] = t;
     }

@@ -57,7 +57,7 @@ struct StageEvents {
 // Launch parameters of one shape class (none of them changes a pixel).
 struct Tuning {
     int ts = 16;            // tile side
-    int batch = 256;        // raster LDS batch
+    int batch = 64;         // raster LDS batch
     int ipt = 4;            // images per projection thread
     int persistent = 0;     // persistent raster workgroups
     int chunk_images = 0;   // images per memory chunk (0 = from the memory budget)

@@ -269,12 +269,21 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
         if (!vis) continue;
         c.rect[o] = make_uint2((uint32_t)ix0 | ((uint32_t)ix1 << 16), (uint32_t)iy0 | ((uint32_t)iy1 << 16));
 
-        // Raster record: conic pre-scaled so that log2(alpha) = p + log2(o)
-        // with p = A dx^2 + B dx dy + C dy^2.  Continuous quantities only
-        // (no binning decision depends on them): hardware reciprocals.
+        // Raster record: the quadratic form of the conic in whitened form,
+        //     log2(alpha) = log2(o) - (a1 dx + b1 dy)^2 - (c1 dy)^2,
+        // i.e. 0.5 log2(e) [dx dy] Sigma^-1 [dx dy]^T factored as W^T W with
+        // W = [[a1, b1], [0, c1]] (Sigma = [[ca, cb], [cb, cc]], det = ca cc - cb^2):
+        //     a1 = sqrt(k cc / det), b1 = -k cb / (det a1), c1 = sqrt(k / cc),
+        // k = 0.5 log2(e).  A sum of squares stays accurate where the expanded
+        // quadratic cancels (long, thin splats far from their centre).
+        // Continuous quantities only (no binning decision depends on them):
+        // hardware reciprocals and square roots.
+        constexpr float kHalfLog2e = 0.72134752044448170f;
+        constexpr float kSqrtHalfLog2e = 0.84932180028801907f;
         const float idet = __builtin_amdgcn_rcpf(det);
-        const float ica = cc * idet, icb = -cb * idet, icc = ca * idet;
-        constexpr float kLog2e = 1.4426950408889634f;
+        const float wa = __builtin_amdgcn_sqrtf(kHalfLog2e * cc * idet);
+        const float wb = -(kHalfLog2e * cb * idet) * __builtin_amdgcn_rcpf(wa);
+        const float wc = kSqrtHalfLog2e * __builtin_amdgcn_rsqf(cc);
         float rgb[3];
         {
             float dx = mu[0] - X[12], dy = mu[1] - X[13], dz = mu[2] - X[14];
@@ -282,8 +291,8 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
             sh_rgb<DEG>(f, dx * inv, dy * inv, dz * inv, rgb);
         }
         float4* rec = c.rec + 3 * o;
-        rec[0] = make_float4(u, v, -0.5f * kLog2e * ica, -kLog2e * icb);
-        rec[1] = make_float4(-0.5f * kLog2e * icc, log2o, tz, r);
+        rec[0] = make_float4(u, v, wa, wb);
+        rec[1] = make_float4(wc, log2o, tz, r);
         rec[2] = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
     }
 }

@@ -3,26 +3,32 @@
 //
 // One workgroup per (image, tile) of the whole chunk, images of all camera
 // slots in one launch.  The tile's depth-sorted Gaussian list is staged into
-// LDS in batches of 256 records (double-buffered: the next batch is fetched
-// into registers while the current one is composited).  Per pixel and
-// Gaussian, with the conic pre-scaled so that log2(alpha) = p:
-//     p = A dx^2 + B dx dy + C dy^2 + log2(o)
+// LDS in batches of records (double-buffered: the next batch is fetched into
+// registers while the current one is composited).  Per pixel and Gaussian,
+// with the conic in whitened form (a1, b1, c1) so that
+//     p = log2(o) - (a1 dx + b1 dy)^2 - (c1 dy)^2 = log2(alpha before the clamp)
 //     p < log2(1/255)          -> skip
 //     alpha = min(0.99, 2^p); T' = T (1 - alpha)
 //     T' < 1e-4                -> stop before adding
 //     C += rgb alpha T, D += z alpha T, T = T'
 //
-// Wave-level culling ("ballot" step): for each batch every lane takes one
-// Gaussian and bounds p over the wave's pixel-centre rectangle from above (p is
-// concave: the maximum is at the mean if it lies inside, else on an edge,
-// where the 1D maximiser is clamped).  Gaussians whose bound stays below
-// log2(1/255) - kCullMargin cannot reach alpha >= 1/255 at any pixel of the
-// block (narrowed to the bounding box of its still-live pixels); the ballot of
-// the survivors is walked bit by bit, so each wave only evaluates Gaussians
-// that touch its pixels, and skips the blending work when no live pixel
-// reaches the alpha threshold.  kCullMargin absorbs binary32
-// rounding of the per-pixel evaluation, so culling never removes a Gaussian a
-// pixel would have accepted and results do not depend on the tiling.
+// Wave-level culling ("ballot" step): for each group of 64 candidates every
+// lane takes one Gaussian and bounds p over the wave's pixel-centre rectangle
+// from above (p is concave: the maximum is at the mean if it lies inside,
+// else on an edge, where the 1D maximiser is clamped).  Gaussians whose bound
+// stays below log2(1/255) - kCullMargin cannot reach alpha >= 1/255 at any
+// pixel of the block (narrowed to the bounding box of its still-live pixels).
+// The same lane writes its Gaussian, re-centred on the 32x32 pixel block that
+// holds the wave, into the wave's own LDS slots; the ballot of the survivors
+// is then walked bit by bit, each survivor costing five FMAs per pixel:
+//     t1 = a1 x + b1 y - s1,  t2 = c1 y - s2,  p = log2(o) - t1^2 - t2^2
+// with (x, y) the pixel centre relative to the block centre and (s1, s2) the
+// whitened mean.  The block (not the tile or the wave) is the origin so that
+// every tile size evaluates the same expression for a pixel and results do
+// not depend on the tiling.  kCullMargin absorbs binary32 rounding of the
+// per-pixel evaluation, so culling never removes a Gaussian a pixel would
+// have accepted.  Blending takes a short path when no pixel of the wave stops
+// at the current Gaussian.
 //
 // Output: rgb = C + T bg, depth = D / (1 - T) (0 where nothing was added),
 // optional alpha = 1 - T, optional work counts, and optionally the fused
@@ -40,9 +46,9 @@ namespace {
 constexpr float kLogAlphaMin = -7.99435343685886f;   // log2(1/255)
 constexpr float kCullMargin = 0.05f;                  // in log2(alpha) units
 // x coordinate given to a pixel once it has stopped (or lies outside the
-// image): p evaluates to -inf there for every Gaussian (|A| is at least the
-// dilation's share, so A dx^2 overflows), so the pixel never takes another
-// Gaussian and needs no separate liveness flag in the per-Gaussian loop.
+// image): t1 overflows to infinity there for every Gaussian (a1 > 0), so p is
+// -inf and the pixel never takes another Gaussian; no separate liveness flag
+// is needed in the per-Gaussian loop.
 constexpr float kDead = 1.0e30f;
 constexpr float kDeadTest = 1.0e29f;
 
@@ -68,41 +74,58 @@ struct Layout {
     }
 };
 
-// Upper bound of p = A x^2 + B x y + C y^2 + lo over [X0, X1] x [Y0, Y1]
-// (coordinates relative to the mean; A, C < 0).
-__device__ __forceinline__ float max_logalpha_rect(float A, float B, float C, float lo, float X0, float X1, float Y0,
+// Orders this wave's LDS writes before its later LDS reads (no instruction:
+// LDS requests of one wave are served in order; this keeps the compiler from
+// moving accesses across it).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Upper bound of p = lo - (a1 x + b1 y)^2 - (c1 y)^2 over [X0, X1] x [Y0, Y1]
+// (coordinates relative to the mean; a1, c1 > 0).
+__device__ __forceinline__ float max_logalpha_rect(float a1, float b1, float c1, float lo, float X0, float X1, float Y0,
                                                    float Y1)
 {
     if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return lo;
-    // argmax over y for fixed x is ky * x (and over x for fixed y, kx * y).  An
-    // approximate reciprocal moves the evaluated point along the edge by a
-    // relative 1e-7, which lowers the bound by a second-order amount only:
-    // the point stays on the edge, so the value is still attained there.
-    const float ky = -B * __builtin_amdgcn_rcpf(2.0f * C);
-    const float kx = -B * __builtin_amdgcn_rcpf(2.0f * A);
-    float best = -INFINITY;
+    // On an edge x = X the quadratic is smallest at y = ky X, on y = Y at
+    // x = kx Y.  An approximate reciprocal moves the evaluated point along the
+    // edge by a relative 1e-7, which lowers the bound by a second-order amount
+    // only: the point stays on the edge, so the value is still attained there.
+    const float ky = -(a1 * b1) * __builtin_amdgcn_rcpf(fmaf(b1, b1, c1 * c1));
+    const float kx = -b1 * __builtin_amdgcn_rcpf(a1);
+    float q;
     {
         const float y = fminf(fmaxf(ky * X0, Y0), Y1);
-        best = fmaxf(best, fmaf(X0, fmaf(A, X0, B * y), C * y * y));
+        const float t = fmaf(a1, X0, b1 * y), w = c1 * y;
+        q = fmaf(t, t, w * w);
     }
     {
         const float y = fminf(fmaxf(ky * X1, Y0), Y1);
-        best = fmaxf(best, fmaf(X1, fmaf(A, X1, B * y), C * y * y));
+        const float t = fmaf(a1, X1, b1 * y), w = c1 * y;
+        q = fminf(q, fmaf(t, t, w * w));
     }
     {
         const float x = fminf(fmaxf(kx * Y0, X0), X1);
-        best = fmaxf(best, fmaf(Y0, fmaf(C, Y0, B * x), A * x * x));
+        const float t = fmaf(a1, x, b1 * Y0), w = c1 * Y0;
+        q = fminf(q, fmaf(t, t, w * w));
     }
     {
         const float x = fminf(fmaxf(kx * Y1, X0), X1);
-        best = fmaxf(best, fmaf(Y1, fmaf(C, Y1, B * x), A * x * x));
+        const float t = fmaf(a1, x, b1 * Y1), w = c1 * Y1;
+        q = fminf(q, fmaf(t, t, w * w));
     }
-    return best + lo;
+    return lo - q;
 }
 
 template <int TS, int kBatch>
 struct RasterLds {
-    float4 a[2][kBatch], b[2][kBatch], c[2][kBatch];
+    float4 a[2][kBatch], b[2][kBatch], c[2][kBatch];    // staged records: (u, v, a1, b1), (c1, lo, z, r), rgb
+    // per wave, the current 64 candidates re-centred on the wave's block:
+    // (a1, b1, c1, -s1), (-s2, lo, z, 0), rgb
+    float4 w[Layout<TS>::kWaves][3][64];
 };
 
 // Composites tile `bid` of the chunk (block id in segment order).
@@ -113,8 +136,8 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
     using L = Layout<TS>;
     constexpr int NT = L::kThreads;
     constexpr int PPT = L::kPpt;
-    constexpr int PER_THREAD = kBatch / NT;     // records each thread stages per batch
-    static_assert(PER_THREAD >= 1 && kBatch % 64 == 0, "batch must be a multiple of 64 and >= the block size");
+    constexpr int PER_THREAD = (kBatch + NT - 1) / NT;     // records each thread stages per batch
+    static_assert(kBatch % 64 == 0, "batch must be a multiple of 64");
     auto& sA = L_.a;
     auto& sB = L_.b;
     auto& sC = L_.c;
@@ -136,13 +159,17 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
     const int w = tid >> 6, lane = __lane_id();
     int ox, oy;
     L::wave_origin(w, &ox, &oy);
+    auto& W = L_.w[w];
     // pixel-centre rectangle of the wave's block
     const float wx0 = (float)(tx * TS + ox) + 0.5f;
     const float wx1 = wx0 + (float)(L::kWaveW - 1);
     const float wy0 = (float)(ty * TS + oy) + 0.5f;
     const float wy1 = wy0 + (float)(L::kWaveH - 1);
+    // centre of the 32x32 pixel block holding the wave: origin of the pixel coordinates
+    const float cxo = (float)((tx * TS + ox) & ~31) + 16.0f;
+    const float cyo = (float)((ty * TS + oy) & ~31) + 16.0f;
 
-    float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
+    float xl[PPT], yl[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
     uint32_t stop_at[PPT], blended[PPT];     // work counters (COUNT only)
     int pxi[PPT], pyi[PPT];
     bool any_live = false;
@@ -153,8 +180,8 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         pxi[k] = tx * TS + ox + lx;
         pyi[k] = ty * TS + oy + ly;
         const bool inside = pxi[k] < im.width && pyi[k] < im.height;
-        px[k] = inside ? (float)pxi[k] + 0.5f : kDead;
-        py[k] = (float)pyi[k] + 0.5f;
+        xl[k] = inside ? ((float)pxi[k] + 0.5f) - cxo : kDead;
+        yl[k] = ((float)pyi[k] + 0.5f) - cyo;
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = D[k] = 0.0f;
         stop_at[k] = 0xFFFFFFFFu;
@@ -173,8 +200,9 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
     auto fetch = [&](uint32_t b0) {
 #pragma unroll
         for (int q = 0; q < PER_THREAD; ++q) {
-            const uint32_t e = b0 + (uint32_t)(q * NT + tid);
-            if (e < end) {
+            const uint32_t slot = (uint32_t)(q * NT + tid);
+            const uint32_t e = b0 + slot;
+            if (slot < (uint32_t)kBatch && e < end) {
                 uint32_t g = list[e];
                 if (g >= n) g = 0;      // guard: list entries are valid indices by construction
                 ra[q] = rec[3 * (size_t)g];
@@ -190,9 +218,12 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
 #pragma unroll
         for (int q = 0; q < PER_THREAD; ++q) {
-            sA[buf][q * NT + tid] = ra[q];
-            sB[buf][q * NT + tid] = rb[q];
-            sC[buf][q * NT + tid] = rc[q];
+            const int slot = q * NT + tid;
+            if (slot < kBatch) {
+                sA[buf][slot] = ra[q];
+                sB[buf][slot] = rb[q];
+                sC[buf][slot] = rc[q];
+            }
         }
         __syncthreads();
         if (b0 + kBatch < end) fetch(b0 + kBatch);
@@ -201,7 +232,7 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             // pixel-centre rectangle still to be shaded: the live pixels' bounding box
             float lx0 = wx0, lx1 = wx1, ly0 = wy0, ly1 = wy1;
             if (PPT == 1) {
-                const uint64_t M = __ballot(px[0] < kDeadTest);  // lane = 8 * row + column
+                const uint64_t M = __ballot(xl[0] < kDeadTest);  // lane = 8 * row + column
                 uint64_t cm = M | (M >> 32);
                 cm |= cm >> 16;
                 cm |= cm >> 8;
@@ -211,7 +242,8 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
                 ly0 = wy0 + (float)(__builtin_ctzll(M) >> 3);
                 ly1 = wy0 + (float)((63 - __builtin_clzll(M)) >> 3);
             }
-            // ballot: which of these 64 Gaussians can touch the live pixels
+            // ballot: which of these 64 Gaussians can touch the live pixels;
+            // survivors are re-centred into the wave's slots
             const int jl = sub + lane;
             bool keep = false;
             if (jl < cnt) {
@@ -219,48 +251,71 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
                 const float4 bq = sB[buf][jl];
                 const float m = max_logalpha_rect(a.z, a.w, bq.x, bq.y, lx0 - a.x, lx1 - a.x, ly0 - a.y, ly1 - a.y);
                 keep = m >= kLogAlphaMin - kCullMargin;
+                if (keep) {
+                    const float du = a.x - cxo, dv = a.y - cyo;
+                    const float s1 = fmaf(a.z, du, a.w * dv), s2 = bq.x * dv;
+                    W[0][lane] = make_float4(a.z, a.w, bq.x, -s1);
+                    W[1][lane] = make_float4(-s2, bq.y, bq.z, 0.0f);
+                    W[2][lane] = sC[buf][jl];
+                }
             }
             uint64_t mask = __ballot(keep);
+            wave_lds_sync();
             while (mask) {
-                const int j = sub + (int)__builtin_ctzll(mask);
+                const int j = (int)__builtin_ctzll(mask);
                 mask &= mask - 1ull;
-                const float4 a = sA[buf][j];
-                const float4 bq = sB[buf][j];
+                const float4 q0 = W[0][j];
+                const float4 q1 = W[1][j];
                 float pw[PPT];
                 bool anyt = false;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    const float dx = px[k] - a.x;
-                    const float dy = py[k] - a.y;
-                    pw[k] = fmaf(dx, fmaf(a.z, dx, a.w * dy), fmaf(bq.x * dy, dy, bq.y));
+                    const float t1 = fmaf(q0.x, xl[k], fmaf(q0.y, yl[k], q0.w));
+                    const float t2 = fmaf(q0.z, yl[k], q1.x);
+                    pw[k] = fmaf(-t1, t1, fmaf(-t2, t2, q1.y));
                     anyt = anyt || pw[k] >= kLogAlphaMin;
                 }
                 if (__ballot(anyt) == 0ull) continue;       // no live pixel of the wave reaches 1/255
-                const float4 col = sC[buf][j];
+                const float4 col = W[2][j];
+                float al[PPT], wgt[PPT];
+                bool anystop = false;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     const bool take = pw[k] >= kLogAlphaMin;
-                    const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(pw[k]));
-                    const float Tn = fmaf(-T[k], alpha, T[k]);
-                    const bool stop = take && Tn < 1e-4f;
-                    const bool add = take && !stop;
-                    const float wgt = add ? alpha * T[k] : 0.0f;
-                    C0[k] = fmaf(col.x, wgt, C0[k]);
-                    C1[k] = fmaf(col.y, wgt, C1[k]);
-                    C2[k] = fmaf(col.z, wgt, C2[k]);
-                    D[k] = fmaf(bq.z, wgt, D[k]);
-                    T[k] = add ? Tn : T[k];
-                    px[k] = stop ? kDead : px[k];
-                    if (COUNT) {
-                        blended[k] += add ? 1u : 0u;
-                        if (stop) stop_at[k] = b0 - start + (uint32_t)j + 1u;
+                    al[k] = take ? fminf(0.99f, __builtin_amdgcn_exp2f(pw[k])) : 0.0f;
+                    wgt[k] = al[k] * T[k];
+                    T[k] = T[k] - wgt[k];                   // unchanged where the pixel does not take it
+                    anystop = anystop || T[k] < 1e-4f;      // only a taking pixel can fall below (T >= 1e-4)
+                }
+                if (__ballot(anystop) != 0ull) {
+                    // rare: a pixel that stops here adds nothing and keeps its
+                    // transmittance (T' + alpha T restores it to within one
+                    // rounding).  The empty asm keeps this a branch rather than
+                    // selects that every blended Gaussian would pay for.
+                    asm volatile("");
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const bool stop = T[k] < 1e-4f;
+                        if (COUNT && stop) stop_at[k] = b0 - start + (uint32_t)(sub + j) + 1u;
+                        T[k] = stop ? T[k] + wgt[k] : T[k];
+                        wgt[k] = stop ? 0.0f : wgt[k];
+                        al[k] = stop ? 0.0f : al[k];
+                        xl[k] = stop ? kDead : xl[k];
                     }
+                }
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    C0[k] = fmaf(col.x, wgt[k], C0[k]);
+                    C1[k] = fmaf(col.y, wgt[k], C1[k]);
+                    C2[k] = fmaf(col.z, wgt[k], C2[k]);
+                    D[k] = fmaf(q1.z, wgt[k], D[k]);
+                    if (COUNT) blended[k] += al[k] > 0.0f ? 1u : 0u;
                 }
             }
             // the wave stops once none of its pixels is live (checked per 64 candidates)
             bool lv = false;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) lv = lv || px[k] < kDeadTest;
+            for (int k = 0; k < PPT; ++k) lv = lv || xl[k] < kDeadTest;
             if (__ballot(lv) == 0ull) wave_live = false;
         }
         buf ^= 1;
@@ -373,19 +428,17 @@ hipError_t launch_ts(const SceneDev& s, const ChunkDev& c, const RasterParams& p
     return p.count_work ? launch_tsc<TS, kBatch, true>(s, c, p, stream) : launch_tsc<TS, kBatch, false>(s, c, p, stream);
 }
 
-// LDS batch sizes: 64 / 128 / 256 records for 8x8 tiles (one wave), 256 / 512
-// for the 256-thread layouts (a batch holds at least one record per thread).
+// LDS batch sizes: 64 / 128 / 256 records for 8x8 tiles (one wave), 64 to 512
+// for the 256-thread layouts (smaller batches leave room for more workgroups
+// per CU; batches below the block size are staged by the first threads).
 template <int TS>
 hipError_t launch_batch(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream)
 {
-    if constexpr (TS == 8) {
-        if (p.batch == 64) return launch_ts<TS, 64>(s, c, p, stream);
-        if (p.batch == 128) return launch_ts<TS, 128>(s, c, p, stream);
-        return launch_ts<TS, 256>(s, c, p, stream);
-    } else {
+    if (p.batch == 64) return launch_ts<TS, 64>(s, c, p, stream);
+    if (p.batch == 128) return launch_ts<TS, 128>(s, c, p, stream);
+    if constexpr (TS != 8)
         if (p.batch == 512) return launch_ts<TS, 512>(s, c, p, stream);
-        return launch_ts<TS, 256>(s, c, p, stream);
-    }
+    return launch_ts<TS, 256>(s, c, p, stream);
 }
 
 }  // namespace

@@ -104,10 +104,21 @@ def test_project_cfg0_matches_spec(R):
     np.testing.assert_array_equal(rec[:, 1], p["v"][vis])
     np.testing.assert_array_equal(rec[:, 7], p["radius"][vis])
     np.testing.assert_array_equal(rec[:, 6].view(np.uint32), p["zbits"][vis])
+    # whitened conic: 0.5 log2(e) q(dx, dy) = (a1 dx + b1 dy)^2 + (c1 dy)^2, from the
+    # specification's dilated covariance (a, b, c) and determinant
+    cov = p["cov"][vis].astype(np.float64)
+    det = p["det"][vis].astype(np.float64)
+    k = 0.5 * LOG2E
+    a1 = np.sqrt(k * cov[:, 2] / det)
+    np.testing.assert_allclose(rec[:, 2], a1, rtol=4e-6)
+    np.testing.assert_allclose(rec[:, 3], -k * cov[:, 1] / (det * a1), rtol=4e-6, atol=1e-9)
+    np.testing.assert_allclose(rec[:, 4], np.sqrt(k / cov[:, 2]), rtol=4e-6)
+    # the factors reproduce the conic of the specification
     con = p["conic"][vis].astype(np.float64)
-    np.testing.assert_allclose(rec[:, 2], -0.5 * LOG2E * con[:, 0], rtol=1e-6, atol=1e-9)
-    np.testing.assert_allclose(rec[:, 3], -LOG2E * con[:, 1], rtol=1e-6, atol=1e-9)
-    np.testing.assert_allclose(rec[:, 4], -0.5 * LOG2E * con[:, 2], rtol=1e-6, atol=1e-9)
+    r64 = rec.astype(np.float64)
+    np.testing.assert_allclose(r64[:, 2] ** 2, k * con[:, 0], rtol=2e-5)
+    np.testing.assert_allclose(2 * r64[:, 2] * r64[:, 3], 2 * k * con[:, 1], rtol=2e-5, atol=1e-9)
+    np.testing.assert_allclose(r64[:, 3] ** 2 + r64[:, 4] ** 2, k * con[:, 2], rtol=2e-5)
     at = attrs64(scene, batch)
     np.testing.assert_allclose(rec[:, 8:11], at["rgb"][vis], atol=2e-6)
     np.testing.assert_allclose(rec[:, 5], np.log2(scene.opacities[vis].astype(np.float64)), atol=2e-6)

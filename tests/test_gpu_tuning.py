@@ -39,7 +39,9 @@ def test_graph_replays_match_eager():
 @pytest.mark.parametrize("params", [dict(tile_size=8, lds_batch=64), dict(tile_size=8, lds_batch=256),
                                     dict(tile_size=32, lds_batch=512), dict(lds_batch=512, images_per_thread=1),
                                     dict(images_per_thread=8, persistent=1), dict(persistent=1, chunk_images=3),
-                                    dict(bin_schedule=0), dict(bin_schedule=1, tile_size=8, lds_batch=128)])
+                                    dict(bin_schedule=0), dict(bin_schedule=1, tile_size=8, lds_batch=128),
+                                    dict(lds_batch=256), dict(lds_batch=128, persistent=1),
+                                    dict(tile_size=32, lds_batch=128)])
 def test_tuning_changes_no_pixel(params):
     torch = _torch()
     from paper_2604_25459_amd import gsr
