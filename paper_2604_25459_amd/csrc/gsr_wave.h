@@ -1,0 +1,83 @@
+// Wave-level (64-lane) primitives.  Prefix scans use DPP lane shifts within
+// rows of 16 lanes and the two row broadcasts, so they cost a handful of VALU
+// instructions and no LDS round trips.  Every function here expects all 64
+// lanes of the wave to be active.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsr {
+namespace {
+
+// DPP controls: row_shr:n (lane i of a 16-lane row reads lane i - n of the
+// same row), row_bcast:15 (lane 15 of each row to the whole next row) and
+// row_bcast:31 (lane 31 to rows 2 and 3).
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShr4 = 0x114;
+constexpr int kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+// Inclusive prefix sum over the lanes.  A lane whose source lies outside its
+// row (or whose row is masked off) receives 0.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr1, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr2, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr4, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr8, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast15, 0xa, 0xf, false);   // rows 1, 3
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast31, 0xc, 0xf, false);   // rows 2, 3
+    return x;
+}
+
+// Inclusive prefix maximum over the lanes (values >= 0; 0 is the identity).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x)
+{
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr1, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr2, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr4, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr8, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast15, 0xa, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast31, 0xc, 0xf, false));
+    return x;
+}
+
+// Value of the last lane (a scalar for the whole wave).
+__device__ __forceinline__ uint32_t wave_last(uint32_t x) { return (uint32_t)__builtin_amdgcn_readlane((int)x, 63); }
+
+// Number of lanes below this one whose bit is set in m.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Lanes holding the same key (low `bits` bits) among lanes with `active`:
+// one ballot per bit; a lane keeps the lanes whose bit equals its own.
+__device__ __forceinline__ uint64_t match_key(uint32_t key, bool active, int bits)
+{
+    const uint64_t a = __ballot(active);
+    uint32_t lo = (uint32_t)a, hi = (uint32_t)(a >> 32);
+    for (int b = 0; b < bits; ++b) {
+        const uint64_t m = __ballot((key >> b) & 1u);
+        const uint32_t own = 0u - ((key >> b) & 1u);       // all ones where this lane's bit is set
+        lo &= ~((uint32_t)m ^ own);
+        hi &= ~((uint32_t)(m >> 32) ^ own);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Orders this wave's LDS writes before its later LDS reads (no instruction:
+// LDS requests of one wave are served in order; this keeps the compiler from
+// moving accesses across it).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace
+}  // namespace gsr

@@ -19,9 +19,13 @@
 //            per tile of the row.
 // The last depth-sort pass leaves every rectangle in depth order and row-list
 // entries carry their x-range, so no stage gathers rectangles by id.
-// Expansions are never written out: each kernel re-expands in LDS, balanced
-// over one wave.  Ranks of equal buckets inside a 64-entry window come from a
-// ballot match; a per-bucket cursor in LDS carries the rank across windows.
+// Expansions are never written out: each kernel re-expands a group of 64
+// items at a time, balanced over one wave (lane = expansion slot).  A slot's
+// item is found by marking each item's first slot and taking a prefix maximum
+// across the lanes; ranks of equal buckets among the 64 slots come from a
+// ballot match, and a per-bucket cursor in LDS carries the rank across
+// iterations.  Item loads run several groups ahead, so a wave waits for its
+// own scattered stores only once per batch of groups.
 //
 // Kernels:
 //   k_tile_hist       tile and tile-row counts as difference arrays (LDS atomics)
@@ -32,71 +36,58 @@
 //   k_rowseg_scan     level 2, first output position of each segment per tile
 //   k_rowtile_scatter level 2
 #include "gsr_internal.h"
+#include "gsr_wave.h"
 
 #include <algorithm>
 
 namespace gsr {
 namespace {
 
-__device__ __forceinline__ uint64_t lanemask_lt64()
-{
-    const int lane = __lane_id();
-    return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
-{
-    const int lane = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
-
-// Lanes holding the same `key` (low `bits` bits) among lanes with `active`.
-__device__ __forceinline__ uint64_t match_key(uint32_t key, bool active, int bits)
-{
-    uint64_t peers = __ballot(active);
-    for (int b = 0; b < bits; ++b) {
-        const bool v = (key >> b) & 1u;
-        const uint64_t m = __ballot(v);
-        peers &= v ? m : ~m;
-    }
-    return peers;
-}
-
-// LDS staging of one group of 64 items and their expansion counts.
-struct Group {
-    uint32_t excl[64];   // exclusive prefix of the counts (counts are >= 1 for valid items)
-    uint32_t a[64];      // first bucket (x0 or y0)
-    uint32_t w[64];      // rectangle width (2D expansion)
-    uint32_t b[64];      // first row (2D expansion)
-    uint32_t g[64];      // Gaussian id
+// Expansion of one group of 64 items (lane = item, in list order): item k
+// covers the buckets first_k .. first_k + cnt_k - 1 and goes, with its two
+// payload words, to each of those buckets' lists at the bucket's cursor, items
+// in lane order (stable).  `store(pos, v0, v1)` writes one placement.  All 64
+// lanes must take part.
+struct ExpandLds {
+    uint4 item[64];      // (first - excl, v0, v1, 0): slot p of the item holds bucket item.x + p
+    uint32_t mark[64];   // first slot of an item in the current 64 slots -> item + 1 (0 elsewhere)
 };
 
-// Item owning expansion slot p: largest k with excl[k] <= p.
-__device__ __forceinline__ uint32_t owner(const Group& grp, uint32_t p)
-{
-    int lo = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-        if (grp.excl[lo + step] <= p) lo += step;
-    return (uint32_t)lo;
-}
-
-// Publish a group: counts -> exclusive prefix; returns the group's total.
-__device__ __forceinline__ uint32_t publish(Group& grp, uint32_t cnt, uint32_t a, uint32_t w, uint32_t b, uint32_t g)
+template <typename Store>
+__device__ __forceinline__ void expand_group(ExpandLds& ex, uint32_t* cursor, uint32_t cnt, uint32_t first,
+                                             uint32_t v0, uint32_t v1, uint32_t n_buckets, int bits, Store store)
 {
     const int lane = __lane_id();
-    const uint32_t inc = wave_incl_scan(cnt);
-    grp.excl[lane] = inc - cnt;
-    grp.a[lane] = a;
-    grp.w[lane] = w;
-    grp.b[lane] = b;
-    grp.g[lane] = g;
-    return __shfl(inc, 63, 64);
+    const uint32_t inc = wave_incl_sum(cnt);
+    const uint32_t excl = inc - cnt;
+    const uint32_t total = wave_last(inc);
+    ex.item[lane] = make_uint4(first - excl, v0, v1, 0u);
+    uint32_t carry = 0;          // owner + 1 of the last slot of the previous iteration
+    for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+        if (cnt != 0 && excl >= p0 && excl < p0 + 64u) ex.mark[excl - p0] = (uint32_t)lane + 1u;
+        wave_lds_sync();
+        const uint32_t mk = ex.mark[lane];
+        ex.mark[lane] = 0u;
+        const uint32_t own = max(wave_incl_max(mk), carry);
+        carry = wave_last(own);
+        const uint32_t p = p0 + (uint32_t)lane;
+        bool ok = p < total && own != 0u;
+        uint4 it = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t bkt = 0;
+        if (ok) {
+            it = ex.item[(own - 1u) & 63u];
+            bkt = it.x + p;
+            ok = bkt < n_buckets;
+        }
+        const uint64_t peers = match_key(bkt, ok, bits);
+        if (ok) {
+            const uint32_t below = lanes_below(peers);
+            const uint32_t basev = cursor[bkt];
+            if (below == 0u) cursor[bkt] = basev + (uint32_t)__popcll(peers);
+            store(basev + below, it.y, it.z);
+        }
+        wave_lds_sync();
+    }
 }
 
 // Depth-ordered Gaussian j of image i: id and tile rectangle (x0, x1, y0, y1).
@@ -180,7 +171,7 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* tot
 {
     const int lane = __lane_id();
     const int w = threadIdx.x >> 6;
-    const uint32_t x = wave_incl_scan(v);
+    const uint32_t x = wave_incl_sum(v);
     if (lane == 63) lds8[w] = x;
     __syncthreads();
     uint32_t pre = 0, tot = 0;
@@ -320,11 +311,14 @@ __global__ __launch_bounds__(256) void k_image_scan(ChunkDev c)
 }
 
 // ------------------------------------------------------------------ level 1
+// Items are loaded this many groups of 64 ahead (see the header).
+constexpr int kAhead = 4;
+
 __global__ __launch_bounds__(64) void k_row_scatter(ChunkDev c, uint64_t n, int row_bits)
 {
     extern __shared__ uint32_t lds[];
-    Group& grp = *reinterpret_cast<Group*>(lds);
-    uint32_t* cursor = lds + sizeof(Group) / 4;
+    ExpandLds& ex = *reinterpret_cast<ExpandLds*>(lds);
+    uint32_t* cursor = lds + sizeof(ExpandLds) / 4;
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
     const uint32_t V = c.n ? c.vis_count[i] : 0u;
@@ -335,50 +329,45 @@ __global__ __launch_bounds__(64) void k_row_scatter(ChunkDev c, uint64_t n, int 
     const uint32_t TY = (uint32_t)im.tiles_y;
     const uint32_t* off = c.row_hist + ((size_t)i * c.tile_blocks + b) * c.ty_max;
     for (uint32_t y = lane; y < TY; y += 64) cursor[y] = off[y];
+    ex.mark[lane] = 0u;
     uint2* out = c.rows + c.row_base[i];
     const uint32_t Rn = c.row_count[i];
-    const uint64_t lt = lanemask_lt64();
-    __syncthreads();
-    // the next group's ids and rectangles are fetched while this group is placed
     const size_t seg = (size_t)i * n;
-    uint32_t g_next = 0;
-    uint2 r_next = make_uint2(0u, 0u);
-    if (j0 + lane < j1) {
-        g_next = c.sv[1][seg + j0 + lane];
-        r_next = c.srect[seg + j0 + lane];
-    }
-    for (uint32_t jb = j0; jb < j1; jb += 64) {
-        uint32_t g = g_next;
-        const uint2 r = r_next;
-        const bool in_group = jb + lane < j1;
-        if (jb + 64 + lane < j1) {
-            g_next = c.sv[1][seg + jb + 64 + lane];
-            r_next = c.srect[seg + jb + 64 + lane];
+    uint32_t gn[kAhead];
+    uint2 rn[kAhead];
+    auto load = [&](uint32_t jb) {
+#pragma unroll
+        for (int w = 0; w < kAhead; ++w) {
+            const uint32_t j = jb + 64u * w + (uint32_t)lane;
+            gn[w] = j < j1 ? c.sv[1][seg + j] : 0u;
+            rn[w] = j < j1 ? c.srect[seg + j] : make_uint2(0u, 0u);
         }
-        const uint32_t x0 = r.x & 0xFFFFu, x1 = r.x >> 16, y0 = r.y & 0xFFFFu, y1 = r.y >> 16;
-        // guard: sorted ids are valid indices by construction
-        const bool okg = in_group && g < n && x1 > x0 && y1 > y0;
-        if (!okg) g = 0;
-        const uint32_t total = publish(grp, okg ? y1 - y0 : 0, y0, x0 | (x1 << 16), 0, g);
-        __syncthreads();
-        for (uint32_t p0 = 0; p0 < total; p0 += 64) {
-            const uint32_t p = p0 + lane;
-            bool ok = p < total;
-            uint32_t k = 0, y = 0;
-            if (ok) {
-                k = owner(grp, p);
-                y = grp.a[k] + (p - grp.excl[k]);
-                ok = y < TY;
-            }
-            const uint64_t peers = match_key(y, ok, row_bits);
-            if (ok) {
-                const uint32_t basev = cursor[y];
-                const uint32_t pos = basev + (uint32_t)__popcll(peers & lt);
-                if (lane == __ffsll((unsigned long long)peers) - 1) cursor[y] = basev + (uint32_t)__popcll(peers);
-                if (pos < Rn) out[pos] = make_uint2(grp.g[k], grp.w[k]);
-            }
+    };
+    load(j0);
+    wave_lds_sync();
+    for (uint32_t jb = j0; jb < j1; jb += 64u * kAhead) {
+        uint32_t gc[kAhead];
+        uint2 rc[kAhead];
+#pragma unroll
+        for (int w = 0; w < kAhead; ++w) {
+            gc[w] = gn[w];
+            rc[w] = rn[w];
         }
-        __syncthreads();
+        if (jb + 64u * kAhead < j1) load(jb + 64u * kAhead);
+#pragma unroll
+        for (int w = 0; w < kAhead; ++w) {
+            const uint32_t jw = jb + 64u * w;
+            if (jw >= j1) break;
+            const uint32_t g = gc[w];
+            const uint2 r = rc[w];
+            const uint32_t x0 = r.x & 0xFFFFu, x1 = r.x >> 16, y0 = r.y & 0xFFFFu, y1 = r.y >> 16;
+            // guard: sorted ids are valid indices by construction
+            const bool okg = jw + (uint32_t)lane < j1 && g < n && x1 > x0 && y1 > y0;
+            expand_group(ex, cursor, okg ? y1 - y0 : 0u, y0, g, x0 | (x1 << 16), TY, row_bits,
+                         [&](uint32_t pos, uint32_t v0, uint32_t v1) {
+                             if (pos < Rn) out[pos] = make_uint2(v0, v1);
+                         });
+        }
     }
 }
 
@@ -427,9 +416,9 @@ __global__ __launch_bounds__(64) void k_rowseg_count(ChunkDev c, int n_seg, uint
     for (int x0 = 0; x0 < TX; x0 += 64) {
         const int x = x0 + lane;
         const int32_t v = x < TX ? diff[x] : 0;
-        const int32_t inc = (int32_t)wave_incl_scan((uint32_t)v) + carry;
+        const int32_t inc = (int32_t)wave_incl_sum((uint32_t)v) + carry;
         if (x < TX) out[x] = (uint32_t)inc;
-        carry = __shfl(inc, 63, 64);
+        carry = (int32_t)wave_last((uint32_t)inc);
     }
 }
 
@@ -458,8 +447,8 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
                                                         const uint32_t* __restrict__ seg_off)
 {
     extern __shared__ uint32_t lds[];
-    Group& grp = *reinterpret_cast<Group*>(lds);
-    uint32_t* cursor = lds + sizeof(Group) / 4;
+    ExpandLds& ex = *reinterpret_cast<ExpandLds*>(lds);
+    uint32_t* cursor = lds + sizeof(ExpandLds) / 4;
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
     const int y = bx / n_seg, sg = bx - y * n_seg;
@@ -478,43 +467,40 @@ __global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, 
         const uint32_t* so = seg_off + (((size_t)i * c.ty_max + y) * n_seg + sg) * c.tx_max;
         for (uint32_t x = lane; x < TX; x += 64) cursor[x] = so[x];
     }
+    ex.mark[lane] = 0u;
     uint32_t* out = c.pairs + c.pair_base[i];
     const uint32_t P = c.pair_count[i];
-    const uint64_t lt = lanemask_lt64();
-    __syncthreads();
-    // the next window of entries is fetched while this one is placed
-    uint2 nxt = r0 + (uint32_t)lane < r1 ? list[r0 + lane] : make_uint2(0u, 0u);
-    for (uint32_t e0 = r0; e0 < r1; e0 += 64) {
-        const uint2 ent = nxt;
-        const bool valid = e0 + (uint32_t)lane < r1;
-        if (e0 + 64u + (uint32_t)lane < r1) nxt = list[e0 + 64u + lane];
-        uint32_t g = 0, x0 = 0, cnt = 0;
-        if (valid) {
-            g = ent.x;
-            x0 = ent.y & 0xFFFFu;
-            const uint32_t x1 = min(ent.y >> 16, TX);
-            cnt = x1 > x0 ? x1 - x0 : 0;
+    uint2 nx[kAhead];
+    auto load = [&](uint32_t eb) {
+#pragma unroll
+        for (int w = 0; w < kAhead; ++w) {
+            const uint32_t e = eb + 64u * w + (uint32_t)lane;
+            nx[w] = e < r1 ? list[e] : make_uint2(0u, 0u);
         }
-        const uint32_t total = publish(grp, cnt, x0, 0, 0, g);
-        __syncthreads();
-        for (uint32_t p0 = 0; p0 < total; p0 += 64) {
-            const uint32_t p = p0 + lane;
-            bool ok = p < total;
-            uint32_t k = 0, x = 0;
-            if (ok) {
-                k = owner(grp, p);
-                x = grp.a[k] + (p - grp.excl[k]);
-                ok = x < TX;
+    };
+    load(r0);
+    wave_lds_sync();
+    for (uint32_t eb = r0; eb < r1; eb += 64u * kAhead) {
+        uint2 cur[kAhead];
+#pragma unroll
+        for (int w = 0; w < kAhead; ++w) cur[w] = nx[w];
+        if (eb + 64u * kAhead < r1) load(eb + 64u * kAhead);
+#pragma unroll
+        for (int w = 0; w < kAhead; ++w) {
+            const uint32_t ew = eb + 64u * w;
+            if (ew >= r1) break;
+            const uint2 ent = cur[w];
+            uint32_t x0 = 0, cnt = 0;
+            if (ew + (uint32_t)lane < r1) {
+                x0 = ent.y & 0xFFFFu;
+                const uint32_t x1 = min(ent.y >> 16, TX);
+                cnt = x1 > x0 ? x1 - x0 : 0u;
             }
-            const uint64_t peers = match_key(x, ok, col_bits);
-            if (ok) {
-                const uint32_t basev = cursor[x];
-                const uint32_t pos = basev + (uint32_t)__popcll(peers & lt);
-                if (lane == __ffsll((unsigned long long)peers) - 1) cursor[x] = basev + (uint32_t)__popcll(peers);
-                if (pos < P) out[pos] = grp.g[k];
-            }
+            expand_group(ex, cursor, cnt, x0, ent.x, 0u, TX, col_bits,
+                         [&](uint32_t pos, uint32_t v0, uint32_t) {
+                             if (pos < P) out[pos] = v0;
+                         });
         }
-        __syncthreads();
     }
 }
 
@@ -599,8 +585,8 @@ __global__ __launch_bounds__(64) void k_rowtile_transpose(ChunkDev c, int n_cc)
             mine[w] = transpose_bits64(cover_of(en));      // window entries covering column tx
             n += (uint32_t)__popcll(mine[w]);
         }
-        const uint32_t incl = wave_incl_scan(n);
-        const uint32_t total = __shfl(incl, 63, 64);
+        const uint32_t incl = wave_incl_sum(n);
+        const uint32_t total = wave_last(incl);
         const uint32_t off = incl - n;
         __syncthreads();
         if (total <= (uint32_t)kStage) {
@@ -689,7 +675,7 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
     if (c.n_img == 0 || s.n == 0) return hipSuccess;
     const uint64_t n = (uint64_t)s.n;
     hipLaunchKernelGGL(k_row_scatter, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(64),
-                       sizeof(Group) + (size_t)c.ty_max * 4, stream, c, n, bits_for(c.ty_max));
+                       sizeof(ExpandLds) + (size_t)c.ty_max * 4, stream, c, n, bits_for(c.ty_max));
     if (schedule == 1) {
         const int n_cc = (c.tx_max + 63) / 64;
         hipLaunchKernelGGL(k_rowtile_transpose, dim3((unsigned)(c.ty_max * n_cc), (unsigned)c.n_img), dim3(64), 0,
@@ -702,7 +688,7 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
             hipLaunchKernelGGL(k_rowseg_scan, dim3((unsigned)c.ty_max, (unsigned)c.n_img), dim3(64), 0, stream, c,
                                n_seg, seg_off);
         }
-        hipLaunchKernelGGL(k_rowtile_scatter, grid, dim3(64), sizeof(Group) + (size_t)c.tx_max * 4, stream, c, n,
+        hipLaunchKernelGGL(k_rowtile_scatter, grid, dim3(64), sizeof(ExpandLds) + (size_t)c.tx_max * 4, stream, c, n,
                            bits_for(c.tx_max), n_seg, (const uint32_t*)seg_off);
     }
     return hipGetLastError();
