@@ -313,17 +313,29 @@ __global__ __launch_bounds__(256) void k_image_scan(ChunkDev c)
 // ------------------------------------------------------------------ level 1
 // Items are loaded this many groups of 64 ahead (see the header).
 constexpr int kAhead = 4;
+// Independent waves per workgroup in the expansion kernels (each wave has its
+// own item range and LDS; more waves per CU than one-wave workgroups allow).
+constexpr int kWavesPerBlock = 4;
 
-__global__ __launch_bounds__(64) void k_row_scatter(ChunkDev c, uint64_t n, int row_bits)
+// LDS words of one wave: its ExpandLds and `buckets` cursors, rounded up to
+// 16 bytes so that every wave's items stay 16-byte aligned.
+__host__ __device__ constexpr size_t expand_lds_words(int buckets)
+{
+    return (sizeof(ExpandLds) / 4 + (size_t)buckets + 3) & ~(size_t)3;
+}
+
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c, uint64_t n, int row_bits)
 {
     extern __shared__ uint32_t lds[];
-    ExpandLds& ex = *reinterpret_cast<ExpandLds*>(lds);
-    uint32_t* cursor = lds + sizeof(ExpandLds) / 4;
+    const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
+    uint32_t* mine = lds + (size_t)wv * expand_lds_words(c.ty_max);
+    ExpandLds& ex = *reinterpret_cast<ExpandLds*>(mine);
+    uint32_t* cursor = mine + sizeof(ExpandLds) / 4;
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-    const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
+    const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x) * kWavesPerBlock + wv;
     const uint32_t V = c.n ? c.vis_count[i] : 0u;
     const uint32_t j0 = (uint32_t)b * kTileGauss;
-    if (j0 >= V) return;
+    if (b >= c.tile_blocks || j0 >= V) return;     // wave-uniform; the waves of a block never wait on each other
     const uint32_t j1 = min(j0 + (uint32_t)kTileGauss, V);
     const ImageInfo im = c.img[i];
     const uint32_t TY = (uint32_t)im.tiles_y;
@@ -443,17 +455,20 @@ __global__ __launch_bounds__(64) void k_rowseg_scan(ChunkDev c, int n_seg, uint3
 }
 
 // Block (y * n_seg + sg, i): segment sg of tile row y of image i.
-__global__ __launch_bounds__(64) void k_rowtile_scatter(ChunkDev c, uint64_t n, int col_bits, int n_seg,
-                                                        const uint32_t* __restrict__ seg_off)
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDev c, uint64_t n, int col_bits,
+                                                                         int n_seg,
+                                                                         const uint32_t* __restrict__ seg_off)
 {
     extern __shared__ uint32_t lds[];
-    ExpandLds& ex = *reinterpret_cast<ExpandLds*>(lds);
-    uint32_t* cursor = lds + sizeof(ExpandLds) / 4;
+    const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
+    uint32_t* mine = lds + (size_t)wv * expand_lds_words(c.tx_max);
+    ExpandLds& ex = *reinterpret_cast<ExpandLds*>(mine);
+    uint32_t* cursor = mine + sizeof(ExpandLds) / 4;
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-    const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
+    const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x) * kWavesPerBlock + wv;
     const int y = bx / n_seg, sg = bx - y * n_seg;
     const ImageInfo im = c.img[i];
-    if (y >= im.tiles_y) return;
+    if (y >= im.tiles_y) return;        // wave-uniform; the waves of a block never wait on each other
     const uint32_t TX = (uint32_t)im.tiles_x;
     const uint32_t* rr = c.row_range + ((size_t)i * c.ty_max + y) * 2;
     uint32_t r0, r1;
@@ -674,8 +689,9 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
 {
     if (c.n_img == 0 || s.n == 0) return hipSuccess;
     const uint64_t n = (uint64_t)s.n;
-    hipLaunchKernelGGL(k_row_scatter, dim3((unsigned)c.tile_blocks, (unsigned)c.n_img), dim3(64),
-                       sizeof(ExpandLds) + (size_t)c.ty_max * 4, stream, c, n, bits_for(c.ty_max));
+    const unsigned rb = (unsigned)((c.tile_blocks + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(k_row_scatter, dim3(rb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
+                       kWavesPerBlock * expand_lds_words(c.ty_max) * 4, stream, c, n, bits_for(c.ty_max));
     if (schedule == 1) {
         const int n_cc = (c.tx_max + 63) / 64;
         hipLaunchKernelGGL(k_rowtile_transpose, dim3((unsigned)(c.ty_max * n_cc), (unsigned)c.n_img), dim3(64), 0,
@@ -688,7 +704,9 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
             hipLaunchKernelGGL(k_rowseg_scan, dim3((unsigned)c.ty_max, (unsigned)c.n_img), dim3(64), 0, stream, c,
                                n_seg, seg_off);
         }
-        hipLaunchKernelGGL(k_rowtile_scatter, grid, dim3(64), sizeof(ExpandLds) + (size_t)c.tx_max * 4, stream, c, n,
+        const unsigned tb = (unsigned)((c.ty_max * n_seg + kWavesPerBlock - 1) / kWavesPerBlock);
+        hipLaunchKernelGGL(k_rowtile_scatter, dim3(tb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
+                           kWavesPerBlock * expand_lds_words(c.tx_max) * 4, stream, c, n,
                            bits_for(c.tx_max), n_seg, (const uint32_t*)seg_off);
     }
     return hipGetLastError();
