@@ -520,65 +520,95 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDe
 }
 
 // ------------------------------------------------------ level 2, bit transpose
-// One wave per (image, tile row, 64 tile columns).  The row list is read 64
-// entries at a time (lane = entry, in list order).  Each lane turns its
-// entry's x-range into a 64-bit mask over the wave's columns; a 64 x 64 bit
-// transpose across the lanes (six butterfly stages of lane exchanges) then
-// leaves in lane x the set of window entries that cover column x, in list
-// order.  Lane x's entries go to its own tile list, after the tile's earlier
-// entries, so every tile list keeps the row list's (depth, index) order: the
-// same lists as the stable scatter, with no ranks or per-column ballots.
+// One wave per (image, tile row, segment, 64 tile columns).  The row list is
+// read 64 entries at a time (lane = entry, in list order).  Each lane turns
+// its entry's x-range into a 64-bit mask over the wave's columns; a 64 x 64
+// bit transpose across the lanes (six butterfly stages) then leaves in lane x
+// the set of group entries that cover column x, in list order.  Lane x appends
+// them to its own tile list at a cursor held in a register, so every tile list
+// keeps the row list's (depth, index) order: the same lists as the stable
+// scatter, with no ranks, owners or per-column ballots.
+
+// Value of lane (lane ^ S): DPP within quads (S = 1, 2) and rows (S = 8,
+// row_ror:8), LDS-crossbar swizzles within 32 lanes (S = 4, 16), a backward
+// permute across the halves (S = 32).
+template <int S>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v)
+{
+    if constexpr (S == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xf, 0xf, false);  // [1,0,3,2]
+    if constexpr (S == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xf, 0xf, false);  // [2,3,0,1]
+    if constexpr (S == 4) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (4 << 10) | 0x1F);
+    if constexpr (S == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xf, 0xf, false);  // row_ror:8
+    if constexpr (S == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (16 << 10) | 0x1F);
+    return __shfl_xor(v, 32, 64);
+}
+
+// One butterfly stage of the transpose for S < 32 (blocks of S bits inside
+// each 32-bit word; m32 marks the low block of each pair): the lower lane of
+// a pair keeps its low blocks and takes the partner's low blocks moved up,
+// the upper lane keeps its high blocks and takes the partner's high blocks
+// moved down.  A rotation by S (upper) or 32 - S (lower) moves the partner's
+// blocks into place; the wrapped-around bits fall outside the taken mask.
+template <int S>
+__device__ __forceinline__ void transpose_stage(uint32_t& lo, uint32_t& hi, uint32_t m32, bool upper)
+{
+    const uint32_t vlo = xor_lane<S>(lo), vhi = xor_lane<S>(hi);
+    const uint32_t keep = upper ? ~m32 : m32;
+    const uint32_t r = upper ? (uint32_t)S : 32u - (uint32_t)S;
+    lo = (lo & keep) | (__builtin_amdgcn_alignbit(vlo, vlo, r) & ~keep);
+    hi = (hi & keep) | (__builtin_amdgcn_alignbit(vhi, vhi, r) & ~keep);
+}
+
+// Lane x of the result has bit k set iff lane k of the input has bit x set.
 __device__ __forceinline__ uint64_t transpose_bits64(uint64_t w)
 {
     const int lane = __lane_id();
-    uint64_t m = 0x00000000FFFFFFFFull;
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)w, s, 64);
-        const uint32_t hi = __shfl_xor((uint32_t)(w >> 32), s, 64);
-        const uint64_t v = ((uint64_t)hi << 32) | lo;
-        if ((lane & s) == 0) w = (w & m) | ((v & m) << s);
-        else w = (w & ~m) | ((v & ~m) >> s);
-        m ^= m << (s >> 1);         // next stage's mask: bits whose index has bit (s/2) clear
+    uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    {
+        // S = 32: the lower lane's high word and the upper lane's low word trade places
+        const bool upper = lane & 32;
+        const uint32_t got = xor_lane<32>(upper ? lo : hi);
+        lo = upper ? got : lo;
+        hi = upper ? hi : got;
     }
-    return w;
+    transpose_stage<16>(lo, hi, 0x0000FFFFu, lane & 16);
+    transpose_stage<8>(lo, hi, 0x00FF00FFu, lane & 8);
+    transpose_stage<4>(lo, hi, 0x0F0F0F0Fu, lane & 4);
+    transpose_stage<2>(lo, hi, 0x33333333u, lane & 2);
+    transpose_stage<1>(lo, hi, 0x55555555u, lane & 1);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// Windows of kWin entries (kWin / 64 transposes); their pairs are staged in
-// LDS tile by tile and written out by consecutive lanes, so each tile's run
-// of the window leaves as consecutive addresses.  A window with more than
-// kStage pairs (rows of very wide splats) is written lane by lane instead.
-constexpr int kWin = 128;
-constexpr int kStage = 2048;
-
-__global__ __launch_bounds__(64) void k_rowtile_transpose(ChunkDev c, int n_cc)
+// Block (gx, i), wave wv: task gx * kWavesPerBlock + wv over
+// ((tile row * n_seg + segment) * n_cc + column window).
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_transpose(ChunkDev c, int n_seg, int n_cc,
+                                                                           const uint32_t* __restrict__ seg_off)
 {
-    __shared__ uint32_t gs[kWin];
-    __shared__ uint32_t st_g[kStage];
-    __shared__ uint8_t st_x[kStage];
-    __shared__ uint32_t off_l[64], cur_l[64], lim_l[64];
+    __shared__ uint32_t gs_all[kWavesPerBlock][64];
+    const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
+    uint32_t* gs = gs_all[wv];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-    const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
-    const int y = bx / n_cc, cc = bx - y * n_cc;
+    const int i = (int)(L / gridDim.x), task = (int)(L - (uint32_t)i * gridDim.x) * kWavesPerBlock + wv;
+    const int cc = task % n_cc, ys = task / n_cc;
+    const int y = ys / n_seg, sg = ys - y * n_seg;
     const ImageInfo im = c.img[i];
     const uint32_t TX = (uint32_t)im.tiles_x;
     const uint32_t base = (uint32_t)cc * 64u;
-    if (y >= im.tiles_y || base >= TX) return;
+    if (y >= im.tiles_y || base >= TX) return;     // wave-uniform; the waves of a block never wait on each other
     const uint32_t* rr = c.row_range + ((size_t)i * c.ty_max + y) * 2;
-    const uint32_t r0 = rr[0], r1 = rr[1];
+    uint32_t r0, r1;
+    segment_of(rr[0], rr[1], sg, n_seg, &r0, &r1);
     if (r0 >= r1) return;
     const uint2* list = c.rows + c.row_base[i];
     uint32_t* out = c.pairs + c.pair_base[i];
+    const uint32_t P = c.pair_count[i];
     const uint32_t tx = base + (uint32_t)lane;
     uint32_t cur = 0, lim = 0;
     if (tx < TX) {
         const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX + tx) * 2;
-        cur = tr[0];
-        lim = tr[1];
+        cur = n_seg == 1 ? tr[0] : seg_off[(((size_t)i * c.ty_max + y) * n_seg + sg) * c.tx_max + tx];
+        lim = min(tr[1], P);
     }
-    lim_l[lane] = lim;
-    // entries past r1 are empty ranges and cover no column
-    auto load = [&](uint32_t e) { return e < r1 ? list[e] : make_uint2(0u, 0u); };
     auto cover_of = [&](uint2 en) {
         const uint32_t x0 = en.y & 0xFFFFu, x1 = en.y >> 16;
         const uint32_t lo = min(max(x0, base) - base, 64u), hi = min(max(x1, base) - base, 64u);
@@ -586,61 +616,35 @@ __global__ __launch_bounds__(64) void k_rowtile_transpose(ChunkDev c, int n_cc)
         const uint64_t below_lo = lo >= 64u ? ~0ull : ((1ull << lo) - 1ull);
         return below_hi & ~below_lo;
     };
-    uint2 next[kWin / 64];
+    uint2 nx[kAhead];
+    auto load = [&](uint32_t eb) {
 #pragma unroll
-    for (int w = 0; w < kWin / 64; ++w) next[w] = load(r0 + 64u * w + lane);
-    for (uint32_t e0 = r0; e0 < r1; e0 += kWin) {
-        uint64_t mine[kWin / 64];
-        uint32_t n = 0;
-#pragma unroll
-        for (int w = 0; w < kWin / 64; ++w) {
-            const uint2 en = next[w];
-            next[w] = load(e0 + kWin + 64u * w + lane);
-            gs[64 * w + lane] = en.x;
-            mine[w] = transpose_bits64(cover_of(en));      // window entries covering column tx
-            n += (uint32_t)__popcll(mine[w]);
+        for (int w = 0; w < kAhead; ++w) {
+            const uint32_t e = eb + 64u * w + (uint32_t)lane;
+            nx[w] = e < r1 ? list[e] : make_uint2(0u, 0u);
         }
-        const uint32_t incl = wave_incl_sum(n);
-        const uint32_t total = wave_last(incl);
-        const uint32_t off = incl - n;
-        __syncthreads();
-        if (total <= (uint32_t)kStage) {
-            // stage tile by tile (lane x owns [off, off + n)), then write out
-            off_l[lane] = off;
-            cur_l[lane] = cur;
-            uint32_t k = off;
+    };
+    load(r0);
+    for (uint32_t eb = r0; eb < r1; eb += 64u * kAhead) {
+        uint2 en[kAhead];
 #pragma unroll
-            for (int w = 0; w < kWin / 64; ++w) {
-                uint64_t m = mine[w];
-                while (m) {
-                    const int e = __builtin_ctzll(m);
-                    m &= m - 1ull;
-                    st_g[k] = gs[64 * w + e];
-                    st_x[k] = (uint8_t)lane;
-                    ++k;
-                }
-            }
-            __syncthreads();
-            for (uint32_t t = (uint32_t)lane; t < total; t += 64u) {
-                const uint32_t x = st_x[t];
-                const uint32_t pos = cur_l[x] + (t - off_l[x]);
-                if (pos < lim_l[x]) out[pos] = st_g[t];
-            }
-        } else {
-            uint32_t cw = cur;
+        for (int w = 0; w < kAhead; ++w) en[w] = nx[w];
+        if (eb + 64u * kAhead < r1) load(eb + 64u * kAhead);
 #pragma unroll
-            for (int w = 0; w < kWin / 64; ++w) {
-                uint64_t m = mine[w];
-                while (m) {
-                    const int e = __builtin_ctzll(m);
-                    m &= m - 1ull;
-                    if (cw < lim) out[cw] = gs[64 * w + e];
-                    ++cw;
-                }
+        for (int w = 0; w < kAhead; ++w) {
+            if (eb + 64u * w >= r1) break;
+            // entries past r1 were loaded as empty ranges and cover no column
+            gs[lane] = en[w].x;
+            uint64_t m = transpose_bits64(cover_of(en[w]));
+            wave_lds_sync();
+            while (m) {
+                const int e = __builtin_ctzll(m);
+                m &= m - 1ull;
+                if (cur < lim) out[cur] = gs[e];
+                ++cur;
             }
+            wave_lds_sync();
         }
-        cur += n;
-        __syncthreads();
     }
 }
 
@@ -692,18 +696,19 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
     const unsigned rb = (unsigned)((c.tile_blocks + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(k_row_scatter, dim3(rb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
                        kWavesPerBlock * expand_lds_words(c.ty_max) * 4, stream, c, n, bits_for(c.ty_max));
+    if (n_seg < 1 || !seg_off) n_seg = 1;
+    const dim3 grid((unsigned)(c.ty_max * n_seg), (unsigned)c.n_img);
+    if (n_seg > 1) {
+        hipLaunchKernelGGL(k_rowseg_count, grid, dim3(64), (size_t)(c.tx_max + 1) * 4, stream, c, n_seg, seg_off);
+        hipLaunchKernelGGL(k_rowseg_scan, dim3((unsigned)c.ty_max, (unsigned)c.n_img), dim3(64), 0, stream, c, n_seg,
+                           seg_off);
+    }
     if (schedule == 1) {
         const int n_cc = (c.tx_max + 63) / 64;
-        hipLaunchKernelGGL(k_rowtile_transpose, dim3((unsigned)(c.ty_max * n_cc), (unsigned)c.n_img), dim3(64), 0,
-                           stream, c, n_cc);
+        const unsigned tb = (unsigned)((c.ty_max * n_seg * n_cc + kWavesPerBlock - 1) / kWavesPerBlock);
+        hipLaunchKernelGGL(k_rowtile_transpose, dim3(tb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock), 0, stream, c,
+                           n_seg, n_cc, (const uint32_t*)seg_off);
     } else {
-        if (n_seg < 1 || !seg_off) n_seg = 1;
-        const dim3 grid((unsigned)(c.ty_max * n_seg), (unsigned)c.n_img);
-        if (n_seg > 1) {
-            hipLaunchKernelGGL(k_rowseg_count, grid, dim3(64), (size_t)(c.tx_max + 1) * 4, stream, c, n_seg, seg_off);
-            hipLaunchKernelGGL(k_rowseg_scan, dim3((unsigned)c.ty_max, (unsigned)c.n_img), dim3(64), 0, stream, c,
-                               n_seg, seg_off);
-        }
         const unsigned tb = (unsigned)((c.ty_max * n_seg + kWavesPerBlock - 1) / kWavesPerBlock);
         hipLaunchKernelGGL(k_rowtile_scatter, dim3(tb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
                            kWavesPerBlock * expand_lds_words(c.tx_max) * 4, stream, c, n,
