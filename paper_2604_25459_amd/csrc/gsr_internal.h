@@ -107,8 +107,8 @@ struct ChunkDev {
 
 // Depth sort geometry.
 constexpr int kSortBlock = 256;
-constexpr int kSortIpt = 8;
-constexpr int kSortItems = kSortBlock * kSortIpt;   // 2048 items per block
+constexpr int kSortIpt = 16;
+constexpr int kSortItems = kSortBlock * kSortIpt;   // 4096 items per block
 // Tile pass geometry: one wave per block, kTileGauss depth-ordered Gaussians per block.
 constexpr int kTileGauss = 4096;
 

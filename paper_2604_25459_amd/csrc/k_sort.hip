@@ -14,6 +14,7 @@
 // digit order, then writes them out in that order, so each digit's run of
 // the block leaves as consecutive addresses.
 #include "gsr_internal.h"
+#include "gsr_wave.h"
 
 namespace gsr {
 namespace {
@@ -43,12 +44,7 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* tot
 {
     const int lane = __lane_id();
     const int w = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+    const uint32_t x = wave_incl_sum(v);
     if (lane == 63) lds8[w] = x;
     __syncthreads();
     uint32_t pre = 0, tot = 0;
