@@ -470,12 +470,12 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     }
     c.pairs = ws.pairs.as<uint32_t>();
     c.rows = ws.rows.as<uint2>();
-    // long tile-row lists are split into segments of about 4096 entries (one wave each)
+    // long tile-row lists are split into segments of about kRowSegEntries entries (one wave each)
     const uint64_t n_rows = (uint64_t)n_img * (uint64_t)c.ty_max;
     const uint64_t per_row = n_rows ? row_total / n_rows : 0;
-    const int n_seg = (int)std::min<uint64_t>(32, std::max<uint64_t>(1, (per_row + 4095) / 4096));
+    const int n_seg = (int)std::min<uint64_t>(32, std::max<uint64_t>(1, (per_row + kRowSegEntries - 1) / kRowSegEntries));
     uint32_t* seg_off = nullptr;
-    if (n_seg > 1 && tu.bin == 0) {
+    if (n_seg > 1) {
         GSR_HIP_TRY(ws.seg_off.ensure(n_rows * (uint64_t)n_seg * (uint64_t)c.tx_max * 4));
         seg_off = ws.seg_off.as<uint32_t>();
     }

@@ -111,6 +111,8 @@ constexpr int kSortIpt = 16;
 constexpr int kSortItems = kSortBlock * kSortIpt;   // 4096 items per block
 // Tile pass geometry: one wave per block, kTileGauss depth-ordered Gaussians per block.
 constexpr int kTileGauss = 4096;
+// Target length of one level-2 segment of a tile-row list (one wave each).
+constexpr int kRowSegEntries = 1024;
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `stream` and return hipGetLastError().
