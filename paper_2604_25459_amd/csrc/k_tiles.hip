@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_image_scan(ChunkDev c)
 
 // ------------------------------------------------------------------ level 1
 // Items are loaded this many groups of 64 ahead (see the header).
-constexpr int kAhead = 4;
+constexpr int kAhead = 8;
 // Independent waves per workgroup in the expansion kernels (each wave has its
 // own item range and LDS; more waves per CU than one-wave workgroups allow).
 constexpr int kWavesPerBlock = 4;
