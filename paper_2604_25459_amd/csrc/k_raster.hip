@@ -126,6 +126,8 @@ struct RasterLds {
     // per wave, the current 64 candidates re-centred on the wave's block:
     // (a1, b1, c1, -s1), (-s2, lo, z, 0), rgb
     float4 w[Layout<TS>::kWaves][3][64];
+    // per wave, whether it still has live pixels after a batch (by batch parity)
+    uint32_t live[2][Layout<TS>::kWaves];
 };
 
 // Composites tile `bid` of the chunk (block id in segment order).
@@ -226,6 +228,14 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             }
         }
         __syncthreads();
+        // every wave's flag from the previous batch is visible after the
+        // barrier, so all waves take the same decision
+        if (b0 != start) {
+            uint32_t any = 0;
+#pragma unroll
+            for (int ww = 0; ww < L::kWaves; ++ww) any |= L_.live[buf ^ 1][ww];
+            if (!any) break;
+        }
         if (b0 + kBatch < end) fetch(b0 + kBatch);
         const int cnt = (int)min((uint32_t)kBatch, end - b0);
         for (int sub = 0; sub < cnt && wave_live; sub += 64) {
@@ -318,8 +328,8 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             for (int k = 0; k < PPT; ++k) lv = lv || xl[k] < kDeadTest;
             if (__ballot(lv) == 0ull) wave_live = false;
         }
+        if (lane == 0) L_.live[buf][w] = wave_live ? 1u : 0u;
         buf ^= 1;
-        if (__syncthreads_count(wave_live && lane == 0 ? 1 : 0) == 0) break;
     }
 
     // observation epilogue parameters of this image (identity when absent)
