@@ -54,21 +54,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Lanes holding the same key (low `bits` bits) among lanes with `active`:
-// one ballot per bit; a lane keeps the lanes whose bit equals its own.
-__device__ __forceinline__ uint64_t match_key(uint32_t key, bool active, int bits)
-{
-    const uint64_t a = __ballot(active);
-    uint32_t lo = (uint32_t)a, hi = (uint32_t)(a >> 32);
-    for (int b = 0; b < bits; ++b) {
-        const uint64_t m = __ballot((key >> b) & 1u);
-        const uint32_t own = 0u - ((key >> b) & 1u);       // all ones where this lane's bit is set
-        lo &= ~((uint32_t)m ^ own);
-        hi &= ~((uint32_t)(m >> 32) ^ own);
-    }
-    return ((uint64_t)hi << 32) | lo;
-}
-
 // Orders this wave's LDS writes before its later LDS reads (no instruction:
 // LDS requests of one wave are served in order; this keeps the compiler from
 // moving accesses across it).

@@ -47,15 +47,17 @@ namespace {
 // covers the buckets first_k .. first_k + cnt_k - 1 and goes, with its two
 // payload words, to each of those buckets' lists at the bucket's cursor, items
 // in lane order (stable).  `store(pos, v0, v1)` writes one placement.  All 64
-// lanes must take part.
+// lanes must take part.  `occ` (one 64-bit lane mask per bucket, zero between
+// calls) collects the slots of each bucket in the current 64: a slot's rank is
+// the number of lower lanes in its bucket's mask.
 struct ExpandLds {
     uint4 item[64];      // (first - excl, v0, v1, 0): slot p of the item holds bucket item.x + p
     uint32_t mark[64];   // first slot of an item in the current 64 slots -> item + 1 (0 elsewhere)
 };
 
 template <typename Store>
-__device__ __forceinline__ void expand_group(ExpandLds& ex, uint32_t* cursor, uint32_t cnt, uint32_t first,
-                                             uint32_t v0, uint32_t v1, uint32_t n_buckets, int bits, Store store)
+__device__ __forceinline__ void expand_group(ExpandLds& ex, uint64_t* occ, uint32_t* cursor, uint32_t cnt,
+                                             uint32_t first, uint32_t v0, uint32_t v1, uint32_t n_buckets, Store store)
 {
     const int lane = __lane_id();
     const uint32_t inc = wave_incl_sum(cnt);
@@ -79,11 +81,16 @@ __device__ __forceinline__ void expand_group(ExpandLds& ex, uint32_t* cursor, ui
             bkt = it.x + p;
             ok = bkt < n_buckets;
         }
-        const uint64_t peers = match_key(bkt, ok, bits);
+        if (ok) atomicOr(reinterpret_cast<unsigned long long*>(&occ[bkt]), 1ull << lane);
+        wave_lds_sync();
         if (ok) {
+            const uint64_t peers = occ[bkt];
             const uint32_t below = lanes_below(peers);
             const uint32_t basev = cursor[bkt];
-            if (below == 0u) cursor[bkt] = basev + (uint32_t)__popcll(peers);
+            if (below == 0u) {          // the bucket's lowest slot advances its cursor and clears its mask
+                cursor[bkt] = basev + (uint32_t)__popcll(peers);
+                occ[bkt] = 0ull;
+            }
             store(basev + below, it.y, it.z);
         }
         wave_lds_sync();
@@ -317,20 +324,22 @@ constexpr int kAhead = 8;
 // own item range and LDS; more waves per CU than one-wave workgroups allow).
 constexpr int kWavesPerBlock = 4;
 
-// LDS words of one wave: its ExpandLds and `buckets` cursors, rounded up to
-// 16 bytes so that every wave's items stay 16-byte aligned.
+// LDS words of one wave: its ExpandLds, `buckets` 64-bit slot masks and
+// `buckets` cursors, rounded up to 16 bytes so that every wave's items stay
+// 16-byte aligned.
 __host__ __device__ constexpr size_t expand_lds_words(int buckets)
 {
-    return (sizeof(ExpandLds) / 4 + (size_t)buckets + 3) & ~(size_t)3;
+    return (sizeof(ExpandLds) / 4 + 3 * (size_t)buckets + 3) & ~(size_t)3;
 }
 
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c, uint64_t n, int row_bits)
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c, uint64_t n)
 {
     extern __shared__ uint32_t lds[];
     const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
     uint32_t* mine = lds + (size_t)wv * expand_lds_words(c.ty_max);
     ExpandLds& ex = *reinterpret_cast<ExpandLds*>(mine);
-    uint32_t* cursor = mine + sizeof(ExpandLds) / 4;
+    uint64_t* occ = reinterpret_cast<uint64_t*>(mine + sizeof(ExpandLds) / 4);
+    uint32_t* cursor = mine + sizeof(ExpandLds) / 4 + 2 * (size_t)c.ty_max;
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x) * kWavesPerBlock + wv;
     const uint32_t V = c.n ? c.vis_count[i] : 0u;
@@ -340,7 +349,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c,
     const ImageInfo im = c.img[i];
     const uint32_t TY = (uint32_t)im.tiles_y;
     const uint32_t* off = c.row_hist + ((size_t)i * c.tile_blocks + b) * c.ty_max;
-    for (uint32_t y = lane; y < TY; y += 64) cursor[y] = off[y];
+    for (uint32_t y = lane; y < TY; y += 64) {
+        cursor[y] = off[y];
+        occ[y] = 0ull;
+    }
     ex.mark[lane] = 0u;
     uint2* out = c.rows + c.row_base[i];
     const uint32_t Rn = c.row_count[i];
@@ -375,7 +387,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c,
             const uint32_t x0 = r.x & 0xFFFFu, x1 = r.x >> 16, y0 = r.y & 0xFFFFu, y1 = r.y >> 16;
             // guard: sorted ids are valid indices by construction
             const bool okg = jw + (uint32_t)lane < j1 && g < n && x1 > x0 && y1 > y0;
-            expand_group(ex, cursor, okg ? y1 - y0 : 0u, y0, g, x0 | (x1 << 16), TY, row_bits,
+            expand_group(ex, occ, cursor, okg ? y1 - y0 : 0u, y0, g, x0 | (x1 << 16), TY,
                          [&](uint32_t pos, uint32_t v0, uint32_t v1) {
                              if (pos < Rn) out[pos] = make_uint2(v0, v1);
                          });
@@ -455,15 +467,15 @@ __global__ __launch_bounds__(64) void k_rowseg_scan(ChunkDev c, int n_seg, uint3
 }
 
 // Block (y * n_seg + sg, i): segment sg of tile row y of image i.
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDev c, uint64_t n, int col_bits,
-                                                                         int n_seg,
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDev c, uint64_t n, int n_seg,
                                                                          const uint32_t* __restrict__ seg_off)
 {
     extern __shared__ uint32_t lds[];
     const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
     uint32_t* mine = lds + (size_t)wv * expand_lds_words(c.tx_max);
     ExpandLds& ex = *reinterpret_cast<ExpandLds*>(mine);
-    uint32_t* cursor = mine + sizeof(ExpandLds) / 4;
+    uint64_t* occ = reinterpret_cast<uint64_t*>(mine + sizeof(ExpandLds) / 4);
+    uint32_t* cursor = mine + sizeof(ExpandLds) / 4 + 2 * (size_t)c.tx_max;
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x) * kWavesPerBlock + wv;
     const int y = bx / n_seg, sg = bx - y * n_seg;
@@ -482,6 +494,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDe
         const uint32_t* so = seg_off + (((size_t)i * c.ty_max + y) * n_seg + sg) * c.tx_max;
         for (uint32_t x = lane; x < TX; x += 64) cursor[x] = so[x];
     }
+    for (uint32_t x = lane; x < TX; x += 64) occ[x] = 0ull;
     ex.mark[lane] = 0u;
     uint32_t* out = c.pairs + c.pair_base[i];
     const uint32_t P = c.pair_count[i];
@@ -511,7 +524,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDe
                 const uint32_t x1 = min(ent.y >> 16, TX);
                 cnt = x1 > x0 ? x1 - x0 : 0u;
             }
-            expand_group(ex, cursor, cnt, x0, ent.x, 0u, TX, col_bits,
+            expand_group(ex, occ, cursor, cnt, x0, ent.x, 0u, TX,
                          [&](uint32_t pos, uint32_t v0, uint32_t) {
                              if (pos < P) out[pos] = v0;
                          });
@@ -663,13 +676,6 @@ __global__ __launch_bounds__(256) void k_debug_keys(ChunkDev c, int image, uint6
     }
 }
 
-int bits_for(int v)
-{
-    int b = 1;
-    while ((1 << b) < v) ++b;
-    return b;
-}
-
 }  // namespace
 
 hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t stream)
@@ -695,7 +701,7 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
     const uint64_t n = (uint64_t)s.n;
     const unsigned rb = (unsigned)((c.tile_blocks + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(k_row_scatter, dim3(rb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
-                       kWavesPerBlock * expand_lds_words(c.ty_max) * 4, stream, c, n, bits_for(c.ty_max));
+                       kWavesPerBlock * expand_lds_words(c.ty_max) * 4, stream, c, n);
     if (n_seg < 1 || !seg_off) n_seg = 1;
     const dim3 grid((unsigned)(c.ty_max * n_seg), (unsigned)c.n_img);
     if (n_seg > 1) {
@@ -711,8 +717,8 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
     } else {
         const unsigned tb = (unsigned)((c.ty_max * n_seg + kWavesPerBlock - 1) / kWavesPerBlock);
         hipLaunchKernelGGL(k_rowtile_scatter, dim3(tb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
-                           kWavesPerBlock * expand_lds_words(c.tx_max) * 4, stream, c, n,
-                           bits_for(c.tx_max), n_seg, (const uint32_t*)seg_off);
+                           kWavesPerBlock * expand_lds_words(c.tx_max) * 4, stream, c, n, n_seg,
+                           (const uint32_t*)seg_off);
     }
     return hipGetLastError();
 }
