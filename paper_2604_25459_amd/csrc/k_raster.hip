@@ -50,6 +50,9 @@ constexpr float kCullMargin = 0.05f;                  // in log2(alpha) units
 // -inf and the pixel never takes another Gaussian; no separate liveness flag
 // is needed in the per-Gaussian loop.
 constexpr float kDead = 1.0e30f;
+// log2(0.99) less a little: a Gaussian whose log2(opacity) is at most this
+// never reaches alpha = 0.99, so its blends skip the clamp.
+constexpr float kLog2ClampFree = -0.0145f;
 constexpr float kDeadTest = 1.0e29f;
 
 // Pixel layout: TS <= 16: one pixel per thread, waves own 8x8 blocks.
@@ -255,12 +258,13 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             // ballot: which of these 64 Gaussians can touch the live pixels;
             // survivors are re-centred into the wave's slots
             const int jl = sub + lane;
-            bool keep = false;
+            bool keep = false, bright = false;
             if (jl < cnt) {
                 const float4 a = sA[buf][jl];
                 const float4 bq = sB[buf][jl];
                 const float m = max_logalpha_rect(a.z, a.w, bq.x, bq.y, lx0 - a.x, lx1 - a.x, ly0 - a.y, ly1 - a.y);
                 keep = m >= kLogAlphaMin - kCullMargin;
+                bright = keep && bq.y > kLog2ClampFree;
                 if (keep) {
                     const float du = a.x - cxo, dv = a.y - cyo;
                     const float s1 = fmaf(a.z, du, a.w * dv), s2 = bq.x * dv;
@@ -270,6 +274,7 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
                 }
             }
             uint64_t mask = __ballot(keep);
+            const uint64_t clampmask = __ballot(bright);       // survivors that may reach alpha = 0.99
             wave_lds_sync();
             while (mask) {
                 const int j = (int)__builtin_ctzll(mask);
@@ -289,10 +294,17 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
                 const float4 col = W[2][j];
                 float al[PPT], wgt[PPT];
                 bool anystop = false;
+                const bool clamp = (clampmask >> j) & 1ull;     // wave-uniform
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     const bool take = pw[k] >= kLogAlphaMin;
-                    al[k] = take ? fminf(0.99f, __builtin_amdgcn_exp2f(pw[k])) : 0.0f;
+                    float e = __builtin_amdgcn_exp2f(pw[k]);
+                    if (clamp) {
+                        // only survivors whose opacity can reach 0.99 pay for the clamp
+                        asm volatile("");
+                        e = fminf(0.99f, e);
+                    }
+                    al[k] = take ? e : 0.0f;
                     wgt[k] = al[k] * T[k];
                     T[k] = T[k] - wgt[k];                   // unchanged where the pixel does not take it
                     anystop = anystop || T[k] < 1e-4f;      // only a taking pixel can fall below (T >= 1e-4)
