@@ -266,8 +266,9 @@ typedef struct {
 int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* desc, void* stream);
 
 /* Binning and projection of image `image` (camera-slot-major index) of
- * `desc`, copied to host arrays.  Synchronous.  Output pointers of `desc` are
- * not used.  GSR_E_INVALID if out->capacity is smaller than the number of
+ * `desc`, copied to host arrays (tile lists built with the level-2 schedule
+ * tuned for this scene and batch shape).  Synchronous.  Output pointers of
+ * `desc` are not used.  GSR_E_INVALID if out->capacity is smaller than the number of
  * pairs (n_pairs is still reported). */
 int gsr_debug_bins(gsr_ctx* ctx, const gsr_render_desc* desc, int image, gsr_bins_out* out);
 int gsr_debug_project(gsr_ctx* ctx, const gsr_render_desc* desc, int image, gsr_proj_out* out);

@@ -674,6 +674,7 @@ int debug_run(gsr_ctx* ctx, const gsr_render_desc* d, int image, Mode mode, Scen
     job->tune.ts = ctx->opt.tile_size;
     job->tune.batch = 64;
     job->tune.ipt = 1;
+    job->tune.bin = tuning_for(ctx, sc, d).bin;     // the tile lists as the tuned renderer builds them
     job->imgs = images_of(d, ctx->opt.tile_size, sc->dev.n_bodies);
     job->viewmats = d->viewmats;
     job->poses = d->body_poses;

@@ -90,9 +90,9 @@ def test_autotune_and_cache_roundtrip(tmp_path):
 
 
 def test_schedules_agree_on_wide_splats():
-    """Splats wider than the image put thousands of pairs into one window of
-    the transposed level-2 schedule (its lane-by-lane path); both schedules
-    must still produce the scatter's pixels bit for bit."""
+    """Splats wider than the image cover every column of a transposed group
+    (64 entries x 64 columns all set); both level-2 schedules must still
+    produce the same pixels bit for bit."""
     torch = _torch()
     from paper_2604_25459_amd import gsr
     from tests.scenes import one_camera, scene_from
@@ -110,6 +110,36 @@ def test_schedules_agree_on_wide_splats():
     for sched in (0, 1):
         R.set_tuning(sid, cams, vm, poses, bin_schedule=sched)
         outs.append(R.render(sid, cams, vm, poses, alpha=True))
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert torch.equal(a, b)
+    R.close()
+
+
+def test_transposed_schedule_on_a_wide_image():
+    """1920 x 1080 at 16-pixel tiles: 120 tile columns, so the transposed
+    level-2 schedule runs two 64-column windows per row segment.  Its tile lists
+    equal the oracle's bit for bit, and both schedules give the same pixels."""
+    torch = _torch()
+    from paper_2604_25459_amd import gsr, synth
+    from oracle import bin_ref
+    scene = synth.make_scene(63, 40_000, 2, 4_000, sh_degree=1, half_box=4.0)
+    rng = np.random.default_rng(21)
+    batch = synth.Batch(cams=[synth.pinhole(1920, 1080, 70.0)], viewmats=synth.orbit_viewmats(rng, 2, 3.0, 5.0)[None],
+                        poses=synth.random_poses(rng, 2, scene.n_bodies))
+    R = gsr.Renderer(0)
+    sid = R.add_synth_scene(scene)
+    cams, vm, poses = gsr.batch_tensors(batch)
+    outs = []
+    for sched in (0, 1):
+        R.set_tuning(sid, cams, vm, poses, bin_schedule=sched)
+        outs.append(R.render(sid, cams, vm, poses, alpha=True))
+        if sched == 1:
+            got = R.debug_bins(sid, cams, vm, poses, 1)
+            ref = bin_ref(scene, batch, 0, 1, R.tile_size)
+            assert ref.ranges.shape[0] == 120 * 68
+            np.testing.assert_array_equal(got["keys"], ref.keys)
+            np.testing.assert_array_equal(got["values"], ref.values)
+            np.testing.assert_array_equal(got["ranges"], ref.ranges)
     for a, b in zip(outs[0][0], outs[1][0]):
         assert torch.equal(a, b)
     R.close()
