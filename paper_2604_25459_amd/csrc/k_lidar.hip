@@ -176,6 +176,7 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
     constexpr int NT = TS * TS;
     constexpr int kLBatch = NT;
     __shared__ float4 sr[kLidarRec][kLBatch];
+    __shared__ uint32_t live_w[2][NT / 64];     // per wave: live rays left after a batch (by batch parity)
     const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
     int sgi = 0;
 #pragma unroll
@@ -230,8 +231,17 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
     const float4* rec = c.rec + (size_t)i * (size_t)s.n * kLidarRec;
     const uint32_t n = (uint32_t)s.n;
     bool wave_live = __ballot(live) != 0ull;
-    for (uint32_t b0 = start; b0 < end; b0 += kLBatch) {
+    int par = 0;
+    for (uint32_t b0 = start; b0 < end; b0 += kLBatch, par ^= 1) {
         __syncthreads();
+        // every wave's flag from the previous batch is visible after the
+        // barrier, so all waves take the same decision
+        if (b0 != start) {
+            uint32_t any = 0;
+#pragma unroll
+            for (int ww = 0; ww < NT / 64; ++ww) any |= live_w[par ^ 1][ww];
+            if (!any) break;
+        }
         const uint32_t e = b0 + (uint32_t)tid;
         if (e < end) {
             uint32_t g = list[e];
@@ -286,7 +296,7 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
             }
             if (__ballot(live) == 0ull) wave_live = false;
         }
-        if (__syncthreads_count(wave_live && lane == 0 ? 1 : 0) == 0) break;
+        if (lane == 0) live_w[par][tid >> 6] = wave_live ? 1u : 0u;
     }
     if (inside) {
         const size_t pix = (size_t)row * im.width + col;
