@@ -314,6 +314,11 @@ Tuning tuning_for(gsr_ctx* ctx, const SceneRes* sc, const gsr_render_desc* d)
 
 namespace {
 
+// Tile rectangles are packed into 4 bytes when every image of the chunk has at
+// most kRect4MaxTiles tiles per axis (half the traffic of the rectangle
+// gather in the last sort pass and of its readers).
+int rect4_format(int tx_max, int ty_max) { return tx_max <= kRect4MaxTiles && ty_max <= kRect4MaxTiles ? 1 : 0; }
+
 ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, int i0, int n_img,
                     const std::vector<ImageInfo>& imgs)
 {
@@ -329,6 +334,7 @@ ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, int i
     c.t_max = t_max;
     c.tx_max = tx_max;
     c.ty_max = ty_max;
+    c.rect4 = rect4_format(tx_max, ty_max);
     c.sort_blocks = p.sort_blocks;
     c.tile_blocks = p.tile_blocks;
     c.img = ws.img.as<ImageInfo>() + i0;
@@ -1104,11 +1110,21 @@ GSR_EXPORT int gsr_debug_project(gsr_ctx* ctx, const gsr_render_desc* d, int ima
         if (hipMemcpy(r.data(), ws->rect.p, (size_t)n * 8, hipMemcpyDeviceToHost) != hipSuccess) {
             rc = fail(GSR_E_DEVICE, "copy of rectangles failed");
         } else {
+            const ImageInfo& im = job.imgs[image];
+            const bool packed = rect4_format(im.tiles_x, im.tiles_y) != 0;   // the debug chunk is this one image
             for (int64_t g = 0; g < n; ++g) {
-                out->rect[4 * g + 0] = (int32_t)(r[2 * g] & 0xFFFF);
-                out->rect[4 * g + 1] = (int32_t)(r[2 * g] >> 16);
-                out->rect[4 * g + 2] = (int32_t)(r[2 * g + 1] & 0xFFFF);
-                out->rect[4 * g + 3] = (int32_t)(r[2 * g + 1] >> 16);
+                if (packed) {
+                    const uint32_t v = r[g];
+                    out->rect[4 * g + 0] = (int32_t)(v & 0xFF);
+                    out->rect[4 * g + 1] = (int32_t)((v >> 8) & 0xFF);
+                    out->rect[4 * g + 2] = (int32_t)((v >> 16) & 0xFF);
+                    out->rect[4 * g + 3] = (int32_t)(v >> 24);
+                } else {
+                    out->rect[4 * g + 0] = (int32_t)(r[2 * g] & 0xFFFF);
+                    out->rect[4 * g + 1] = (int32_t)(r[2 * g] >> 16);
+                    out->rect[4 * g + 2] = (int32_t)(r[2 * g + 1] & 0xFFFF);
+                    out->rect[4 * g + 3] = (int32_t)(r[2 * g + 1] >> 16);
+                }
             }
         }
     }

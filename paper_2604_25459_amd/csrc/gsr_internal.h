@@ -73,6 +73,35 @@ struct RasterSeg {
     uint32_t tiles_per_image;
 };
 constexpr int kMaxSegs = 8;
+constexpr int kRect4MaxTiles = 255;
+
+// Tile rectangle [x0, x1) x [y0, y1) of entry k in either format.
+__device__ __forceinline__ void put_rect(void* a, int rect4, size_t k, uint32_t x0, uint32_t x1, uint32_t y0,
+                                         uint32_t y1)
+{
+    if (rect4) static_cast<uint32_t*>(a)[k] = x0 | (x1 << 8) | (y0 << 16) | (y1 << 24);
+    else static_cast<uint2*>(a)[k] = make_uint2(x0 | (x1 << 16), y0 | (y1 << 16));
+}
+// Raw entry k (the u32 in .x for the packed format), decoded by decode_rect.
+__device__ __forceinline__ uint2 raw_rect(const void* a, int rect4, size_t k)
+{
+    return rect4 ? make_uint2(static_cast<const uint32_t*>(a)[k], 0u) : static_cast<const uint2*>(a)[k];
+}
+__device__ __forceinline__ void decode_rect(uint2 r, int rect4, uint32_t* x0, uint32_t* x1, uint32_t* y0,
+                                            uint32_t* y1)
+{
+    if (rect4) {
+        *x0 = r.x & 0xFFu;
+        *x1 = (r.x >> 8) & 0xFFu;
+        *y0 = (r.x >> 16) & 0xFFu;
+        *y1 = r.x >> 24;
+    } else {
+        *x0 = r.x & 0xFFFFu;
+        *x1 = r.x >> 16;
+        *y0 = r.y & 0xFFFFu;
+        *y1 = r.y >> 16;
+    }
+}
 
 // Per-chunk device buffers and sizes handed to the kernels.
 struct ChunkDev {
@@ -84,7 +113,7 @@ struct ChunkDev {
     const ImageInfo* img;      // [n_img]
     float* xform;              // [n_img][n_bodies + 1][16]
     uint32_t* keyz;            // [n_img][n] depth bits or kInvalidKey
-    uint2* rect;               // [n_img][n] (x0 | x1 << 16, y0 | y1 << 16)
+    uint2* rect;               // [n_img][n] tile rectangle (format: rect4 below)
     float4* rec;               // [n_img][n][3] raster records ([..][5] for LiDAR)
     uint32_t* sk[2];           // depth-sort keys, ping-pong [n_img][n]
     uint32_t* sv[2];           // depth-sort values (Gaussian ids); sorted result in sv[1]
@@ -98,6 +127,10 @@ struct ChunkDev {
     uint32_t* pairs;           // [total pairs] Gaussian id per (tile, depth)-sorted entry
     int ty_max;                // largest tile-row count of an image in the chunk
     int tx_max;                // largest tile-column count
+    // Rectangle format of rect / srect: 1 = one u32 per entry, bytes (x0, x1, y0,
+    // y1), used when every image has at most kRect4MaxTiles tiles per axis; 0 =
+    // one uint2 per entry (x0 | x1 << 16, y0 | y1 << 16).
+    int rect4;
     uint32_t* row_hist;        // [n_img][tile_blocks][ty_max] per-block row counts, then offsets
     uint32_t* row_range;       // [n_img][ty_max][2] local [start, end) of each tile-row list
     uint32_t* row_count;       // [n_img] R_i (entries of all row lists)

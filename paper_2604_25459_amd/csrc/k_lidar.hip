@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
         c.keyz[o] = vis ? __float_as_uint(D) : kInvalidKey;
         if (!vis) continue;
         const int x0 = c0 / ts, x1 = (c1 + ts - 1) / ts, y0 = r0 / ts, y1 = (r1 + ts - 1) / ts;
-        c.rect[o] = make_uint2((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16));
+        put_rect(c.rect, c.rect4, o, (uint32_t)x0, (uint32_t)x1, (uint32_t)y0, (uint32_t)y1);
         // whitening W = S^-1 (A Rg)^T: row k = (A Rg)[:, k] / s_k
         float Rs[9];
         mat3_mul(A, Rg, Rs);

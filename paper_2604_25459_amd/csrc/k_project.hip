@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
         const size_t o = (size_t)i * (size_t)s.n + (size_t)g;
         c.keyz[o] = vis ? __float_as_uint(tz) : kInvalidKey;
         if (!vis) continue;
-        c.rect[o] = make_uint2((uint32_t)ix0 | ((uint32_t)ix1 << 16), (uint32_t)iy0 | ((uint32_t)iy1 << 16));
+        put_rect(c.rect, c.rect4, o, (uint32_t)ix0, (uint32_t)ix1, (uint32_t)iy0, (uint32_t)iy1);
 
         // Raster record: the quadratic form of the conic in whitened form,
         //     log2(alpha) = log2(o) - (a1 dx + b1 dy)^2 - (c1 dy)^2,

@@ -114,7 +114,8 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
                                                       uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                       const uint32_t* __restrict__ counts, uint64_t n, int shift,
                                                       const uint32_t* __restrict__ hist, int blocks,
-                                                      const uint2* __restrict__ rect, uint2* __restrict__ srect)
+                                                      const uint2* __restrict__ rect, uint2* __restrict__ srect,
+                                                      int rect4)
 {
     __shared__ uint32_t cnt[4][256];
     __shared__ uint32_t lstart[256], gbase[256], lds8[8];
@@ -187,7 +188,10 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
         if (pos < n) {      // guard: offsets are consistent by construction
             kout[seg + pos] = k;
             vout[seg + pos] = v;
-            if (LAST && v < n) srect[seg + pos] = rect[seg + v];
+            if (LAST && v < n) {
+                if (rect4) reinterpret_cast<uint32_t*>(srect)[seg + pos] = reinterpret_cast<const uint32_t*>(rect)[seg + v];
+                else srect[seg + pos] = rect[seg + v];
+            }
         }
     }
 }
@@ -205,7 +209,7 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
     hipLaunchKernelGGL(k_sort_scan<true>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
                        c.vis_count, n);
     hipLaunchKernelGGL((k_sort_scatter<true, false>), grid, dim3(256), 0, stream, c.keyz, (const uint32_t*)nullptr,
-                       c.sk[0], c.sv[0], c.vis_count, n, 0, c.sort_hist, c.sort_blocks, c.rect, c.srect);
+                       c.sk[0], c.sv[0], c.vis_count, n, 0, c.sort_hist, c.sort_blocks, c.rect, c.srect, c.rect4);
     int src = 0;
     for (int pass = 1; pass < 4; ++pass) {
         const int shift = 8 * pass;
@@ -216,11 +220,11 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
         if (pass == 3)
             hipLaunchKernelGGL((k_sort_scatter<false, true>), grid, dim3(256), 0, stream, c.sk[src], c.sv[src],
                                c.sk[src ^ 1], c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks, c.rect,
-                               c.srect);
+                               c.srect, c.rect4);
         else
             hipLaunchKernelGGL((k_sort_scatter<false, false>), grid, dim3(256), 0, stream, c.sk[src], c.sv[src],
                                c.sk[src ^ 1], c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks,
-                               c.rect, c.srect);
+                               c.rect, c.srect, c.rect4);
         src ^= 1;
     }
     // pass 0 wrote buffer 0; passes 1..3 alternate, so the sorted result is in buffer 1

@@ -106,11 +106,7 @@ __device__ __forceinline__ bool sorted_rect(const ChunkDev& c, uint64_t n, int i
     if (j >= j1) return false;
     *g = c.sv[1][(size_t)i * n + j];
     if (*g >= n) return false;      // guard: sorted ids are valid indices by construction
-    const uint2 r = c.srect[(size_t)i * n + j];
-    *x0 = r.x & 0xFFFFu;
-    *x1 = r.x >> 16;
-    *y0 = r.y & 0xFFFFu;
-    *y1 = r.y >> 16;
+    decode_rect(raw_rect(c.srect, c.rect4, (size_t)i * n + j), c.rect4, x0, x1, y0, y1);
     return *x1 > *x0 && *y1 > *y0;
 }
 
@@ -364,7 +360,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c,
         for (int w = 0; w < kAhead; ++w) {
             const uint32_t j = jb + 64u * w + (uint32_t)lane;
             gn[w] = j < j1 ? c.sv[1][seg + j] : 0u;
-            rn[w] = j < j1 ? c.srect[seg + j] : make_uint2(0u, 0u);
+            rn[w] = j < j1 ? raw_rect(c.srect, c.rect4, seg + j) : make_uint2(0u, 0u);
         }
     };
     load(j0);
@@ -384,7 +380,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c,
             if (jw >= j1) break;
             const uint32_t g = gc[w];
             const uint2 r = rc[w];
-            const uint32_t x0 = r.x & 0xFFFFu, x1 = r.x >> 16, y0 = r.y & 0xFFFFu, y1 = r.y >> 16;
+            uint32_t x0, x1, y0, y1;
+            decode_rect(r, c.rect4, &x0, &x1, &y0, &y1);
             // guard: sorted ids are valid indices by construction
             const bool okg = jw + (uint32_t)lane < j1 && g < n && x1 > x0 && y1 > y0;
             expand_group(ex, occ, cursor, okg ? y1 - y0 : 0u, y0, g, x0 | (x1 << 16), TY,
