@@ -350,6 +350,30 @@ def test_many_tiny_images_one_launch(R):
     R.remove_scene(sid)
 
 
+def test_rectangles_beyond_255_tiles_per_axis(R):
+    """A 4160 x 64 panorama: 260 tile columns, more than the packed 4-byte
+    rectangle holds, so the chunk keeps the 2 x 16-bit rectangle format;
+    projection rectangles, tile lists and pixels still match the oracle."""
+    scene = synth.make_scene(64, 20_000, 1, 2_000, sh_degree=1, half_box=5.0)
+    rng = np.random.default_rng(14)
+    cam = synth.pinhole(4160, 64, 120.0)
+    batch = synth.Batch(cams=[cam], viewmats=synth.orbit_viewmats(rng, 1, 1.0, 1.5)[None],
+                        poses=synth.random_poses(rng, 1, scene.n_bodies))
+    sid = _upload(R, scene)
+    from paper_2604_25459_amd import gsr
+    cams, vm, poses = gsr.batch_tensors(batch)
+    proj = R.debug_project(sid, cams, vm, poses, 0, scene.n)
+    p = project32(scene, batch, 0, 0, R.tile_size)
+    vis = p["visible"]
+    assert p["rect"][vis][:, 1].max() > 255
+    np.testing.assert_array_equal(proj["rect"][vis], p["rect"][vis])
+    ref = _check_bins(R, sid, scene, batch, 0, 0)
+    assert ref.tiles_x == 260
+    got = _render(R, sid, batch)
+    _check_image(_img(got, 0, 0), render_ref(scene, batch, 0, 0, R.tile_size), "4160x64")
+    R.remove_scene(sid)
+
+
 def test_stage_totals_match_oracle_bins():
     """The profiled renderer's totals of visible Gaussians and (tile,
     Gaussian) pairs equal the sums of the oracle's binning over the images."""
