@@ -97,15 +97,12 @@ __device__ __forceinline__ void expand_group(ExpandLds& ex, uint64_t* occ, uint3
     }
 }
 
-// Depth-ordered Gaussian j of image i: id and tile rectangle (x0, x1, y0, y1).
-__device__ __forceinline__ bool sorted_rect(const ChunkDev& c, uint64_t n, int i, uint32_t j, uint32_t j1, uint32_t* g,
+// Tile rectangle (x0, x1, y0, y1) of the depth-ordered Gaussian j of image i.
+__device__ __forceinline__ bool sorted_rect(const ChunkDev& c, uint64_t n, int i, uint32_t j, uint32_t j1,
                                             uint32_t* x0, uint32_t* x1, uint32_t* y0, uint32_t* y1)
 {
-    *g = 0;
     *x0 = *x1 = *y0 = *y1 = 0;
     if (j >= j1) return false;
-    *g = c.sv[1][(size_t)i * n + j];
-    if (*g >= n) return false;      // guard: sorted ids are valid indices by construction
     decode_rect(raw_rect(c.srect, c.rect4, (size_t)i * n + j), c.rect4, x0, x1, y0, y1);
     return *x1 > *x0 && *y1 > *y0;
 }
@@ -143,8 +140,8 @@ __global__ __launch_bounds__(256) void k_tile_hist(ChunkDev c, uint64_t n)
     for (int y = tid; y < Q1; y += 256) rdiff[y] = 0;
     __syncthreads();
     for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += 256) {
-        uint32_t g, x0, x1, y0, y1;
-        if (sorted_rect(c, n, i, j, j1, &g, &x0, &x1, &y0, &y1) && x1 <= (uint32_t)im.tiles_x &&
+        uint32_t x0, x1, y0, y1;
+        if (sorted_rect(c, n, i, j, j1, &x0, &x1, &y0, &y1) && x1 <= (uint32_t)im.tiles_x &&
             y1 <= (uint32_t)im.tiles_y) {
             atomicAdd(&diff[y0 * P1 + x0], 1);
             atomicAdd(&diff[y0 * P1 + x1], -1);
