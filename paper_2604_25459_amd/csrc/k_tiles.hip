@@ -46,13 +46,15 @@ namespace {
 // Expansion of one group of 64 items (lane = item, in list order): item k
 // covers the buckets first_k .. first_k + cnt_k - 1 and goes, with its two
 // payload words, to each of those buckets' lists at the bucket's cursor, items
-// in lane order (stable).  `store(pos, v0, v1)` writes one placement.  All 64
-// lanes must take part.  `occ` (one 64-bit lane mask per bucket, zero between
-// calls) collects the slots of each bucket in the current 64: a slot's rank is
-// the number of lower lanes in its bucket's mask.
+// in list order (stable).  `store(pos, v0, v1)` writes one placement.  All 64
+// lanes must take part.  Slots are expanded 128 at a time, two per lane
+// (p0 + lane and p0 + 64 + lane); `occ` holds two 64-bit lane masks per bucket
+// (zero between calls), one per half, which collect the bucket's slots: a
+// slot's rank is the number of its bucket's slots in lower lanes of its own
+// half, plus all of them in the first half when it lies in the second.
 struct ExpandLds {
     uint4 item[64];      // (first - excl, v0, v1, 0): slot p of the item holds bucket item.x + p
-    uint32_t mark[64];   // first slot of an item in the current 64 slots -> item + 1 (0 elsewhere)
+    uint32_t mark[128];  // first slot of an item in the current 128 slots -> item + 1 (0 elsewhere)
 };
 
 template <typename Store>
@@ -64,34 +66,64 @@ __device__ __forceinline__ void expand_group(ExpandLds& ex, uint64_t* occ, uint3
     const uint32_t excl = inc - cnt;
     const uint32_t total = wave_last(inc);
     ex.item[lane] = make_uint4(first - excl, v0, v1, 0u);
+    const uint64_t bit = 1ull << lane;
     uint32_t carry = 0;          // owner + 1 of the last slot of the previous iteration
-    for (uint32_t p0 = 0; p0 < total; p0 += 64) {
-        if (cnt != 0 && excl >= p0 && excl < p0 + 64u) ex.mark[excl - p0] = (uint32_t)lane + 1u;
+    for (uint32_t p0 = 0; p0 < total; p0 += 128) {
+        if (cnt != 0 && excl >= p0 && excl < p0 + 128u) ex.mark[excl - p0] = (uint32_t)lane + 1u;
         wave_lds_sync();
-        const uint32_t mk = ex.mark[lane];
+        const uint32_t mka = ex.mark[lane], mkb = ex.mark[64 + lane];
         ex.mark[lane] = 0u;
-        const uint32_t own = max(wave_incl_max(mk), carry);
-        carry = wave_last(own);
-        const uint32_t p = p0 + (uint32_t)lane;
-        bool ok = p < total && own != 0u;
-        uint4 it = make_uint4(0u, 0u, 0u, 0u);
-        uint32_t bkt = 0;
-        if (ok) {
-            it = ex.item[(own - 1u) & 63u];
-            bkt = it.x + p;
-            ok = bkt < n_buckets;
+        ex.mark[64 + lane] = 0u;
+        const uint32_t owna = max(wave_incl_max(mka), carry);
+        const uint32_t ownb = max(wave_incl_max(mkb), wave_last(owna));
+        carry = wave_last(ownb);
+        const uint32_t pa = p0 + (uint32_t)lane, pb = pa + 64u;
+        bool oka = pa < total && owna != 0u, okb = pb < total && ownb != 0u;
+        uint4 ita = make_uint4(0u, 0u, 0u, 0u), itb = ita;
+        uint32_t ba = 0, bb = 0;
+        if (oka) {
+            ita = ex.item[(owna - 1u) & 63u];
+            ba = ita.x + pa;
+            oka = ba < n_buckets;
         }
-        if (ok) atomicOr(reinterpret_cast<unsigned long long*>(&occ[bkt]), 1ull << lane);
+        if (okb) {
+            itb = ex.item[(ownb - 1u) & 63u];
+            bb = itb.x + pb;
+            okb = bb < n_buckets;
+        }
+        if (oka) atomicOr(reinterpret_cast<unsigned long long*>(&occ[2 * ba]), bit);
+        if (okb) atomicOr(reinterpret_cast<unsigned long long*>(&occ[2 * bb + 1]), bit);
         wave_lds_sync();
-        if (ok) {
-            const uint64_t peers = occ[bkt];
-            const uint32_t below = lanes_below(peers);
-            const uint32_t basev = cursor[bkt];
-            if (below == 0u) {          // the bucket's lowest slot advances its cursor and clears its mask
-                cursor[bkt] = basev + (uint32_t)__popcll(peers);
-                occ[bkt] = 0ull;
+        // every read precedes the cursor and mask updates below (LDS requests
+        // of one wave are served in order)
+        uint64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+        uint32_t basea = 0, baseb = 0;
+        if (oka) {
+            a0 = occ[2 * ba];
+            a1 = occ[2 * ba + 1];
+            basea = cursor[ba];
+        }
+        if (okb) {
+            b0 = occ[2 * bb];
+            b1 = occ[2 * bb + 1];
+            baseb = cursor[bb];
+        }
+        if (oka) {
+            const uint32_t below = lanes_below(a0);
+            if (below == 0u) {          // the bucket's first slot advances its cursor and clears its masks
+                cursor[ba] = basea + (uint32_t)(__popcll(a0) + __popcll(a1));
+                occ[2 * ba] = 0ull;
+                occ[2 * ba + 1] = 0ull;
             }
-            store(basev + below, it.y, it.z);
+            store(basea + below, ita.y, ita.z);
+        }
+        if (okb) {
+            const uint32_t below = lanes_below(b1);
+            if (b0 == 0ull && below == 0u) {
+                cursor[bb] = baseb + (uint32_t)__popcll(b1);
+                occ[2 * bb + 1] = 0ull;
+            }
+            store(baseb + (uint32_t)__popcll(b0) + below, itb.y, itb.z);
         }
         wave_lds_sync();
     }
@@ -317,12 +349,12 @@ constexpr int kAhead = 8;
 // own item range and LDS; more waves per CU than one-wave workgroups allow).
 constexpr int kWavesPerBlock = 4;
 
-// LDS words of one wave: its ExpandLds, `buckets` 64-bit slot masks and
-// `buckets` cursors, rounded up to 16 bytes so that every wave's items stay
-// 16-byte aligned.
+// LDS words of one wave: its ExpandLds, two 64-bit slot masks and a cursor per
+// bucket, rounded up to 16 bytes so that every wave's items stay 16-byte
+// aligned.
 __host__ __device__ constexpr size_t expand_lds_words(int buckets)
 {
-    return (sizeof(ExpandLds) / 4 + 3 * (size_t)buckets + 3) & ~(size_t)3;
+    return (sizeof(ExpandLds) / 4 + 5 * (size_t)buckets + 3) & ~(size_t)3;
 }
 
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c, uint64_t n)
@@ -332,7 +364,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c,
     uint32_t* mine = lds + (size_t)wv * expand_lds_words(c.ty_max);
     ExpandLds& ex = *reinterpret_cast<ExpandLds*>(mine);
     uint64_t* occ = reinterpret_cast<uint64_t*>(mine + sizeof(ExpandLds) / 4);
-    uint32_t* cursor = mine + sizeof(ExpandLds) / 4 + 2 * (size_t)c.ty_max;
+    uint32_t* cursor = mine + sizeof(ExpandLds) / 4 + 4 * (size_t)c.ty_max;
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x) * kWavesPerBlock + wv;
     const uint32_t V = c.n ? c.vis_count[i] : 0u;
@@ -344,9 +376,11 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c,
     const uint32_t* off = c.row_hist + ((size_t)i * c.tile_blocks + b) * c.ty_max;
     for (uint32_t y = lane; y < TY; y += 64) {
         cursor[y] = off[y];
-        occ[y] = 0ull;
+        occ[2 * y] = 0ull;
+        occ[2 * y + 1] = 0ull;
     }
     ex.mark[lane] = 0u;
+    ex.mark[64 + lane] = 0u;
     uint2* out = c.rows + c.row_base[i];
     const uint32_t Rn = c.row_count[i];
     const size_t seg = (size_t)i * n;
@@ -469,7 +503,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDe
     uint32_t* mine = lds + (size_t)wv * expand_lds_words(c.tx_max);
     ExpandLds& ex = *reinterpret_cast<ExpandLds*>(mine);
     uint64_t* occ = reinterpret_cast<uint64_t*>(mine + sizeof(ExpandLds) / 4);
-    uint32_t* cursor = mine + sizeof(ExpandLds) / 4 + 2 * (size_t)c.tx_max;
+    uint32_t* cursor = mine + sizeof(ExpandLds) / 4 + 4 * (size_t)c.tx_max;
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x) * kWavesPerBlock + wv;
     const int y = bx / n_seg, sg = bx - y * n_seg;
@@ -488,8 +522,12 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDe
         const uint32_t* so = seg_off + (((size_t)i * c.ty_max + y) * n_seg + sg) * c.tx_max;
         for (uint32_t x = lane; x < TX; x += 64) cursor[x] = so[x];
     }
-    for (uint32_t x = lane; x < TX; x += 64) occ[x] = 0ull;
+    for (uint32_t x = lane; x < TX; x += 64) {
+        occ[2 * x] = 0ull;
+        occ[2 * x + 1] = 0ull;
+    }
     ex.mark[lane] = 0u;
+    ex.mark[64 + lane] = 0u;
     uint32_t* out = c.pairs + c.pair_base[i];
     const uint32_t P = c.pair_count[i];
     uint2 nx[kAhead];
