@@ -161,11 +161,11 @@ hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t s
 hipError_t launch_project_lidar(const SceneDev& s, const ChunkDev& c, int ts, int ipt, hipStream_t stream);
 
 // Stable two-level scatter: depth-ordered Gaussians -> tile-row lists -> tile lists.
-// schedule 0: level 2 as a stable scatter (one wave per tile row, ballot
-// ranks); 1: by a bit transpose (one lane per tile column appends the window
-// entries that cover it).  Both give identical tile lists.
-// n_seg: segments per tile-row list for schedule 0 (seg_off: n_img * ty_max *
-// n_seg * tx_max words of scratch when n_seg > 1).
+// schedule 0: level 2 as a stable expansion (one wave per row segment, ranks
+// from per-bucket lane masks); 1: by a bit transpose (one lane per tile column
+// appends the group entries that cover it).  Both give identical tile lists.
+// n_seg: segments per tile-row list (seg_off: n_img * ty_max * n_seg * tx_max
+// words of scratch when n_seg > 1).
 hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedule, int n_seg, uint32_t* seg_off,
                                hipStream_t stream);
 struct RasterParams {

@@ -14,18 +14,18 @@
 //   level 1  depth-ordered Gaussians -> one list per tile row (a Gaussian
 //            appears in each row its rectangle spans), blocks of kTileGauss
 //            Gaussians, one output stream per tile row;
-//   level 2  one block per (image, tile row) walks its row list in order and
-//            expands each entry into the tiles of that row, one output stream
-//            per tile of the row.
+//   level 2  one wave per segment of an (image, tile row) list walks it in
+//            order and expands each entry into the tiles of that row, one
+//            output stream per tile of the row.
 // The last depth-sort pass leaves every rectangle in depth order and row-list
 // entries carry their x-range, so no stage gathers rectangles by id.
 // Expansions are never written out: each kernel re-expands a group of 64
-// items at a time, balanced over one wave (lane = expansion slot).  A slot's
-// item is found by marking each item's first slot and taking a prefix maximum
-// across the lanes; ranks of equal buckets among the 64 slots come from a
-// ballot match, and a per-bucket cursor in LDS carries the rank across
-// iterations.  Item loads run several groups ahead, so a wave waits for its
-// own scattered stores only once per batch of groups.
+// items at a time, balanced over one wave (two expansion slots per lane).  A
+// slot's item is found by marking each item's first slot and taking a prefix
+// maximum across the lanes; ranks of equal buckets among the slots come from
+// per-bucket lane masks in LDS, and a per-bucket cursor in LDS carries the
+// rank across iterations.  Item loads run several groups ahead, so a wave
+// waits for its own scattered stores only once per batch of groups.
 //
 // Kernels:
 //   k_tile_hist       tile and tile-row counts as difference arrays (LDS atomics)
