@@ -211,6 +211,10 @@ def main():
     ap.add_argument("--no-storage-check", dest="storage_check", action="store_false",
                     help="skip the FP16/BF16 storage leg (throughput and per-image error)")
     ap.add_argument("--no-graphs", action="store_true", help="launch every stage eagerly (no graph replay)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run every memory chunk on the render stream (no two-stream chunk overlap)")
+    ap.add_argument("--no-one-stream-leg", dest="one_stream_leg", action="store_false",
+                    help="skip the comparison leg that runs the same steps on one stream")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary of two rocprofv3 --pmc runs of this bench and exit")
     ap.add_argument("--pmc-out", default=os.path.join(ROOT, PMC_SUMMARY))
@@ -230,8 +234,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build renders on one GPU only; run with --gpus 1 (multi-GPU sharding is "
-                          "described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "libgsr renders on one GPU per process and this benchmark times one GPU; "
+                          "run with --gpus 1"}))
         sys.exit(2)
 
     import numpy as np
@@ -251,7 +255,7 @@ def main():
     log(f"[bench] config {args.config}: generating workload")
     scene, batch = synth.make_config(args.config, n_envs=args.envs or None)
     E, C = batch.n_envs, batch.n_cams
-    R = gsr.Renderer(0, tile_size=args.tile, profile=True, graphs=not args.no_graphs)
+    R = gsr.Renderer(0, tile_size=args.tile, profile=True, graphs=not args.no_graphs, overlap=not args.no_overlap)
     sid = R.add_synth_scene(scene, args.storage)
     cams, vm, _ = gsr.batch_tensors(batch)
     dev = torch.device("cuda", 0)
@@ -284,6 +288,30 @@ def main():
     value = E * args.steps / sec
     ms_per_step = 1000.0 * sec / args.steps
     log(f"[bench] {value:.1f} env-frames/s, {ms_per_step:.2f} ms/step, stages {st}")
+
+    # the same steps with every chunk on the render stream: the gain of the
+    # two-stream overlap, and a stage breakdown in which no stages share the GPU
+    one_stream = None
+    if not args.no_overlap and args.one_stream_leg:
+        R1 = gsr.Renderer(0, tile_size=args.tile, profile=True, graphs=not args.no_graphs, overlap=False)
+        sid1 = R1.add_synth_scene(scene, args.storage)
+        if tuning:
+            R1.set_tuning(sid1, cams, vm, poses[0], **{k: v for k, v in tuning.items() if k != "ms"})
+        R1.render_into(sid1, cams, vm, poses[0], rgb, depth, None, tuple(batch.bg))
+        torch.cuda.synchronize()
+        R1.stage_times(reset=True)
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            R1.render_into(sid1, cams, vm, poses[args.warmup + s], rgb, depth, None, tuple(batch.bg))
+        torch.cuda.synchronize()
+        osec = time.perf_counter() - t0
+        ost = R1.stage_times(reset=True)
+        one_stream = {"value": E * args.steps / osec, "unit": "env-frames/s",
+                      "ms_per_step": 1000.0 * osec / args.steps,
+                      "stages_ms_per_step": {k: v / args.steps for k, v in ost.items() if k in R.STAGES}}
+        R1.close()
+        del R1
+        log(f"[bench] one stream: {one_stream['value']:.1f} env-frames/s, stages {one_stream['stages_ms_per_step']}")
 
     # policy-ready observations: same workload, u8 pixels with per-image exposure /
     # contrast / brightness randomisation fused into the rasteriser, no float colour
@@ -468,13 +496,14 @@ def main():
         "config": {"workload": synth.CONFIG_NAMES[args.config], "envs": E, "cams": C,
                    "resolution": [[c.width, c.height] for c in cams], "gaussians": scene.n,
                    "sh_degree": scene.sh_degree, "storage": args.storage, "tile": args.tile,
-                   "tuning": tuning},
+                   "tuning": tuning, "chunk_streams": 1 if args.no_overlap else 2},
         "plain_path": plain,
         "observation_path": observation,
         "lidar": lidar,
         "half_storage": storage,
         "serving": serving,
         "stages_ms_per_step": {k: v / args.steps for k, v in st.items() if k in R.STAGES},
+        "one_stream": one_stream,
         "path": path,
         "host": host,
         "roofline": roof,

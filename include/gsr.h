@@ -76,7 +76,11 @@ typedef struct {
     int profile;            /* 1 = record HIP events around every pipeline stage (see gsr_stage_times) */
     int graphs;             /* 0 = capture the per-chunk stages of gsr_render into hipGraphs and replay them
                                (default); -1 = launch every kernel eagerly */
-    int reserved[6];
+    int overlap;            /* 0 = when a render has several memory chunks, run alternate chunks on two streams
+                               (the caller's and an internal one, joined back before the call's work ends) with
+                               a second working set, so one chunk's binning overlaps another's rasterisation
+                               (default); -1 = one stream, one working set */
+    int reserved[5];
 } gsr_options;
 
 /* A scene: static background plus Gaussian clusters bound to rigid bodies
@@ -209,7 +213,11 @@ int gsr_scene_info(gsr_ctx* ctx, uint64_t scene_id, int64_t* n, int* n_bodies, i
  * memory chunk.  Inputs and outputs are caller-owned device memory and must
  * stay valid until the stream passes this call.  The call blocks the host
  * thread once per chunk until that chunk's pair count is known (to size the
- * tile lists), then returns with rasterisation still in flight.
+ * tile lists), then returns with rasterisation still in flight.  With several
+ * chunks, odd chunks run on an internal stream of the context (see
+ * gsr_options.overlap) that waits for the caller's stream at the call's start
+ * and is joined back into it before the call returns, so work the caller
+ * queues on `stream` afterwards sees every image finished.
  * gsr_render_plain: same contract and results, one image at a time (one
  * launch chain per image, per-image sort): the reference per-environment path. */
 int gsr_render(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
@@ -364,7 +372,10 @@ int gsr_tuning_load(gsr_ctx* ctx, const char* path);
 
 /* Stage timers of a context created with profile = 1: device milliseconds
  * accumulated over the renders since the last reset, measured with HIP events
- * recorded on the render stream.  ms[0] compose + project, ms[1] depth sort,
+ * recorded on the stream each chunk runs on (with two-stream overlap the
+ * stages of neighbouring chunks share the GPU, so a stage's time includes the
+ * slowdown from the other stream and the stages can sum to more than the
+ * wall time).  ms[0] compose + project, ms[1] depth sort,
  * ms[2] tile count, ms[3] tile scatter, ms[4] raster, ms[5] launches of the
  * raster kernel, ms[6] renders timed; if n >= 10 also the totals over the
  * timed renders of ms[7] visible Gaussians, ms[8] (tile, Gaussian) pairs,

@@ -88,6 +88,10 @@ Workspace::~Workspace()
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     counter.release();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    twin.reset();
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
 }
 
 // ------------------------------------------------------------------ planning
@@ -410,8 +414,30 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     const Tuning& tu = job.tune;
     const bool prof = ctx->opt.profile && mode == Mode::kRender;
     StageEvents ev;
+    // events of a chunk that fails before they are queued for reading go back to the spares
+    struct Lease {
+        gsr_ctx* ctx;
+        StageEvents& ev;
+        bool queued = false;
+        ~Lease()
+        {
+            if (queued) return;
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            for (hipEvent_t e : ev.e)
+                if (e) ctx->spare_events.push_back(e);
+        }
+    } lease{ctx, ev};
     if (prof) {
-        for (hipEvent_t& e : ev.e) GSR_HIP_TRY(hipEventCreate(&e));
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            for (hipEvent_t& e : ev.e) {
+                if (ctx->spare_events.empty()) break;
+                e = ctx->spare_events.back();
+                ctx->spare_events.pop_back();
+            }
+        }
+        for (hipEvent_t& e : ev.e)
+            if (!e) GSR_HIP_TRY(hipEventCreate(&e));
         GSR_HIP_TRY(hipEventRecord(ev.e[0], st));
     }
     // everything the captured launches depend on
@@ -535,6 +561,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
         GSR_HIP_TRY(hipEventRecord(ev.e[5], st));
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->pending.push_back(ev);
+        lease.queued = true;
     }
     return GSR_OK;
 }
@@ -552,7 +579,7 @@ Workspace* acquire_workspace_locked(gsr_ctx* ctx, hipStream_t stream)
 }
 
 int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_in, hipStream_t st, bool plain,
-               bool graphs)
+               bool graphs, bool two_streams)
 {
     if (job_in.imgs.empty()) return GSR_OK;
     RenderJob job = job_in;
@@ -576,15 +603,48 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
     GSR_HIP_TRY(hipMemcpyAsync(ws.img.p, ws.h_img, job.imgs.size() * sizeof(ImageInfo), hipMemcpyHostToDevice, st));
     if (plain) job.tune.ipt = 1;
     const bool use_graphs = graphs && !plain && ctx->opt.graphs >= 0;
+    // Two streams: even chunks on the caller's stream in `ws`, odd chunks on
+    // ws.side in ws.twin.  The host's wait for chunk k+1's pair total then
+    // ends while chunk k still rasterises, and chunk k+1's lists and raster
+    // follow on the other stream, so binning and raster of neighbouring
+    // chunks share the GPU.  Each workspace is used by one stream only.
+    const int n_chunks = (int)((job.imgs.size() + plan.chunk - 1) / plan.chunk);
+    const bool two = two_streams && !plain && ctx->opt.overlap >= 0 && n_chunks > 1;
+    Workspace* wk[2] = {&ws, &ws};
+    hipStream_t sq[2] = {st, st};
+    if (two) {
+        if (!ws.twin) ws.twin.reset(new (std::nothrow) Workspace());
+        if (!ws.twin) return fail(GSR_E_OOM, "workspace allocation failed");
+        Workspace& t = *ws.twin;
+        if (!ws.side) GSR_HIP_TRY(hipStreamCreateWithFlags(&ws.side, hipStreamNonBlocking));
+        if (!ws.ev_fork) GSR_HIP_TRY(hipEventCreateWithFlags(&ws.ev_fork, hipEventDisableTiming));
+        if (!ws.ev_join) GSR_HIP_TRY(hipEventCreateWithFlags(&ws.ev_join, hipEventDisableTiming));
+        // the twin's earlier work was joined into `st` before ws.ev_done
+        GSR_HIP_TRY(ensure_workspace(t, sc, plan, job.imgs.size(), rec_bytes));
+        std::memcpy(t.h_img, job.imgs.data(), job.imgs.size() * sizeof(ImageInfo));
+        GSR_HIP_TRY(hipMemcpyAsync(t.img.p, t.h_img, job.imgs.size() * sizeof(ImageInfo), hipMemcpyHostToDevice, st));
+        GSR_HIP_TRY(hipEventRecord(ws.ev_fork, st));
+        GSR_HIP_TRY(hipStreamWaitEvent(ws.side, ws.ev_fork, 0));
+        wk[1] = &t;
+        sq[1] = ws.side;
+    }
     int chunk_idx = 0;
-    for (int i0 = 0; i0 < (int)job.imgs.size(); i0 += plan.chunk, ++chunk_idx) {
+    int rc = GSR_OK;
+    for (int i0 = 0; i0 < (int)job.imgs.size() && !rc; i0 += plan.chunk, ++chunk_idx) {
         const int n_img = std::min<int>(plan.chunk, (int)job.imgs.size() - i0);
+        const int h = chunk_idx & 1;
         uint64_t total = 0;
-        const int rc = run_chunk(ctx, ws, sc, job, plan, i0, n_img, chunk_idx, st, Mode::kRender, use_graphs, &total);
-        if (rc) {
-            if (rc == GSR_E_DEVICE) ctx->poisoned = true;
-            return rc;
-        }
+        rc = run_chunk(ctx, *wk[h], sc, job, plan, i0, n_img, chunk_idx, sq[h], Mode::kRender, use_graphs, &total);
+    }
+    if (two) {
+        // join the side stream even after a failure, so ws.ev_done covers it
+        const hipError_t e1 = hipEventRecord(ws.ev_join, ws.side);
+        const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(st, ws.ev_join, 0) : e1;
+        if (e2 != hipSuccess && !rc) rc = hip_fail(e2, "joining the side stream");
+    }
+    if (rc) {
+        if (rc == GSR_E_DEVICE) ctx->poisoned = true;
+        return rc;
     }
     GSR_HIP_TRY(hipEventRecord(ws.ev_done, st));
     ws.used = true;
@@ -647,7 +707,7 @@ int render_impl(gsr_ctx* ctx, const gsr_render_desc* d, void* stream, bool plain
         job.poses = d->body_poses;
         job.viewmat_floats = (size_t)d->n_cams * d->n_envs * 12;
         job.pose_floats = (size_t)d->n_envs * sc->dev.n_bodies * 7;
-        rc = render_job(ctx, *ws, sc, job, st, plain, true);
+        rc = render_job(ctx, *ws, sc, job, st, plain, true, true);
     }
     if (!rc) rc = mark_scene_use(ctx, sc, st);
     {
@@ -753,6 +813,8 @@ GSR_EXPORT int gsr_destroy(gsr_ctx* ctx)
         for (StageEvents& ev : ctx->pending)
             for (hipEvent_t e : ev.e) (void)hipEventDestroy(e);
         ctx->pending.clear();
+        for (hipEvent_t e : ctx->spare_events) (void)hipEventDestroy(e);
+        ctx->spare_events.clear();
         ctx->pool.clear();
         ctx->scenes.clear();
     }
@@ -877,7 +939,7 @@ GSR_EXPORT int gsr_stage_times(gsr_ctx* ctx, double* ms, int n, int reset)
             ctx->stage_ms[k] += t;
         }
         ctx->raster_launches += 1;
-        for (hipEvent_t e : ev.e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev.e) ctx->spare_events.push_back(e);
     }
     ctx->pending.clear();
     for (int k = 0; k < 5; ++k) ms[k] = ctx->stage_ms[k];
@@ -1028,7 +1090,7 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
         job.poses = d->body_poses;
         job.viewmat_floats = (size_t)d->n_lidars * E * 12;
         job.pose_floats = (size_t)E * B * 7;
-        return render_job(ctx, *ws, sc, job, st, false, false);
+        return render_job(ctx, *ws, sc, job, st, false, false, true);
     };
     rc = body();
     if (!rc) rc = mark_scene_use(ctx, sc, st);

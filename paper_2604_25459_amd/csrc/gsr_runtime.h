@@ -88,6 +88,11 @@ struct Workspace {
     DevBuf counter;         // persistent raster tile counter
     hipStream_t capture_stream = nullptr;          // graphs are captured here, launched on the caller's stream
     std::map<std::pair<int, int>, StageGraph> graphs;   // (chunk index, stage) -> executable graph
+    // Second half of a two-stream render: odd chunks run on `side` in `twin`'s
+    // buffers, so one chunk's binning overlaps the previous chunk's raster.
+    std::unique_ptr<Workspace> twin;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ~Workspace();
 };
 
@@ -126,9 +131,11 @@ hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& 
                             size_t rec_bytes = 48);
 
 // Enqueue the whole job on `st` (blocks once per chunk for its pair count);
-// `graphs` allows replaying captured stage graphs (batched path only).
+// `graphs` allows replaying captured stage graphs (batched path only);
+// `two_streams` allows running alternate chunks on ws.side in ws.twin (when
+// the context's overlap option is on), joined back into `st`.
 int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, hipStream_t st, bool plain,
-               bool graphs);
+               bool graphs, bool two_streams);
 
 // Scene lookup that pins the scene against destruction; release_scene unpins.
 SceneRes* acquire_scene(gsr_ctx* ctx, uint64_t id);
@@ -148,6 +155,7 @@ struct gsr_ctx {
     uint64_t next_id = 1;
     std::vector<std::unique_ptr<gsr::Workspace>> pool;
     std::vector<gsr::StageEvents> pending;            // recorded, not yet read
+    std::vector<hipEvent_t> spare_events;             // read stage events, reused by later renders
     double stage_ms[5] = {0, 0, 0, 0, 0};
     double raster_launches = 0, renders = 0;
     double count_visible = 0, count_pairs = 0, count_rows = 0;   // profiled renders

@@ -119,8 +119,10 @@ int render_batch(gsr_server* srv, Workspace& ws, hipStream_t st, const std::vect
     std::stable_sort(job.imgs.begin(), job.imgs.end(), [](const ImageInfo& a, const ImageInfo& b) {
         return a.width != b.width ? a.width < b.width : a.height < b.height;
     });
-    // batches change composition from one to the next: launched eagerly, not captured
-    int rc = render_job(ctx, ws, sc, job, st, false, false);
+    // batches change composition from one to the next: launched eagerly, not
+    // captured; one working set per batch, as the memory admission assumes
+    // (the server's own streams already overlap batches)
+    int rc = render_job(ctx, ws, sc, job, st, false, false, false);
     if (!rc) rc = mark_scene_use(ctx, sc, st);
     if (!rc) GSR_HIP_TRY(hipStreamSynchronize(st));
     return rc;

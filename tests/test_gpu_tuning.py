@@ -36,6 +36,52 @@ def test_graph_replays_match_eager():
     Re.close()
 
 
+def test_two_stream_chunks_match_one_stream():
+    """Alternate memory chunks on two streams give the bits of one stream, and
+    work queued on the caller's stream after the call sees finished images."""
+    torch = _torch()
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(3, n_envs=8)       # 16 images in chunks of 3: six chunks
+    R1 = gsr.Renderer(0, overlap=False)
+    R2 = gsr.Renderer(0)
+    s1, s2 = R1.add_synth_scene(scene), R2.add_synth_scene(scene)
+    cams, vm, poses = gsr.batch_tensors(batch)
+    R1.set_tuning(s1, cams, vm, poses, chunk_images=3)
+    R2.set_tuning(s2, cams, vm, poses, chunk_images=3)
+    dev = vm.device
+    for step in range(3):                 # new poses every step: graph capture, then replays
+        poses = torch.from_numpy(synth.make_poses(3, step, 8, scene.n_bodies)).to(dev)
+        ref = [[t.clone() for t in slot] for slot in R1.render(s1, cams, vm, poses, alpha=True)]
+        got = [[t.clone() for t in slot] for slot in R2.render(s2, cams, vm, poses, alpha=True)]
+        torch.cuda.synchronize()
+        for slot_ref, slot_got in zip(ref, got):
+            for a, b in zip(slot_ref, slot_got):
+                assert torch.equal(a, b), f"step {step}"
+    R1.close()
+    R2.close()
+
+
+def test_two_stream_lidar_chunks_match_one_stream():
+    torch = _torch()
+    from paper_2604_25459_amd import gsr
+    scene = synth.make_scene(52, 120_000, 3, 20_000, sh_degree=0, half_box=3.0)
+    rng = np.random.default_rng(7)
+    E = 12
+    lid = synth.rotating_lidar(16, 256, -20, 20)
+    vm = torch.from_numpy(synth.sensor_viewmats(rng, E, 0.5, 2.5, 0.1)[None].copy()).cuda()
+    poses = torch.from_numpy(synth.random_poses(rng, E, scene.n_bodies)).cuda()
+    out = []
+    for overlap in (False, True):
+        R = gsr.Renderer(0, chunk_bytes=64 << 20, overlap=overlap)   # a few scans per chunk
+        sid = R.add_synth_scene(scene)
+        rng_, hit = R.render_lidar(sid, [lid], vm, poses)[0]
+        out.append((rng_.clone(), hit.clone()))
+        torch.cuda.synchronize()
+        R.close()
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert (out[0][1] > 0.1).sum() > 100
+
+
 @pytest.mark.parametrize("params", [dict(tile_size=8, lds_batch=64), dict(tile_size=8, lds_batch=256),
                                     dict(tile_size=32, lds_batch=512), dict(lds_batch=512, images_per_thread=1),
                                     dict(images_per_thread=8, persistent=1), dict(persistent=1, chunk_images=3),
