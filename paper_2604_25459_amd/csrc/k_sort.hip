@@ -108,7 +108,8 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
 }
 
 // LAST: also gathers each Gaussian's tile rectangle into depth order (once,
-// so later stages read rectangles contiguously).
+// so later stages read rectangles contiguously), and writes only the values:
+// later stages read the depth order, not the keys.
 template <bool FIRST, bool LAST>
 __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
         const uint32_t dg = (k >> shift) & 255u;
         const uint32_t pos = gbase[dg] + (t - lstart[dg]);
         if (pos < n) {      // guard: offsets are consistent by construction
-            kout[seg + pos] = k;
+            if (!LAST) kout[seg + pos] = k;     // the final keys are not read again
             vout[seg + pos] = v;
             if (LAST && v < n) {
                 if (rect4) reinterpret_cast<uint32_t*>(srect)[seg + pos] = reinterpret_cast<const uint32_t*>(rect)[seg + v];
@@ -227,7 +228,8 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
                                c.rect, c.srect, c.rect4);
         src ^= 1;
     }
-    // pass 0 wrote buffer 0; passes 1..3 alternate, so the sorted result is in buffer 1
+    // pass 0 wrote buffer 0; passes 1..3 alternate, so the sorted values are in sv[1] (the last
+    // pass writes no keys)
     return hipGetLastError();
 }
 
