@@ -421,7 +421,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
         bool queued = false;
         ~Lease()
         {
-            if (queued) return;
+            if (queued || !ev.e[0]) return;
             std::lock_guard<std::mutex> lk(ctx->mu);
             for (hipEvent_t e : ev.e)
                 if (e) ctx->spare_events.push_back(e);
