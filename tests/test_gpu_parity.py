@@ -210,11 +210,17 @@ def test_cfg1_batch_independence_and_plain(R):
 
 
 def test_cfg2_full_batch_sampled(R):
+    # the benchmark's launch configuration: four 512-image chunks, alternate
+    # chunks on the second stream; envs from even and odd chunks
     scene, batch = synth.make_config(2)
     sid = _upload(R, scene)
+    from paper_2604_25459_amd import gsr
+    cams, vm, poses = gsr.batch_tensors(batch)
+    R.set_tuning(sid, cams, vm, poses, tile_size=16, lds_batch=64, images_per_thread=8, persistent=0,
+                 chunk_images=0, bin_schedule=0)
     got = _render(R, sid, batch)
     assert tuple(got[0][0].shape) == (2048, 480, 640, 3)
-    for e in (0, 1337):
+    for e in (0, 700, 1337, 2047):
         _check_bins(R, sid, scene, batch, 0, e)
         ref = render_ref(scene, batch, 0, e, R.tile_size)
         _check_image(_img(got, 0, e), ref, f"cfg2 env {e}")
