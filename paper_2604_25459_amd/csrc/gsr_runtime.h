@@ -86,7 +86,7 @@ struct Workspace {
     bool used = false;      // ev_done has been recorded at least once
     bool in_call = false;   // owned by a render call right now
     DevBuf counter;         // persistent raster tile counter
-    hipStream_t capture_stream = nullptr;          // graphs are captured here, launched on the caller's stream
+    hipStream_t capture_stream = nullptr;          // graphs are captured here, launched on the chunk's stream
     std::map<std::pair<int, int>, StageGraph> graphs;   // (chunk index, stage) -> executable graph
     // Second half of a two-stream render: odd chunks run on `side` in `twin`'s
     // buffers, so one chunk's binning overlaps the previous chunk's raster.
