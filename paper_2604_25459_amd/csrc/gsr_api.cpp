@@ -368,7 +368,7 @@ ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, int i
 
 // One pipeline stage, launched eagerly or as a captured graph.  Graphs are
 // captured on the workspace's private stream (capture executes nothing) and
-// launched on the caller's stream; a graph is re-captured when anything its
+// launched on the chunk's stream; a graph is re-captured when anything its
 // launches depend on (buffers, sizes, parameters) changed.
 int run_stage(Workspace& ws, bool graph, int chunk_idx, int stage, const std::vector<uint64_t>& key, hipStream_t st,
               const std::function<hipError_t(hipStream_t)>& fn)
