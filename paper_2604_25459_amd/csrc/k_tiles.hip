@@ -495,7 +495,7 @@ __global__ __launch_bounds__(64) void k_rowseg_scan(ChunkDev c, int n_seg, uint3
 }
 
 // Block (y * n_seg + sg, i): segment sg of tile row y of image i.
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDev c, uint64_t n, int n_seg,
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDev c, int n_seg,
                                                                          const uint32_t* __restrict__ seg_off)
 {
     extern __shared__ uint32_t lds[];
@@ -749,7 +749,7 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
     } else {
         const unsigned tb = (unsigned)((c.ty_max * n_seg + kWavesPerBlock - 1) / kWavesPerBlock);
         hipLaunchKernelGGL(k_rowtile_scatter, dim3(tb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
-                           kWavesPerBlock * expand_lds_words(c.tx_max) * 4, stream, c, n, n_seg,
+                           kWavesPerBlock * expand_lds_words(c.tx_max) * 4, stream, c, n_seg,
                            (const uint32_t*)seg_off);
     }
     return hipGetLastError();
