@@ -93,6 +93,14 @@ __device__ __forceinline__ float max_logalpha_rect(float a1, float b1, float c1,
                                                    float Y1)
 {
     if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return lo;
+    // The quadratic is convex with its minimum at the mean, which lies outside
+    // the rectangle, so its minimum over the rectangle lies on an edge that
+    // faces the mean: x = X0 if X0 > 0, x = X1 if X1 < 0, and likewise in y.
+    // One x edge and one y edge are evaluated; where the mean lies between
+    // X0 and X1 (or Y0 and Y1) the edge taken in that axis is just more of
+    // the rectangle, which cannot lower the minimum.
+    const float Xe = X0 > 0.0f ? X0 : X1;
+    const float Ye = Y0 > 0.0f ? Y0 : Y1;
     // On an edge x = X the quadratic is smallest at y = ky X, on y = Y at
     // x = kx Y.  An approximate reciprocal moves the evaluated point along the
     // edge by a relative 1e-7, which lowers the bound by a second-order amount
@@ -101,23 +109,13 @@ __device__ __forceinline__ float max_logalpha_rect(float a1, float b1, float c1,
     const float kx = -b1 * __builtin_amdgcn_rcpf(a1);
     float q;
     {
-        const float y = fminf(fmaxf(ky * X0, Y0), Y1);
-        const float t = fmaf(a1, X0, b1 * y), w = c1 * y;
+        const float y = fminf(fmaxf(ky * Xe, Y0), Y1);
+        const float t = fmaf(a1, Xe, b1 * y), w = c1 * y;
         q = fmaf(t, t, w * w);
     }
     {
-        const float y = fminf(fmaxf(ky * X1, Y0), Y1);
-        const float t = fmaf(a1, X1, b1 * y), w = c1 * y;
-        q = fminf(q, fmaf(t, t, w * w));
-    }
-    {
-        const float x = fminf(fmaxf(kx * Y0, X0), X1);
-        const float t = fmaf(a1, x, b1 * Y0), w = c1 * Y0;
-        q = fminf(q, fmaf(t, t, w * w));
-    }
-    {
-        const float x = fminf(fmaxf(kx * Y1, X0), X1);
-        const float t = fmaf(a1, x, b1 * Y1), w = c1 * Y1;
+        const float x = fminf(fmaxf(kx * Ye, X0), X1);
+        const float t = fmaf(a1, x, b1 * Ye), w = c1 * Ye;
         q = fminf(q, fmaf(t, t, w * w));
     }
     return lo - q;
