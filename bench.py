@@ -35,6 +35,11 @@ FLOPS_ACCEPT = 11
 # taken on other sources gives no traffic figure.
 RASTER_SOURCES = ("paper_2604_25459_amd/csrc/k_raster.hip",)
 PMC_SUMMARY = "profiles/k_raster_cfg2_2048env_640x480_f32_pmc.json"
+UTIL_SUMMARY = "profiles/k_raster_cfg2_2048env_640x480_f32_valu_lds.json"
+UTIL_COUNTERS = ("SQ_ACTIVE_INST_VALU", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_LDS_LOAD_BANDWIDTH", "SQ_BUSY_CU_CYCLES",
+                 "GRBM_GUI_ACTIVE")
+# LDS read bandwidth of a CDNA4 compute unit (bytes per clock)
+LDS_BYTES_PER_CLK = 256
 CALIB_BYTES = 1 << 30
 
 
@@ -80,6 +85,65 @@ def pmc_summary(fetch_csv, write_csv, out_path, command):
         json.dump(out, f, indent=1)
         f.write("\n")
     print(json.dumps(out))
+
+
+def util_summary(counter_csv, agent_csv, out_path, command):
+    """Condense one counter run (UTIL_COUNTERS) into the rasteriser's VALU
+    and LDS use per launch.  The SQ counters are summed over the SIMDs of
+    the chip; GRBM_GUI_ACTIVE over its XCDs, so it divided by their number is
+    the launch's duration in shader clocks.  VALU busy = quad-cycles of VALU
+    issue x 4 / (SIMDs x clocks); LDS busy = cycles with indexed LDS work /
+    (CUs x clocks); LDS bytes = 64-byte units loaded x 64."""
+    with open(agent_csv) as f:
+        agent = next(r for r in csv.DictReader(f) if r["Agent_Type"] == "GPU")
+    n_xcc, cus = int(agent["Num_Xcc"]), int(agent["Cu_Count"])
+    simds = cus * int(agent["Simd_Per_Cu"])
+    clk_mhz = float(agent["Max_Engine_Clk_Fcompute"])
+    per = {}
+    with open(counter_csv) as f:
+        for r in csv.DictReader(f):
+            if "k_raster<" not in r["Kernel_Name"]:
+                continue
+            d = per.setdefault(r["Dispatch_Id"], {})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+            d["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    launches = [d for d in per.values() if all(c in d for c in UTIL_COUNTERS)]
+    if not launches:
+        raise SystemExit(f"no rasteriser dispatch with all of {UTIL_COUNTERS} in {counter_csv}")
+    rows = []
+    for d in launches:
+        clocks = d["GRBM_GUI_ACTIVE"] / n_xcc
+        rows.append({"ms": d["ns"] * 1e-6, "clock_ghz": clocks / d["ns"],
+                     "valu_busy": d["SQ_ACTIVE_INST_VALU"] * 4.0 / (simds * clocks),
+                     "cu_busy": d["SQ_BUSY_CU_CYCLES"] * 4.0 / (simds * clocks),
+                     "lds_busy": d["SQ_LDS_IDX_ACTIVE"] / (cus * clocks),
+                     "lds_bytes": d["SQ_INSTS_LDS_LOAD_BANDWIDTH"] * 64.0})
+    mean = {k: sum(r[k] for r in rows) / len(rows) for k in rows[0]}
+    lds_gbs = mean["lds_bytes"] / (mean["ms"] * 1e-3) / 1e9
+    lds_peak = cus * LDS_BYTES_PER_CLK * clk_mhz * 1e6 / 1e9
+    out = {"command": command, "source_sha256": raster_source_hash(), "sources": list(RASTER_SOURCES),
+           "counters": list(UTIL_COUNTERS), "dispatches": len(rows), "cus": cus, "simds": simds, "xcds": n_xcc,
+           "avg_ms": mean["ms"], "clock_ghz": mean["clock_ghz"], "valu_busy": mean["valu_busy"],
+           "cu_busy": mean["cu_busy"], "lds_busy": mean["lds_busy"], "lds_read_bytes_per_launch": mean["lds_bytes"],
+           "lds_read_gbs": lds_gbs, "lds_peak_gbs": lds_peak, "lds_read_frac": lds_gbs / lds_peak,
+           "lds_peak_basis": f"{cus} CUs x {LDS_BYTES_PER_CLK} B/clock x {clk_mhz:.0f} MHz"}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
+def measured_util():
+    """VALU / LDS use of the rasteriser from the committed counter summary,
+    or None when it was taken on other rasteriser sources."""
+    path = os.path.join(ROOT, UTIL_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        s = json.load(f)
+    if s.get("source_sha256") != raster_source_hash():
+        return None
+    return {k: s[k] for k in ("valu_busy", "lds_busy", "lds_read_gbs", "lds_peak_gbs", "lds_read_frac", "clock_ghz")}
 
 
 def measured_traffic(tuning):
@@ -217,12 +281,19 @@ def main():
                     help="skip the comparison leg that runs the same steps on one stream")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary of two rocprofv3 --pmc runs of this bench and exit")
-    ap.add_argument("--pmc-out", default=os.path.join(ROOT, PMC_SUMMARY))
+    ap.add_argument("--pmc-util-summary", nargs=2, metavar=("COUNTER_CSV", "AGENT_CSV"),
+                    help="write the VALU / LDS summary of one rocprofv3 --pmc run of this bench and exit")
+    ap.add_argument("--pmc-out", default=None, help="output of --pmc-summary / --pmc-util-summary")
     ap.add_argument("--pmc-command", default="", help="command line recorded in the counter summary")
     ap.add_argument("--pmc-tuning", default="", help="JSON of the launch parameters the counted run used")
     args = ap.parse_args()
 
+    if args.pmc_util_summary:
+        util_summary(args.pmc_util_summary[0], args.pmc_util_summary[1],
+                     args.pmc_out or os.path.join(ROOT, UTIL_SUMMARY), args.pmc_command)
+        return
     if args.pmc_summary:
+        args.pmc_out = args.pmc_out or os.path.join(ROOT, PMC_SUMMARY)
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_out, args.pmc_command)
         if args.pmc_tuning:
             with open(args.pmc_out) as f:
@@ -470,6 +541,11 @@ def main():
                 "flop_per_launch": flops_launch,
                 "visits_per_pixel": visits / (npx * args.steps), "accepts_per_pixel": accepts / (npx * args.steps),
                 "units": "list entries up to each pixel's termination x 11 flop + blended Gaussians x 11 flop"}
+        if traffic is not None:
+            # counted HBM bytes over the launch time measured here
+            roof["hbm_gbs"] = traffic / (raster_ms * 1e-3) / 1e9
+            roof["hbm_frac"] = roof["hbm_gbs"] / HBM_PEAK_GBS
+        roof["valu_lds"] = measured_util()
         log(f"[bench] raster {roof['visits_per_pixel']:.1f} visits, {roof['accepts_per_pixel']:.1f} blends per "
             f"pixel; {achieved:.2f} TFLOP/s algorithmic over {raster_ms:.2f} ms per launch")
 
