@@ -80,7 +80,8 @@ typedef struct {
     int overlap;            /* 0 = when a render has several memory chunks, run alternate chunks on two streams
                                (the caller's and an internal one, joined back before the call's work ends) with
                                a second working set, so one chunk's binning overlaps another's rasterisation
-                               (default); -1 = one stream, one working set */
+                               (default; a render whose second working set does not fit in device memory
+                               runs on one stream); -1 = one stream, one working set */
     int reserved[5];
 } gsr_options;
 

@@ -609,18 +609,28 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
     // follow on the other stream, so binning and raster of neighbouring
     // chunks share the GPU.  Each workspace is used by one stream only.
     const int n_chunks = (int)((job.imgs.size() + plan.chunk - 1) / plan.chunk);
-    const bool two = two_streams && !plain && ctx->opt.overlap >= 0 && n_chunks > 1;
+    bool two = two_streams && !plain && ctx->opt.overlap >= 0 && n_chunks > 1;
     Workspace* wk[2] = {&ws, &ws};
     hipStream_t sq[2] = {st, st};
     if (two) {
         if (!ws.twin) ws.twin.reset(new (std::nothrow) Workspace());
         if (!ws.twin) return fail(GSR_E_OOM, "workspace allocation failed");
-        Workspace& t = *ws.twin;
         if (!ws.side) GSR_HIP_TRY(hipStreamCreateWithFlags(&ws.side, hipStreamNonBlocking));
         if (!ws.ev_fork) GSR_HIP_TRY(hipEventCreateWithFlags(&ws.ev_fork, hipEventDisableTiming));
         if (!ws.ev_join) GSR_HIP_TRY(hipEventCreateWithFlags(&ws.ev_join, hipEventDisableTiming));
         // the twin's earlier work was joined into `st` before ws.ev_done
-        GSR_HIP_TRY(ensure_workspace(t, sc, plan, job.imgs.size(), rec_bytes));
+        const hipError_t e = ensure_workspace(*ws.twin, sc, plan, job.imgs.size(), rec_bytes);
+        if (e == hipErrorOutOfMemory) {
+            // no room for a second working set: free it and render on one stream
+            (void)hipGetLastError();
+            ws.twin.reset();
+            two = false;
+        } else if (e != hipSuccess) {
+            return hip_fail(e, "ensure_workspace (second working set)");
+        }
+    }
+    if (two) {
+        Workspace& t = *ws.twin;
         std::memcpy(t.h_img, job.imgs.data(), job.imgs.size() * sizeof(ImageInfo));
         GSR_HIP_TRY(hipMemcpyAsync(t.img.p, t.h_img, job.imgs.size() * sizeof(ImageInfo), hipMemcpyHostToDevice, st));
         GSR_HIP_TRY(hipEventRecord(ws.ev_fork, st));
