@@ -35,6 +35,7 @@
 // observation epilogue (gain, contrast about 0.5, brightness, clamp to
 // [0, 1], then bytes or halves) on the colour before it leaves registers.
 #include "gsr_internal.h"
+#include "gsr_wave.h"
 
 #include <hip/hip_fp16.h>
 
@@ -77,16 +78,6 @@ struct Layout {
     }
 };
 
-// Orders this wave's LDS writes before its later LDS reads (no instruction:
-// LDS requests of one wave are served in order; this keeps the compiler from
-// moving accesses across it).
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Upper bound of p = lo - (a1 x + b1 y)^2 - (c1 y)^2 over [X0, X1] x [Y0, Y1]
 // (coordinates relative to the mean; a1, c1 > 0).
 __device__ __forceinline__ float max_logalpha_rect(float a1, float b1, float c1, float lo, float X0, float X1, float Y0,
@@ -124,9 +115,13 @@ __device__ __forceinline__ float max_logalpha_rect(float a1, float b1, float c1,
 template <int TS, int kBatch>
 struct RasterLds {
     float4 a[2][kBatch], b[2][kBatch], c[2][kBatch];    // staged records: (u, v, a1, b1), (c1, lo, z, r), rgb
-    // per wave, the current 64 candidates re-centred on the wave's block:
-    // (a1, b1, c1, -s1), (-s2, lo, z, 0), rgb
-    float4 w[Layout<TS>::kWaves][3][64];
+    // per wave, the survivors of the current 64 candidates re-centred on the
+    // wave's block, packed in candidate order, 10 floats each:
+    // a1, b1, c1, -s1, -s2, lo, R, G, B, z (a pair of survivors = five
+    // 16-byte words; survivor k starts at float 10 k)
+    float4 w[Layout<TS>::kWaves][160];
+    uint32_t bright[Layout<TS>::kWaves][64];   // survivor may reach alpha = 0.99
+    uint32_t origin[Layout<TS>::kWaves][64];   // candidate index of the survivor (work counts)
     // per wave, whether it still has live pixels after a batch (by batch parity)
     uint32_t live[2][Layout<TS>::kWaves];
 };
@@ -162,7 +157,7 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
     const int w = tid >> 6, lane = __lane_id();
     int ox, oy;
     L::wave_origin(w, &ox, &oy);
-    auto& W = L_.w[w];
+    float* const Wf = reinterpret_cast<float*>(L_.w[w]);
     // pixel-centre rectangle of the wave's block
     const float wx0 = (float)(tx * TS + ox) + 0.5f;
     const float wx1 = wx0 + (float)(L::kWaveW - 1);
@@ -254,45 +249,52 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
                 ly1 = wy0 + (float)((63 - __builtin_clzll(M)) >> 3);
             }
             // ballot: which of these 64 Gaussians can touch the live pixels;
-            // survivors are re-centred into the wave's slots
+            // survivors are re-centred and packed into the wave's slots
             const int jl = sub + lane;
             bool keep = false, bright = false;
+            float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), bq = a;
             if (jl < cnt) {
-                const float4 a = sA[buf][jl];
-                const float4 bq = sB[buf][jl];
+                a = sA[buf][jl];
+                bq = sB[buf][jl];
                 const float m = max_logalpha_rect(a.z, a.w, bq.x, bq.y, lx0 - a.x, lx1 - a.x, ly0 - a.y, ly1 - a.y);
                 keep = m >= kLogAlphaMin - kCullMargin;
                 bright = keep && bq.y > kLog2ClampFree;
-                if (keep) {
-                    const float du = a.x - cxo, dv = a.y - cyo;
-                    const float s1 = fmaf(a.z, du, a.w * dv), s2 = bq.x * dv;
-                    W[0][lane] = make_float4(a.z, a.w, bq.x, -s1);
-                    W[1][lane] = make_float4(-s2, bq.y, bq.z, 0.0f);
-                    W[2][lane] = sC[buf][jl];
-                }
             }
-            uint64_t mask = __ballot(keep);
-            const uint64_t clampmask = __ballot(bright);       // survivors that may reach alpha = 0.99
+            const uint64_t mask = __ballot(keep);
+            const uint32_t n_surv = (uint32_t)__popcll(mask);
+            if (keep) {
+                const uint32_t r = lanes_below(mask);
+                const float du = a.x - cxo, dv = a.y - cyo;
+                const float s1 = fmaf(a.z, du, a.w * dv), s2 = bq.x * dv;
+                const float4 col = sC[buf][jl];
+                float2* d = reinterpret_cast<float2*>(Wf + 10u * r);     // 8-byte aligned
+                d[0] = make_float2(a.z, a.w);
+                d[1] = make_float2(bq.x, -s1);
+                d[2] = make_float2(-s2, bq.y);
+                d[3] = make_float2(col.x, col.y);
+                d[4] = make_float2(col.z, bq.z);
+                L_.bright[w][r] = bright ? 1u : 0u;
+                if (COUNT) L_.origin[w][r] = (uint32_t)jl;
+            }
             wave_lds_sync();
-            while (mask) {
-                const int j = (int)__builtin_ctzll(mask);
-                mask &= mask - 1ull;
-                const float4 q0 = W[0][j];
-                const float4 q1 = W[1][j];
+            // bit k: survivor k may reach alpha = 0.99 (only those pay for the clamp)
+            const uint64_t clampmask = __ballot((uint32_t)lane < n_surv && L_.bright[w][lane] != 0u);
+            // one survivor: a1, b1, c1, -s1 in q0; -s2, lo, z; colour
+            auto shade = [&](const float4 q0, float ms2, float lo, float z, float cr, float cg, float cb,
+                             uint32_t k_surv) {
                 float pw[PPT];
                 bool anyt = false;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     const float t1 = fmaf(q0.x, xl[k], fmaf(q0.y, yl[k], q0.w));
-                    const float t2 = fmaf(q0.z, yl[k], q1.x);
-                    pw[k] = fmaf(-t1, t1, fmaf(-t2, t2, q1.y));
+                    const float t2 = fmaf(q0.z, yl[k], ms2);
+                    pw[k] = fmaf(-t1, t1, fmaf(-t2, t2, lo));
                     anyt = anyt || pw[k] >= kLogAlphaMin;
                 }
-                if (__ballot(anyt) == 0ull) continue;       // no live pixel of the wave reaches 1/255
-                const float4 col = W[2][j];
+                if (__ballot(anyt) == 0ull) return;        // no live pixel of the wave reaches 1/255
                 float al[PPT], wgt[PPT];
                 bool anystop = false;
-                const bool clamp = (clampmask >> j) & 1ull;     // wave-uniform
+                const bool clamp = (clampmask >> k_surv) & 1ull;     // wave-uniform
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     const bool take = pw[k] >= kLogAlphaMin;
@@ -313,10 +315,12 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
                     // rounding).  The empty asm keeps this a branch rather than
                     // selects that every blended Gaussian would pay for.
                     asm volatile("");
+                    uint32_t at = 0;
+                    if (COUNT) at = b0 - start + L_.origin[w][k_surv] + 1u;
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) {
                         const bool stop = T[k] < 1e-4f;
-                        if (COUNT && stop) stop_at[k] = b0 - start + (uint32_t)(sub + j) + 1u;
+                        if (COUNT && stop) stop_at[k] = at;
                         T[k] = stop ? T[k] + wgt[k] : T[k];
                         wgt[k] = stop ? 0.0f : wgt[k];
                         al[k] = stop ? 0.0f : al[k];
@@ -325,11 +329,22 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
                 }
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    C0[k] = fmaf(col.x, wgt[k], C0[k]);
-                    C1[k] = fmaf(col.y, wgt[k], C1[k]);
-                    C2[k] = fmaf(col.z, wgt[k], C2[k]);
-                    D[k] = fmaf(q1.z, wgt[k], D[k]);
+                    C0[k] = fmaf(cr, wgt[k], C0[k]);
+                    C1[k] = fmaf(cg, wgt[k], C1[k]);
+                    C2[k] = fmaf(cb, wgt[k], C2[k]);
+                    D[k] = fmaf(z, wgt[k], D[k]);
                     if (COUNT) blended[k] += al[k] > 0.0f ? 1u : 0u;
+                }
+            };
+            // survivors two at a time: five 16-byte reads per pair (the second
+            // survivor's last two words are read only when it exists)
+            for (uint32_t k = 0; k < n_surv; k += 2) {
+                const float4* P = reinterpret_cast<const float4*>(Wf + 10u * k);     // 16-byte aligned (k even)
+                const float4 r0 = P[0], r1 = P[1], r2 = P[2];
+                shade(r0, r1.x, r1.y, r2.y, r1.z, r1.w, r2.x, k);
+                if (k + 1 < n_surv) {
+                    const float4 r3 = P[3], r4 = P[4];
+                    shade(make_float4(r2.z, r2.w, r3.x, r3.y), r3.z, r3.w, r4.w, r4.x, r4.y, r4.z, k + 1);
                 }
             }
             // the wave stops once none of its pixels is live (checked per 64 candidates)
