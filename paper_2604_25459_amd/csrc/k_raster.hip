@@ -292,48 +292,39 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
                     anyt = anyt || pw[k] >= kLogAlphaMin;
                 }
                 if (__ballot(anyt) == 0ull) return;        // no live pixel of the wave reaches 1/255
-                float al[PPT], wgt[PPT];
-                bool anystop = false;
                 const bool clamp = (clampmask >> k_surv) & 1ull;     // wave-uniform
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    const bool take = pw[k] >= kLogAlphaMin;
-                    float e = __builtin_amdgcn_exp2f(pw[k]);
-                    if (clamp) {
-                        // only survivors whose opacity can reach 0.99 pay for the clamp
+                    if (pw[k] >= kLogAlphaMin) {
+                        // only the pixels that take the Gaussian run this
+                        // (exec mask; the others keep T and the sums as they
+                        // are, which adding 0 would have left them)
                         asm volatile("");
-                        e = fminf(0.99f, e);
+                        float e = __builtin_amdgcn_exp2f(pw[k]);
+                        if (clamp) {
+                            // only survivors whose opacity can reach 0.99 pay for the clamp
+                            asm volatile("");
+                            e = fminf(0.99f, e);
+                        }
+                        float wgt = e * T[k];
+                        T[k] = T[k] - wgt;
+                        if (__ballot(T[k] < 1e-4f) != 0ull) {
+                            // rare: a pixel that stops here adds nothing and
+                            // keeps its transmittance (T' + alpha T restores it
+                            // to within one rounding)
+                            asm volatile("");
+                            const bool stop = T[k] < 1e-4f;
+                            if (COUNT && stop) stop_at[k] = b0 - start + L_.origin[w][k_surv] + 1u;
+                            T[k] = stop ? T[k] + wgt : T[k];
+                            wgt = stop ? 0.0f : wgt;
+                            xl[k] = stop ? kDead : xl[k];
+                        }
+                        C0[k] = fmaf(cr, wgt, C0[k]);
+                        C1[k] = fmaf(cg, wgt, C1[k]);
+                        C2[k] = fmaf(cb, wgt, C2[k]);
+                        D[k] = fmaf(z, wgt, D[k]);
+                        if (COUNT) blended[k] += wgt > 0.0f ? 1u : 0u;
                     }
-                    al[k] = take ? e : 0.0f;
-                    wgt[k] = al[k] * T[k];
-                    T[k] = T[k] - wgt[k];                   // unchanged where the pixel does not take it
-                    anystop = anystop || T[k] < 1e-4f;      // only a taking pixel can fall below (T >= 1e-4)
-                }
-                if (__ballot(anystop) != 0ull) {
-                    // rare: a pixel that stops here adds nothing and keeps its
-                    // transmittance (T' + alpha T restores it to within one
-                    // rounding).  The empty asm keeps this a branch rather than
-                    // selects that every blended Gaussian would pay for.
-                    asm volatile("");
-                    uint32_t at = 0;
-                    if (COUNT) at = b0 - start + L_.origin[w][k_surv] + 1u;
-#pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        const bool stop = T[k] < 1e-4f;
-                        if (COUNT && stop) stop_at[k] = at;
-                        T[k] = stop ? T[k] + wgt[k] : T[k];
-                        wgt[k] = stop ? 0.0f : wgt[k];
-                        al[k] = stop ? 0.0f : al[k];
-                        xl[k] = stop ? kDead : xl[k];
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    C0[k] = fmaf(cr, wgt[k], C0[k]);
-                    C1[k] = fmaf(cg, wgt[k], C1[k]);
-                    C2[k] = fmaf(cb, wgt[k], C2[k]);
-                    D[k] = fmaf(z, wgt[k], D[k]);
-                    if (COUNT) blended[k] += al[k] > 0.0f ? 1u : 0u;
                 }
             };
             // survivors two at a time: five 16-byte reads per pair (the second
