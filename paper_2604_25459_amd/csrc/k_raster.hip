@@ -117,7 +117,7 @@ struct RasterLds {
     float4 a[2][kBatch], b[2][kBatch], c[2][kBatch];    // staged records: (u, v, a1, b1), (c1, lo, z, r), rgb
     // per wave, the survivors of the current 64 candidates re-centred on the
     // wave's block, packed in candidate order, 10 floats each:
-    // a1, b1, c1, -s1, -s2, lo, R, G, B, z (a pair of survivors = five
+    // a1, b1, c1, lo, -s1, -s2, R, G, B, z (a pair of survivors = five
     // 16-byte words; survivor k starts at float 10 k)
     float4 w[Layout<TS>::kWaves][160];
     uint32_t bright[Layout<TS>::kWaves][64];   // survivor may reach alpha = 0.99
@@ -251,34 +251,38 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             // ballot: which of these 64 Gaussians can touch the live pixels;
             // survivors are re-centred and packed into the wave's slots
             const int jl = sub + lane;
-            bool keep = false, bright = false;
-            float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), bq = a;
-            if (jl < cnt) {
-                a = sA[buf][jl];
-                bq = sB[buf][jl];
-                const float m = max_logalpha_rect(a.z, a.w, bq.x, bq.y, lx0 - a.x, lx1 - a.x, ly0 - a.y, ly1 - a.y);
-                keep = m >= kLogAlphaMin - kCullMargin;
-                bright = keep && bq.y > kLog2ClampFree;
-            }
+            // lanes past the batch's end test its last candidate and keep nothing
+            const int jc = jl < cnt ? jl : cnt - 1;
+            const float4 a = sA[buf][jc], bq = sB[buf][jc];
+            const float m = max_logalpha_rect(a.z, a.w, bq.x, bq.y, lx0 - a.x, lx1 - a.x, ly0 - a.y, ly1 - a.y);
+            const bool keep = jl < cnt && m >= kLogAlphaMin - kCullMargin;
+            const bool bright = keep && bq.y > kLog2ClampFree;
             const uint64_t mask = __ballot(keep);
+            const uint64_t bright_lanes = __ballot(bright);
             const uint32_t n_surv = (uint32_t)__popcll(mask);
+            const uint32_t r = lanes_below(mask);
             if (keep) {
-                const uint32_t r = lanes_below(mask);
                 const float du = a.x - cxo, dv = a.y - cyo;
                 const float s1 = fmaf(a.z, du, a.w * dv), s2 = bq.x * dv;
                 const float4 col = sC[buf][jl];
                 float2* d = reinterpret_cast<float2*>(Wf + 10u * r);     // 8-byte aligned
                 d[0] = make_float2(a.z, a.w);
-                d[1] = make_float2(bq.x, -s1);
-                d[2] = make_float2(-s2, bq.y);
+                d[1] = make_float2(bq.x, bq.y);
+                d[2] = make_float2(-s1, -s2);
                 d[3] = make_float2(col.x, col.y);
                 d[4] = make_float2(col.z, bq.z);
-                L_.bright[w][r] = bright ? 1u : 0u;
                 if (COUNT) L_.origin[w][r] = (uint32_t)jl;
             }
+            // bit k: survivor k may reach alpha = 0.99 (only those pay for the
+            // clamp); bright survivors are rare, so the packed mask is built
+            // only when the batch has one
+            uint64_t clampmask = 0;
+            if (bright_lanes != 0ull) {
+                if (keep) L_.bright[w][r] = bright ? 1u : 0u;
+                wave_lds_sync();
+                clampmask = __ballot((uint32_t)lane < n_surv && L_.bright[w][lane] != 0u);
+            }
             wave_lds_sync();
-            // bit k: survivor k may reach alpha = 0.99 (only those pay for the clamp)
-            const uint64_t clampmask = __ballot((uint32_t)lane < n_surv && L_.bright[w][lane] != 0u);
             // one survivor: a1, b1, c1, -s1 in q0; -s2, lo, z; colour
             auto shade = [&](const float4 q0, float ms2, float lo, float z, float cr, float cg, float cb,
                              uint32_t k_surv) {
@@ -332,10 +336,10 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             for (uint32_t k = 0; k < n_surv; k += 2) {
                 const float4* P = reinterpret_cast<const float4*>(Wf + 10u * k);     // 16-byte aligned (k even)
                 const float4 r0 = P[0], r1 = P[1], r2 = P[2];
-                shade(r0, r1.x, r1.y, r2.y, r1.z, r1.w, r2.x, k);
+                shade(make_float4(r0.x, r0.y, r0.z, r1.x), r1.y, r0.w, r2.y, r1.z, r1.w, r2.x, k);
                 if (k + 1 < n_surv) {
                     const float4 r3 = P[3], r4 = P[4];
-                    shade(make_float4(r2.z, r2.w, r3.x, r3.y), r3.z, r3.w, r4.w, r4.x, r4.y, r4.z, k + 1);
+                    shade(make_float4(r2.z, r2.w, r3.x, r3.z), r3.w, r3.y, r4.w, r4.x, r4.y, r4.z, k + 1);
                 }
             }
             // the wave stops once none of its pixels is live (checked per 64 candidates)
