@@ -285,14 +285,19 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
                 const float wz = fmaf(m2.z, pz, fmaf(m2.y, py, m2.x * px));
                 const float qq = fmaf(wz, wz, fmaf(wy, wy, wx * wx));
                 const float la = fmaf(-0.72134752044448170f, qq, m3.x);      // log2 o - q/2 log2 e
-                const bool take = tstar > near && la >= kLidarLogAlphaMin;
-                const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(la));
-                const float Tn = fmaf(-T, alpha, T);
-                const bool stop = take && Tn < 1e-4f;
-                const bool add = take && !stop;
-                Rg = add ? fmaf(tstar, alpha * T, Rg) : Rg;
-                T = add ? Tn : T;
-                live = live && !stop;
+                if (tstar > near && la >= kLidarLogAlphaMin) {
+                    // only the rays that take the Gaussian run this (exec mask);
+                    // the empty asm keeps it a branch rather than selects
+                    asm volatile("");
+                    const float alpha = fminf(0.99f, __builtin_amdgcn_exp2f(la));
+                    const float Tn = fmaf(-T, alpha, T);
+                    if (Tn < 1e-4f) {
+                        live = false;                   // stops here, adds nothing
+                    } else {
+                        Rg = fmaf(tstar, alpha * T, Rg);
+                        T = Tn;
+                    }
+                }
             }
             if (__ballot(live) == 0ull) wave_live = false;
         }
