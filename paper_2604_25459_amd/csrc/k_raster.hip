@@ -212,6 +212,10 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
     if (start < end) fetch(start);
     int buf = 0;
     bool wave_live = __ballot(any_live) != 0ull;
+    // pixel-centre rectangle still to be shaded (the live pixels' bounding
+    // box), recomputed only when the set of live pixels has changed
+    float lx0 = wx0, lx1 = wx1, ly0 = wy0, ly1 = wy1;
+    uint64_t live_seen = 0;
 
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
 #pragma unroll
@@ -235,18 +239,19 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         if (b0 + kBatch < end) fetch(b0 + kBatch);
         const int cnt = (int)min((uint32_t)kBatch, end - b0);
         for (int sub = 0; sub < cnt && wave_live; sub += 64) {
-            // pixel-centre rectangle still to be shaded: the live pixels' bounding box
-            float lx0 = wx0, lx1 = wx1, ly0 = wy0, ly1 = wy1;
             if (PPT == 1) {
                 const uint64_t M = __ballot(xl[0] < kDeadTest);  // lane = 8 * row + column
-                uint64_t cm = M | (M >> 32);
-                cm |= cm >> 16;
-                cm |= cm >> 8;
-                cm &= 0xFFull;
-                lx0 = wx0 + (float)__builtin_ctzll(cm);
-                lx1 = wx0 + (float)(63 - __builtin_clzll(cm));
-                ly0 = wy0 + (float)(__builtin_ctzll(M) >> 3);
-                ly1 = wy0 + (float)((63 - __builtin_clzll(M)) >> 3);
+                if (M != live_seen) {
+                    live_seen = M;
+                    uint64_t cm = M | (M >> 32);
+                    cm |= cm >> 16;
+                    cm |= cm >> 8;
+                    cm &= 0xFFull;
+                    lx0 = wx0 + (float)__builtin_ctzll(cm);
+                    lx1 = wx0 + (float)(63 - __builtin_clzll(cm));
+                    ly0 = wy0 + (float)(__builtin_ctzll(M) >> 3);
+                    ly1 = wy0 + (float)((63 - __builtin_clzll(M)) >> 3);
+                }
             }
             // ballot: which of these 64 Gaussians can touch the live pixels;
             // survivors are re-centred and packed into the wave's slots
