@@ -19,16 +19,19 @@
 // stays below log2(1/255) - kCullMargin cannot reach alpha >= 1/255 at any
 // pixel of the block (narrowed to the bounding box of its still-live pixels).
 // The same lane writes its Gaussian, re-centred on the 32x32 pixel block that
-// holds the wave, into the wave's own LDS slots; the ballot of the survivors
-// is then walked bit by bit, each survivor costing five FMAs per pixel:
+// holds the wave, into the wave's own LDS slots, packed by its rank among the
+// survivors (10 floats each), and the wave walks the survivors two at a time
+// (a pair is five 16-byte LDS reads: on this GPU an LDS read costs about the
+// same per instruction whatever its width or active lanes, so fewer, wider
+// reads are what count).  Each survivor costs five FMAs per pixel:
 //     t1 = a1 x + b1 y - s1,  t2 = c1 y - s2,  p = log2(o) - t1^2 - t2^2
 // with (x, y) the pixel centre relative to the block centre and (s1, s2) the
 // whitened mean.  The block (not the tile or the wave) is the origin so that
 // every tile size evaluates the same expression for a pixel and results do
 // not depend on the tiling.  kCullMargin absorbs binary32 rounding of the
 // per-pixel evaluation, so culling never removes a Gaussian a pixel would
-// have accepted.  Blending takes a short path when no pixel of the wave stops
-// at the current Gaussian.
+// have accepted.  Blending runs under the mask of the pixels that take the
+// Gaussian and takes a short path when none of them stops at it.
 //
 // Output: rgb = C + T bg, depth = D / (1 - T) (0 where nothing was added),
 // optional alpha = 1 - T, optional work counts, and optionally the fused
