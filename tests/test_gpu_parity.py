@@ -181,6 +181,35 @@ def test_ragged_100x75_random_scene(R, bg):
     R.remove_scene(sid)
 
 
+def test_full_survivor_batches_and_opaque_splats(R):
+    """Every wave's batches of 64 candidates survive whole (wide, faint
+    splats: survivor packs of 64, the last pair at the end of the slots), with
+    near-opaque splats (opacity >= 0.99: the 0.99 clamp) in between that stop
+    pixels; bins bit for bit, pixels against the oracle, at several LDS batch
+    sizes."""
+    rng = np.random.default_rng(17)
+    n_faint, n_opaque = 300, 40
+    means = np.concatenate([rng.uniform([-0.3, -0.2, 1.0], [0.3, 0.2, 3.0], (n_faint, 3)),
+                            rng.uniform([-0.5, -0.35, 1.0], [0.5, 0.35, 3.0], (n_opaque, 3))])
+    scales = np.concatenate([np.full((n_faint, 3), 0.6), np.exp(rng.normal(math.log(0.03), 0.3, (n_opaque, 3)))])
+    opac = np.concatenate([rng.uniform(0.01, 0.03, n_faint), rng.choice([0.991, 0.995, 0.999, 1.0], n_opaque)])
+    order = rng.permutation(n_faint + n_opaque)          # opaque splats interleaved in index order
+    sh = rng.uniform(0, 1, (n_faint + n_opaque, 1, 3))
+    scene = scene_from(means[order], scales[order], rng.standard_normal((n_faint + n_opaque, 4)), opac[order],
+                       sh, 0)
+    batch = one_camera(72, 56, 60.0, bg=(0.2, 0.3, 0.4))
+    sid = _upload(R, scene)
+    _check_bins(R, sid, scene, batch, 0, 0)
+    ref = render_ref(scene, batch, 0, 0, R.tile_size)
+    from paper_2604_25459_amd import gsr
+    cams, vm, poses = gsr.batch_tensors(batch)
+    for lds_batch in (64, 128, 256):
+        R.set_tuning(sid, cams, vm, poses, lds_batch=lds_batch)
+        got = _render(R, sid, batch)
+        _check_image(_img(got, 0, 0), ref, f"full batches + opaque, lds_batch {lds_batch}")
+    R.remove_scene(sid)
+
+
 # ------------------------------------------------------------------ batched configs (sampled envs)
 def test_cfg1_all_envs_batched(R):
     scene, batch = synth.make_config(1)
