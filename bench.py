@@ -168,27 +168,167 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _free():
+    """Drop unreferenced tensors and hand PyTorch's cached blocks back, so the
+    library's own allocations in the next leg find the memory."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def sampled_envs(E, k):
+    """k distinct envs spread over [0, E) (seeded, reproducible)."""
+    out = []
+    for j in range(E):
+        e = (j * 997) % E
+        if e not in out:
+            out.append(e)
+        if len(out) == min(k, E):
+            break
+    return out
+
+
+def oracle_error(scene, batch, images, tile, pairs):
+    """Per-image error of GPU images against the float64 oracle on the scene's
+    original float32 attributes.  `images` maps (slot, env) to the GPU's
+    float32 RGB [H, W, 3] (numpy); `pairs` lists the (slot, env) keys.  Pixels
+    with a threshold decision near its boundary (flagged by the oracle) are
+    reported apart, since either branch is admissible there."""
+    import numpy as np
+    from oracle import render_ref
+    rows = []
+    for c, e in pairs:
+        ref = render_ref(scene, batch, c, e, tile, variants=False)
+        d = np.abs(np.asarray(images[(c, e)], np.float64) - ref.rgb)
+        calm = ref.nflag == 0
+        mse = float(np.mean(d * d))
+        rows.append({"slot": c, "env": e, "max_abs": float(d.max()),
+                     "max_abs_unflagged": float(d[calm].max()) if calm.any() else 0.0,
+                     "mean_abs": float(d.mean()), "flagged_pixels": int((~calm).sum()),
+                     "psnr_db": float(10.0 * np.log10(1.0 / mse)) if mse > 0 else float("inf")})
+    ps = [r["psnr_db"] for r in rows]
+    return {"reference": "float64 oracle on the original float32 attributes", "images": len(rows),
+            "max_abs_max": max(r["max_abs"] for r in rows),
+            "max_abs_unflagged_max": max(r["max_abs_unflagged"] for r in rows),
+            "mean_abs_mean": sum(r["mean_abs"] for r in rows) / len(rows),
+            "psnr_db_min": min(ps), "psnr_db_median": float(np.median(ps)), "per_image": rows}
+
+
+def gpu_images(cams, E, rgb, pairs):
+    """(slot, env) -> float32 RGB [H, W, 3] as numpy, from a flat render output."""
+    out, base = {}, 0
+    for c, cam in enumerate(cams):
+        n = E * cam.width * cam.height * 3
+        view = rgb[base:base + n].view(E, cam.height, cam.width, 3)
+        for (cc, e) in pairs:
+            if cc == c:
+                out[(c, e)] = view[e].cpu().numpy()
+        base += n
+    return out
+
+
+def timed_steps(R, sid, cams, vm, poses, rgb, depth, bg, steps, first=0, obs=None):
+    """Seconds for `steps` renders (poses[first + s]) bracketed by device syncs."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        R.render_into(sid, cams, vm, poses[(first + s) % len(poses)], rgb, depth, None, bg, obs=obs)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def plain_rate(R, sid, batch, poses_t, n_envs, bg):
+    """Env-frames/s of the plain per-env path (one image per launch chain,
+    host sync per image) over the first n_envs envs, after one warm render."""
+    import torch
+    from paper_2604_25459_amd import gsr
+    pe = min(n_envs, batch.n_envs)
+    sub = batch.subset(range(pe))
+    pcams, pvm, _ = gsr.batch_tensors(sub)
+    prgb, pdep, _ = R.alloc_outputs(pcams, pe)
+    pp = poses_t[:pe].contiguous()
+    R.render_into(sid, pcams, pvm, pp, prgb, pdep, None, bg, plain=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R.render_into(sid, pcams, pvm, pp, prgb, pdep, None, bg, plain=True)
+    torch.cuda.synchronize()
+    return {"value": pe / (time.perf_counter() - t0), "unit": "env-frames/s", "envs_timed": pe}
+
+
+def config_leg(cfg, storage, args, steps, n_plain, n_err):
+    """Batched throughput of workload `cfg` (autotuned, poses resampled each
+    step), the plain per-env path's rate, and per-image error against the
+    oracle on sampled envs of the last timed step."""
+    import numpy as np
+    import torch
+    from paper_2604_25459_amd import gsr, synth
+    dev = torch.device("cuda", 0)
+    log(f"[cfg{cfg}] generating workload")
+    scene, batch = synth.make_config(cfg)
+    E, C = batch.n_envs, batch.n_cams
+    bg = tuple(float(x) for x in batch.bg)
+    R = gsr.Renderer(0, tile_size=args.tile, profile=True)
+    try:
+        sid = R.add_synth_scene(scene, storage)
+        cams, vm, _ = gsr.batch_tensors(batch)
+        warm = max(2, args.warmup)
+        pose_np = [synth.make_poses(cfg, s, E, scene.n_bodies) for s in range(warm + steps)]
+        poses = [torch.from_numpy(p).to(dev) for p in pose_np]
+        rgb, depth, _ = R.alloc_outputs(cams, E)
+        tuning = R.autotune(sid, cams, vm, poses[0], rgb, depth) if not args.no_autotune else None
+        for s in range(warm):
+            R.render_into(sid, cams, vm, poses[s], rgb, depth, None, bg)
+        sec = timed_steps(R, sid, cams, vm, poses, rgb, depth, bg, steps, first=warm)
+        value = E * steps / sec
+        out = {"workload": synth.CONFIG_NAMES[cfg], "storage": storage, "envs": E, "cams": C,
+               "resolution": [[c.width, c.height] for c in cams], "gaussians": scene.n, "steps": steps,
+               "value": value, "unit": "env-frames/s", "ms_per_step": 1000.0 * sec / steps, "tuning": tuning}
+        log(f"[cfg{cfg}] {value:.1f} env-frames/s ({1000.0 * sec / steps:.3f} ms/step), tuning {tuning}")
+        last = warm + steps - 1
+        if n_err:
+            pairs = [(c, e) for c in range(C) for e in sampled_envs(E, n_err)]
+            imgs = gpu_images(cams, E, rgb, pairs)
+            b_last = synth.Batch(cams=batch.cams, viewmats=batch.viewmats, poses=pose_np[last], bg=batch.bg)
+            out["error_vs_oracle"] = oracle_error(scene, b_last, imgs, args.tile, pairs)
+            log(f"[cfg{cfg}] error vs oracle: max-abs {out['error_vs_oracle']['max_abs_max']:.3g} "
+                f"(unflagged {out['error_vs_oracle']['max_abs_unflagged_max']:.3g}), "
+                f"PSNR min {out['error_vs_oracle']['psnr_db_min']:.1f} dB")
+        if n_plain:
+            out["plain_path"] = plain_rate(R, sid, batch, poses[last], n_plain, bg)
+            log(f"[cfg{cfg}] plain path {out['plain_path']['value']:.1f} env-frames/s")
+        del rgb, depth, poses
+        return out
+    finally:
+        R.close()
+
+
 def run_serving(R, args):
-    """Replay the first `serve_seconds` of the seeded Poisson trace (200 req/s,
-    1-256 envs, 128x128 / 320x240 / 640x480, FP16 scenes of 50k-1M Gaussians
-    plus 4-16 bodies) in real time through the continuous-batching server.
-    Latency = submission to completion on the device."""
+    """Replay the seeded Poisson trace (200 req/s, 1-256 envs, 128x128 /
+    320x240 / 640x480, a pool of FP16 scenes of 50k-1M Gaussians plus 4-16
+    bodies) in real time through the continuous-batching server; then the
+    first `plain_serve_seconds` of the same trace through the plain per-env
+    path, one request at a time in arrival order (the baseline without
+    batching).  Latency = completion on the device - scheduled arrival."""
     import threading
     import numpy as np
     import torch
     from paper_2604_25459_amd import gsr, synth
 
     dev = torch.device("cuda", 0)
-    trace = [r for r in synth.serving_trace() if r.arrival_s < args.serve_seconds]
     K = max(1, min(args.serve_scenes, 32))
+    trace = [r for r in synth.serving_trace(pool=32) if r.arrival_s < args.serve_seconds]
     log(f"[serve] {len(trace)} requests over {args.serve_seconds:.0f} s, pool of {K} resident scenes (FP16)")
-    scenes = [synth.serving_pool_scene(k) for k in range(K)]
-    sids = [R.add_synth_scene(sc, "f16") for sc in scenes]
-    prepared = []
-    for idx, req in enumerate(trace):
-        sc = scenes[req.scene % K]
-        b = synth.serving_batch(req, sc, idx)
-        prepared.append((req, req.scene % K, b))
+    scenes, sids = [], []
+    for k in range(K):
+        sc = synth.serving_pool_scene(k)
+        scenes.append(sc)
+        sids.append(R.add_synth_scene(sc, "f16"))
+    log(f"[serve] scene pool resident: {sum(s.n for s in scenes)} Gaussians")
+    prepared = [(req, req.scene % K, synth.serving_batch(req, scenes[req.scene % K], idx))
+                for idx, req in enumerate(trace)]
     S = gsr.Server(R, n_streams=args.serve_streams)
     # warm the server's workspaces (one request per resolution)
     for w, h in synth.SERVE_RESOLUTIONS:
@@ -200,72 +340,121 @@ def run_serving(R, args):
     base = S.stats()
     tickets = []
     lock = threading.Lock()
-    done_images = [0]
-    lat = []
-    t0 = time.perf_counter()
+    infos = []
+    t0_us = time.monotonic_ns() // 1000
 
     def producer():
-        for req, si, b in prepared:
-            now = time.perf_counter() - t0
-            if req.arrival_s > now:
-                time.sleep(req.arrival_s - now)
+        for k, (req, si, b) in enumerate(prepared):
+            now = time.monotonic_ns() // 1000 - t0_us
+            if req.arrival_s * 1e6 > now:
+                time.sleep((req.arrival_s * 1e6 - now) * 1e-6)
             cams, vm, poses = gsr.batch_tensors(b)
             rgb, depth, _ = R.alloc_outputs(cams, b.n_envs)
             torch.cuda.current_stream(dev).synchronize()
             t = S.submit(sids[si], cams, vm, poses, rgb, depth)
             with lock:
-                tickets.append((t, b.n_envs * b.n_cams))
+                tickets.append((t, k, b.n_envs * b.n_cams))
         with lock:
-            tickets.append((None, 0))
+            tickets.append((None, -1, 0))
 
     th = threading.Thread(target=producer)
     th.start()
     k = 0
+    n_img = 0
     while True:
         with lock:
             item = tickets[k] if k < len(tickets) else False
         if item is False:
             time.sleep(0.0005)
             continue
-        t, n_img = item
+        t, idx, ni = item
         if t is None:
             break
         info = S.wait(t)
-        lat.append(info["t_complete_us"] - info["t_submit_us"])
-        done_images[0] += n_img
+        infos.append((idx, info))
+        n_img += ni
         k += 1
-    wall = time.perf_counter() - t0
+    wall = (time.monotonic_ns() // 1000 - t0_us) * 1e-6
     th.join()
     st = S.stats()
     S.close()
+    arr = np.array([prepared[i][0].arrival_s * 1e6 + t0_us for i, _ in infos])
+    done = np.array([inf["t_complete_us"] for _, inf in infos], np.float64)
+    sub = np.array([inf["t_submit_us"] for _, inf in infos], np.float64)
+    lat = (done - arr) / 1000.0
+    lat_sub = (done - sub) / 1000.0
+    breq = np.array([inf["batch_requests"] for _, inf in infos])
+    hist = {str(v): int((breq == v).sum()) for v in sorted(set(breq.tolist()))}
+    out = {"requests": st["completed"] - base["completed"], "arrival_rate_hz": 200.0,
+           "trace_seconds": args.serve_seconds, "scenes": K, "streams": args.serve_streams,
+           "latency_p50_ms": float(np.percentile(lat, 50)), "latency_p99_ms": float(np.percentile(lat, 99)),
+           "latency_max_ms": float(lat.max()),
+           "latency_from_submit_p50_ms": float(np.percentile(lat_sub, 50)),
+           "latency_from_submit_p99_ms": float(np.percentile(lat_sub, 99)),
+           "env_frames_per_s": n_img / wall, "wall_s": wall,
+           "batches": st["batches"] - base["batches"], "mean_batch_requests": st["mean_batch_requests"],
+           "requests_by_batch_size": hist,
+           "requests_merged": int((breq > 1).sum())}
+    log(f"[serve] p50 {out['latency_p50_ms']:.2f} ms, p99 {out['latency_p99_ms']:.2f} ms, "
+        f"{out['env_frames_per_s']:.0f} env-frames/s, {out['requests_merged']} requests merged")
+
+    # the plain per-env path on the first seconds of the same trace
+    if args.plain_serve_seconds > 0:
+        pre = [(i, p) for i, p in enumerate(prepared) if p[0].arrival_s < args.plain_serve_seconds]
+        lat_p = []
+        n_pimg = 0
+        t0 = time.monotonic_ns() // 1000
+        for i, (req, si, b) in pre:
+            now = time.monotonic_ns() // 1000 - t0
+            if req.arrival_s * 1e6 > now:
+                time.sleep((req.arrival_s * 1e6 - now) * 1e-6)
+            cams, vm, poses = gsr.batch_tensors(b)
+            rgb, depth, _ = R.alloc_outputs(cams, b.n_envs)
+            R.render_into(sids[si], cams, vm, poses, rgb, depth, plain=True)
+            torch.cuda.synchronize()
+            lat_p.append((time.monotonic_ns() // 1000 - t0) - req.arrival_s * 1e6)
+            n_pimg += b.n_envs * b.n_cams
+        pwall = (time.monotonic_ns() // 1000 - t0) * 1e-6
+        lat_p = np.asarray(lat_p) / 1000.0
+        served_same = np.array([lat[j] for j, (i, _) in enumerate(infos)
+                                if prepared[i][0].arrival_s < args.plain_serve_seconds])
+        out["plain_path"] = {
+            "trace_seconds": args.plain_serve_seconds, "requests": len(pre),
+            "latency_p50_ms": float(np.percentile(lat_p, 50)), "latency_p99_ms": float(np.percentile(lat_p, 99)),
+            "latency_max_ms": float(lat_p.max()), "env_frames_per_s": n_pimg / pwall, "wall_s": pwall,
+            "served_same_requests_p50_ms": float(np.percentile(served_same, 50)),
+            "served_same_requests_p99_ms": float(np.percentile(served_same, 99)),
+            "policy": "one request at a time in arrival order, gsr_render_plain, host sync per image"}
+        log(f"[serve] plain path on the first {args.plain_serve_seconds:.0f} s: "
+            f"p50 {out['plain_path']['latency_p50_ms']:.1f} ms, p99 {out['plain_path']['latency_p99_ms']:.1f} ms "
+            f"(served: p99 {out['plain_path']['served_same_requests_p99_ms']:.1f} ms)")
     for sid in sids:
         R.remove_scene(sid)
-    n = st["completed"] - base["completed"]
-    lat_ms = np.asarray(lat, np.float64) / 1000.0
-    out = {"requests": n, "arrival_rate_hz": 200.0, "trace_seconds": args.serve_seconds, "scenes": K,
-           "streams": args.serve_streams, "latency_p50_ms": float(np.percentile(lat_ms, 50)),
-           "latency_p99_ms": float(np.percentile(lat_ms, 99)), "latency_max_ms": float(lat_ms.max()),
-           "env_frames_per_s": done_images[0] / wall, "wall_s": wall,
-           "mean_batch_requests": st["mean_batch_requests"], "batches": st["batches"] - base["batches"]}
-    log(f"[serve] {out}")
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--envs", type=int, default=0, help="truncate the workload's env count (0 = full)")
     ap.add_argument("--plain-envs", type=int, default=64, help="envs timed on the plain per-env path (0 = skip)")
-    ap.add_argument("--cpu-images", type=int, default=3, help="images rendered by the CPU oracle (0 = skip)")
+    ap.add_argument("--cpu-images", type=int, default=16, help="envs rendered by the CPU oracle (0 = skip)")
+    ap.add_argument("--cpu-images-1t", type=int, default=2, help="envs rendered by the oracle on one thread")
+    ap.add_argument("--err-envs", type=int, default=4,
+                    help="sampled envs per workload whose images are checked against the oracle (0 = skip)")
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="seconds of the Poisson serving trace replayed in real time (0 = skip)")
-    ap.add_argument("--serve-scenes", type=int, default=8, help="resident scenes in the serving pool (trace uses 32)")
+    ap.add_argument("--serve-scenes", type=int, default=32, help="resident scenes in the serving pool")
     ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--plain-serve-seconds", type=float, default=5.0,
+                    help="seconds of the same trace replayed through the plain per-env path (0 = skip)")
+    ap.add_argument("--no-configs", dest="configs", action="store_false",
+                    help="skip the legs of workloads 0, 1 and 3")
     ap.add_argument("--no-autotune", action="store_true", help="skip the launch-parameter autotuner")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first copy 1 GiB device to device (calibrates the memory counters)")
@@ -309,10 +498,28 @@ def main():
                           "run with --gpus 1"}))
         sys.exit(2)
 
+    import traceback
+
     import numpy as np
     import torch
 
     from paper_2604_25459_amd import gsr, synth
+
+    out = {"metric": "env-frames/s at 640x480 x 2048 envs vs plain path; p50/p99 request latency",
+           "value": None, "unit": "env-frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.storage, "data": "synthetic"}
+
+    def leg(name, fn):
+        """Run one optional leg; a failure becomes {"error": ...} and the rest goes on."""
+        t0 = time.perf_counter()
+        try:
+            out[name] = fn()
+        except Exception as ex:      # noqa: BLE001 -- recorded in the JSON line
+            traceback.print_exc()
+            out[name] = {"error": f"{type(ex).__name__}: {ex}"}
+        log(f"[bench] leg {name} took {time.perf_counter() - t0:.1f} s")
+        _free()
 
     if args.calibration_copy:
         x = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -323,18 +530,19 @@ def main():
         del x, y
         log("[bench] calibration: 1 GiB device-to-device copy done")
 
+    # ------------------------------------------------------------ headline
     log(f"[bench] config {args.config}: generating workload")
     scene, batch = synth.make_config(args.config, n_envs=args.envs or None)
     E, C = batch.n_envs, batch.n_cams
+    bg = tuple(float(x) for x in batch.bg)
     R = gsr.Renderer(0, tile_size=args.tile, profile=True, graphs=not args.no_graphs, overlap=not args.no_overlap)
     sid = R.add_synth_scene(scene, args.storage)
     cams, vm, _ = gsr.batch_tensors(batch)
     dev = torch.device("cuda", 0)
     n_pose_steps = args.warmup + args.steps
-    poses = [torch.from_numpy(synth.make_poses(args.config, s, E, scene.n_bodies)).to(dev)
-             for s in range(n_pose_steps)]
+    pose_np = [synth.make_poses(args.config, s, E, scene.n_bodies) for s in range(n_pose_steps)]
+    poses = [torch.from_numpy(p).to(dev) for p in pose_np]
     rgb, depth, _ = R.alloc_outputs(cams, E)
-    stream = torch.cuda.current_stream(dev)
 
     tuning = None
     if not args.no_autotune:
@@ -343,51 +551,118 @@ def main():
         log(f"[bench] autotuned in {time.perf_counter() - t0:.1f} s: {tuning}")
     log(f"[bench] warmup {args.warmup} steps of {E} envs x {C} cams")
     for s in range(args.warmup):
-        R.render_into(sid, cams, vm, poses[s], rgb, depth, None, tuple(batch.bg))
+        R.render_into(sid, cams, vm, poses[s], rgb, depth, None, bg)
     torch.cuda.synchronize()
     R.stage_times(reset=True)
 
     log(f"[bench] timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        R.render_into(sid, cams, vm, poses[args.warmup + s], rgb, depth, None, tuple(batch.bg))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    sec = timed_steps(R, sid, cams, vm, poses, rgb, depth, bg, args.steps, first=args.warmup)
     st = R.stage_times(reset=True)
-    sec = t1 - t0
     value = E * args.steps / sec
     ms_per_step = 1000.0 * sec / args.steps
     log(f"[bench] {value:.1f} env-frames/s, {ms_per_step:.2f} ms/step, stages {st}")
+    out.update({"value": value, "ms_per_step": ms_per_step,
+                "config": {"workload": synth.CONFIG_NAMES[args.config], "envs": E, "cams": C,
+                           "resolution": [[c.width, c.height] for c in cams], "gaussians": scene.n,
+                           "sh_degree": scene.sh_degree, "storage": args.storage, "tile": args.tile,
+                           "tuning": tuning, "chunk_streams": 1 if args.no_overlap else 2},
+                "stages_ms_per_step": {k: v / args.steps for k, v in st.items() if k in R.STAGES}})
+    last = args.warmup + args.steps - 1
+
+    # whole-path algorithmic HBM bytes per env-frame with the measured V and P
+    # per image: V (R + 8) + P (12 + 24 + 4 + R) + W H 16 + scene / E, R = 40 B
+    n_img_step = E * C
+    V = st["visible"] / max(st["renders"], 1) / n_img_step
+    P = st["pairs"] / max(st["renders"], 1) / n_img_step
+    px_env = sum(c.width * c.height for c in cams)
+    scene_bytes = R.scene_info(sid)[2]
+    b_alg = C * (V * 48 + P * 80) + px_env * 16 + scene_bytes / E
+    out["path"] = {"visible_per_image": V, "pairs_per_image": P, "pairs_per_step": P * n_img_step,
+                   "alg_bytes_per_env_frame": b_alg, "alg_hbm_frac": b_alg * value / (HBM_PEAK_GBS * 1e9)}
+    props = torch.cuda.get_device_properties(dev)
+    out["host"] = {"gpu": props.name, "arch": getattr(props, "gcnArchName", ""),
+                   "host_cores": len(os.sched_getaffinity(0)), "nproc": os.cpu_count()}
+
+    # roofline of the dominant kernel (the rasteriser, bound by vector ALU
+    # work): exact per-pixel work of every timed step, from counting renders
+    # of the same poses with the same launch parameters (untimed)
+    def roofline():
+        raster_ms = st["raster"] / max(st["raster_launches"], 1)
+        if args.no_count or raster_ms <= 0:
+            return None
+        npx = rgb.numel() // 3
+        work = torch.empty(npx * 2, dtype=torch.int32, device=dev)
+        scratch_rgb = torch.empty_like(rgb)
+        scratch_depth = torch.empty_like(depth)
+        visits = accepts = 0
+        for s in range(args.steps):
+            R.render_into(sid, cams, vm, poses[args.warmup + s], scratch_rgb, scratch_depth, None, bg, work=work)
+            w = work.view(npx, 2)
+            visits += int(w[:, 0].sum(dtype=torch.int64))
+            accepts += int(w[:, 1].sum(dtype=torch.int64))
+        torch.cuda.synchronize()
+        R.stage_times(reset=True)
+        del work, scratch_rgb, scratch_depth
+        flops_step = (visits * FLOPS_EVAL + accepts * FLOPS_ACCEPT) / args.steps
+        launches_per_step = st["raster_launches"] / args.steps
+        flops_launch = flops_step / launches_per_step
+        achieved = flops_launch / (raster_ms * 1e-3) / 1e12
+        traffic = measured_traffic(tuning)
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": "k_raster", "avg_ms": raster_ms, "launches_per_step": launches_per_step,
+                "flop_per_launch": flops_launch,
+                "visits_per_pixel": visits / (npx * args.steps), "accepts_per_pixel": accepts / (npx * args.steps),
+                "units": "list entries up to each pixel's termination x 11 flop + blended Gaussians x 11 flop"}
+        if traffic is not None:
+            roof["hbm_gbs"] = traffic / (raster_ms * 1e-3) / 1e9
+            roof["hbm_frac"] = roof["hbm_gbs"] / HBM_PEAK_GBS
+        roof["valu_lds"] = measured_util()
+        log(f"[bench] raster {roof['visits_per_pixel']:.1f} visits, {roof['accepts_per_pixel']:.1f} blends per "
+            f"pixel; {achieved:.2f} TFLOP/s algorithmic over {raster_ms:.2f} ms per launch")
+        return roof
+
+    leg("roofline", roofline)
+
+    # per-image error of the timed path's last step against the oracle
+    def headline_error():
+        pairs = [(c, e) for c in range(C) for e in sampled_envs(E, args.err_envs)]
+        imgs = gpu_images(cams, E, rgb, pairs)
+        b_last = synth.Batch(cams=batch.cams, viewmats=batch.viewmats, poses=pose_np[last], bg=batch.bg)
+        r = oracle_error(scene, b_last, imgs, args.tile, pairs)
+        log(f"[bench] error vs oracle: max-abs {r['max_abs_max']:.3g} (unflagged {r['max_abs_unflagged_max']:.3g})")
+        return r
+
+    if args.err_envs:
+        leg("error_vs_oracle", headline_error)
 
     # the same steps with every chunk on the render stream: the gain of the
     # two-stream overlap, and a stage breakdown in which no stages share the GPU
-    one_stream = None
-    if not args.no_overlap and args.one_stream_leg:
+    def one_stream_leg():
         R1 = gsr.Renderer(0, tile_size=args.tile, profile=True, graphs=not args.no_graphs, overlap=False)
-        sid1 = R1.add_synth_scene(scene, args.storage)
-        if tuning:
-            R1.set_tuning(sid1, cams, vm, poses[0], **{k: v for k, v in tuning.items() if k != "ms"})
-        R1.render_into(sid1, cams, vm, poses[0], rgb, depth, None, tuple(batch.bg))
-        torch.cuda.synchronize()
-        R1.stage_times(reset=True)
-        t0 = time.perf_counter()
-        for s in range(args.steps):
-            R1.render_into(sid1, cams, vm, poses[args.warmup + s], rgb, depth, None, tuple(batch.bg))
-        torch.cuda.synchronize()
-        osec = time.perf_counter() - t0
-        ost = R1.stage_times(reset=True)
-        one_stream = {"value": E * args.steps / osec, "unit": "env-frames/s",
-                      "ms_per_step": 1000.0 * osec / args.steps,
-                      "stages_ms_per_step": {k: v / args.steps for k, v in ost.items() if k in R.STAGES}}
-        R1.close()
-        del R1
-        log(f"[bench] one stream: {one_stream['value']:.1f} env-frames/s, stages {one_stream['stages_ms_per_step']}")
+        try:
+            sid1 = R1.add_synth_scene(scene, args.storage)
+            if tuning:
+                R1.set_tuning(sid1, cams, vm, poses[0], **{k: v for k, v in tuning.items() if k != "ms"})
+            R1.render_into(sid1, cams, vm, poses[0], rgb, depth, None, bg)
+            torch.cuda.synchronize()
+            R1.stage_times(reset=True)
+            osec = timed_steps(R1, sid1, cams, vm, poses, rgb, depth, bg, args.steps, first=args.warmup)
+            ost = R1.stage_times(reset=True)
+            r = {"value": E * args.steps / osec, "unit": "env-frames/s", "ms_per_step": 1000.0 * osec / args.steps,
+                 "stages_ms_per_step": {k: v / args.steps for k, v in ost.items() if k in R.STAGES}}
+            log(f"[bench] one stream: {r['value']:.1f} env-frames/s, stages {r['stages_ms_per_step']}")
+            return r
+        finally:
+            R1.close()
+
+    if not args.no_overlap and args.one_stream_leg:
+        leg("one_stream", one_stream_leg)
 
     # policy-ready observations: same workload, u8 pixels with per-image exposure /
     # contrast / brightness randomisation fused into the rasteriser, no float colour
-    observation = None
-    if args.obs_steps:
+    def observation_leg():
         g = torch.Generator().manual_seed(7)
         n_img = E * C
         gain = (2.0 ** (torch.rand(n_img, generator=g) - 0.5)).to(dev)
@@ -395,24 +670,19 @@ def main():
         bright = (0.1 * torch.rand(n_img, generator=g) - 0.05).to(dev)
         obs_out = torch.empty(rgb.numel(), dtype=torch.uint8, device=dev)
         obs = gsr.Observation("u8", obs_out, gain, contrast, bright)
-        R.render_into(sid, cams, vm, poses[args.warmup], None, depth, None, tuple(batch.bg), obs=obs)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s in range(args.obs_steps):
-            R.render_into(sid, cams, vm, poses[args.warmup + s % args.steps], None, depth, None, tuple(batch.bg),
-                          obs=obs)
-        torch.cuda.synchronize()
-        osec = time.perf_counter() - t0
+        R.render_into(sid, cams, vm, poses[args.warmup], None, depth, None, bg, obs=obs)
+        osec = timed_steps(R, sid, cams, vm, poses, None, depth, bg, args.obs_steps, first=args.warmup, obs=obs)
         R.stage_times(reset=True)
-        observation = {"value": E * args.obs_steps / osec, "unit": "env-frames/s", "format": "u8",
-                       "steps": args.obs_steps, "randomisation": "gain 2^U[-0.5,0.5], contrast U[0.8,1.2], "
-                                                                  "brightness U[-0.05,0.05] per image"}
-        del obs_out
-        log(f"[bench] observation path (u8 + randomisation) {observation['value']:.1f} env-frames/s")
+        r = {"value": E * args.obs_steps / osec, "unit": "env-frames/s", "format": "u8", "steps": args.obs_steps,
+             "randomisation": "gain 2^U[-0.5,0.5], contrast U[0.8,1.2], brightness U[-0.05,0.05] per image"}
+        log(f"[bench] observation path (u8 + randomisation) {r['value']:.1f} env-frames/s")
+        return r
+
+    if args.obs_steps:
+        leg("observation_path", observation_leg)
 
     # batch LiDAR on the same scene and poses: one rotating 32 x 1024 sensor per env
-    lidar = None
-    if args.lidar_steps:
+    def lidar_leg():
         lid = synth.rotating_lidar(32, 1024, -25.0, 15.0)
         lrng = np.random.default_rng(11)
         lvm = torch.from_numpy(synth.sensor_viewmats(lrng, E, 0.5, 3.0, 0.2)[None]).to(dev)
@@ -428,163 +698,126 @@ def main():
         torch.cuda.synchronize()
         lsec = time.perf_counter() - t0
         lst = R.stage_times(reset=True)
-        lidar = {"value": E * args.lidar_steps / lsec, "unit": "env-scans/s",
-                 "rays_per_s": n_rays * args.lidar_steps / lsec, "steps": args.lidar_steps,
-                 "sensor": "rotating, 32 beams [-25, 15] deg x 1024 columns", "envs": E,
-                 "ms_per_step": 1000.0 * lsec / args.lidar_steps,
-                 "stages_ms_per_step": {k: v / args.lidar_steps for k, v in lst.items() if k in R.STAGES},
-                 "hit_fraction": float((l_hit > 0.5).float().mean())}
-        del l_range, l_hit
-        log(f"[bench] LiDAR {lidar['value']:.1f} env-scans/s ({lidar['rays_per_s'] / 1e9:.2f} G rays/s)")
+        r = {"value": E * args.lidar_steps / lsec, "unit": "env-scans/s",
+             "rays_per_s": n_rays * args.lidar_steps / lsec, "steps": args.lidar_steps,
+             "sensor": "rotating, 32 beams [-25, 15] deg x 1024 columns", "envs": E,
+             "ms_per_step": 1000.0 * lsec / args.lidar_steps,
+             "stages_ms_per_step": {k: v / args.lidar_steps for k, v in lst.items() if k in R.STAGES},
+             "hit_fraction": float((l_hit > 0.5).float().mean())}
+        log(f"[bench] LiDAR {r['value']:.1f} env-scans/s ({r['rays_per_s'] / 1e9:.2f} G rays/s)")
+        return r
 
-    # half-precision storage: throughput of the same step, and the per-image
-    # error of every image against the float32-storage render of the same
-    # step (storage error; both are checked against the oracle in the tests)
-    storage = None
-    if args.storage_check and args.storage == "f32":
-        storage = {}
+    if args.lidar_steps:
+        leg("lidar", lidar_leg)
+
+    # half-precision storage on the same workload, with the float32 leg's
+    # launch parameters: throughput, per-image error against the oracle on
+    # the original float32 attributes (sampled envs), and against the
+    # float32-storage render of the same step (every image, float32 math)
+    def storage_leg():
+        res = {}
         ref_rgb = rgb.clone()                    # last timed step, float32 storage
-        last = poses[args.warmup + args.steps - 1]
         for st_name in ("f16", "bf16"):
             hsid = R.add_synth_scene(scene, st_name)
-            R.render_into(hsid, cams, vm, last, rgb, depth, None, tuple(batch.bg))
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for s in range(args.steps):
-                R.render_into(hsid, cams, vm, poses[args.warmup + s], rgb, depth, None, tuple(batch.bg))
-            torch.cuda.synchronize()
-            hsec = time.perf_counter() - t0
-            R.stage_times(reset=True)
-            per_img = []
-            base = 0
-            for cam in cams:                     # per camera slot: [E, H*W*3]
-                n = E * cam.width * cam.height * 3
-                d = (rgb[base:base + n] - ref_rgb[base:base + n]).view(E, -1).double()
-                per_img.append((d.abs().amax(dim=1), d.abs().mean(dim=1), (d * d).mean(dim=1)))
-                base += n
-            mx = torch.cat([p[0] for p in per_img]).cpu().numpy()
-            ma = torch.cat([p[1] for p in per_img]).cpu().numpy()
-            mse = torch.cat([p[2] for p in per_img]).cpu().numpy()
-            psnr = 10.0 * np.log10(1.0 / np.maximum(mse, 1e-30))
-            storage[st_name] = {"value": E * args.steps / hsec, "unit": "env-frames/s",
-                                "scene_bytes": R.scene_info(hsid)[2],
-                                "error_vs_f32_storage_per_image": {
-                                    "images": int(mx.size), "max_abs_max": float(mx.max()),
-                                    "mean_abs_mean": float(ma.mean()), "psnr_db_min": float(psnr.min()),
-                                    "psnr_db_median": float(np.median(psnr))}}
-            R.remove_scene(hsid)
-            log(f"[bench] {st_name} storage: {storage[st_name]}")
+            try:
+                if tuning:
+                    R.set_tuning(hsid, cams, vm, poses[0], **{k: v for k, v in tuning.items() if k != "ms"})
+                R.render_into(hsid, cams, vm, poses[last], rgb, depth, None, bg)
+                hsec = timed_steps(R, hsid, cams, vm, poses, rgb, depth, bg, args.steps, first=args.warmup)
+                R.stage_times(reset=True)
+                mx, ma, mse = [], [], []
+                base = 0
+                for cam in cams:                 # per camera slot, a few images at a time
+                    hw3 = cam.width * cam.height * 3
+                    for e0 in range(0, E, 64):
+                        e1 = min(E, e0 + 64)
+                        d = (rgb[base + e0 * hw3:base + e1 * hw3] - ref_rgb[base + e0 * hw3:base + e1 * hw3])
+                        d = d.view(e1 - e0, hw3).abs_()
+                        mx.append(d.amax(dim=1))
+                        ma.append(d.mean(dim=1))
+                        mse.append((d * d).mean(dim=1))
+                        del d
+                    base += E * hw3
+                mx = torch.cat(mx).cpu().numpy()
+                ma = torch.cat(ma).cpu().numpy()
+                mse = torch.cat(mse).cpu().numpy().astype(np.float64)
+                psnr = 10.0 * np.log10(1.0 / np.maximum(mse, 1e-30))
+                r = {"value": E * args.steps / hsec, "unit": "env-frames/s", "scene_bytes": R.scene_info(hsid)[2],
+                     "error_vs_f32_storage_per_image": {
+                         "images": int(mx.size), "max_abs_max": float(mx.max()), "mean_abs_mean": float(ma.mean()),
+                         "psnr_db_min": float(psnr.min()), "psnr_db_median": float(np.median(psnr))}}
+                if args.err_envs:
+                    pairs = [(c, e) for c in range(C) for e in sampled_envs(E, args.err_envs)]
+                    imgs = gpu_images(cams, E, rgb, pairs)
+                    b_last = synth.Batch(cams=batch.cams, viewmats=batch.viewmats, poses=pose_np[last], bg=batch.bg)
+                    r["error_vs_oracle"] = oracle_error(scene, b_last, imgs, args.tile, pairs)
+                res[st_name] = r
+                log(f"[bench] {st_name} storage: {r['value']:.1f} env-frames/s, "
+                    f"vs oracle max-abs {r.get('error_vs_oracle', {}).get('max_abs_max')}, "
+                    f"PSNR min {r.get('error_vs_oracle', {}).get('psnr_db_min')}")
+            finally:
+                R.remove_scene(hsid)
         del ref_rgb
+        return res
+
+    if args.storage_check and args.storage == "f32":
+        leg("half_storage", storage_leg)
 
     # plain per-env path on a subset (same GPU, same kernels, one image per launch chain)
-    plain = None
     if args.plain_envs:
-        pe = min(args.plain_envs, E)
-        sub = batch.subset(range(pe))
-        pcams, pvm, _ = gsr.batch_tensors(sub)
-        prgb, pdep, _ = R.alloc_outputs(pcams, pe)
-        pposes = poses[args.warmup][:pe].contiguous()
-        R.render_into(sid, pcams, pvm, pposes, prgb, pdep, None, tuple(batch.bg), plain=True)
-        torch.cuda.synchronize()
-        R.stage_times(reset=True)
-        t0 = time.perf_counter()
-        R.render_into(sid, pcams, pvm, pposes, prgb, pdep, None, tuple(batch.bg), plain=True)
-        torch.cuda.synchronize()
-        psec = time.perf_counter() - t0
-        R.stage_times(reset=True)
-        plain = {"value": pe / psec, "unit": "env-frames/s", "envs_timed": pe}
-        log(f"[bench] plain path {plain['value']:.1f} env-frames/s over {pe} envs")
+        leg("plain_path", lambda: plain_rate(R, sid, batch, poses[last], args.plain_envs, bg))
 
-    serving = run_serving(R, args) if args.serve_seconds > 0 else None
+    # the other workloads: 0 (plain 128x96), 1 (64 x 320x240), 3 (512 x two uneven cameras, BF16)
+    if args.configs:
+        cfgs = {}
+
+        def cfg_legs():
+            for cfg, storage, steps, n_plain in ((0, "f32", 200, 1), (1, "f32", 50, 64), (3, "bf16", args.steps, 64)):
+                try:
+                    cfgs[str(cfg)] = config_leg(cfg, storage, args, steps, n_plain, max(1, args.err_envs // 2))
+                except Exception as ex:      # noqa: BLE001
+                    traceback.print_exc()
+                    cfgs[str(cfg)] = {"error": f"{type(ex).__name__}: {ex}"}
+                _free()
+            return cfgs
+
+        leg("configs", cfg_legs)
+
+    if args.serve_seconds > 0:
+        leg("serving", lambda: run_serving(R, args))
 
     # oracle on the host cores, bounded sample of the same workload
-    cpu = None
-    if args.cpu_images:
-        from oracle import oracle_threads, render_ref
-        b0 = synth.make_config(args.config, n_envs=args.envs or None, step=args.warmup)[1]
+    def cpu_leg():
+        from oracle import oracle_threads, render_ref, set_oracle_threads
+        b0 = synth.Batch(cams=batch.cams, viewmats=batch.viewmats, poses=pose_np[args.warmup], bg=batch.bg)
+        envs = sampled_envs(E, args.cpu_images)
         cores = oracle_threads()
         t0 = time.perf_counter()
-        for k in range(args.cpu_images):
-            render_ref(scene, b0, 0, (k * 997) % E, args.tile, variants=False)
+        for e in envs:
+            for c in range(C):
+                render_ref(scene, b0, c, e, args.tile, variants=False)
         csec = time.perf_counter() - t0
-        cpu = {"value": args.cpu_images / csec, "unit": "env-frames/s", "cores": cores, "kind": "oracle",
-               "sample": f"{args.cpu_images} envs of step {args.warmup} (float32 binning spec on one thread + "
-                         f"float64 compositing on {cores} OpenMP threads)"}
-        log(f"[bench] oracle {cpu['value']:.3f} env-frames/s on {cores} cores")
+        r = {"value": len(envs) / csec, "unit": "env-frames/s", "cores": cores, "kind": "oracle",
+             "sample": f"{len(envs)} envs of step {args.warmup} (float32 binning spec on one thread + "
+                       f"float64 compositing on {cores} OpenMP threads)"}
+        if args.cpu_images_1t:
+            set_oracle_threads(1)
+            try:
+                envs1 = envs[:args.cpu_images_1t]
+                t0 = time.perf_counter()
+                for e in envs1:
+                    for c in range(C):
+                        render_ref(scene, b0, c, e, args.tile, variants=False)
+                r["single_thread"] = {"value": len(envs1) / (time.perf_counter() - t0), "unit": "env-frames/s",
+                                      "cores": 1, "envs": len(envs1)}
+            finally:
+                set_oracle_threads(cores)
+        log(f"[bench] oracle {r['value']:.3f} env-frames/s on {cores} cores")
+        return r
 
-    # roofline of the dominant kernel (the rasteriser, bound by vector ALU
-    # work): exact per-pixel work of every timed step, from counting renders
-    # of the same poses with the same launch parameters (untimed)
-    roof = None
-    raster_ms = st["raster"] / max(st["raster_launches"], 1)
-    if not args.no_count and raster_ms > 0:
-        npx = rgb.numel() // 3
-        work = torch.empty(npx * 2, dtype=torch.int32, device=dev)
-        visits = accepts = 0
-        for s in range(args.steps):
-            R.render_into(sid, cams, vm, poses[args.warmup + s], rgb, depth, None, tuple(batch.bg), work=work)
-            w = work.view(npx, 2)
-            visits += int(w[:, 0].sum(dtype=torch.int64))
-            accepts += int(w[:, 1].sum(dtype=torch.int64))
-        torch.cuda.synchronize()
-        R.stage_times(reset=True)
-        del work
-        flops_step = (visits * FLOPS_EVAL + accepts * FLOPS_ACCEPT) / args.steps
-        launches_per_step = st["raster_launches"] / args.steps
-        flops_launch = flops_step / launches_per_step
-        achieved = flops_launch / (raster_ms * 1e-3) / 1e12
-        traffic = measured_traffic(tuning)
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
-                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": "k_raster", "avg_ms": raster_ms, "launches_per_step": launches_per_step,
-                "flop_per_launch": flops_launch,
-                "visits_per_pixel": visits / (npx * args.steps), "accepts_per_pixel": accepts / (npx * args.steps),
-                "units": "list entries up to each pixel's termination x 11 flop + blended Gaussians x 11 flop"}
-        if traffic is not None:
-            # counted HBM bytes over the launch time measured here
-            roof["hbm_gbs"] = traffic / (raster_ms * 1e-3) / 1e9
-            roof["hbm_frac"] = roof["hbm_gbs"] / HBM_PEAK_GBS
-        roof["valu_lds"] = measured_util()
-        log(f"[bench] raster {roof['visits_per_pixel']:.1f} visits, {roof['accepts_per_pixel']:.1f} blends per "
-            f"pixel; {achieved:.2f} TFLOP/s algorithmic over {raster_ms:.2f} ms per launch")
+    if args.cpu_images:
+        leg("cpu_baseline", cpu_leg)
 
-    # whole-path algorithmic HBM bytes per env-frame with the measured V and P
-    # per image: V (R + 8) + P (12 + 24 + 4 + R) + W H 16 + scene / E, R = 40 B
-    n_img_step = E * C
-    V = st["visible"] / max(st["renders"], 1) / n_img_step
-    P = st["pairs"] / max(st["renders"], 1) / n_img_step
-    px_env = sum(c.width * c.height for c in cams)
-    scene_bytes = R.scene_info(sid)[2]
-    b_alg = C * (V * 48 + P * 80) + px_env * 16 + scene_bytes / E
-    path = {"visible_per_image": V, "pairs_per_image": P, "pairs_per_step": P * n_img_step,
-            "alg_bytes_per_env_frame": b_alg,
-            "alg_hbm_frac": b_alg * value / (HBM_PEAK_GBS * 1e9)}
-    props = torch.cuda.get_device_properties(dev)
-    host = {"gpu": props.name, "arch": getattr(props, "gcnArchName", ""),
-            "host_cores": len(os.sched_getaffinity(0)), "nproc": os.cpu_count()}
-
-    out = {
-        "metric": "env-frames/s at 640x480 x 2048 envs vs plain path; p50/p99 request latency",
-        "value": value, "unit": "env-frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.storage if args.storage != "f32" else "f32", "data": "synthetic",
-        "config": {"workload": synth.CONFIG_NAMES[args.config], "envs": E, "cams": C,
-                   "resolution": [[c.width, c.height] for c in cams], "gaussians": scene.n,
-                   "sh_degree": scene.sh_degree, "storage": args.storage, "tile": args.tile,
-                   "tuning": tuning, "chunk_streams": 1 if args.no_overlap else 2},
-        "plain_path": plain,
-        "observation_path": observation,
-        "lidar": lidar,
-        "half_storage": storage,
-        "serving": serving,
-        "stages_ms_per_step": {k: v / args.steps for k, v in st.items() if k in R.STAGES},
-        "one_stream": one_stream,
-        "path": path,
-        "host": host,
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
     print(json.dumps(out), flush=True)
     R.close()
 

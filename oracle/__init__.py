@@ -27,7 +27,7 @@ Gaussian clusters with their rigid bodies, "Rigid-Link Gaussian Kinematics"):
 """
 from .spec32 import bin_ref, quat_to_rot32  # noqa: F401
 from .attrs64 import attrs64  # noqa: F401
-from .render import render_ref, composite64, oracle_threads  # noqa: F401
+from .render import render_ref, composite64, oracle_threads, set_oracle_threads  # noqa: F401
 from .brute import brute_ref  # noqa: F401
 from .observe import observe64, observe32, observe_codes, quantise_u8  # noqa: F401
 from .lidar import lidar_ref, ray_directions  # noqa: F401

@@ -107,6 +107,17 @@ int oracle_threads(void)
 #endif
 }
 
+/* Sets the team size of later compositing calls (n >= 1); returns the new size. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return oracle_threads();
+}
+
 int oracle_composite(int W, int H, int ts, int tiles_x, const int64_t *ranges, const uint32_t *values,
                      const double *u, const double *v, const double *ca, const double *cb, const double *cc,
                      const double *op, const double *rgb, const double *z, const double *bg,

@@ -54,6 +54,8 @@ def _load():
                                          + [P] * 7)
         lib.oracle_composite.restype = ctypes.c_int
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -61,6 +63,11 @@ def _load():
 def oracle_threads() -> int:
     """Threads the float64 compositing runs on (the float32 binning is one thread)."""
     return int(_load().oracle_threads())
+
+
+def set_oracle_threads(n: int) -> int:
+    """Team size of later float64 compositing calls; returns it."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def _ptr(a: Optional[np.ndarray]):

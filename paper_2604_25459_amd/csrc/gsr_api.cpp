@@ -73,6 +73,19 @@ SceneRes::~SceneRes()
     if (last_use) (void)hipEventDestroy(last_use);
 }
 
+void Workspace::drop_graphs_of(uint64_t uid)
+{
+    for (auto it = graphs.begin(); it != graphs.end();) {
+        if (it->second.scene_uid == uid) {
+            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+            it = graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    if (twin) twin->drop_graphs_of(uid);
+}
+
 Workspace::~Workspace()
 {
     for (DevBuf* b : {&img, &xform, &keyz, &rect, &srect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &vis_count,
@@ -370,8 +383,8 @@ ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, int i
 // captured on the workspace's private stream (capture executes nothing) and
 // launched on the chunk's stream; a graph is re-captured when anything its
 // launches depend on (buffers, sizes, parameters) changed.
-int run_stage(Workspace& ws, bool graph, int chunk_idx, int stage, const std::vector<uint64_t>& key, hipStream_t st,
-              const std::function<hipError_t(hipStream_t)>& fn)
+int run_stage(Workspace& ws, bool graph, int chunk_idx, int stage, uint64_t scene_uid, const std::vector<uint64_t>& key,
+              hipStream_t st, const std::function<hipError_t(hipStream_t)>& fn)
 {
     if (!graph) {
         GSR_HIP_TRY(fn(st));
@@ -399,6 +412,7 @@ int run_stage(Workspace& ws, bool graph, int chunk_idx, int stage, const std::ve
             return hip_fail(e3, "hipGraphInstantiate");
         }
         g.key = key;
+        g.scene_uid = scene_uid;
     }
     GSR_HIP_TRY(hipGraphLaunch(g.exec, st));
     return GSR_OK;
@@ -440,8 +454,15 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
             if (!e) GSR_HIP_TRY(hipEventCreate(&e));
         GSR_HIP_TRY(hipEventRecord(ev.e[0], st));
     }
-    // everything the captured launches depend on
-    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)sc, (uint64_t)s.n, (uint64_t)(uintptr_t)c.img, (uint64_t)n_img,
+    // everything the captured launches depend on: the scene by its never-reused
+    // uid and by what selects and feeds its kernels (storage format and SH
+    // degree pick the projection's instantiation), the chunk's buffers, sizes
+    // and launch parameters
+    std::vector<uint64_t> key = {sc->uid, (uint64_t)s.n, (uint64_t)s.storage, (uint64_t)s.degree,
+                                 (uint64_t)s.n_bodies, (uint64_t)s.sh_chunks, (uint64_t)(uintptr_t)s.pos,
+                                 (uint64_t)(uintptr_t)s.rot, (uint64_t)(uintptr_t)s.scale, (uint64_t)(uintptr_t)s.sh,
+                                 (uint64_t)(uintptr_t)s.body_off, (uint64_t)job.lidar,
+                                 (uint64_t)(uintptr_t)c.img, (uint64_t)n_img,
                                  (uint64_t)c.t_max, (uint64_t)c.tx_max, (uint64_t)c.ty_max, (uint64_t)c.sort_blocks,
                                  (uint64_t)c.tile_blocks, (uint64_t)tu.ts, (uint64_t)tu.batch, (uint64_t)tu.ipt,
                                  (uint64_t)tu.persistent, (uint64_t)(uintptr_t)job.viewmats,
@@ -455,7 +476,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     for (int k = 0; k < n_img; ++k)
         key.push_back(((uint64_t)job.imgs[i0 + k].width << 32) | (uint64_t)job.imgs[i0 + k].height);
 
-    int rc = run_stage(ws, graph, chunk_idx, 0, key, st, [&](hipStream_t q) {
+    int rc = run_stage(ws, graph, chunk_idx, 0, sc->uid, key, st, [&](hipStream_t q) {
         hipError_t e = launch_compose(s, c, job.viewmats, job.poses, q);
         if (e == hipSuccess)
             e = job.lidar ? launch_project_lidar(s, c, tu.ts, tu.ipt, q)
@@ -465,10 +486,10 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     if (rc) return rc;
     if (mode == Mode::kProject) return GSR_OK;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[1], st));
-    rc = run_stage(ws, graph, chunk_idx, 1, key, st, [&](hipStream_t q) { return launch_depth_sort(s, c, q); });
+    rc = run_stage(ws, graph, chunk_idx, 1, sc->uid, key, st, [&](hipStream_t q) { return launch_depth_sort(s, c, q); });
     if (rc) return rc;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[2], st));
-    rc = run_stage(ws, graph, chunk_idx, 2, key, st, [&](hipStream_t q) {
+    rc = run_stage(ws, graph, chunk_idx, 2, sc->uid, key, st, [&](hipStream_t q) {
         hipError_t e = launch_tile_count(s, c, q);
         if (e == hipSuccess)
             e = hipMemcpyAsync(ws.h_total, c.pair_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, q);
@@ -492,14 +513,19 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
         ctx->count_visible += (double)ws.h_total[2];
     }
     // everything enqueued before ev_total has completed, including earlier chunks: growing is safe
-    if (ws.pairs.bytes < total * 4) {
-        const size_t want = std::max<size_t>(total * 4, (size_t)((double)ws.pairs.bytes * 1.5));
-        GSR_HIP_TRY(ws.pairs.ensure(std::max<size_t>(want + (total * 4) / 8, 1 << 20)));
-    }
-    if (ws.rows.bytes < row_total * 8) {
-        const size_t want = std::max<size_t>(row_total * 8, (size_t)((double)ws.rows.bytes * 1.5));
-        GSR_HIP_TRY(ws.rows.ensure(std::max<size_t>(want + (row_total * 8) / 8, 1 << 20)));
-    }
+    auto grow = [&](DevBuf& b, uint64_t entries, size_t entry_bytes, const char* what) -> int {
+        const size_t need = (size_t)entries * entry_bytes;
+        if (b.bytes >= need) return GSR_OK;
+        const size_t want = std::max<size_t>(std::max<size_t>(need, (size_t)((double)b.bytes * 1.5)) + need / 8, 1 << 20);
+        const hipError_t e = b.ensure(want);
+        if (e == hipSuccess) return GSR_OK;
+        char msg[256];
+        std::snprintf(msg, sizeof msg, "%s list of a %d-image chunk: %llu entries, %zu bytes requested (%s)", what,
+                      n_img, (unsigned long long)entries, want, hipGetErrorString(e));
+        return fail(e == hipErrorOutOfMemory ? GSR_E_OOM : GSR_E_DEVICE, msg);
+    };
+    if ((rc = grow(ws.pairs, total, 4, "tile")) != GSR_OK) return rc;
+    if ((rc = grow(ws.rows, row_total, 8, "tile-row")) != GSR_OK) return rc;
     c.pairs = ws.pairs.as<uint32_t>();
     c.rows = ws.rows.as<uint2>();
     // long tile-row lists are split into segments of about kRowSegEntries entries (one wave each)
@@ -515,7 +541,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     key.push_back((uint64_t)(uintptr_t)c.rows);
     key.push_back((uint64_t)n_seg);
     key.push_back((uint64_t)(uintptr_t)seg_off);
-    rc = run_stage(ws, graph, chunk_idx, 3, key, st,
+    rc = run_stage(ws, graph, chunk_idx, 3, sc->uid, key, st,
                    [&](hipStream_t q) { return launch_tile_scatter(s, c, tu.bin, n_seg, seg_off, q); });
     if (rc) return rc;
     if (mode == Mode::kBins) return GSR_OK;
@@ -551,10 +577,10 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     key.push_back((uint64_t)(uintptr_t)rp.counter);
     key.push_back((uint64_t)rp.count_work);
     if (job.lidar) {
-        rc = run_stage(ws, graph, chunk_idx, 4, key, st,
+        rc = run_stage(ws, graph, chunk_idx, 4, sc->uid, key, st,
                        [&](hipStream_t q) { return launch_raster_lidar(s, c, rp, q); });
     } else {
-        rc = run_stage(ws, graph, chunk_idx, 4, key, st, [&](hipStream_t q) { return launch_raster(s, c, rp, q); });
+        rc = run_stage(ws, graph, chunk_idx, 4, sc->uid, key, st, [&](hipStream_t q) { return launch_raster(s, c, rp, q); });
     }
     if (rc) return rc;
     if (prof) {
@@ -570,12 +596,19 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
 
 Workspace* acquire_workspace_locked(gsr_ctx* ctx, hipStream_t stream)
 {
+    Workspace* got = nullptr;
     for (auto& w : ctx->pool)
-        if (!w->in_call && (!w->used || w->last_stream == stream)) return w.get();
+        if (!got && !w->in_call && (!w->used || w->last_stream == stream)) got = w.get();
     for (auto& w : ctx->pool)
-        if (!w->in_call && hipEventQuery(w->ev_done) == hipSuccess) return w.get();
-    ctx->pool.emplace_back(new Workspace());
-    return ctx->pool.back().get();
+        if (!got && !w->in_call && hipEventQuery(w->ev_done) == hipSuccess) got = w.get();
+    if (!got) {
+        ctx->pool.emplace_back(new Workspace());
+        got = ctx->pool.back().get();
+    }
+    // graphs of scenes destroyed while the workspace was in a call
+    for (uint64_t uid : got->dead_scenes) got->drop_graphs_of(uid);
+    got->dead_scenes.clear();
+    return got;
 }
 
 int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_in, hipStream_t st, bool plain,
@@ -902,6 +935,8 @@ GSR_EXPORT int gsr_scene_create(gsr_ctx* ctx, const gsr_scene_desc* d, uint64_t*
     dv.sh = sc->sh.p;
     dv.body_off = sc->body_off.as<int>();
     sc->bytes = (int64_t)(sc->pos.bytes + sc->rot.bytes + sc->scale.bytes + sc->sh.bytes + sc->body_off.bytes);
+    static std::atomic<uint64_t> next_uid{1};
+    sc->uid = next_uid.fetch_add(1);
     std::lock_guard<std::mutex> lk(ctx->mu);
     const uint64_t id = ctx->next_id++;
     ctx->scenes[id] = std::move(sc);
@@ -919,6 +954,12 @@ GSR_EXPORT int gsr_scene_destroy(gsr_ctx* ctx, uint64_t scene_id)
     if (sc->in_calls.load() > 0) return fail(GSR_E_BUSY, "scene is used by a render call in progress");
     if (sc->used && sc->last_use && hipEventQuery(sc->last_use) == hipErrorNotReady)
         return fail(GSR_E_BUSY, "scene is used by in-flight work");
+    // captured graphs hold the scene's device pointers: drop them now where no
+    // call owns the workspace, else when the workspace is next handed out
+    for (auto& w : ctx->pool) {
+        if (w->in_call) w->dead_scenes.push_back(sc->uid);
+        else w->drop_graphs_of(sc->uid);
+    }
     ctx->scenes.erase(it);
     return GSR_OK;
 }

@@ -41,6 +41,7 @@ struct DevBuf {
 
 struct SceneRes {
     SceneDev dev{};
+    uint64_t uid = 0;                 // process-wide, never reused: identifies the scene in captured graphs
     DevBuf pos, rot, scale, sh, body_off;
     int64_t bytes = 0;
     hipEvent_t last_use = nullptr;   // recorded after the last render that used the scene
@@ -68,6 +69,7 @@ struct Tuning {
 // Captured launch sequence of one pipeline stage of one chunk.
 struct StageGraph {
     std::vector<uint64_t> key;
+    uint64_t scene_uid = 0;          // scene whose buffers the captured launches read
     hipGraphExec_t exec = nullptr;
 };
 
@@ -88,6 +90,9 @@ struct Workspace {
     DevBuf counter;         // persistent raster tile counter
     hipStream_t capture_stream = nullptr;          // graphs are captured here, launched on the chunk's stream
     std::map<std::pair<int, int>, StageGraph> graphs;   // (chunk index, stage) -> executable graph
+    std::vector<uint64_t> dead_scenes;   // uids of scenes destroyed while this workspace was in a call
+    // Drops every captured graph (here and in the twin) that reads scene `uid`.
+    void drop_graphs_of(uint64_t uid);
     // Second half of a two-stream render: odd chunks run on `side` in `twin`'s
     // buffers, so one chunk's binning overlaps the previous chunk's raster.
     std::unique_ptr<Workspace> twin;

@@ -273,6 +273,26 @@ def test_half_storage_cfg1(R, storage):
     R.remove_scene(sid)
 
 
+def test_scene_replaced_in_one_context(R):
+    """A scene destroyed and replaced by one of the same size but another
+    storage format: the replacement's renders (captured as graphs by the
+    first) must read the new scene, not replay the old one's launches."""
+    scene, batch = synth.make_config(1, n_envs=4)
+    first = _upload(R, scene, "f16")
+    for _ in range(2):                       # the second render replays the captured graphs
+        _render(R, first, batch)
+    R.remove_scene(first)
+    sid = _upload(R, scene, "bf16")
+    at = decoded_attrs(scene, "bf16")
+    for _ in range(2):
+        got = _render(R, sid, batch)
+    for e in (0, 3):
+        _check_bins(R, sid, scene, batch, 0, e, attrs=at)
+        ref = render_ref(scene, batch, 0, e, R.tile_size, attrs=at)
+        _check_image(_img(got, 0, e), ref, f"cfg1 bf16 after f16 env {e}")
+    R.remove_scene(sid)
+
+
 def test_cfg3_uneven_two_slots(R):
     scene, batch = synth.make_config(3, n_envs=16)
     sid = _upload(R, scene, "bf16")
