@@ -281,6 +281,7 @@ def test_scene_replaced_in_one_context(R):
     first = _upload(R, scene, "f16")
     for _ in range(2):                       # the second render replays the captured graphs
         _render(R, first, batch)
+    _torch().cuda.synchronize()              # destroying a scene with renders in flight is refused
     R.remove_scene(first)
     sid = _upload(R, scene, "bf16")
     at = decoded_attrs(scene, "bf16")
