@@ -343,19 +343,29 @@ def run_serving(R, args):
     infos = []
     t0_us = time.monotonic_ns() // 1000
 
+    refused = []
+
     def producer():
-        for k, (req, si, b) in enumerate(prepared):
-            now = time.monotonic_ns() // 1000 - t0_us
-            if req.arrival_s * 1e6 > now:
-                time.sleep((req.arrival_s * 1e6 - now) * 1e-6)
-            cams, vm, poses = gsr.batch_tensors(b)
-            rgb, depth, _ = R.alloc_outputs(cams, b.n_envs)
-            torch.cuda.current_stream(dev).synchronize()
-            t = S.submit(sids[si], cams, vm, poses, rgb, depth)
+        try:
+            for k, (req, si, b) in enumerate(prepared):
+                now = time.monotonic_ns() // 1000 - t0_us
+                if req.arrival_s * 1e6 > now:
+                    time.sleep((req.arrival_s * 1e6 - now) * 1e-6)
+                cams, vm, poses = gsr.batch_tensors(b)
+                rgb, depth, _ = R.alloc_outputs(cams, b.n_envs)
+                torch.cuda.current_stream(dev).synchronize()
+                try:
+                    t = S.submit(sids[si], cams, vm, poses, rgb, depth)
+                except gsr.GsrError as ex:
+                    if ex.code != gsr.GSR_E_REJECTED:
+                        raise
+                    refused.append(k)
+                    continue
+                with lock:
+                    tickets.append((t, k, b.n_envs * b.n_cams))
+        finally:
             with lock:
-                tickets.append((t, k, b.n_envs * b.n_cams))
-        with lock:
-            tickets.append((None, -1, 0))
+                tickets.append((None, -1, 0))     # the waiter stops here, also after an error
 
     th = threading.Thread(target=producer)
     th.start()
@@ -393,7 +403,7 @@ def run_serving(R, args):
            "latency_from_submit_p99_ms": float(np.percentile(lat_sub, 99)),
            "env_frames_per_s": n_img / wall, "wall_s": wall,
            "batches": st["batches"] - base["batches"], "mean_batch_requests": st["mean_batch_requests"],
-           "requests_by_batch_size": hist,
+           "requests_by_batch_size": hist, "requests_rejected": len(refused),
            "requests_merged": int((breq > 1).sum())}
     log(f"[serve] p50 {out['latency_p50_ms']:.2f} ms, p99 {out['latency_p99_ms']:.2f} ms, "
         f"{out['env_frames_per_s']:.0f} env-frames/s, {out['requests_merged']} requests merged")

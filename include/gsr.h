@@ -50,7 +50,7 @@ extern "C" {
 #define GSR_E_DEVICE (-3)    /* no gfx950 device, or a HIP call failed */
 #define GSR_E_NOT_FOUND (-4) /* unknown scene id or ticket */
 #define GSR_E_BUSY (-5)      /* scene still referenced by in-flight work */
-#define GSR_E_REJECTED (-6)  /* request can never fit the server's memory budget */
+#define GSR_E_REJECTED (-6)  /* request can never fit the server's memory budget (one image too large) */
 #define GSR_E_OVERFLOW (-7)  /* internal capacity exceeded (only surfaced if a retry fails) */
 #define GSR_E_TIMEOUT (-8)   /* gsr_wait timed out */
 
@@ -290,9 +290,12 @@ int gsr_debug_project(gsr_ctx* ctx, const gsr_render_desc* desc, int image, gsr_
  * request and merge later pending requests of the same scene into one batched
  * launch (any resolutions, up to 8 image sizes and max_batch_images images);
  * requests that arrive while batches run join the next batch a worker forms,
- * and batches on different streams overlap on the device.  A request is
- * admitted when its estimated working memory fits in memory_budget next to
- * the requests in flight; it waits in the queue otherwise.  Results are
+ * and batches on different streams overlap on the device.  A batch is
+ * rendered in memory chunks of at most min(memory_budget, the context's
+ * chunk_bytes) of estimated working memory (at least one image each), so a
+ * request occupies min(all its images, one chunk) while it runs.  A request is
+ * admitted when that fits in memory_budget next to the requests in flight; it
+ * waits in the queue otherwise.  Results are
  * identical to rendering the request alone: no per-image computation depends
  * on the batch. */
 typedef struct {
@@ -327,8 +330,9 @@ int gsr_server_create(gsr_ctx* ctx, const gsr_server_cfg* cfg, gsr_server** out)
 /* Queues a render request; thread-safe, non-blocking.  The descriptor is
  * validated (as gsr_render) and copied, including its camera array; its device
  * buffers (viewmats, body_poses, outputs) must stay valid and untouched until
- * gsr_wait reports the request complete.  GSR_E_REJECTED if the request alone
- * exceeds memory_budget. */
+ * gsr_wait reports the request complete.  GSR_E_REJECTED if one image of the
+ * request alone exceeds memory_budget (or the request has more images than
+ * max_batch_images). */
 int gsr_submit(gsr_server* srv, const gsr_render_desc* desc, uint64_t* ticket);
 /* Waits for a request: timeout_us < 0 waits forever, 0 polls.  Returns the
  * request's status (GSR_E_TIMEOUT if it is not complete yet); once a completed

@@ -236,8 +236,9 @@ size_t image_bytes_estimate(const SceneRes* sc, int width, int height, int ts)
 }
 
 ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain,
-                      int chunk_images, size_t rec_bytes)
+                      int chunk_images, size_t rec_bytes, int64_t chunk_bytes)
 {
+    const size_t budget = (size_t)(chunk_bytes > 0 ? chunk_bytes : ctx->opt.chunk_bytes);
     ChunkPlan p{};
     p.t_max = p.tx_max = p.ty_max = 1;
     for (const ImageInfo& im : imgs) {
@@ -252,7 +253,7 @@ ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<
         p.chunk = 1;
     } else {
         const size_t per = per_image_bytes(sc, p.t_max, p.ty_max, p.sort_blocks, p.tile_blocks, rec_bytes);
-        size_t c = std::max<size_t>(1, (size_t)ctx->opt.chunk_bytes / std::max<size_t>(per, 1));
+        size_t c = std::max<size_t>(1, budget / std::max<size_t>(per, 1));
         if (chunk_images > 0) c = std::min<size_t>(c, (size_t)chunk_images);
         p.chunk = (int)std::min<size_t>(c, imgs.size());
     }
@@ -617,7 +618,7 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
     if (job_in.imgs.empty()) return GSR_OK;
     RenderJob job = job_in;
     const size_t rec_bytes = job.lidar ? 80 : 48;
-    const ChunkPlan plan = plan_chunks(ctx, sc, job.imgs, plain, job.tune.chunk_images, rec_bytes);
+    const ChunkPlan plan = plan_chunks(ctx, sc, job.imgs, plain, job.tune.chunk_images, rec_bytes, job.chunk_bytes);
     // buffers may be reallocated: earlier work on this workspace must be finished
     if (ws.used) GSR_HIP_TRY(hipEventSynchronize(ws.ev_done));
     GSR_HIP_TRY(ensure_workspace(ws, sc, plan, job.imgs.size(), rec_bytes));

@@ -111,6 +111,7 @@ struct RenderJob {
     size_t pose_floats = 0;
     Tuning tune;
     bool lidar = false;                // LiDAR ray grids instead of camera images
+    int64_t chunk_bytes = 0;           // working-memory budget of one chunk (0: the context's option)
 };
 
 enum class Mode { kRender, kBins, kProject };
@@ -127,7 +128,7 @@ std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies)
 int validate_desc(const gsr_ctx* ctx, const gsr_render_desc* d, const SceneRes* sc, bool need_outputs);
 size_t image_bytes_estimate(const SceneRes* sc, int width, int height, int ts);
 ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain,
-                      int chunk_images = 0, size_t rec_bytes = 48);
+                      int chunk_images = 0, size_t rec_bytes = 48, int64_t chunk_bytes = 0);
 // Shape-class key of a render descriptor (scene, envs, camera sizes).
 std::string shape_key(const SceneRes* sc, const gsr_render_desc* d);
 // Tuning a render of `d` uses: the tuned entry of its shape class or the context defaults.

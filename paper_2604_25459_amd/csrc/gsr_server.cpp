@@ -39,7 +39,8 @@ struct Request {
     gsr_observation obs{};
     SceneRes* scene = nullptr;
     int n_images = 0;
-    int64_t bytes = 0;
+    int64_t bytes = 0;          // working memory while rendering: min(all images, one memory chunk)
+    int64_t image_bytes = 0;    // largest single-image estimate
     gsr_req_info info{};
     bool done = false;
 };
@@ -64,6 +65,13 @@ struct gsr_server {
 };
 
 namespace {
+
+// Working-memory budget of one chunk of a served batch: the context's chunk
+// size, never more than the server's whole memory budget.
+int64_t server_chunk_bytes(const gsr_server* srv)
+{
+    return std::min<int64_t>(srv->ctx->opt.chunk_bytes, srv->cfg.memory_budget);
+}
 
 // Render one batch on the worker's stream; returns the batch status.
 int render_batch(gsr_server* srv, Workspace& ws, hipStream_t st, const std::vector<Request*>& batch)
@@ -115,6 +123,7 @@ int render_batch(gsr_server* srv, Workspace& ws, hipStream_t st, const std::vect
     job.tune.ts = ctx->opt.tile_size;
     job.tune.batch = ctx->opt.tile_size == 8 ? 64 : 256;
     job.tune.ipt = ctx->opt.images_per_thread;
+    job.chunk_bytes = server_chunk_bytes(srv);
     // images of equal size contiguous (one raster segment each)
     std::stable_sort(job.imgs.begin(), job.imgs.end(), [](const ImageInfo& a, const ImageInfo& b) {
         return a.width != b.width ? a.width < b.width : a.height < b.height;
@@ -163,13 +172,17 @@ void worker_main(gsr_server* srv)
             batch.push_back(head);
             batch_bytes = head->bytes;
             batch_images = head->n_images;
+            const int64_t chunk = server_chunk_bytes(srv);
+            int64_t sum_bytes = head->bytes, img_max = head->image_bytes;
             for (auto it = srv->pending.begin(); it != srv->pending.end();) {
                 Request* r = *it;
+                const int64_t merged = std::min(sum_bytes + r->bytes, std::max(std::max(img_max, r->image_bytes), chunk));
                 if (r->scene == head->scene && batch_images + r->n_images <= srv->cfg.max_batch_images &&
-                    srv->in_flight_bytes + batch_bytes + r->bytes <= srv->cfg.memory_budget &&
-                    distinct_sizes(batch, r) <= kMaxSegs) {
+                    srv->in_flight_bytes + merged <= srv->cfg.memory_budget && distinct_sizes(batch, r) <= kMaxSegs) {
                     batch.push_back(r);
-                    batch_bytes += r->bytes;
+                    sum_bytes += r->bytes;
+                    img_max = std::max(img_max, r->image_bytes);
+                    batch_bytes = merged;
                     batch_images += r->n_images;
                     it = srv->pending.erase(it);
                 } else {
@@ -256,14 +269,21 @@ GSR_EXPORT int gsr_submit(gsr_server* srv, const gsr_render_desc* d, uint64_t* t
     }
     r->scene = sc;
     r->n_images = d->n_envs * d->n_cams;
-    for (const gsr_camera& c : r->cams)
-        r->bytes += (int64_t)image_bytes_estimate(sc, c.width, c.height, ctx->opt.tile_size) * d->n_envs;
+    int64_t all = 0;
+    for (const gsr_camera& c : r->cams) {
+        const int64_t one = (int64_t)image_bytes_estimate(sc, c.width, c.height, ctx->opt.tile_size);
+        all += one * d->n_envs;
+        r->image_bytes = std::max(r->image_bytes, one);
+    }
+    // a render holds one memory chunk of images at a time (at least one
+    // image): that is what the request occupies while it runs
+    r->bytes = std::min(all, std::max(r->image_bytes, server_chunk_bytes(srv)));
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stopping) {
         release_scene(sc);
         return fail(GSR_E_INVALID, "server is shutting down");
     }
-    if (r->bytes > srv->cfg.memory_budget || r->n_images > srv->cfg.max_batch_images) {
+    if (r->image_bytes > srv->cfg.memory_budget || r->n_images > srv->cfg.max_batch_images) {
         srv->rejected += 1;
         release_scene(sc);
         return fail(GSR_E_REJECTED, "request can never fit the server's memory budget or batch size");

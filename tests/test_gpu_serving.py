@@ -67,21 +67,29 @@ def test_server_results_equal_solo_renders():
 
 
 def test_server_memory_admission():
-    _torch()
+    """A request larger than the server's memory budget is rendered in chunks
+    that fit it (and equals its solo render); one whose single image can never
+    fit is rejected; the memory in flight never exceeds the budget."""
+    torch = _torch()
     from paper_2604_25459_amd import gsr
     R = gsr.Renderer(0)
     scene = _scene(13, 20_000, 2)
     sid = R.add_synth_scene(scene)
+    huge = synth.make_scene(14, 800_000, 0, 0, sh_degree=0, half_box=4.0)
+    hid = R.add_synth_scene(huge)
     budget = 96 << 20
     S = gsr.Server(R, n_streams=2, memory_budget=budget)
     rng = np.random.default_rng(9)
-    big = _request(rng, scene, 64, [(640, 480)])
-    cams, vm, poses = gsr.batch_tensors(big)
-    rgb, depth, _ = R.alloc_outputs(cams, big.n_envs)
+    one = _request(rng, huge, 1, [(640, 480)])      # one image of an 800k-Gaussian scene: > 96 MiB
+    cams, vm, poses = gsr.batch_tensors(one)
+    rgb, depth, _ = R.alloc_outputs(cams, one.n_envs)
     with pytest.raises(gsr.GsrError) as ei:
-        S.submit(sid, cams, vm, poses, rgb, depth)
+        S.submit(hid, cams, vm, poses, rgb, depth)
     assert ei.value.code == gsr.GSR_E_REJECTED
-    tickets = []
+    big = _request(rng, scene, 64, [(640, 480)])    # 64 images: more than the budget, rendered in chunks
+    bc, bv, bp = gsr.batch_tensors(big)
+    brgb, bdepth, _ = R.alloc_outputs(bc, big.n_envs)
+    tickets = [S.submit(sid, bc, bv, bp, brgb, bdepth, bg=tuple(big.bg))]
     keep = []
     for k in range(6):
         b = _request(rng, scene, 4, [(320, 240)])
@@ -92,8 +100,11 @@ def test_server_memory_admission():
     for t in tickets:
         S.wait(t)
     st = S.stats()
-    assert st["rejected"] == 1 and st["completed"] == 6
+    assert st["rejected"] == 1 and st["completed"] == 7
     assert 0 < st["in_flight_bytes_max"] <= budget
+    solo = R.render(sid, bc, bv, bp, bg=tuple(big.bg))
+    got = R.split(bc, big.n_envs, brgb, bdepth)
+    assert torch.equal(solo[0][0], got[0][0]) and torch.equal(solo[0][1], got[0][1])
     with pytest.raises(gsr.GsrError) as ei:
         S.wait(tickets[0])
     assert ei.value.code == gsr.GSR_E_NOT_FOUND
