@@ -30,4 +30,4 @@ from .attrs64 import attrs64  # noqa: F401
 from .render import render_ref, composite64, oracle_threads, set_oracle_threads  # noqa: F401
 from .brute import brute_ref  # noqa: F401
 from .observe import observe64, observe32, observe_codes, quantise_u8  # noqa: F401
-from .lidar import lidar_ref, ray_directions  # noqa: F401
+from .lidar import lidar_ref, lidar_ray_variants, ray_directions  # noqa: F401

@@ -19,10 +19,14 @@
  *
  * Threshold decisions taken within a relative distance `margin` of their
  * boundary (|alpha*255 - 1| or |T'/1e-4 - 1|) are "flagged": a float32
- * implementation may legitimately take either branch.  For a pixel with
- * flagged decisions every combination of the first `max_flags` of them is
- * evaluated (depth-first over decision strings), giving up to 2^max_flags
- * admissible results; the first is the unflipped one.
+ * implementation may legitimately take either branch.  A variant of a pixel is
+ * one run in which flip bit k inverts the k-th flagged decision met along the
+ * list (counting the decisions of that run, so flipping an early one can bring
+ * later ones into play).  oracle_composite evaluates, for every pixel, the
+ * variants of the first `max_flags` flagged decisions (2^max_flags results,
+ * the first unflipped); oracle_pixel_variants enumerates every variant of one
+ * pixel, widening the flip set until no run meets more flagged decisions than
+ * it covers.
  */
 #include <math.h>
 #include <stdint.h>
@@ -123,7 +127,8 @@ int oracle_composite(int W, int H, int ts, int tiles_x, const int64_t *ranges, c
                      const double *op, const double *rgb, const double *z, const double *bg,
                      double margin, int max_flags,
                      double *out_rgb, double *out_depth, double *out_alpha,
-                     double *var_rgb, double *var_depth, int32_t *nflag_out, int64_t *visited_out)
+                     double *var_rgb, double *var_depth, double *var_alpha, int32_t *nflag_out,
+                     int64_t *visited_out)
 {
     gattr_t A = {u, v, ca, cb, cc, op, rgb, z};
     const int nvar = 1 << max_flags;
@@ -158,9 +163,46 @@ int oracle_composite(int W, int H, int ts, int tiles_x, const int64_t *ranges, c
                     d[2] = rf.rgb[2];
                 }
                 if (var_depth) var_depth[(size_t)f * npix + p] = rf.depth;
+                if (var_alpha) var_alpha[(size_t)f * npix + p] = rf.alpha;
             }
             nflag_out[p] = r0.nflag + (unresolved ? 65536 : 0);
         }
     }
     return 0;
+}
+
+/*
+ * Every admissible result of pixel (x, y): all 2^m variants, where m is the
+ * smallest flip-set size such that no variant run meets more than m flagged
+ * decisions (m starts at the unflipped run's count).  Results go to
+ * out_rgb [2^m][3], out_depth [2^m], out_alpha [2^m] (room for 2^max_m each);
+ * returns 2^m, or -1 if m would exceed max_m.
+ */
+int oracle_pixel_variants(int x, int y, int ts, int tiles_x, const int64_t *ranges, const uint32_t *values,
+                          const double *u, const double *v, const double *ca, const double *cb, const double *cc,
+                          const double *op, const double *rgb, const double *z, const double *bg, double margin,
+                          int max_m, double *out_rgb, double *out_depth, double *out_alpha)
+{
+    gattr_t A = {u, v, ca, cb, cc, op, rgb, z};
+    const int64_t t = (int64_t)(y / ts) * tiles_x + (x / ts);
+    const int64_t s0 = ranges[2 * t], s1 = ranges[2 * t + 1];
+    const double px = x + 0.5, py = y + 0.5;
+    pix_t r;
+    run_pixel(values + s0, s1 - s0, px, py, &A, bg, margin, 0u, 31, &r);
+    int m = r.nflag;
+    for (;;) {
+        if (m > max_m) return -1;
+        int widest = m;
+        for (unsigned f = 0; f < (1u << m); ++f) {
+            run_pixel(values + s0, s1 - s0, px, py, &A, bg, margin, f, m, &r);
+            if (r.nflag > widest) widest = r.nflag;
+            out_rgb[3 * (size_t)f + 0] = r.rgb[0];
+            out_rgb[3 * (size_t)f + 1] = r.rgb[1];
+            out_rgb[3 * (size_t)f + 2] = r.rgb[2];
+            out_depth[f] = r.depth;
+            out_alpha[f] = r.alpha;
+        }
+        if (widest == m) return (int)(1u << m);
+        m = widest;
+    }
 }

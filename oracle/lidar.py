@@ -69,9 +69,9 @@ def centre_order(scene, batch, l: int, e: int, attrs=None) -> np.ndarray:
     return idx[np.lexsort((idx, keys))]
 
 
-def lidar_ref(scene, batch, l: int = 0, e: int = 0, attrs=None, margin: float = 1e-3) -> LidarRef:
-    """Range and hit of every ray of LiDAR slot ``l`` of env ``e``."""
-    lid = batch.cams[l]
+def _sensor_frame(scene, batch, l, e, attrs):
+    """Sensor-frame means m_s (N, 3), whitening matrices S^-1 R^T (N, 3, 3)
+    and opacities, in float64 (rigid-body posing, then world -> sensor)."""
     at = attrs or {}
     mu = np.asarray(at.get("means", scene.means), np.float64)
     s = np.asarray(at.get("scales", scene.scales), np.float64)
@@ -91,7 +91,33 @@ def lidar_ref(scene, batch, l: int = 0, e: int = 0, attrs=None, margin: float = 
     m_s = (np.einsum("nij,nj->ni", Rb, mu) + tb) @ Wv.T + wv                 # sensor-frame means
     R_s = Wv[None] @ Rb @ quat_to_rot64(qg)                                   # sensor-frame rotations
     Wh = np.transpose(R_s, (0, 2, 1)) / s[:, :, None]                         # whitening S^-1 R^T
+    return m_s, Wh, op
 
+
+def _peak(d, m, W, o):
+    """Peak response of Gaussians (centre m, whitening W, opacity o) along
+    rays x(t) = t d: t* = argmin |W (t d - m)|^2 and alpha = min(0.99,
+    o exp(-q(t*)/2)).  d is (rays, 3) for one Gaussian or (3,) for many."""
+    if d.ndim == 2:                                       # many rays, one Gaussian
+        dw = d @ W.T
+        mw = W @ m
+        tstar = (dw @ mw) / np.einsum("ij,ij->i", dw, dw)
+        p = m[None] - tstar[:, None] * d
+        pw = p @ W.T
+    else:                                                 # one ray, many Gaussians
+        dw = np.einsum("nij,j->ni", W, d)
+        mw = np.einsum("nij,nj->ni", W, m)
+        tstar = np.einsum("ni,ni->n", dw, mw) / np.einsum("ni,ni->n", dw, dw)
+        p = m - tstar[:, None] * d[None]
+        pw = np.einsum("nij,nj->ni", W, p)
+    q = np.einsum("ij,ij->i", pw, pw)
+    return tstar, np.minimum(0.99, o * np.exp(-0.5 * q))
+
+
+def lidar_ref(scene, batch, l: int = 0, e: int = 0, attrs=None, margin: float = 1e-3) -> LidarRef:
+    """Range and hit of every ray of LiDAR slot ``l`` of env ``e``."""
+    lid = batch.cams[l]
+    m_s, Wh, op = _sensor_frame(scene, batch, l, e, attrs)
     d = ray_directions(lid).reshape(-1, 3)
     n_rays = d.shape[0]
     near = float(np.float32(lid.near_range))
@@ -101,12 +127,7 @@ def lidar_ref(scene, batch, l: int = 0, e: int = 0, attrs=None, margin: float = 
     flagged = np.zeros(n_rays, bool)
     order = centre_order(scene, batch, l, e, attrs)
     for g in order:
-        dw = d @ Wh[g].T                                  # (rays, 3) whitened directions
-        mw = Wh[g] @ m_s[g]
-        tstar = (dw @ mw) / np.einsum("ij,ij->i", dw, dw)
-        p = m_s[g][None] - tstar[:, None] * d             # offset of the centre from the closest ray point
-        q = np.einsum("ij,ij->i", p @ Wh[g].T, p @ Wh[g].T)
-        a = np.minimum(0.99, op[g] * np.exp(-0.5 * q))
+        tstar, a = _peak(d, m_s[g], Wh[g], op[g])
         front = tstar > near
         take = live & front & (a >= ALPHA_MIN)
         flagged |= live & front & (np.abs(a * 255.0 - 1.0) < margin)
@@ -122,3 +143,60 @@ def lidar_ref(scene, batch, l: int = 0, e: int = 0, attrs=None, margin: float = 
     rng = np.where(T < 1.0, Rg / np.maximum(hit, 1e-300), 0.0)
     H, W = lid.height, lid.width
     return LidarRef(range=rng.reshape(H, W), hit=hit.reshape(H, W), flagged=flagged.reshape(H, W), order=order)
+
+
+def _ray_run(tstar, a, near, margin, flips, max_flags):
+    """One ray composited over per-Gaussian (t*, alpha) in compositing order,
+    with the same flagged decisions as lidar_ref, taken in this order per
+    Gaussian: in front of the near range, alpha >= 1/255, transmittance
+    stop.  Flip bit k inverts the k-th flagged decision met.  Returns
+    (range, hit, flagged decisions met)."""
+    T, R, nflag = 1.0, 0.0, 0
+    added = False
+
+    def decide(value, is_flagged):
+        nonlocal nflag
+        if is_flagged:
+            if nflag < max_flags and (flips >> nflag) & 1:
+                value = not value
+            nflag += 1
+        return value
+
+    for ts, al in zip(tstar, a):
+        near_flag = abs(ts - near) < margin * max(1.0, near) and al >= ALPHA_MIN * (1 - margin)
+        if not decide(ts > near, near_flag):
+            continue
+        if not decide(al >= ALPHA_MIN, abs(al * 255.0 - 1.0) < margin):
+            continue
+        Tn = T * (1.0 - al)
+        if decide(Tn < T_MIN, abs(Tn / T_MIN - 1.0) < margin):
+            break
+        R += ts * al * T
+        T = Tn
+        added = True
+    hit = 1.0 - T
+    return (R / hit if added else 0.0), hit, nflag
+
+
+def lidar_ray_variants(scene, batch, l: int, e: int, row: int, col: int, attrs=None, margin: float = 1e-3,
+                       max_m: int = 12):
+    """Every admissible (range, hit) of ray (row, col) of LiDAR slot ``l`` of
+    env ``e``: all combinations of its flagged decisions, widened until no
+    combination meets a flagged decision outside the enumerated ones
+    (arrays of 2^m values; [0] is lidar_ref's result)."""
+    lid = batch.cams[l]
+    m_s, Wh, op = _sensor_frame(scene, batch, l, e, attrs)
+    order = centre_order(scene, batch, l, e, attrs)
+    d = ray_directions(lid)[row, col]
+    with np.errstate(all="ignore"):
+        tstar, a = _peak(d, m_s[order], Wh[order], op[order])
+    near = float(np.float32(lid.near_range))
+    m = _ray_run(tstar, a, near, margin, 0, 0)[2]
+    while True:
+        if m > max_m:
+            raise RuntimeError(f"ray ({row}, {col}) has more than {max_m} flagged decisions")
+        runs = [_ray_run(tstar, a, near, margin, f, m) for f in range(1 << m)]
+        widest = max(r[2] for r in runs)
+        if widest == m:
+            return np.array([r[0] for r in runs]), np.array([r[1] for r in runs])
+        m = widest

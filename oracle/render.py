@@ -51,8 +51,11 @@ def _load():
         lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.oracle_composite.argtypes = ([ctypes.c_int] * 4 + [P, P] + [P] * 9 + [ctypes.c_double, ctypes.c_int]
-                                         + [P] * 7)
+                                         + [P] * 8)
         lib.oracle_composite.restype = ctypes.c_int
+        lib.oracle_pixel_variants.argtypes = ([ctypes.c_int] * 4 + [P, P] + [P] * 9 + [ctypes.c_double, ctypes.c_int]
+                                              + [P] * 3)
+        lib.oracle_pixel_variants.restype = ctypes.c_int
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_set_threads.restype = ctypes.c_int
@@ -81,11 +84,29 @@ class RefImage:
     alpha: np.ndarray        # (H, W)
     var_rgb: np.ndarray      # (V, H, W, 3) admissible alternatives (V = 2^max_flags), [0] = rgb
     var_depth: np.ndarray    # (V, H, W)
+    var_alpha: np.ndarray    # (V, H, W)
     nflag: np.ndarray        # (H, W) flagged decisions of the primary run
-    unresolved: np.ndarray   # (H, W) bool: more flagged decisions than enumerated
+    unresolved: np.ndarray   # (H, W) bool: more flagged decisions than enumerated in var_*
     visited: np.ndarray      # (H, W) list entries visited up to termination
     bins: Optional[Bins] = None
     attrs: Optional[Dict[str, np.ndarray]] = None
+    _args: Optional[tuple] = None   # compositing inputs, for pixel_variants
+
+    def pixel_variants(self, x: int, y: int, max_m: int = 16):
+        """Every admissible (rgb [V, 3], depth [V], alpha [V]) of pixel (x, y):
+        all combinations of its flagged decisions, widened until no variant
+        meets a flagged decision outside them.  Raises if that takes more than
+        max_m flags."""
+        lib = _load()
+        ts, tiles_x, ranges, values, arrs, bg, margin = self._args
+        n = 1 << max_m
+        o_rgb, o_dep, o_alp = np.empty((n, 3)), np.empty(n), np.empty(n)
+        k = lib.oracle_pixel_variants(int(x), int(y), int(ts), int(tiles_x), _ptr(ranges), _ptr(values),
+                                      *[_ptr(a) for a in arrs], _ptr(bg), float(margin), int(max_m),
+                                      _ptr(o_rgb), _ptr(o_dep), _ptr(o_alp))
+        if k < 0:
+            raise RuntimeError(f"pixel ({x}, {y}) has more than {max_m} flagged decisions")
+        return o_rgb[:k].copy(), o_dep[:k].copy(), o_alp[:k].copy()
 
 
 def composite64(bins: Bins, at: Dict[str, np.ndarray], width: int, height: int, ts: int, bg,
@@ -107,16 +128,19 @@ def composite64(bins: Bins, at: Dict[str, np.ndarray], width: int, height: int, 
     out_alpha = np.empty((H, W))
     var_rgb = np.empty((nvar, H, W, 3)) if variants else None
     var_depth = np.empty((nvar, H, W)) if variants else None
+    var_alpha = np.empty((nvar, H, W)) if variants else None
     nflag = np.empty((H, W), np.int32)
     visited = np.empty((H, W), np.int64)
     lib.oracle_composite(W, H, int(ts), int(bins.tiles_x), _ptr(ranges), _ptr(values), _ptr(u), _ptr(v),
                          _ptr(ca), _ptr(cb), _ptr(cc), _ptr(op), _ptr(rgb), _ptr(z), _ptr(bg),
                          float(margin), int(max_flags), _ptr(out_rgb), _ptr(out_depth), _ptr(out_alpha),
-                         _ptr(var_rgb), _ptr(var_depth), _ptr(nflag), _ptr(visited))
+                         _ptr(var_rgb), _ptr(var_depth), _ptr(var_alpha), _ptr(nflag), _ptr(visited))
     if not variants:
-        var_rgb, var_depth = out_rgb[None], out_depth[None]
+        var_rgb, var_depth, var_alpha = out_rgb[None], out_depth[None], out_alpha[None]
     return RefImage(rgb=out_rgb, depth=out_depth, alpha=out_alpha, var_rgb=var_rgb, var_depth=var_depth,
-                    nflag=nflag & 0xFFFF, unresolved=nflag >= 65536, visited=visited)
+                    var_alpha=var_alpha, nflag=nflag & 0xFFFF, unresolved=nflag >= 65536, visited=visited,
+                    _args=(int(ts), int(bins.tiles_x), ranges, values, (u, v, ca, cb, cc, op, rgb, z), bg,
+                           float(margin)))
 
 
 def render_ref(scene, batch, c: int = 0, e: int = 0, ts: int = 16, bg=None, cutoff: float = 3.33,

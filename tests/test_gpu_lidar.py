@@ -40,15 +40,28 @@ def _tensors(batch):
             torch.from_numpy(np.ascontiguousarray(batch.poses, np.float32)).to(dev))
 
 
-def _compare(got_range, got_hit, ref, label, min_hits=20):
-    ok = ~ref.flagged
+def _compare(got_range, got_hit, ref, label, scene, batch, l, e, min_hits=20):
+    """Every ray matches the oracle's result, or, if one of its threshold
+    decisions is flagged, one of its admissible results (all enumerated)."""
+    from oracle import lidar_ray_variants
+
+    def within(r, h, rr, hh):
+        return (np.abs(h - hh) <= HIT_TOL) & (np.abs(r - rr) / np.maximum(1.0, rr) <= RANGE_REL)
+
+    ok = within(got_range, got_hit, ref.range, ref.hit)
+    calm = ~ref.flagged
+    by_variant = 0
+    for y, x in zip(*np.nonzero(~ok & ref.flagged)):
+        rr, hh = lidar_ray_variants(scene, batch, l, e, y, x)
+        if within(got_range[y, x], got_hit[y, x], rr, hh).any():
+            ok[y, x] = True
+            by_variant += 1
     e_hit = np.abs(got_hit - ref.hit)
     e_rng = np.abs(got_range - ref.range) / np.maximum(1.0, ref.range)
-    print(f"[{label}] rays {ok.size} flagged {int((~ok).sum())} hits {int((ref.hit > 0).sum())} "
-          f"max hit err {e_hit[ok].max():.2e} max range rel err {e_rng[ok].max():.2e}", flush=True)
-    assert (~ok).mean() < 0.05
-    assert e_hit[ok].max() <= HIT_TOL
-    assert e_rng[ok].max() <= RANGE_REL
+    print(f"[{label}] rays {ok.size} flagged {int(ref.flagged.sum())} matched by a variant {by_variant} "
+          f"hits {int((ref.hit > 0).sum())} max hit err (unflagged) {e_hit[calm].max():.2e} "
+          f"max range rel err (unflagged) {e_rng[calm].max():.2e}", flush=True)
+    assert ok.all(), (label, int((~ok).sum()))
     assert (ref.hit > 0.1).sum() >= min_hits   # the scans see something
 
 
@@ -76,7 +89,8 @@ def test_lidar_rotating_and_mounted_match_oracle(R):
     out = R.render_lidar(sid, [rot, sec], vm_t, poses_t)
     for l, e in ((0, 0), (0, 2), (1, 1)):
         ref = lidar_ref(scene, batch, l, e)
-        _compare(out[l][0][e].cpu().numpy(), out[l][1][e].cpu().numpy(), ref, f"lidar {l} env {e}")
+        _compare(out[l][0][e].cpu().numpy(), out[l][1][e].cpu().numpy(), ref, f"lidar {l} env {e}", scene, batch, l,
+                 e)
     # the same scans again: deterministic
     again = R.render_lidar(sid, [rot, sec], vm_t, poses_t)
     import torch
@@ -97,7 +111,7 @@ def test_lidar_seam_and_near_sensor(R):
     vm_t, poses_t = _tensors(batch)
     out = R.render_lidar(sid, [lid], vm_t, poses_t)
     ref = lidar_ref(scene, batch, 0, 0)
-    _compare(out[0][0][0].cpu().numpy(), out[0][1][0].cpu().numpy(), ref, "seam", min_hits=5)
+    _compare(out[0][0][0].cpu().numpy(), out[0][1][0].cpu().numpy(), ref, "seam", scene, batch, 0, 0, min_hits=5)
     assert ref.hit[4, 0] > 0.3 and ref.hit[4, -1] > 0.3
     R.remove_scene(sid)
 

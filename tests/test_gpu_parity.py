@@ -74,15 +74,14 @@ def _check_bins(R, sid, scene, batch, c, e, attrs=None):
 
 
 def _check_image(got, ref, label, rgb_tol=1e-3):
+    """RGB, depth and alpha of every pixel against the oracle: the primary
+    result, or for a pixel with flagged threshold decisions one of its
+    admissible variants (all of them enumerated; rgb, depth and alpha from the
+    same variant)."""
     rgb, depth, alpha = got
-    res = compare(rgb, depth, ref, rgb_tol=rgb_tol)
+    res = compare(rgb, depth, ref, gpu_alpha=alpha, rgb_tol=rgb_tol)
     print(f"[{label}] {res}", flush=True)
     assert res["ok"], (label, res)
-    assert res["n_unresolved"] <= max(2, res["n_pix"] // 20000)
-    # alpha of the primary result; a pixel with a flagged threshold decision may
-    # take the other admissible branch (its colour was checked against all of them)
-    calm = ref.nflag == 0
-    np.testing.assert_allclose(alpha[calm], ref.alpha[calm], atol=2e-3)
     return res
 
 

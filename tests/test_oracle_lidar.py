@@ -135,3 +135,30 @@ def test_full_turn_seam():
     ref = lidar_ref(scene, _batch(lid))
     assert ref.hit[0, 0] > 0.5 and ref.hit[0, -1] > 0.5
     assert ref.hit[0, 0] == pytest.approx(ref.hit[0, -1], rel=1e-6)
+
+
+@pytest.mark.parametrize("delta", [1e-4, -1e-4])
+def test_flagged_ray_lists_both_branches(delta):
+    """A ray passing a Gaussian (opacity 0.5) at the distance where its peak
+    alpha is (1 + delta)/255: the ray is flagged, and its admissible results
+    are 'taken' (hit alpha, range t* = D cos phi) and 'skipped' (nothing), the
+    float64 branch first."""
+    from oracle import lidar_ray_variants
+    el = np.float32(math.radians(1.0))
+    lid = synth.LidarSpec(width=4, height=1, az0=float(np.float32(-math.pi)), az_step=float(np.float32(math.pi / 2)),
+                          elevations=np.array([el], np.float32), near_range=0.05)
+    az = -math.pi + 2.5 * math.pi / 2
+    D, o = 4.0, 0.5
+    h = D * math.sin(float(el))                                     # closest approach of the ray
+    sigma = h / math.sqrt(2.0 * math.log(o * 255.0 / (1.0 + delta)))
+    scene = scene_from([D * np.array([math.cos(az), math.sin(az), 0.0])], [sigma] * 3, opac=o, degree=0)
+    b = _batch(lid)
+    ref = lidar_ref(scene, b)
+    assert ref.flagged[0, 2] and not ref.flagged[0, 0]
+    rng, hit = lidar_ray_variants(scene, b, 0, 0, 0, 2)
+    assert rng.shape == (2,)
+    taken = (pytest.approx(D * math.cos(float(el)), rel=1e-5), pytest.approx((1.0 + delta) / 255.0, rel=2e-5))
+    skipped = (0.0, 0.0)
+    first, second = (taken, skipped) if delta > 0 else (skipped, taken)
+    assert (rng[0], hit[0]) == first and (rng[1], hit[1]) == second
+    assert rng[0] == ref.range[0, 2] and hit[0] == ref.hit[0, 2]
