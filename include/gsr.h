@@ -174,6 +174,8 @@ typedef struct {
     int64_t n_visible;            /* out */
     int32_t tiles_x, tiles_y;     /* out */
     int64_t tile_base;            /* out: global tile id of the image's first tile */
+    int32_t tile_size;            /* out: tile side the lists were built with (the tuned one) */
+    int32_t reserved0;
 } gsr_bins_out;
 
 /* Per-Gaussian projection of one image (for parity checks).  Host arrays of
@@ -275,11 +277,15 @@ typedef struct {
  * before any device work. */
 int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* desc, void* stream);
 
-/* Binning and projection of image `image` (camera-slot-major index) of
- * `desc`, copied to host arrays (tile lists built with the level-2 schedule
- * tuned for this scene and batch shape).  Synchronous.  Output pointers of
- * `desc` are not used.  GSR_E_INVALID if out->capacity is smaller than the number of
- * pairs (n_pairs is still reported). */
+/* gsr_debug_bins: the sorted (tile, depth) keys, Gaussian ids and tile ranges
+ * of image `image` (camera-slot-major index) of `desc`, as gsr_render builds
+ * them: the same launch parameters (tuned for this scene and batch shape),
+ * memory chunks, captured graphs and two streams, every chunk up to the one
+ * holding the image stopping after its tile lists; the image's lists are read
+ * from that chunk's buffers.  gsr_debug_project: the projection of image
+ * `image` alone (one-image chunk, context defaults).  Both synchronous; output
+ * pointers of `desc` are not used.  GSR_E_INVALID if out->capacity is smaller
+ * than the number of pairs (n_pairs is still reported). */
 int gsr_debug_bins(gsr_ctx* ctx, const gsr_render_desc* desc, int image, gsr_bins_out* out);
 int gsr_debug_project(gsr_ctx* ctx, const gsr_render_desc* desc, int image, gsr_proj_out* out);
 
@@ -351,8 +357,8 @@ int gsr_server_destroy(gsr_server* srv);
  * per raster round, images per projection thread, persistent raster
  * workgroups, images per memory chunk.  They are kept per shape class (scene,
  * env count, camera sizes); gsr_render of a tuned class uses them.  Sort keys
- * and tile lists reported by gsr_debug_bins always use the context's
- * tile_size. */
+ * and tile lists reported by gsr_debug_bins use the tuned tile size (reported in
+ * gsr_bins_out.tile_size). */
 typedef struct {
     int tile_size;          /* 8, 16, 32 */
     int lds_batch;          /* 64/128/256 for 8x8 tiles, 64/128/256/512 otherwise */

@@ -678,7 +678,15 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
         const int n_img = std::min<int>(plan.chunk, (int)job.imgs.size() - i0);
         const int h = chunk_idx & 1;
         uint64_t total = 0;
-        rc = run_chunk(ctx, *wk[h], sc, job, plan, i0, n_img, chunk_idx, sq[h], Mode::kRender, use_graphs, &total);
+        rc = run_chunk(ctx, *wk[h], sc, job, plan, i0, n_img, chunk_idx, sq[h], job.mode, use_graphs, &total);
+        if (!rc && job.stop && job.stop->image >= i0 && job.stop->image < i0 + n_img) {
+            job.stop->ws = wk[h];
+            job.stop->i0 = i0;
+            job.stop->n_img = n_img;
+            job.stop->plan = plan;
+            job.stop->pairs = total;
+            break;
+        }
     }
     if (two) {
         // join the side stream even after a failure, so ws.ev_done covers it
@@ -1158,43 +1166,81 @@ GSR_EXPORT int gsr_debug_bins(gsr_ctx* ctx, const gsr_render_desc* d, int image,
 {
     if (!ctx) return fail(GSR_E_INVALID, "ctx is NULL");
     if (!d || !out) return fail(GSR_E_INVALID, "desc / out is NULL");
-    SceneRes* sc = nullptr;
-    Workspace* ws = nullptr;
-    RenderJob job;
-    ChunkPlan plan{};
-    uint64_t total = 0;
-    int rc = debug_run(ctx, d, image, Mode::kBins, &sc, &ws, &job, &plan, &total);
-    if (!rc) {
+    if (ctx->poisoned) return fail(GSR_E_DEVICE, "context poisoned by an earlier device fault");
+    SceneRes* sc = acquire_scene(ctx, d->scene_id);
+    if (!sc) return fail(GSR_E_NOT_FOUND, "unknown scene id");
+    int rc = validate_desc(ctx, d, sc, false);
+    if (!rc && (image < 0 || image >= d->n_envs * d->n_cams)) rc = fail(GSR_E_INVALID, "image index out of range");
+    if (rc) {
+        release_scene(sc);
+        return rc;
+    }
+    Workspace* ws;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ws = acquire_workspace_locked(ctx, nullptr);
+        ws->in_call = true;
+    }
+    // The render sequence of gsr_render (its tuning, memory chunks, captured
+    // graphs and two streams), every chunk up to the one holding `image`
+    // stopping after its tile lists; the image's lists are then read from
+    // that chunk's buffers.
+    auto body = [&]() -> int {
+        GSR_HIP_TRY(hipSetDevice(ctx->device));
+        RenderJob job;
+        job.tune = tuning_for(ctx, sc, d);
+        job.imgs = images_of(d, job.tune.ts, sc->dev.n_bodies);
+        job.viewmats = d->viewmats;
+        job.poses = d->body_poses;
+        job.viewmat_floats = (size_t)d->n_cams * d->n_envs * 12;
+        job.pose_floats = (size_t)d->n_envs * sc->dev.n_bodies * 7;
+        job.mode = Mode::kBins;
+        DebugStop stop;
+        stop.image = image;
+        job.stop = &stop;
+        int r = render_job(ctx, *ws, sc, job, nullptr, false, true, true);
+        if (r) return r;
+        GSR_HIP_TRY(hipDeviceSynchronize());
+        if (!stop.ws) return fail(GSR_E_DEVICE, "debug stop not reached");
+        Workspace& cw = *stop.ws;
+        const int k = image - stop.i0;
         const ImageInfo& im = job.imgs[image];
         const int T = im.tiles_x * im.tiles_y;
-        uint32_t vis = 0;
-        if (sc->dev.n > 0 && hipMemcpy(&vis, ws->vis_count.p, 4, hipMemcpyDeviceToHost) != hipSuccess)
-            rc = fail(GSR_E_DEVICE, "copy of the visible count failed");
-        out->n_pairs = (int64_t)total;
+        ChunkDev c = chunk_view(cw, sc, stop.plan, stop.i0, stop.n_img, job.imgs);
+        uint32_t vis = 0, npairs = 0;
+        uint64_t pbase = 0;
+        if (sc->dev.n > 0) GSR_HIP_TRY(hipMemcpy(&vis, c.vis_count + k, 4, hipMemcpyDeviceToHost));
+        GSR_HIP_TRY(hipMemcpy(&npairs, c.pair_count + k, 4, hipMemcpyDeviceToHost));
+        GSR_HIP_TRY(hipMemcpy(&pbase, c.pair_base + k, 8, hipMemcpyDeviceToHost));
+        out->n_pairs = npairs;
         out->n_visible = vis;
         out->tiles_x = im.tiles_x;
         out->tiles_y = im.tiles_y;
         out->tile_base = im.key_tile_base;
-        if (!rc && out->ranges) {
-            if (out->ranges_capacity < T) rc = fail(GSR_E_INVALID, "ranges_capacity smaller than the tile count");
-            else if (hipMemcpy(out->ranges, ws->tile_range.p, (size_t)T * 8, hipMemcpyDeviceToHost) != hipSuccess)
-                rc = fail(GSR_E_DEVICE, "copy of tile ranges failed");
+        out->tile_size = job.tune.ts;
+        if (out->ranges) {
+            if (out->ranges_capacity < T) return fail(GSR_E_INVALID, "ranges_capacity smaller than the tile count");
+            GSR_HIP_TRY(hipMemcpy(out->ranges, c.tile_range + (size_t)k * c.t_max * 2, (size_t)T * 8,
+                                  hipMemcpyDeviceToHost));
         }
-        if (!rc && (int64_t)total > out->capacity) rc = fail(GSR_E_INVALID, "capacity smaller than the number of pairs");
-        if (!rc && total > 0) {
-            ChunkDev c = chunk_view(*ws, sc, plan, image, 1, job.imgs);
-            if (ws->debug.ensure(total * 8) != hipSuccess) rc = fail(GSR_E_OOM, "debug key buffer");
-            if (!rc && launch_debug_keys(c, 0, (uint64_t)sc->dev.n, c.pairs, total, ws->debug.as<uint64_t>(),
-                                         nullptr) != hipSuccess)
-                rc = fail(GSR_E_DEVICE, "debug key kernel");
-            if (!rc && hipDeviceSynchronize() != hipSuccess) rc = fail(GSR_E_DEVICE, "debug key kernel failed");
-            if (!rc && out->keys && hipMemcpy(out->keys, ws->debug.p, total * 8, hipMemcpyDeviceToHost) != hipSuccess)
-                rc = fail(GSR_E_DEVICE, "copy of keys failed");
-            if (!rc && out->values && hipMemcpy(out->values, ws->pairs.p, total * 4, hipMemcpyDeviceToHost) != hipSuccess)
-                rc = fail(GSR_E_DEVICE, "copy of values failed");
-        }
+        if ((int64_t)npairs > out->capacity) return fail(GSR_E_INVALID, "capacity smaller than the number of pairs");
+        if (npairs == 0) return GSR_OK;
+        GSR_HIP_TRY(cw.debug.ensure((size_t)npairs * 8));
+        GSR_HIP_TRY(launch_debug_keys(c, k, (uint64_t)sc->dev.n, c.pairs + pbase, npairs, cw.debug.as<uint64_t>(),
+                                      nullptr));
+        GSR_HIP_TRY(hipDeviceSynchronize());
+        if (out->keys) GSR_HIP_TRY(hipMemcpy(out->keys, cw.debug.p, (size_t)npairs * 8, hipMemcpyDeviceToHost));
+        if (out->values)
+            GSR_HIP_TRY(hipMemcpy(out->values, c.pairs + pbase, (size_t)npairs * 4, hipMemcpyDeviceToHost));
+        return GSR_OK;
+    };
+    rc = body();
+    if (rc == GSR_E_DEVICE) ctx->poisoned = true;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ws->in_call = false;
     }
-    debug_finish(ctx, sc, ws);
+    release_scene(sc);
     return rc;
 }
 

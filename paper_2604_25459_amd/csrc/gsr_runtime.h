@@ -101,6 +101,25 @@ struct Workspace {
     ~Workspace();
 };
 
+enum class Mode { kRender, kBins, kProject };
+
+struct ChunkPlan {
+    int chunk;          // images per chunk
+    int t_max;          // max tiles of any image
+    int tx_max, ty_max; // max tile columns / rows of any image
+    int sort_blocks, tile_blocks;
+};
+
+// Debug stop of a render sequence: the job ends after the chunk that holds
+// image `image`, and reports where that chunk's buffers are.
+struct DebugStop {
+    int image = -1;
+    Workspace* ws = nullptr;   // working set of that chunk (the context's or its twin)
+    int i0 = 0, n_img = 0;     // the chunk's first image and image count
+    ChunkPlan plan{};
+    uint64_t pairs = 0;        // the chunk's pair total
+};
+
 // Images of one launch sequence (possibly from several requests), grouped so
 // that images of equal size are contiguous.
 struct RenderJob {
@@ -112,15 +131,8 @@ struct RenderJob {
     Tuning tune;
     bool lidar = false;                // LiDAR ray grids instead of camera images
     int64_t chunk_bytes = 0;           // working-memory budget of one chunk (0: the context's option)
-};
-
-enum class Mode { kRender, kBins, kProject };
-
-struct ChunkPlan {
-    int chunk;          // images per chunk
-    int t_max;          // max tiles of any image
-    int tx_max, ty_max; // max tile columns / rows of any image
-    int sort_blocks, tile_blocks;
+    Mode mode = Mode::kRender;         // kBins: every chunk stops after its tile lists (no raster)
+    DebugStop* stop = nullptr;         // optional debug stop (see DebugStop)
 };
 
 // Validated per-request image list of a render descriptor (camera-slot-major).

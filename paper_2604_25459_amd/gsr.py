@@ -81,7 +81,8 @@ class LidarRenderDesc(C.Structure):
 class BinsOut(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("keys", C.c_void_p), ("values", C.c_void_p), ("ranges", C.c_void_p),
                 ("ranges_capacity", C.c_int64), ("n_pairs", C.c_int64), ("n_visible", C.c_int64),
-                ("tiles_x", C.c_int32), ("tiles_y", C.c_int32), ("tile_base", C.c_int64)]
+                ("tiles_x", C.c_int32), ("tiles_y", C.c_int32), ("tile_base", C.c_int64), ("tile_size", C.c_int32),
+                ("reserved0", C.c_int32)]
 
 
 class ProjOut(C.Structure):
@@ -409,12 +410,14 @@ class Renderer:
 
     # ---------------------------------------------------------- debug
     def debug_bins(self, sid, cams, viewmats, poses, image: int, capacity: int = 1 << 22):
+        """Keys, ids and tile ranges of one image as gsr_render builds them
+        (tuned launch parameters; ``tile_size`` reports the tile side used)."""
         d, carr = self._desc(sid, cams, viewmats, poses, (0, 0, 0))
         for _ in range(2):
             keys = np.empty(capacity, np.uint64)
             vals = np.empty(capacity, np.uint32)
             cam = cams[image // int(viewmats.shape[1])]
-            T = ((cam.width + self.tile_size - 1) // self.tile_size) * ((cam.height + self.tile_size - 1) // self.tile_size)
+            T = ((cam.width + 7) // 8) * ((cam.height + 7) // 8)      # room for the smallest tile size
             ranges = np.empty((T, 2), np.uint32)
             o = BinsOut(capacity=capacity, keys=keys.ctypes.data, values=vals.ctypes.data, ranges=ranges.ctypes.data,
                         ranges_capacity=T)
@@ -424,9 +427,10 @@ class Renderer:
                 continue
             _check(rc)
             n = int(o.n_pairs)
-            return dict(keys=keys[:n].copy(), values=vals[:n].copy(), ranges=ranges.astype(np.int64),
+            nt = int(o.tiles_x) * int(o.tiles_y)
+            return dict(keys=keys[:n].copy(), values=vals[:n].copy(), ranges=ranges[:nt].astype(np.int64),
                         n_visible=int(o.n_visible), tiles_x=int(o.tiles_x), tiles_y=int(o.tiles_y),
-                        tile_base=int(o.tile_base))
+                        tile_base=int(o.tile_base), tile_size=int(o.tile_size))
         raise GsrError(GSR_E_INVALID, "debug_bins capacity retry failed")
 
     def debug_project(self, sid, cams, viewmats, poses, image: int, n: int):

@@ -52,7 +52,7 @@ def test_attached_camera_bins_and_pixels(R):
     for c, e in ((1, 0), (1, 3), (0, 2)):
         image = batch.image_index(c, e)
         got = R.debug_bins(sid, cams, vm, poses, image)
-        ref_b = bin_ref(scene, batch, c, e, R.tile_size)
+        ref_b = bin_ref(scene, batch, c, e, got["tile_size"])
         np.testing.assert_array_equal(got["keys"], ref_b.keys)
         np.testing.assert_array_equal(got["values"], ref_b.values)
         np.testing.assert_array_equal(got["ranges"], ref_b.ranges)

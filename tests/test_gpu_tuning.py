@@ -87,7 +87,8 @@ def test_two_stream_lidar_chunks_match_one_stream():
                                     dict(images_per_thread=8, persistent=1), dict(persistent=1, chunk_images=3),
                                     dict(bin_schedule=0), dict(bin_schedule=1, tile_size=8, lds_batch=128),
                                     dict(lds_batch=256), dict(lds_batch=128, persistent=1),
-                                    dict(tile_size=32, lds_batch=128)])
+                                    dict(tile_size=32, lds_batch=128), dict(images_per_thread=16),
+                                    dict(images_per_thread=16, chunk_images=2, tile_size=8)])
 def test_tuning_changes_no_pixel(params):
     torch = _torch()
     from paper_2604_25459_amd import gsr
@@ -181,7 +182,7 @@ def test_transposed_schedule_on_a_wide_image():
         outs.append(R.render(sid, cams, vm, poses, alpha=True))
         if sched == 1:
             got = R.debug_bins(sid, cams, vm, poses, 1)
-            ref = bin_ref(scene, batch, 0, 1, R.tile_size)
+            ref = bin_ref(scene, batch, 0, 1, got["tile_size"])
             assert ref.ranges.shape[0] == 120 * 68
             np.testing.assert_array_equal(got["keys"], ref.keys)
             np.testing.assert_array_equal(got["values"], ref.values)
