@@ -227,6 +227,32 @@ int gsr_scene_info(gsr_ctx* ctx, uint64_t scene_id, int64_t* n, int* n_bodies, i
 int gsr_render(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
 int gsr_render_plain(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
 
+/* ---- rendering without device allocation ----------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ * gsr_render_noalloc renders like gsr_render (same kernels; every image
+ * bit-identical to gsr_render's with the context's default launch parameters)
+ * but calls no hipMalloc / hipFree and no allocating library routine: all of
+ * its device working memory lies in one fixed scratch array of
+ * GSR_NOALLOC_SCRATCH_BYTES per device, which the library holds on every
+ * device it runs on until the process ends (its address is resolved by
+ * gsr_create).  Images go through it in chunks that fit; the call blocks the
+ * host once per chunk (as gsr_render does) and returns with the last chunk's
+ * rasterisation in flight on `stream`.
+ * Limits and errors: at most GSR_NOALLOC_MAX_IMAGES images per call, and one
+ * image's working memory (about 84 bytes per Gaussian of the scene plus its
+ * tile lists) must fit the scratch -- GSR_E_INVALID before any device work
+ * when a call exceeds them, GSR_E_OVERFLOW when one image's tile lists turn
+ * out larger than the scratch left for them (outputs of earlier images of the
+ * call are then written, later ones are not).
+ * Every call on a device shares that device's scratch, which keeps the last
+ * call's contents (nothing in it is assumed zero).  Calls are serialised: a
+ * call's work on `stream` waits for the previous call's work on any stream,
+ * and host threads take turns. */
+#define GSR_NOALLOC_SCRATCH_BYTES (256ll << 20)
+#define GSR_NOALLOC_MAX_IMAGES 4096
+int gsr_render_noalloc(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
+
 /* ---- batch LiDAR -----------------------------------------------------
  * Ray casting of the same resident Gaussians, posed with the same rigid-body
  * kinematics, for rotating and solid-state LiDARs (the paper's batch LiDAR

@@ -23,7 +23,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["k_project.hip", "k_sort.hip", "k_tiles.hip", "k_raster.hip", "k_lidar.hip", "gsr_api.cpp",
-           "gsr_server.cpp"]
+           "gsr_server.cpp", "gsr_noalloc.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

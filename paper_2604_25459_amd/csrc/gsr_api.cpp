@@ -88,10 +88,12 @@ void Workspace::drop_graphs_of(uint64_t uid)
 
 Workspace::~Workspace()
 {
-    for (DevBuf* b : {&img, &xform, &keyz, &rect, &srect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &vis_count,
+    // a fixed workspace's buffers point into memory it does not own
+    if (!fixed)
+        for (DevBuf* b : {&img, &xform, &keyz, &rect, &srect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &vis_count,
                       &tile_hist, &tile_range, &pair_count, &pair_base, &pairs, &row_hist, &row_range, &row_count,
-                      &row_base, &rows, &debug, &stage_vm, &stage_pose, &stage_elev, &seg_off})
-        b->release();
+                          &row_base, &rows, &debug, &stage_vm, &stage_pose, &stage_elev, &seg_off, &counter})
+            b->release();
     if (h_total) (void)hipHostFree(h_total);
     if (h_img) (void)hipHostFree(h_img);
     if (h_elev) (void)hipHostFree(h_elev);
@@ -99,7 +101,6 @@ Workspace::~Workspace()
     if (ev_done) (void)hipEventDestroy(ev_done);
     for (auto& kv : graphs)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-    counter.release();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     twin.reset();
     if (side) (void)hipStreamDestroy(side);
@@ -159,8 +160,14 @@ int validate_desc(const gsr_ctx* ctx, const gsr_render_desc* d, const SceneRes* 
 
 std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies)
 {
+    std::vector<ImageInfo> v((size_t)d->n_envs * d->n_cams);
+    fill_images(d, ts, n_bodies, v.data());
+    return v;
+}
+
+void fill_images(const gsr_render_desc* d, int ts, int n_bodies, ImageInfo* v)
+{
     const int E = d->n_envs;
-    std::vector<ImageInfo> v((size_t)E * d->n_cams);
     uint64_t tile_base = 0, pixel_base = 0;
     for (int c = 0; c < d->n_cams; ++c) {
         const gsr_camera& cam = d->cams[c];
@@ -207,7 +214,6 @@ std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies)
             pixel_base += (uint64_t)cam.width * cam.height;
         }
     }
-    return v;
 }
 
 namespace {
@@ -260,35 +266,44 @@ ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<
     return p;
 }
 
-hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, size_t n_images_total,
-                            size_t rec_bytes)
+WorkspaceSizes workspace_sizes(const SceneRes* sc, const ChunkPlan& p, size_t n_images_total, size_t rec_bytes)
 {
     const size_t n = (size_t)std::max<int64_t>(sc->dev.n, 1);
     const size_t I = (size_t)p.chunk;
+    WorkspaceSizes z{};
+    int k = 0;
+    auto add = [&](DevBuf Workspace::*b, size_t bytes) { z.b[k++] = {b, bytes}; };
+    add(&Workspace::img, n_images_total * sizeof(ImageInfo));
+    add(&Workspace::xform, I * (sc->dev.n_bodies + 1) * 64);
+    add(&Workspace::keyz, I * n * 4);
+    add(&Workspace::rect, I * n * 8);
+    add(&Workspace::srect, I * n * 8);
+    add(&Workspace::rec, I * n * rec_bytes);
+    add(&Workspace::sk0, I * n * 4);
+    add(&Workspace::sk1, I * n * 4);
+    add(&Workspace::sv0, I * n * 4);
+    add(&Workspace::sv1, I * n * 4);
+    add(&Workspace::sort_hist, I * p.sort_blocks * 256 * 4);
+    add(&Workspace::vis_count, I * 4);
+    add(&Workspace::tile_hist, I * (size_t)(p.tx_max + 1) * (p.ty_max + 1) * 4);
+    add(&Workspace::tile_range, I * (size_t)p.t_max * 8);
+    add(&Workspace::pair_count, I * 4);
+    add(&Workspace::pair_base, (I + 2) * 8);
+    add(&Workspace::row_hist, I * p.tile_blocks * (size_t)p.ty_max * 4);
+    add(&Workspace::row_range, I * (size_t)p.ty_max * 8);
+    add(&Workspace::row_count, I * 4);
+    add(&Workspace::row_base, (I + 1) * 8);
+    z.count = k;
+    return z;
+}
+
+hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, size_t n_images_total,
+                            size_t rec_bytes)
+{
     hipError_t e;
-#define ENS(buf, bytes) \
-    if ((e = ws.buf.ensure(bytes)) != hipSuccess) return e
-    ENS(img, n_images_total * sizeof(ImageInfo));
-    ENS(xform, I * (sc->dev.n_bodies + 1) * 64);
-    ENS(keyz, I * n * 4);
-    ENS(rect, I * n * 8);
-    ENS(srect, I * n * 8);
-    ENS(rec, I * n * rec_bytes);
-    ENS(sk0, I * n * 4);
-    ENS(sk1, I * n * 4);
-    ENS(sv0, I * n * 4);
-    ENS(sv1, I * n * 4);
-    ENS(sort_hist, I * p.sort_blocks * 256 * 4);
-    ENS(vis_count, I * 4);
-    ENS(tile_hist, I * (size_t)(p.tx_max + 1) * (p.ty_max + 1) * 4);
-    ENS(tile_range, I * (size_t)p.t_max * 8);
-    ENS(pair_count, I * 4);
-    ENS(pair_base, (I + 2) * 8);
-    ENS(row_hist, I * p.tile_blocks * (size_t)p.ty_max * 4);
-    ENS(row_range, I * (size_t)p.ty_max * 8);
-    ENS(row_count, I * 4);
-    ENS(row_base, (I + 1) * 8);
-#undef ENS
+    const WorkspaceSizes z = workspace_sizes(sc, p, n_images_total, rec_bytes);
+    for (int k = 0; k < z.count; ++k)
+        if ((e = (ws.*(z.b[k].buf)).ensure(z.b[k].bytes)) != hipSuccess) return e;
     if (!ws.h_total) {
         if ((e = hipHostMalloc((void**)&ws.h_total, 64, hipHostMallocDefault)) != hipSuccess) return e;
     }
@@ -419,6 +434,8 @@ int run_stage(Workspace& ws, bool graph, int chunk_idx, int stage, uint64_t scen
     return GSR_OK;
 }
 
+}  // namespace
+
 // Enqueue the pipeline of images [i0, i0 + n_img) of `job` (image descriptions
 // already on the device).  `pairs_total` receives the chunk's pair count.
 int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, const ChunkPlan& plan, int i0,
@@ -427,7 +444,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     ChunkDev c = chunk_view(ws, sc, plan, i0, n_img, job.imgs);
     const SceneDev& s = sc->dev;
     const Tuning& tu = job.tune;
-    const bool prof = ctx->opt.profile && mode == Mode::kRender;
+    const bool prof = ctx->opt.profile && mode == Mode::kRender && !ws.fixed;
     StageEvents ev;
     // events of a chunk that fails before they are queued for reading go back to the spares
     struct Lease {
@@ -459,7 +476,9 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     // uid and by what selects and feeds its kernels (storage format and SH
     // degree pick the projection's instantiation), the chunk's buffers, sizes
     // and launch parameters
-    std::vector<uint64_t> key = {sc->uid, (uint64_t)s.n, (uint64_t)s.storage, (uint64_t)s.degree,
+    std::vector<uint64_t> key;
+    if (graph)
+        key = {sc->uid, (uint64_t)s.n, (uint64_t)s.storage, (uint64_t)s.degree,
                                  (uint64_t)s.n_bodies, (uint64_t)s.sh_chunks, (uint64_t)(uintptr_t)s.pos,
                                  (uint64_t)(uintptr_t)s.rot, (uint64_t)(uintptr_t)s.scale, (uint64_t)(uintptr_t)s.sh,
                                  (uint64_t)(uintptr_t)s.body_off, (uint64_t)job.lidar,
@@ -469,13 +488,15 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
                                  (uint64_t)tu.persistent, (uint64_t)(uintptr_t)job.viewmats,
                                  (uint64_t)(uintptr_t)job.poses, (uint64_t)(uintptr_t)ws.h_total,
                                  (uint64_t)(ctx->opt.cutoff * 1.0e6f), (uint64_t)tu.bin};
-    for (void* ptr : {(void*)c.xform, (void*)c.keyz, (void*)c.rect, (void*)c.srect, (void*)c.rec, (void*)c.sk[0],
-                      (void*)c.sk[1], (void*)c.sv[0], (void*)c.sv[1], (void*)c.sort_hist, (void*)c.vis_count,
-                      (void*)c.tile_hist, (void*)c.tile_range, (void*)c.pair_count, (void*)c.pair_base,
-                      (void*)c.row_hist, (void*)c.row_range, (void*)c.row_count, (void*)c.row_base})
-        key.push_back((uint64_t)(uintptr_t)ptr);
-    for (int k = 0; k < n_img; ++k)
-        key.push_back(((uint64_t)job.imgs[i0 + k].width << 32) | (uint64_t)job.imgs[i0 + k].height);
+    if (graph) {
+        for (void* ptr : {(void*)c.xform, (void*)c.keyz, (void*)c.rect, (void*)c.srect, (void*)c.rec, (void*)c.sk[0],
+                          (void*)c.sk[1], (void*)c.sv[0], (void*)c.sv[1], (void*)c.sort_hist, (void*)c.vis_count,
+                          (void*)c.tile_hist, (void*)c.tile_range, (void*)c.pair_count, (void*)c.pair_base,
+                          (void*)c.row_hist, (void*)c.row_range, (void*)c.row_count, (void*)c.row_base})
+            key.push_back((uint64_t)(uintptr_t)ptr);
+        for (int k = 0; k < n_img; ++k)
+            key.push_back(((uint64_t)job.imgs[i0 + k].width << 32) | (uint64_t)job.imgs[i0 + k].height);
+    }
 
     int rc = run_stage(ws, graph, chunk_idx, 0, sc->uid, key, st, [&](hipStream_t q) {
         hipError_t e = launch_compose(s, c, job.viewmats, job.poses, q);
@@ -525,23 +546,39 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
                       n_img, (unsigned long long)entries, want, hipGetErrorString(e));
         return fail(e == hipErrorOutOfMemory ? GSR_E_OOM : GSR_E_DEVICE, msg);
     };
-    if ((rc = grow(ws.pairs, total, 4, "tile")) != GSR_OK) return rc;
-    if ((rc = grow(ws.rows, row_total, 8, "tile-row")) != GSR_OK) return rc;
-    c.pairs = ws.pairs.as<uint32_t>();
-    c.rows = ws.rows.as<uint2>();
     // long tile-row lists are split into segments of about kRowSegEntries entries (one wave each)
     const uint64_t n_rows = (uint64_t)n_img * (uint64_t)c.ty_max;
     const uint64_t per_row = n_rows ? row_total / n_rows : 0;
     const int n_seg = (int)std::min<uint64_t>(32, std::max<uint64_t>(1, (per_row + kRowSegEntries - 1) / kRowSegEntries));
-    uint32_t* seg_off = nullptr;
-    if (n_seg > 1) {
-        GSR_HIP_TRY(ws.seg_off.ensure(n_rows * (uint64_t)n_seg * (uint64_t)c.tx_max * 4));
-        seg_off = ws.seg_off.as<uint32_t>();
+    const size_t seg_bytes = n_seg > 1 ? (size_t)(n_rows * (uint64_t)n_seg * (uint64_t)c.tx_max * 4) : 0;
+    if (ws.fixed) {
+        // lists carved from the fixed list region; the caller re-plans on GSR_E_OVERFLOW
+        const size_t bp = ((size_t)total * 4 + 255) & ~(size_t)255, br = ((size_t)row_total * 8 + 255) & ~(size_t)255;
+        if (bp + br + seg_bytes > ws.list_bytes) {
+            char msg[256];
+            std::snprintf(msg, sizeof msg,
+                          "%d-image chunk needs %zu bytes of tile lists (%llu pairs, %llu row entries); %zu available",
+                          n_img, bp + br + seg_bytes, (unsigned long long)total, (unsigned long long)row_total,
+                          ws.list_bytes);
+            return fail(GSR_E_OVERFLOW, msg);
+        }
+        ws.pairs = {ws.list_base, bp};
+        ws.rows = {ws.list_base + bp, br};
+        ws.seg_off = {ws.list_base + bp + br, seg_bytes};
+    } else {
+        if ((rc = grow(ws.pairs, total, 4, "tile")) != GSR_OK) return rc;
+        if ((rc = grow(ws.rows, row_total, 8, "tile-row")) != GSR_OK) return rc;
+        if (n_seg > 1) GSR_HIP_TRY(ws.seg_off.ensure(seg_bytes));
     }
-    key.push_back((uint64_t)(uintptr_t)c.pairs);
-    key.push_back((uint64_t)(uintptr_t)c.rows);
-    key.push_back((uint64_t)n_seg);
-    key.push_back((uint64_t)(uintptr_t)seg_off);
+    c.pairs = ws.pairs.as<uint32_t>();
+    c.rows = ws.rows.as<uint2>();
+    uint32_t* seg_off = n_seg > 1 ? ws.seg_off.as<uint32_t>() : nullptr;
+    if (graph) {
+        key.push_back((uint64_t)(uintptr_t)c.pairs);
+        key.push_back((uint64_t)(uintptr_t)c.rows);
+        key.push_back((uint64_t)n_seg);
+        key.push_back((uint64_t)(uintptr_t)seg_off);
+    }
     rc = run_stage(ws, graph, chunk_idx, 3, sc->uid, key, st,
                    [&](hipStream_t q) { return launch_tile_scatter(s, c, tu.bin, n_seg, seg_off, q); });
     if (rc) return rc;
@@ -556,7 +593,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     for (int k = 0; k < n_img; ++k) rp.count_work |= job.imgs[i0 + k].out_work != nullptr;
     rp.persistent_blocks = ctx->cu_count * (tu.ts == 8 ? 16 : 4);
     if (tu.persistent) {
-        GSR_HIP_TRY(ws.counter.ensure(256));
+        if (!ws.fixed) GSR_HIP_TRY(ws.counter.ensure(256));
         rp.counter = ws.counter.as<uint32_t>();
     }
     uint32_t blocks = 0;
@@ -575,8 +612,10 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
         k = m;
     }
     rp.n_blocks = blocks;
-    key.push_back((uint64_t)(uintptr_t)rp.counter);
-    key.push_back((uint64_t)rp.count_work);
+    if (graph) {
+        key.push_back((uint64_t)(uintptr_t)rp.counter);
+        key.push_back((uint64_t)rp.count_work);
+    }
     if (job.lidar) {
         rc = run_stage(ws, graph, chunk_idx, 4, sc->uid, key, st,
                        [&](hipStream_t q) { return launch_raster_lidar(s, c, rp, q); });
@@ -592,8 +631,6 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     }
     return GSR_OK;
 }
-
-}  // namespace
 
 Workspace* acquire_workspace_locked(gsr_ctx* ctx, hipStream_t stream)
 {
@@ -851,6 +888,11 @@ GSR_EXPORT int gsr_create(int device, const gsr_options* opt, gsr_ctx** out)
     ctx->device = device;
     ctx->opt = o;
     ctx->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    const int rc = noalloc_setup(device);
+    if (rc) {
+        delete ctx;
+        return rc;
+    }
     *out = ctx;
     return GSR_OK;
 }
@@ -944,6 +986,8 @@ GSR_EXPORT int gsr_scene_create(gsr_ctx* ctx, const gsr_scene_desc* d, uint64_t*
     dv.sh = sc->sh.p;
     dv.body_off = sc->body_off.as<int>();
     sc->bytes = (int64_t)(sc->pos.bytes + sc->rot.bytes + sc->scale.bytes + sc->sh.bytes + sc->body_off.bytes);
+    // created here so that marking the scene's use allocates nothing
+    GSR_HIP_TRY(hipEventCreateWithFlags(&sc->last_use, hipEventDisableTiming));
     static std::atomic<uint64_t> next_uid{1};
     sc->uid = next_uid.fetch_add(1);
     std::lock_guard<std::mutex> lk(ctx->mu);

@@ -98,7 +98,23 @@ struct Workspace {
     std::unique_ptr<Workspace> twin;
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // Fixed workspace: every buffer points into memory the workspace does not
+    // own (never grown or freed); the tile lists of a chunk are carved from
+    // [list_base, list_base + list_bytes), and a chunk whose lists do not fit
+    // fails with GSR_E_OVERFLOW before its lists are written.
+    bool fixed = false;
+    char* list_base = nullptr;
+    size_t list_bytes = 0;
     ~Workspace();
+};
+
+// Per-chunk buffers of a workspace and their sizes for a plan.
+struct WorkspaceSizes {
+    struct Item {
+        DevBuf Workspace::*buf;
+        size_t bytes;
+    } b[24];
+    int count;
 };
 
 enum class Mode { kRender, kBins, kProject };
@@ -137,6 +153,8 @@ struct RenderJob {
 
 // Validated per-request image list of a render descriptor (camera-slot-major).
 std::vector<ImageInfo> images_of(const gsr_render_desc* d, int ts, int n_bodies);
+// The same list written into out[E * C].
+void fill_images(const gsr_render_desc* d, int ts, int n_bodies, ImageInfo* out);
 int validate_desc(const gsr_ctx* ctx, const gsr_render_desc* d, const SceneRes* sc, bool need_outputs);
 size_t image_bytes_estimate(const SceneRes* sc, int width, int height, int ts);
 ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<ImageInfo>& imgs, bool plain,
@@ -147,6 +165,18 @@ std::string shape_key(const SceneRes* sc, const gsr_render_desc* d);
 Tuning tuning_for(gsr_ctx* ctx, const SceneRes* sc, const gsr_render_desc* d);
 hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, size_t n_images_total,
                             size_t rec_bytes = 48);
+WorkspaceSizes workspace_sizes(const SceneRes* sc, const ChunkPlan& p, size_t n_images_total, size_t rec_bytes = 48);
+
+// Enqueue the pipeline of images [i0, i0 + n_img) of `job` on `st` (image
+// descriptions already on the device); blocks until the chunk's list totals
+// are known.  `pairs_total` receives the chunk's pair count.
+int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, const ChunkPlan& plan, int i0,
+              int n_img, int chunk_idx, hipStream_t st, Mode mode, bool graph, uint64_t* pairs_total);
+
+// Set-up of the allocation-free render path on `device` (the current device):
+// resolves the device address of its scratch array and allocates its pinned
+// staging, once per device.  Called by gsr_create.
+int noalloc_setup(int device);
 
 // Enqueue the whole job on `st` (blocks once per chunk for its pair count);
 // `graphs` allows replaying captured stage graphs (batched path only);

@@ -116,6 +116,7 @@ SIGNATURES = {
     "gsr_scene_info": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_render": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_render_plain": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_render_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_render_lidar": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_debug_bins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "gsr_debug_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
@@ -323,14 +324,16 @@ class Renderer:
         return out
 
     def render_into(self, sid, cams, viewmats, poses, rgb, depth, alpha=None, bg=(0.0, 0.0, 0.0), plain=False,
-                    stream=None, work=None, obs=None):
+                    stream=None, work=None, obs=None, noalloc=False):
         """viewmats: CUDA float32 [C, E, 3, 4]; poses: CUDA float32 [E, B, 7]; work: optional CUDA int32
         [pixels * 2] receiving (visited list entries, blended Gaussians) per pixel; obs: optional
-        Observation (rgb may then be None)."""
+        Observation (rgb may then be None); noalloc: gsr_render_noalloc (working memory in the
+        library's fixed scratch)."""
         import torch
         d, carr = self._desc(sid, cams, viewmats, poses, bg, rgb, depth, alpha, work, obs)
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
-        fn = load().gsr_render_plain if plain else load().gsr_render
+        lib = load()
+        fn = lib.gsr_render_noalloc if noalloc else lib.gsr_render_plain if plain else lib.gsr_render
         _check(fn(self._h, C.byref(d), C.c_void_p(st)))
         del carr
 
