@@ -75,6 +75,17 @@ struct RasterSeg {
 constexpr int kMaxSegs = 8;
 constexpr int kRect4MaxTiles = 255;
 
+// Streaming store of 16 bytes: non-temporal, for whole cache lines of a
+// stream that is read back only after it has left L2 and the Infinity Cache
+// (the projection's records, written 1 KB per wave instruction).  Scattered
+// or partial-line streams keep ordinary stores, which L2 combines.
+__device__ __forceinline__ void store_stream(float4* p, float4 v)
+{
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    const f32x4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p));
+}
+
 // Tile rectangle [x0, x1) x [y0, y1) of entry k in either format.
 __device__ __forceinline__ void put_rect(void* a, int rect4, size_t k, uint32_t x0, uint32_t x1, uint32_t y0,
                                          uint32_t y1)

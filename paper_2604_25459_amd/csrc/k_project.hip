@@ -16,6 +16,7 @@
 // bucket, with a 1 % margin), so no pixel that could take the Gaussian is
 // left out of its tiles.
 #include "gsr_device.h"
+#include "gsr_wave.h"
 
 namespace gsr {
 namespace {
@@ -134,14 +135,27 @@ __device__ __forceinline__ void sh_rgb(const float* f, float x, float y, float z
 // its Gaussian once and projects it into each image of its group.  Blocks are
 // renumbered so that one XCD runs every image group of a run of Gaussian
 // blocks back to back: the scene is fetched into each L2 about once.
+// The image descriptions and transform rows come in as restrict arguments:
+// nothing the kernel writes aliases them, so uniform reads of them can be
+// scalar loads.  Records leave through LDS: a wave's 64 records (48 bytes
+// each, one per lane) are written to LDS and stored back lane-contiguously,
+// 1 KB per store instruction, instead of each lane storing its own 48 bytes
+// (three times the cache lines per instruction).  Lanes past the last
+// Gaussian stay in the loop (as invisible) so that every store slot of the
+// wave has a lane.
 template <int ST, int DEG>
-__global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts, float cutoff, int ipt)
+__global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, const ImageInfo* __restrict__ imgs,
+                                                 const float* __restrict__ xform, int ts, float cutoff, int ipt)
 {
+    __shared__ float4 stage[4][3 * 64];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
-    const int64_t g = (int64_t)bx * 256 + threadIdx.x;
-    if (g >= s.n) return;
+    const int64_t g_lane = (int64_t)bx * 256 + threadIdx.x;
+    const bool valid = g_lane < s.n;
+    const int64_t g = valid ? g_lane : s.n - 1;       // loads of lanes past the end read the last Gaussian
     const int i_begin = (int)by * ipt;
+    const int lane = __lane_id();
+    float4* const st = stage[threadIdx.x >> 6];
 
     int slot = 0;
     if (s.n_bodies > 0 && g >= s.body_off[0]) {
@@ -200,11 +214,11 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
     // opacity bucket with 1 % to spare for the rounding of the extents.
     const float qmax = opacity_qmax(op);
 
-    for (int ii = 0; ii < ipt; ++ii) {
-        const int i = i_begin + ii;
-        if (i >= c.n_img) break;
-        const ImageInfo im = c.img[i];
-        const float* X = c.xform + ((size_t)i * (s.n_bodies + 1) + slot) * 16;
+    // one image: X is the image's transform row for the Gaussian's body slot
+    auto project_into = [&](int i_any, int sl) {
+        const int i = __builtin_amdgcn_readfirstlane(i_any);      // the same in every lane
+        const ImageInfo im = imgs[i];
+        const float* X = xform + ((size_t)i * (s.n_bodies + 1) + sl) * 16;
         float A[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) A[k] = X[k];
@@ -258,42 +272,63 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, int ts,
         const float y0 = fminf(fmaxf(floorf((v - ry) * inv_ts), 0.0f), (float)im.tiles_y);
         const float y1 = fminf(fmaxf(floorf((v + ry) * inv_ts) + 1.0f, 0.0f), (float)im.tiles_y);
 
-        bool vis = isfinite(tx) && isfinite(ty) && isfinite(tz) && tz > im.near_plane && op >= alpha_min &&
+        bool vis = valid && isfinite(tx) && isfinite(ty) && isfinite(tz) && tz > im.near_plane && op >= alpha_min &&
                    isfinite(det) && det > 0.0f && isfinite(r) && isfinite(u) && isfinite(v);
         const int ix0 = vis ? (int)x0 : 0, ix1 = vis ? (int)x1 : 0;
         const int iy0 = vis ? (int)y0 : 0, iy1 = vis ? (int)y1 : 0;
         vis = vis && ix1 > ix0 && iy1 > iy0;
 
-        const size_t o = (size_t)i * (size_t)s.n + (size_t)g;
-        c.keyz[o] = vis ? __float_as_uint(tz) : kInvalidKey;
-        if (!vis) continue;
-        put_rect(c.rect, c.rect4, o, (uint32_t)ix0, (uint32_t)ix1, (uint32_t)iy0, (uint32_t)iy1);
+        const size_t o = (size_t)i * (size_t)s.n + (size_t)g_lane;
+        if (valid) c.keyz[o] = vis ? __float_as_uint(tz) : kInvalidKey;
+        const uint64_t vmask = __ballot(vis);
+        if (vmask == 0ull) return;              // wave-uniform
+        if (vis) {
+            put_rect(c.rect, c.rect4, o, (uint32_t)ix0, (uint32_t)ix1, (uint32_t)iy0, (uint32_t)iy1);
 
-        // Raster record: the quadratic form of the conic in whitened form,
-        //     log2(alpha) = log2(o) - (a1 dx + b1 dy)^2 - (c1 dy)^2,
-        // i.e. 0.5 log2(e) [dx dy] Sigma^-1 [dx dy]^T factored as W^T W with
-        // W = [[a1, b1], [0, c1]] (Sigma = [[ca, cb], [cb, cc]], det = ca cc - cb^2):
-        //     a1 = sqrt(k cc / det), b1 = -k cb / (det a1), c1 = sqrt(k / cc),
-        // k = 0.5 log2(e).  A sum of squares stays accurate where the expanded
-        // quadratic cancels (long, thin splats far from their centre).
-        // Continuous quantities only (no binning decision depends on them):
-        // hardware reciprocals and square roots.
-        constexpr float kHalfLog2e = 0.72134752044448170f;
-        constexpr float kSqrtHalfLog2e = 0.84932180028801907f;
-        const float idet = __builtin_amdgcn_rcpf(det);
-        const float wa = __builtin_amdgcn_sqrtf(kHalfLog2e * cc * idet);
-        const float wb = -(kHalfLog2e * cb * idet) * __builtin_amdgcn_rcpf(wa);
-        const float wc = kSqrtHalfLog2e * __builtin_amdgcn_rsqf(cc);
-        float rgb[3];
-        {
-            float dx = mu[0] - X[12], dy = mu[1] - X[13], dz = mu[2] - X[14];
-            const float inv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
-            sh_rgb<DEG>(f, dx * inv, dy * inv, dz * inv, rgb);
+            // Raster record: the quadratic form of the conic in whitened form,
+            //     log2(alpha) = log2(o) - (a1 dx + b1 dy)^2 - (c1 dy)^2,
+            // i.e. 0.5 log2(e) [dx dy] Sigma^-1 [dx dy]^T factored as W^T W with
+            // W = [[a1, b1], [0, c1]] (Sigma = [[ca, cb], [cb, cc]], det = ca cc - cb^2):
+            //     a1 = sqrt(k cc / det), b1 = -k cb / (det a1), c1 = sqrt(k / cc),
+            // k = 0.5 log2(e).  A sum of squares stays accurate where the expanded
+            // quadratic cancels (long, thin splats far from their centre).
+            // Continuous quantities only (no binning decision depends on them):
+            // hardware reciprocals and square roots.
+            constexpr float kHalfLog2e = 0.72134752044448170f;
+            constexpr float kSqrtHalfLog2e = 0.84932180028801907f;
+            const float idet = __builtin_amdgcn_rcpf(det);
+            const float wa = __builtin_amdgcn_sqrtf(kHalfLog2e * cc * idet);
+            const float wb = -(kHalfLog2e * cb * idet) * __builtin_amdgcn_rcpf(wa);
+            const float wc = kSqrtHalfLog2e * __builtin_amdgcn_rsqf(cc);
+            float rgb[3];
+            {
+                float dx = mu[0] - X[12], dy = mu[1] - X[13], dz = mu[2] - X[14];
+                const float inv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+                sh_rgb<DEG>(f, dx * inv, dy * inv, dz * inv, rgb);
+            }
+            st[3 * lane] = make_float4(u, v, wa, wb);
+            st[3 * lane + 1] = make_float4(wc, log2o, tz, r);
+            st[3 * lane + 2] = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
         }
-        float4* rec = c.rec + 3 * o;
-        rec[0] = make_float4(u, v, wa, wb);
-        rec[1] = make_float4(wc, log2o, tz, r);
-        rec[2] = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+        wave_lds_sync();
+        // float4 q of the wave's records belongs to lane q / 3
+        float4* rec = c.rec + 3 * (o - (size_t)lane);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int q = lane + 64 * k;
+            if ((vmask >> (q / 3)) & 1ull) store_stream(rec + q, st[q]);
+        }
+        wave_lds_sync();
+    };
+    const int i_end = min(i_begin + ipt, c.n_img);
+    // Waves whose Gaussians all ride on one body (nearly all: bodies are
+    // contiguous runs of storage order) read the transform rows through a
+    // wave-uniform address, i.e. scalar loads into scalar registers.
+    const int slot0 = __builtin_amdgcn_readfirstlane(slot);
+    if (__ballot(slot != slot0) == 0ull) {
+        for (int i = i_begin; i < i_end; ++i) project_into(i, slot0);
+    } else {
+        for (int i = i_begin; i < i_end; ++i) project_into(i, slot);
     }
 }
 
@@ -356,10 +391,10 @@ static hipError_t project_st(const SceneDev& s, const ChunkDev& c, int ts, float
 {
     const dim3 grid((unsigned)((s.n + 255) / 256), (unsigned)((c.n_img + ipt - 1) / ipt));
     switch (s.degree) {
-    case 0: hipLaunchKernelGGL((k_project<ST, 0>), grid, dim3(256), 0, st, s, c, ts, cutoff, ipt); break;
-    case 1: hipLaunchKernelGGL((k_project<ST, 1>), grid, dim3(256), 0, st, s, c, ts, cutoff, ipt); break;
-    case 2: hipLaunchKernelGGL((k_project<ST, 2>), grid, dim3(256), 0, st, s, c, ts, cutoff, ipt); break;
-    default: hipLaunchKernelGGL((k_project<ST, 3>), grid, dim3(256), 0, st, s, c, ts, cutoff, ipt); break;
+    case 0: hipLaunchKernelGGL((k_project<ST, 0>), grid, dim3(256), 0, st, s, c, c.img, c.xform, ts, cutoff, ipt); break;
+    case 1: hipLaunchKernelGGL((k_project<ST, 1>), grid, dim3(256), 0, st, s, c, c.img, c.xform, ts, cutoff, ipt); break;
+    case 2: hipLaunchKernelGGL((k_project<ST, 2>), grid, dim3(256), 0, st, s, c, c.img, c.xform, ts, cutoff, ipt); break;
+    default: hipLaunchKernelGGL((k_project<ST, 3>), grid, dim3(256), 0, st, s, c, c.img, c.xform, ts, cutoff, ipt); break;
     }
     return hipGetLastError();
 }
