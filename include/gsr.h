@@ -196,6 +196,14 @@ typedef struct {
 int gsr_create(int device, const gsr_options* opt, gsr_ctx** out);
 int gsr_destroy(gsr_ctx* ctx);
 
+/* gsr_trim: releases the device and pinned host memory of the context's
+ * working sets that no call is using (buffers sized by earlier renders,
+ * captured graphs, second-stream working sets), after their last work has
+ * finished; scenes and tuning stay.  The next render allocates what it needs
+ * again.  `freed_bytes` (may be NULL) receives the change of the device's
+ * free memory over the call. */
+int gsr_trim(gsr_ctx* ctx, int64_t* freed_bytes);
+
 /* ---- scenes ----------------------------------------------------------
  * gsr_scene_create copies the caller's arrays into device memory in the
  * requested storage format and returns an id; the caller may free its arrays

@@ -442,6 +442,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
               int n_img, int chunk_idx, hipStream_t st, Mode mode, bool graph, uint64_t* pairs_total)
 {
     ChunkDev c = chunk_view(ws, sc, plan, i0, n_img, job.imgs);
+    c.err = ctx->d_err;
     const SceneDev& s = sc->dev;
     const Tuning& tu = job.tune;
     const bool prof = ctx->opt.profile && mode == Mode::kRender && !ws.fixed;
@@ -519,12 +520,23 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
             e = hipMemcpyAsync(ws.h_total + 1, c.row_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, q);
         if (e == hipSuccess)
             e = hipMemcpyAsync(ws.h_total + 2, c.pair_base + n_img + 1, sizeof(uint64_t), hipMemcpyDeviceToHost, q);
+        if (e == hipSuccess) e = hipMemcpyAsync(ws.h_total + 3, c.err, sizeof(uint32_t), hipMemcpyDeviceToHost, q);
         return e;
     });
     if (rc) return rc;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[3], st));
     GSR_HIP_TRY(hipEventRecord(ws.ev_total, st));
     GSR_HIP_TRY(hipEventSynchronize(ws.ev_total));
+    // kernels of this or an earlier chunk met an entry their inputs cannot hold
+    const uint32_t err = reinterpret_cast<const uint32_t*>(ws.h_total + 3)[0];
+    if (err) {
+        ctx->poisoned = true;
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "device consistency check failed (error bits 0x%x: %s)", err,
+                      err & kErrListEntry ? "tile list entry out of range"
+                      : err & kErrSortSlot ? "depth-sort offset out of range" : "tile-row entry out of range");
+        return fail(GSR_E_DEVICE, msg);
+    }
     const uint64_t total = ws.h_total[0];
     const uint64_t row_total = ws.h_total[1];
     *pairs_total = total;
@@ -888,8 +900,15 @@ GSR_EXPORT int gsr_create(int device, const gsr_options* opt, gsr_ctx** out)
     ctx->device = device;
     ctx->opt = o;
     ctx->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    const int rc = noalloc_setup(device);
+    int rc = noalloc_setup(device);
+    if (!rc) {
+        // consistency bits the kernels raise (zero until something impossible happens)
+        hipError_t e = hipMalloc((void**)&ctx->d_err, 256);
+        if (e == hipSuccess) e = hipMemset(ctx->d_err, 0, 256);
+        if (e != hipSuccess) rc = hip_fail(e, "context error word");
+    }
     if (rc) {
+        if (ctx->d_err) (void)hipFree(ctx->d_err);
         delete ctx;
         return rc;
     }
@@ -911,8 +930,31 @@ GSR_EXPORT int gsr_destroy(gsr_ctx* ctx)
         ctx->spare_events.clear();
         ctx->pool.clear();
         ctx->scenes.clear();
+        if (ctx->d_err) (void)hipFree(ctx->d_err);
     }
     delete ctx;
+    return GSR_OK;
+}
+
+GSR_EXPORT int gsr_trim(gsr_ctx* ctx, int64_t* freed_bytes)
+{
+    if (!ctx) return fail(GSR_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    GSR_HIP_TRY(hipSetDevice(ctx->device));
+    size_t before = 0, after = 0, total = 0;
+    GSR_HIP_TRY(hipMemGetInfo(&before, &total));
+    for (auto it = ctx->pool.begin(); it != ctx->pool.end();) {
+        Workspace* w = it->get();
+        if (w->in_call) {
+            ++it;
+            continue;
+        }
+        // its last render (and its twin's, joined into the same stream) must have finished
+        if (w->used) GSR_HIP_TRY(hipEventSynchronize(w->ev_done));
+        it = ctx->pool.erase(it);
+    }
+    GSR_HIP_TRY(hipMemGetInfo(&after, &total));
+    if (freed_bytes) *freed_bytes = (int64_t)after - (int64_t)before;
     return GSR_OK;
 }
 

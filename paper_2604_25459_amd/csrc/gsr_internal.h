@@ -147,7 +147,14 @@ struct ChunkDev {
     uint32_t* row_count;       // [n_img] R_i (entries of all row lists)
     uint64_t* row_base;        // [n_img + 1] exclusive prefix of R_i
     uint2* rows;               // [total row entries] (Gaussian id, x0 | x1 << 16) per (row, depth)-sorted entry
+    uint32_t* err;             // device word of the context: kErr* bits set by a kernel that meets an entry its
+                               // inputs cannot contain (checked by the host at every chunk; poisons the context)
 };
+
+// Bits of ChunkDev::err.
+constexpr uint32_t kErrListEntry = 1u;    // a tile list held a Gaussian id >= n
+constexpr uint32_t kErrSortSlot = 2u;     // a depth-sort rank or offset fell outside its segment
+constexpr uint32_t kErrRowEntry = 4u;     // a depth-ordered id >= n reached the tile-row expansion
 
 // Depth sort geometry.
 constexpr int kSortBlock = 256;

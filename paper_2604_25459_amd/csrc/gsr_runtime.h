@@ -78,7 +78,8 @@ struct Workspace {
     DevBuf img, xform, keyz, rect, srect, rec, sk0, sk1, sv0, sv1, sort_hist, vis_count, tile_hist, tile_range,
         pair_count, pair_base, pairs, row_hist, row_range, row_count, row_base, rows, debug, stage_vm, stage_pose,
         stage_elev, seg_off;
-    uint64_t* h_total = nullptr;   // pinned: [0] pairs, [1] row entries, [2] visible Gaussians of the current chunk
+    uint64_t* h_total = nullptr;   // pinned: [0] pairs, [1] row entries, [2] visible Gaussians of the current chunk,
+                                   // [3] low word: the context's device consistency bits
     ImageInfo* h_img = nullptr;    // pinned staging for image descriptions
     size_t h_img_cap = 0;
     float* h_elev = nullptr;       // pinned staging for LiDAR beam elevations
@@ -208,6 +209,7 @@ struct gsr_ctx {
     double raster_launches = 0, renders = 0;
     double count_visible = 0, count_pairs = 0, count_rows = 0;   // profiled renders
     std::atomic<bool> poisoned{false};
+    uint32_t* d_err = nullptr;                        // device consistency bits (ChunkDev::err), read at every chunk
     std::map<std::string, gsr::Tuning> tuned;         // shape class -> launch parameters
     int cu_count = 256;
 };

@@ -245,7 +245,10 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
         const uint32_t e = b0 + (uint32_t)tid;
         if (e < end) {
             uint32_t g = list[e];
-            if (g >= n) g = 0;          // guard: list entries are valid indices by construction
+            if (g >= n) {               // impossible by construction: report it, read a valid record
+                atomicOr(c.err, kErrListEntry);
+                g = 0;
+            }
 #pragma unroll
             for (int k = 0; k < kLidarRec; ++k) sr[k][tid] = rec[kLidarRec * (size_t)g + k];
         }

@@ -198,6 +198,7 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
 
     // register staging of the next batch
     float4 ra[PER_THREAD], rb[PER_THREAD], rc[PER_THREAD];
+    bool bad_entry = false;
     auto fetch = [&](uint32_t b0) {
 #pragma unroll
         for (int q = 0; q < PER_THREAD; ++q) {
@@ -205,7 +206,10 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             const uint32_t e = b0 + slot;
             if (slot < (uint32_t)kBatch && e < end) {
                 uint32_t g = list[e];
-                if (g >= n) g = 0;      // guard: list entries are valid indices by construction
+                if (g >= n) {           // impossible by construction: reported at the end, a valid record read
+                    bad_entry = true;
+                    g = 0;
+                }
                 ra[q] = rec[3 * (size_t)g];
                 rb[q] = rec[3 * (size_t)g + 1];
                 rc[q] = rec[3 * (size_t)g + 2];
@@ -359,6 +363,8 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         if (lane == 0) L_.live[buf][w] = wave_live ? 1u : 0u;
         buf ^= 1;
     }
+
+    if (bad_entry) atomicOr(c.err, kErrListEntry);
 
     // observation epilogue parameters of this image (identity when absent)
     float gain = 1.0f, contrast = 1.0f, bright = 0.0f;

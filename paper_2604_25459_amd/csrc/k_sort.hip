@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ counts, uint64_t n, int shift,
                                                       const uint32_t* __restrict__ hist, int blocks,
                                                       const uint2* __restrict__ rect, uint2* __restrict__ srect,
-                                                      int rect4)
+                                                      int rect4, uint32_t* __restrict__ err)
 {
     __shared__ uint32_t cnt[4][256];
     __shared__ uint32_t lstart[256], gbase[256], lds8[8];
@@ -173,9 +173,11 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
             const uint32_t basev = cnt[w][dg];
             const uint32_t lpos = basev + (uint32_t)__popcll(peers & lt);
             if (lane == __ffsll((unsigned long long)peers) - 1) cnt[w][dg] = basev + (uint32_t)__popcll(peers);
-            if (lpos < (uint32_t)kSortItems) {     // guard: lpos < n_items <= kSortItems by construction
+            if (lpos < (uint32_t)kSortItems) {     // lpos < n_items <= kSortItems by construction
                 skey[lpos] = key[k];
                 sval[lpos] = val[k];
+            } else {
+                atomicOr(err, kErrSortSlot);
             }
         }
     }
@@ -186,7 +188,8 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
         const uint32_t k = skey[t], v = sval[t];
         const uint32_t dg = (k >> shift) & 255u;
         const uint32_t pos = gbase[dg] + (t - lstart[dg]);
-        if (pos < n) {      // guard: offsets are consistent by construction
+        if (pos >= n) atomicOr(err, kErrSortSlot);     // offsets are consistent by construction
+        if (pos < n) {
             if (!LAST) kout[seg + pos] = k;     // the final keys are not read again
             vout[seg + pos] = v;
             if (LAST && v < n) {
@@ -210,7 +213,8 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
     hipLaunchKernelGGL(k_sort_scan<true>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
                        c.vis_count, n);
     hipLaunchKernelGGL((k_sort_scatter<true, false>), grid, dim3(256), 0, stream, c.keyz, (const uint32_t*)nullptr,
-                       c.sk[0], c.sv[0], c.vis_count, n, 0, c.sort_hist, c.sort_blocks, c.rect, c.srect, c.rect4);
+                       c.sk[0], c.sv[0], c.vis_count, n, 0, c.sort_hist, c.sort_blocks, c.rect, c.srect, c.rect4,
+                       c.err);
     int src = 0;
     for (int pass = 1; pass < 4; ++pass) {
         const int shift = 8 * pass;
@@ -221,11 +225,11 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
         if (pass == 3)
             hipLaunchKernelGGL((k_sort_scatter<false, true>), grid, dim3(256), 0, stream, c.sk[src], c.sv[src],
                                c.sk[src ^ 1], c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks, c.rect,
-                               c.srect, c.rect4);
+                               c.srect, c.rect4, c.err);
         else
             hipLaunchKernelGGL((k_sort_scatter<false, false>), grid, dim3(256), 0, stream, c.sk[src], c.sv[src],
                                c.sk[src ^ 1], c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks,
-                               c.rect, c.srect, c.rect4);
+                               c.rect, c.srect, c.rect4, c.err);
         src ^= 1;
     }
     // pass 0 wrote buffer 0; passes 1..3 alternate, so the sorted values are in sv[1] (the last

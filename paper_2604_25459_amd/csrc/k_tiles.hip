@@ -413,8 +413,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c,
             const uint2 r = rc[w];
             uint32_t x0, x1, y0, y1;
             decode_rect(r, c.rect4, &x0, &x1, &y0, &y1);
-            // guard: sorted ids are valid indices by construction
-            const bool okg = jw + (uint32_t)lane < j1 && g < n && x1 > x0 && y1 > y0;
+            const bool inside = jw + (uint32_t)lane < j1;
+            if (inside && g >= n) atomicOr(c.err, kErrRowEntry);   // impossible by construction: report it
+            const bool okg = inside && g < n && x1 > x0 && y1 > y0;
             expand_group(ex, occ, cursor, okg ? y1 - y0 : 0u, y0, g, x0 | (x1 << 16), TY,
                          [&](uint32_t pos, uint32_t v0, uint32_t v1) {
                              if (pos < Rn) out[pos] = make_uint2(v0, v1);

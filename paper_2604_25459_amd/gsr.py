@@ -111,6 +111,7 @@ class Stats(C.Structure):
 SIGNATURES = {
     "gsr_create": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p]),
     "gsr_destroy": (C.c_int, [C.c_void_p]),
+    "gsr_trim": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gsr_scene_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsr_scene_destroy": (C.c_int, [C.c_void_p, C.c_uint64]),
     "gsr_scene_info": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -236,6 +237,12 @@ class Renderer:
             pass
 
     STAGES = ("project", "depth_sort", "tile_count", "tile_scatter", "raster")
+
+    def trim(self) -> int:
+        """Release idle working memory (gsr_trim); returns the bytes freed on the device."""
+        freed = C.c_int64(0)
+        _check(load().gsr_trim(self._h, C.byref(freed)))
+        return int(freed.value)
 
     def stage_times(self, reset: bool = True):
         """Device ms per stage accumulated since the last reset (profile=True)."""

@@ -47,6 +47,7 @@ def test_null_arguments_rejected():
     assert lib.gsr_scene_destroy(None, 1) == gsr.GSR_E_INVALID
     assert lib.gsr_render_plain(None, None, None) == gsr.GSR_E_INVALID
     assert lib.gsr_render_noalloc(None, None, None) == gsr.GSR_E_INVALID
+    assert lib.gsr_trim(None, None) == gsr.GSR_E_INVALID
     assert lib.gsr_debug_bins(None, None, 0, None) == gsr.GSR_E_INVALID
     assert lib.gsr_debug_project(None, None, 0, None) == gsr.GSR_E_INVALID
     assert lib.gsr_scene_info(None, 1, None, None, None) == gsr.GSR_E_INVALID

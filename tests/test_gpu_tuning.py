@@ -61,6 +61,30 @@ def test_two_stream_chunks_match_one_stream():
     R2.close()
 
 
+def test_trim_releases_working_memory_and_changes_no_pixel():
+    """gsr_trim frees the idle working sets (two-stream chunks hold two); the
+    next render allocates again and gives the same bits."""
+    torch = _torch()
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(3, n_envs=8)
+    R = gsr.Renderer(0)
+    sid = R.add_synth_scene(scene)
+    cams, vm, poses = gsr.batch_tensors(batch)
+    R.set_tuning(sid, cams, vm, poses, chunk_images=3)
+    ref = [[t.clone() for t in slot] for slot in R.render(sid, cams, vm, poses, alpha=True)]
+    torch.cuda.synchronize()
+    freed = R.trim()
+    print("trim freed", freed, flush=True)
+    assert freed > 100 << 20                 # the working sets of a 596k-Gaussian scene
+    assert R.trim() <= 4 << 20               # nothing left to free
+    got = R.render(sid, cams, vm, poses, alpha=True)
+    torch.cuda.synchronize()
+    for slot_ref, slot_got in zip(ref, got):
+        for a, b in zip(slot_ref, slot_got):
+            assert torch.equal(a, b)
+    R.close()
+
+
 def test_two_stream_lidar_chunks_match_one_stream():
     torch = _torch()
     from paper_2604_25459_amd import gsr
