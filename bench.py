@@ -715,6 +715,24 @@ def main():
              "stages_ms_per_step": {k: v / args.lidar_steps for k, v in lst.items() if k in R.STAGES},
              "hit_fraction": float((l_hit > 0.5).float().mean())}
         log(f"[bench] LiDAR {r['value']:.1f} env-scans/s ({r['rays_per_s'] / 1e9:.2f} G rays/s)")
+        # heightmap scanner: a 64 x 64 grid of downward rays at 5 cm under each sensor
+        hm = synth.height_grid(64, 64, 0.05)
+        n_hm = E * hm.width * hm.height
+        h_range = torch.empty(n_hm, dtype=torch.float32, device=dev)
+        h_hit = torch.empty(n_hm, dtype=torch.float32, device=dev)
+        R.render_lidar_into(sid, [hm], lvm, poses[args.warmup], h_range, h_hit)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.lidar_steps):
+            R.render_lidar_into(sid, [hm], lvm, poses[args.warmup + s % args.steps], h_range, h_hit)
+        torch.cuda.synchronize()
+        hsec = time.perf_counter() - t0
+        R.stage_times(reset=True)
+        r["heightmap"] = {"value": E * args.lidar_steps / hsec, "unit": "env-scans/s",
+                          "sensor": "heightmap grid, 64 x 64 downward rays at 0.05 m", "envs": E,
+                          "ms_per_step": 1000.0 * hsec / args.lidar_steps,
+                          "hit_fraction": float((h_hit > 0.5).float().mean())}
+        log(f"[bench] heightmap {r['heightmap']['value']:.1f} env-scans/s")
         return r
 
     if args.lidar_steps:

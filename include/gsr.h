@@ -285,13 +285,28 @@ int gsr_render_noalloc(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
  *     hit   = 1 - T  (the return probability).
  * Rays are binned into TS x TS tiles of the grid by conservative angular
  * bounds of each Gaussian's alpha >= 1/255 ellipsoid, so the result equals
- * casting every ray against every Gaussian. */
+ * casting every ray against every Gaussian.
+ *
+ * Heightmap scanner (pattern GSR_LIDAR_GRID; the paper's heightmap sensing
+ * for locomotion, Table "tab:lidar"): an H x W grid of parallel rays cast
+ * along -z of the sensor frame from its z = 0 plane, ray (r, c) starting at
+ * (x0 + (c + 0.5) dx, y0 + (r + 0.5) dy, 0); t* and alpha as above with the
+ * ray x(t) = origin + t (0, 0, -1), composited in the order of the
+ * Gaussians' depths below the plane (max(0, -z) of the centre in binary32,
+ * ties by index), so range = the expected depth of the surface below the
+ * sensor plane (its height there is -range) and hit = 1 - T.  Rays are
+ * binned by the sensor-plane footprint of each Gaussian's alpha >= 1/255
+ * ellipsoid (a disc, widened by a relative 1e-4 against rounding). */
+#define GSR_LIDAR_ANGULAR 0   /* rays from the sensor origin: beam elevations x azimuth columns */
+#define GSR_LIDAR_GRID 1      /* heightmap: parallel rays along -z from a grid on the sensor's z = 0 plane */
 typedef struct {
-    int width, height;            /* W columns, H beams; 1..8192 each */
-    float az0, az_step;           /* radians; az_step > 0, W az_step <= 2 pi */
-    const float* elevations;      /* host [H], radians, strictly ascending, within (-pi/2, pi/2) */
+    int width, height;            /* W columns, H beams (grid: W along x, H along y); 1..8192 each */
+    float az0, az_step;           /* ANGULAR: radians; az_step > 0, W az_step <= 2 pi */
+    const float* elevations;      /* ANGULAR: host [H], radians, strictly ascending, within (-pi/2, pi/2) */
     float near_range;             /* returns at t* <= near_range are ignored; > 0 */
     int attach_body;              /* -1: viewmats are world -> sensor; b: body-b -> sensor (as for cameras) */
+    int pattern;                  /* GSR_LIDAR_ANGULAR (0) or GSR_LIDAR_GRID */
+    float x0, y0, dx, dy;         /* GRID: metres in the sensor frame; dx, dy > 0 */
 } gsr_lidar;
 
 typedef struct {

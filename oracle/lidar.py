@@ -16,6 +16,12 @@ formulas; the reading used here (also in the design notes):
   rules: skip alpha < 1/255, stop before adding when T (1 - alpha) < 1e-4;
   range = sum t* alpha T / (1 - T) (0 where nothing was added), hit = 1 - T.
 
+* a heightmap scanner (pattern 1) is a grid of parallel rays x(t) = o + t d
+  with d = (0, 0, -1) from the points o = (x0 + (c + 0.5) dx, y0 + (r + 0.5)
+  dy, 0) of the sensor plane; the same peak response along each ray, and the
+  compositing order is the depth of the centre below that plane, max(0, -z)
+  in binary32 (ties by index).
+
 ``lidar_ref`` is that definition written out per ray in float64 against
 every Gaussian (no binning), posing with the rigid-body kinematics of the
 camera path.  Only the compositing order is taken from binary32 (the centre
@@ -44,8 +50,24 @@ class LidarRef:
     order: np.ndarray       # composited Gaussians in order (indices)
 
 
+def is_grid(lid) -> bool:
+    return int(getattr(lid, "pattern", 0)) == 1
+
+
+def ray_origins(lid) -> np.ndarray:
+    """(H, W, 3) float64 ray origins: the sensor origin, or (heightmap) the
+    grid points of the sensor plane."""
+    o = np.zeros((lid.height, lid.width, 3))
+    if is_grid(lid):
+        o[..., 0] = float(np.float32(lid.x0)) + (np.arange(lid.width)[None, :] + 0.5) * float(np.float32(lid.dx))
+        o[..., 1] = float(np.float32(lid.y0)) + (np.arange(lid.height)[:, None] + 0.5) * float(np.float32(lid.dy))
+    return o
+
+
 def ray_directions(lid) -> np.ndarray:
     """(H, W, 3) float64 unit directions of a LiDAR grid."""
+    if is_grid(lid):
+        return np.broadcast_to(np.array([0.0, 0.0, -1.0]), (lid.height, lid.width, 3)).copy()
     az = float(np.float32(lid.az0)) + (np.arange(lid.width) + 0.5) * float(np.float32(lid.az_step))
     el = np.asarray(lid.elevations, np.float32).astype(np.float64)
     ce, se = np.cos(el)[:, None], np.sin(el)[:, None]
@@ -54,7 +76,8 @@ def ray_directions(lid) -> np.ndarray:
 
 
 def centre_order(scene, batch, l: int, e: int, attrs=None) -> np.ndarray:
-    """Gaussians in compositing order: binary32 centre distance, then index."""
+    """Gaussians in compositing order: binary32 centre distance (heightmap:
+    depth below the sensor plane, max(0, -z)), then index."""
     at = attrs or {}
     means = np.asarray(at.get("means", scene.means), F)
     opac = np.asarray(at.get("opacities", scene.opacities), F)
@@ -62,8 +85,13 @@ def centre_order(scene, batch, l: int, e: int, attrs=None) -> np.ndarray:
     slot = scene.body_of() + 1
     with np.errstate(all="ignore"):
         t = affine32(As[slot], means, as_[slot])
-        D = np.sqrt((t[:, 0] * t[:, 0] + t[:, 1] * t[:, 1]) + t[:, 2] * t[:, 2])
-    ok = np.isfinite(D) & (D > F(0)) & (opac >= F(1.0) / F(255.0))
+        if is_grid(batch.cams[l]):
+            depth = -t[:, 2]
+            D = np.where(depth > F(0), depth, F(0)).astype(F)
+            ok = np.isfinite(t).all(axis=1) & (opac >= F(1.0) / F(255.0))
+        else:
+            D = np.sqrt((t[:, 0] * t[:, 0] + t[:, 1] * t[:, 1]) + t[:, 2] * t[:, 2])
+            ok = np.isfinite(D) & (D > F(0)) & (opac >= F(1.0) / F(255.0))
     idx = np.nonzero(ok)[0]
     keys = D.view(np.uint32)[idx]
     return idx[np.lexsort((idx, keys))]
@@ -94,21 +122,24 @@ def _sensor_frame(scene, batch, l, e, attrs):
     return m_s, Wh, op
 
 
-def _peak(d, m, W, o):
+def _peak(d, m, W, o, org):
     """Peak response of Gaussians (centre m, whitening W, opacity o) along
-    rays x(t) = t d: t* = argmin |W (t d - m)|^2 and alpha = min(0.99,
-    o exp(-q(t*)/2)).  d is (rays, 3) for one Gaussian or (3,) for many."""
+    rays x(t) = org + t d: t* = argmin |W (org + t d - m)|^2 and alpha =
+    min(0.99, o exp(-q(t*)/2)).  d and org are (rays, 3) for one Gaussian or
+    (3,) for many."""
     if d.ndim == 2:                                       # many rays, one Gaussian
+        rel = m[None] - org
         dw = d @ W.T
-        mw = W @ m
-        tstar = (dw @ mw) / np.einsum("ij,ij->i", dw, dw)
-        p = m[None] - tstar[:, None] * d
+        mw = rel @ W.T
+        tstar = np.einsum("ij,ij->i", dw, mw) / np.einsum("ij,ij->i", dw, dw)
+        p = rel - tstar[:, None] * d
         pw = p @ W.T
     else:                                                 # one ray, many Gaussians
+        rel = m - org[None]
         dw = np.einsum("nij,j->ni", W, d)
-        mw = np.einsum("nij,nj->ni", W, m)
+        mw = np.einsum("nij,nj->ni", W, rel)
         tstar = np.einsum("ni,ni->n", dw, mw) / np.einsum("ni,ni->n", dw, dw)
-        p = m - tstar[:, None] * d[None]
+        p = rel - tstar[:, None] * d[None]
         pw = np.einsum("nij,nj->ni", W, p)
     q = np.einsum("ij,ij->i", pw, pw)
     return tstar, np.minimum(0.99, o * np.exp(-0.5 * q))
@@ -119,6 +150,7 @@ def lidar_ref(scene, batch, l: int = 0, e: int = 0, attrs=None, margin: float = 
     lid = batch.cams[l]
     m_s, Wh, op = _sensor_frame(scene, batch, l, e, attrs)
     d = ray_directions(lid).reshape(-1, 3)
+    org = ray_origins(lid).reshape(-1, 3)
     n_rays = d.shape[0]
     near = float(np.float32(lid.near_range))
     T = np.ones(n_rays)
@@ -127,7 +159,7 @@ def lidar_ref(scene, batch, l: int = 0, e: int = 0, attrs=None, margin: float = 
     flagged = np.zeros(n_rays, bool)
     order = centre_order(scene, batch, l, e, attrs)
     for g in order:
-        tstar, a = _peak(d, m_s[g], Wh[g], op[g])
+        tstar, a = _peak(d, m_s[g], Wh[g], op[g], org)
         front = tstar > near
         take = live & front & (a >= ALPHA_MIN)
         flagged |= live & front & (np.abs(a * 255.0 - 1.0) < margin)
@@ -188,8 +220,13 @@ def lidar_ray_variants(scene, batch, l: int, e: int, row: int, col: int, attrs=N
     m_s, Wh, op = _sensor_frame(scene, batch, l, e, attrs)
     order = centre_order(scene, batch, l, e, attrs)
     d = ray_directions(lid)[row, col]
+    org = ray_origins(lid)[row, col]
     with np.errstate(all="ignore"):
-        tstar, a = _peak(d, m_s[order], Wh[order], op[order])
+        tstar, a = _peak(d, m_s[order], Wh[order], op[order], org)
+    # Gaussians below (1 - margin) / 255 at their peak can be neither taken nor
+    # flagged: only the others are walked
+    keep = a >= ALPHA_MIN * (1.0 - margin)
+    tstar, a = tstar[keep], a[keep]
     near = float(np.float32(lid.near_range))
     m = _ray_run(tstar, a, near, margin, 0, 0)[2]
     while True:

@@ -1137,13 +1137,22 @@ int validate_lidar(const gsr_ctx* ctx, const gsr_lidar_desc* d, const SceneRes* 
         const gsr_lidar& L = d->lidars[l];
         if (L.width < 1 || L.height < 1 || L.width > 8192 || L.height > 8192)
             return fail(GSR_E_INVALID, "LiDAR grid size must be in 1..8192");
-        if (!(L.az_step > 0.0f) || !std::isfinite(L.az0) || (double)L.width * L.az_step > two_pi * (1.0 + 1e-6))
-            return fail(GSR_E_INVALID, "az_step must be > 0 with width * az_step <= 2 pi");
-        if (!L.elevations) return fail(GSR_E_INVALID, "elevations is NULL");
-        for (int r = 0; r < L.height; ++r) {
-            const float e = L.elevations[r];
-            if (!(e > -1.5707963f && e < 1.5707963f)) return fail(GSR_E_INVALID, "elevations must lie in (-pi/2, pi/2)");
-            if (r > 0 && !(e > L.elevations[r - 1])) return fail(GSR_E_INVALID, "elevations must ascend strictly");
+        if (L.pattern == GSR_LIDAR_GRID) {
+            if (!(L.dx > 0.0f) || !(L.dy > 0.0f) || !std::isfinite(L.dx) || !std::isfinite(L.dy) ||
+                !std::isfinite(L.x0) || !std::isfinite(L.y0))
+                return fail(GSR_E_INVALID, "heightmap grid: x0, y0 finite and dx, dy > 0");
+        } else if (L.pattern == GSR_LIDAR_ANGULAR) {
+            if (!(L.az_step > 0.0f) || !std::isfinite(L.az0) || (double)L.width * L.az_step > two_pi * (1.0 + 1e-6))
+                return fail(GSR_E_INVALID, "az_step must be > 0 with width * az_step <= 2 pi");
+            if (!L.elevations) return fail(GSR_E_INVALID, "elevations is NULL");
+            for (int r = 0; r < L.height; ++r) {
+                const float e = L.elevations[r];
+                if (!(e > -1.5707963f && e < 1.5707963f))
+                    return fail(GSR_E_INVALID, "elevations must lie in (-pi/2, pi/2)");
+                if (r > 0 && !(e > L.elevations[r - 1])) return fail(GSR_E_INVALID, "elevations must ascend strictly");
+            }
+        } else {
+            return fail(GSR_E_INVALID, "LiDAR pattern must be GSR_LIDAR_ANGULAR or GSR_LIDAR_GRID");
         }
         if (!(L.near_range > 0.0f)) return fail(GSR_E_INVALID, "near_range must be > 0");
         if (L.attach_body < -1 || L.attach_body >= sc->dev.n_bodies)
@@ -1182,7 +1191,9 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
         // the device (earlier work on this workspace must be done with them)
         if (ws->used) GSR_HIP_TRY(hipEventSynchronize(ws->ev_done));
         size_t n_elev = 0;
-        for (int l = 0; l < d->n_lidars; ++l) n_elev += (size_t)d->lidars[l].height;
+        for (int l = 0; l < d->n_lidars; ++l)
+            if (d->lidars[l].pattern == GSR_LIDAR_ANGULAR) n_elev += (size_t)d->lidars[l].height;
+        n_elev = std::max<size_t>(n_elev, 1);
         if (ws->h_elev_cap < n_elev) {
             if (ws->h_elev) (void)hipHostFree(ws->h_elev);
             ws->h_elev = nullptr;
@@ -1202,20 +1213,28 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
         size_t eo = 0;
         for (int l = 0; l < d->n_lidars; ++l) {
             const gsr_lidar& L = d->lidars[l];
-            std::memcpy(ws->h_elev + eo, L.elevations, (size_t)L.height * sizeof(float));
+            const bool grid = L.pattern == GSR_LIDAR_GRID;
+            if (!grid) std::memcpy(ws->h_elev + eo, L.elevations, (size_t)L.height * sizeof(float));
             const int tx = (L.width + ts - 1) / ts, ty = (L.height + ts - 1) / ts;
             for (int e = 0; e < E; ++e) {
                 ImageInfo& im = job.imgs[(size_t)l * E + e];
                 std::memset(&im, 0, sizeof im);
-                im.kind = 1;
+                im.kind = grid ? 2 : 1;
                 im.width = L.width;
                 im.height = L.height;
                 im.tiles_x = tx;
                 im.tiles_y = ty;
                 im.near_plane = L.near_range;
-                im.az0 = L.az0;
-                im.az_step = L.az_step;
-                im.elev = ws->stage_elev.as<float>() + eo;
+                if (grid) {
+                    im.gx0 = L.x0;
+                    im.gy0 = L.y0;
+                    im.gdx = L.dx;
+                    im.gdy = L.dy;
+                } else {
+                    im.az0 = L.az0;
+                    im.az_step = L.az_step;
+                    im.elev = ws->stage_elev.as<float>() + eo;
+                }
                 im.attach_body = L.attach_body;
                 im.key_tile_base = (uint32_t)tile_base;
                 im.vm_off = (uint32_t)(((size_t)l * E + e) * 12);
@@ -1225,7 +1244,7 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
                 tile_base += (uint64_t)tx * ty;
                 ray_base += (uint64_t)L.width * L.height;
             }
-            eo += (size_t)L.height;
+            if (!grid) eo += (size_t)L.height;
         }
         GSR_HIP_TRY(hipMemcpyAsync(ws->stage_elev.p, ws->h_elev, n_elev * sizeof(float), hipMemcpyHostToDevice, st));
         // grids of equal size contiguous (one raster segment each)

@@ -44,10 +44,11 @@ struct ImageInfo {
     const float* obs_bright;
     int obs_fmt;              // GSR_OBS_U8 / GSR_OBS_F16
     uint32_t obs_idx;         // c * E + e within the image's request
-    // LiDAR images (kind 1): width x height ray grid, range -> out_depth, hit -> out_alpha
-    int kind;                 // 0 camera, 1 LiDAR
-    float az0, az_step;       // ray azimuths az0 + (c + 0.5) az_step
-    const float* elev;        // device [height] beam elevations, ascending
+    // LiDAR images (kind 1 angular, 2 heightmap grid): width x height rays, range -> out_depth, hit -> out_alpha
+    int kind;                 // 0 camera, 1 angular LiDAR, 2 heightmap grid
+    float az0, az_step;       // kind 1: ray azimuths az0 + (c + 0.5) az_step
+    const float* elev;        // kind 1: device [height] beam elevations, ascending
+    float gx0, gy0, gdx, gdy; // kind 2: ray (r, c) starts at (gx0 + (c + 0.5) gdx, gy0 + (r + 0.5) gdy, 0), along -z
 };
 
 // Resident scene, device pointers.

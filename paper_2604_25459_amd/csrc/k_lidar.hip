@@ -61,6 +61,18 @@ __device__ __forceinline__ void column_range(float a0, float a1, float az0, floa
     *c1 = x1;
 }
 
+// Grid rays with index k in [0, n) whose origin c0 + (k + 0.5) step lies in
+// [a0, a1]; an empty range when none.
+__device__ __forceinline__ void column_range_grid(float a0, float a1, float c0, float step, int n, int* k0, int* k1)
+{
+    const float lo = (a0 - c0) / step - 0.5f;
+    const float hi = (a1 - c0) / step - 0.5f;
+    int x0 = (int)ceilf(fmaxf(lo, -1.0f));
+    int x1 = (int)floorf(fminf(hi, (float)n)) + 1;
+    *k0 = max(x0, 0);
+    *k1 = min(x1, n);
+}
+
 template <int ST>
 __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, int ts, int ipt)
 {
@@ -92,13 +104,26 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
         const float tx = ((A[0] * mu[0] + A[1] * mu[1]) + A[2] * mu[2]) + X[9];
         const float ty = ((A[3] * mu[0] + A[4] * mu[1]) + A[5] * mu[2]) + X[10];
         const float tz = ((A[6] * mu[0] + A[7] * mu[1]) + A[8] * mu[2]) + X[11];
-        const float D = sqrtf((tx * tx + ty * ty) + tz * tz);
+        const bool grid = im.kind == 2;
+        // key: centre distance (angular), depth of the centre below the sensor plane (grid)
+        const float D = grid ? (-tz > 0.0f ? -tz : 0.0f) : sqrtf((tx * tx + ty * ty) + tz * tz);
         const size_t o = (size_t)i * (size_t)s.n + (size_t)g;
-        const bool ok = isfinite(tx) && isfinite(ty) && isfinite(tz) && op >= 1.0f / 255.0f && D > 0.0f &&
-                        isfinite(D) && sc[0] > 0.0f && sc[1] > 0.0f && sc[2] > 0.0f;
+        bool ok = isfinite(tx) && isfinite(ty) && isfinite(tz) && op >= 1.0f / 255.0f && isfinite(D) &&
+                  sc[0] > 0.0f && sc[1] > 0.0f && sc[2] > 0.0f;
         int r0 = 0, r1 = 0, c0 = 0, c1 = 0;
         float cone_c = -2.0f;                           // cosine of the cone half-angle; -2 = every direction
-        if (ok) {
+        float disc = 0.0f;                              // grid: footprint radius on the sensor plane
+        if (grid) {
+            // the alpha >= 1/255 ellipsoid lies in the sphere of radius rho: rays (which look
+            // down from z = 0) can reach it only if it dips below the plane, and only inside
+            // its footprint disc (widened against the rounding of the ray origins)
+            ok = ok && tz < rho;
+            disc = rho * 1.0001f + 1e-6f * ((((1.0f + fabsf(tx)) + fabsf(ty)) + fabsf(im.gx0)) + fabsf(im.gy0));
+            if (ok) {
+                column_range_grid(tx - disc, tx + disc, im.gx0, im.gdx, im.width, &c0, &c1);
+                column_range_grid(ty - disc, ty + disc, im.gy0, im.gdy, im.height, &r0, &r1);
+            }
+        } else if ((ok = ok && D > 0.0f)) {
             if (D <= rho * 1.001f + 1e-6f) {            // the sensor may sit inside: every ray
                 r0 = 0;
                 r1 = im.height;
@@ -159,42 +184,47 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
         rec[1] = make_float4(W[3], W[4], W[5], ty);
         rec[2] = make_float4(W[6], W[7], W[8], tz);
         rec[3] = make_float4(log2o, w0, w1, w2);
-        const float iD = 1.0f / D;
-        rec[4] = make_float4(tx * iD, ty * iD, tz * iD, cone_c);
+        if (grid) {
+            rec[4] = make_float4(tx, ty, disc, 0.0f);
+        } else {
+            const float iD = 1.0f / D;
+            rec[4] = make_float4(tx * iD, ty * iD, tz * iD, cone_c);
+        }
     }
 }
 
 // One workgroup per TS x TS tile of rays; batches of kLBatch records in LDS.
-// Wave-level culling: each wave bounds its rays by a cone (axis = their
-// normalised mean direction, half-angle beta = the widest ray), and a
-// Gaussian survives when its own cone (half-angle alpha around its centre
-// direction, as used for the tile rectangle) comes within alpha + beta of
-// that axis; only survivors are evaluated, bit by bit of the wave's ballot.
+// Wave-level culling.  Angular rays: each wave bounds its rays by a cone
+// (axis = their normalised mean direction, half-angle beta = the widest ray),
+// and a Gaussian survives when its own cone (half-angle alpha around its
+// centre direction, as used for the tile rectangle) comes within alpha + beta
+// of that axis.  Grid rays: the wave's ray origins span a rectangle of the
+// sensor plane, and a Gaussian survives when its footprint disc reaches it.
+// Only survivors are evaluated, bit by bit of the wave's ballot.
 template <int TS>
-__global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c, RasterParams p)
+struct LidarLds {
+    float4 sr[kLidarRec][TS * TS];
+    uint32_t live_w[2][TS * TS / 64];     // per wave: live rays left after a batch (by batch parity)
+};
+
+template <int TS, bool GRID>
+__device__ __forceinline__ void lidar_tile(const SceneDev& s, const ChunkDev& c, int i, const ImageInfo& im, int tx,
+                                           int ty, uint32_t t, LidarLds<TS>& L_)
 {
     constexpr int NT = TS * TS;
     constexpr int kLBatch = NT;
-    __shared__ float4 sr[kLidarRec][kLBatch];
-    __shared__ uint32_t live_w[2][NT / 64];     // per wave: live rays left after a batch (by batch parity)
-    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
-    int sgi = 0;
-#pragma unroll
-    for (int k = 1; k < kMaxSegs; ++k)
-        if (k < p.n_segs && bid >= p.segs[k].first_tile) sgi = k;
-    const RasterSeg seg = p.segs[sgi];
-    const uint32_t rel = bid - seg.first_tile;
-    const uint32_t io = rel / seg.tiles_per_image;
-    const uint32_t t = rel - io * seg.tiles_per_image;
-    const int i = (int)(seg.first_image + io);
-    const ImageInfo im = c.img[i];
-    const int tx = (int)(t % (uint32_t)im.tiles_x);
-    const int ty = (int)(t / (uint32_t)im.tiles_x);
+    auto& sr = L_.sr;
+    auto& live_w = L_.live_w;
     const int tid = threadIdx.x, lane = __lane_id();
     const int col = tx * TS + (tid % TS), row = ty * TS + (tid / TS);
     const bool inside = col < im.width && row < im.height;
-    float d[3] = {0.0f, 0.0f, 0.0f};
-    if (inside) {
+    // ray: origin o (grid; the sensor origin otherwise) and direction d
+    float d[3] = {0.0f, 0.0f, GRID ? -1.0f : 0.0f};
+    float ox = 0.0f, oy = 0.0f;
+    if (GRID) {
+        ox = im.gx0 + ((float)col + 0.5f) * im.gdx;
+        oy = im.gy0 + ((float)row + 0.5f) * im.gdy;
+    } else if (inside) {
         const float az = im.az0 + ((float)col + 0.5f) * im.az_step;
         const float el = im.elev[row];
         float sa, ca, se, ce;
@@ -204,23 +234,38 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
         d[1] = ce * sa;
         d[2] = se;
     }
-    // the wave's cone: axis w, cos / sin of its half-angle (culling off when wider than 90 degrees)
+    // the wave's bound: a cone (angular; culling off when wider than 90 degrees) or the
+    // rectangle of its ray origins (grid)
     float w[3] = {d[0], d[1], d[2]};
+    bool cull = true;
+    float cb = 1.0f, sb = 0.0f;
+    float bx0 = inside ? ox : 3.0e38f, bx1 = inside ? ox : -3.0e38f;
+    float by0 = inside ? oy : 3.0e38f, by1 = inside ? oy : -3.0e38f;
+    if (GRID) {
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1)
+        for (int m = 1; m < 64; m <<= 1) {
+            bx0 = fminf(bx0, __shfl_xor(bx0, m, 64));
+            bx1 = fmaxf(bx1, __shfl_xor(bx1, m, 64));
+            by0 = fminf(by0, __shfl_xor(by0, m, 64));
+            by1 = fmaxf(by1, __shfl_xor(by1, m, 64));
+        }
+    } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) w[k] += __shfl_xor(w[k], m, 64);
-    const float wn = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-    bool cull = wn > 0.0f;
-    if (cull)
+        for (int m = 1; m < 64; m <<= 1)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) w[k] /= wn;
-    float cb = inside ? d[0] * w[0] + d[1] * w[1] + d[2] * w[2] : 1.0f;
+            for (int k = 0; k < 3; ++k) w[k] += __shfl_xor(w[k], m, 64);
+        const float wn = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        cull = wn > 0.0f;
+        if (cull)
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) cb = fminf(cb, __shfl_xor(cb, m, 64));
-    cb = cb - 1e-5f;                                  // rounding of the directions and of the axis
-    cull = cull && cb > 0.0f;
-    const float sb = sqrtf(fmaxf(0.0f, 1.0f - cb * cb));
+            for (int k = 0; k < 3; ++k) w[k] /= wn;
+        cb = inside ? d[0] * w[0] + d[1] * w[1] + d[2] * w[2] : 1.0f;
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) cb = fminf(cb, __shfl_xor(cb, m, 64));
+        cb = cb - 1e-5f;                              // rounding of the directions and of the axis
+        cull = cull && cb > 0.0f;
+        sb = sqrtf(fmaxf(0.0f, 1.0f - cb * cb));
+    }
 
     bool live = inside;
     float T = 1.0f, Rg = 0.0f;
@@ -231,6 +276,7 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
     const float4* rec = c.rec + (size_t)i * (size_t)s.n * kLidarRec;
     const uint32_t n = (uint32_t)s.n;
     bool wave_live = __ballot(live) != 0ull;
+    bool bad_entry = false;
     int par = 0;
     for (uint32_t b0 = start; b0 < end; b0 += kLBatch, par ^= 1) {
         __syncthreads();
@@ -245,8 +291,8 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
         const uint32_t e = b0 + (uint32_t)tid;
         if (e < end) {
             uint32_t g = list[e];
-            if (g >= n) {               // impossible by construction: report it, read a valid record
-                atomicOr(c.err, kErrListEntry);
+            if (g >= n) {               // impossible by construction: reported at the end, a valid record read
+                bad_entry = true;
                 g = 0;
             }
 #pragma unroll
@@ -259,7 +305,12 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
             bool keep = false;
             if (jl < cnt) {
                 const float4 cn = sr[4][jl];
-                if (!cull || cn.w < -1.5f) {
+                if (GRID) {
+                    // distance from the footprint centre to the origin rectangle, against the disc radius
+                    const float ex = fmaxf(0.0f, fmaxf(bx0 - cn.x, cn.x - bx1));
+                    const float ey = fmaxf(0.0f, fmaxf(by0 - cn.y, cn.y - by1));
+                    keep = ex * ex + ey * ey <= cn.z * cn.z * 1.0001f;
+                } else if (!cull || cn.w < -1.5f) {
                     keep = true;
                 } else {
                     const float sa = sqrtf(fmaxf(0.0f, 1.0f - cn.w * cn.w));
@@ -277,11 +328,20 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
                 const float dy = fmaf(m1.z, d[2], fmaf(m1.y, d[1], m1.x * d[0]));
                 const float dz = fmaf(m2.z, d[2], fmaf(m2.y, d[1], m2.x * d[0]));
                 const float aa = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                const float bb = fmaf(dz, m3.w, fmaf(dy, m3.z, dx * m3.y));
+                // centre relative to the ray origin, and W times it
+                float cx = m0.w, cy = m1.w, wcx = m3.y, wcy = m3.z, wcz = m3.w;
+                if (GRID) {
+                    cx = m0.w - ox;
+                    cy = m1.w - oy;
+                    wcx = m3.y - fmaf(m0.y, oy, m0.x * ox);
+                    wcy = m3.z - fmaf(m1.y, oy, m1.x * ox);
+                    wcz = m3.w - fmaf(m2.y, oy, m2.x * ox);
+                }
+                const float bb = fmaf(dz, wcz, fmaf(dy, wcy, dx * wcx));
                 const float tstar = bb * __builtin_amdgcn_rcpf(aa);
                 // offset of the centre from the ray's closest point, in metres, then whitened
-                const float px = fmaf(-tstar, d[0], m0.w);
-                const float py = fmaf(-tstar, d[1], m1.w);
+                const float px = fmaf(-tstar, d[0], cx);
+                const float py = fmaf(-tstar, d[1], cy);
                 const float pz = fmaf(-tstar, d[2], m2.w);
                 const float wx = fmaf(m0.z, pz, fmaf(m0.y, py, m0.x * px));
                 const float wy = fmaf(m1.z, pz, fmaf(m1.y, py, m1.x * px));
@@ -306,11 +366,33 @@ __global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c
         }
         if (lane == 0) live_w[par][tid >> 6] = wave_live ? 1u : 0u;
     }
+    if (bad_entry) atomicOr(c.err, kErrListEntry);
     if (inside) {
         const size_t pix = (size_t)row * im.width + col;
         im.out_depth[pix] = T < 1.0f ? Rg / (1.0f - T) : 0.0f;
         if (im.out_alpha) im.out_alpha[pix] = 1.0f - T;
     }
+}
+
+template <int TS>
+__global__ __launch_bounds__(TS * TS) void k_raster_lidar(SceneDev s, ChunkDev c, RasterParams p)
+{
+    __shared__ LidarLds<TS> lds;
+    const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    int sgi = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxSegs; ++k)
+        if (k < p.n_segs && bid >= p.segs[k].first_tile) sgi = k;
+    const RasterSeg seg = p.segs[sgi];
+    const uint32_t rel = bid - seg.first_tile;
+    const uint32_t io = rel / seg.tiles_per_image;
+    const uint32_t t = rel - io * seg.tiles_per_image;
+    const int i = (int)(seg.first_image + io);
+    const ImageInfo im = c.img[i];
+    const int tx = (int)(t % (uint32_t)im.tiles_x);
+    const int ty = (int)(t / (uint32_t)im.tiles_x);
+    if (im.kind == 2) lidar_tile<TS, true>(s, c, i, im, tx, ty, t, lds);     // workgroup-uniform
+    else lidar_tile<TS, false>(s, c, i, im, tx, ty, t, lds);
 }
 
 template <int ST>

@@ -69,7 +69,8 @@ class RenderDesc(C.Structure):
 
 class LidarDesc(C.Structure):
     _fields_ = [("width", C.c_int), ("height", C.c_int), ("az0", C.c_float), ("az_step", C.c_float),
-                ("elevations", C.c_void_p), ("near_range", C.c_float), ("attach_body", C.c_int)]
+                ("elevations", C.c_void_p), ("near_range", C.c_float), ("attach_body", C.c_int),
+                ("pattern", C.c_int), ("x0", C.c_float), ("y0", C.c_float), ("dx", C.c_float), ("dy", C.c_float)]
 
 
 class LidarRenderDesc(C.Structure):
@@ -361,8 +362,10 @@ class Renderer:
             el = np.ascontiguousarray(np.asarray(l.elevations, np.float32))
             keep.append(el)
             arr[k] = LidarDesc(width=int(l.width), height=int(l.height), az0=float(l.az0), az_step=float(l.az_step),
-                               elevations=el.ctypes.data, near_range=float(l.near_range),
-                               attach_body=int(l.attach_body))
+                               elevations=el.ctypes.data if el.size else None, near_range=float(l.near_range),
+                               attach_body=int(l.attach_body), pattern=int(getattr(l, "pattern", 0)),
+                               x0=float(getattr(l, "x0", 0.0)), y0=float(getattr(l, "y0", 0.0)),
+                               dx=float(getattr(l, "dx", 0.0)), dy=float(getattr(l, "dy", 0.0)))
         d = LidarRenderDesc(scene_id=sid, n_envs=int(viewmats.shape[1]), n_lidars=len(lidars),
                             lidars=C.addressof(arr), viewmats=_ptr(viewmats),
                             body_poses=_ptr(poses) if poses is not None and poses.numel() else None,

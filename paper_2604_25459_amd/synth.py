@@ -218,9 +218,12 @@ def orbit_viewmats(rng: np.random.Generator, n: int, r_lo: float, r_hi: float,
 # --------------------------------------------------------------------------
 @dataclass
 class LidarSpec:
-    """A ray grid (sensor frame x forward, y left, z up): ``height`` beams at
-    ``elevations`` (radians, ascending) x ``width`` columns at azimuths
-    az0 + (c + 0.5) az_step."""
+    """A ray grid (sensor frame x forward, y left, z up).  pattern 0
+    (angular): ``height`` beams at ``elevations`` (radians, ascending) x
+    ``width`` columns at azimuths az0 + (c + 0.5) az_step, rays from the
+    sensor origin.  pattern 1 (heightmap grid): ``height`` x ``width``
+    parallel rays along -z from the sensor's z = 0 plane, ray (r, c) starting
+    at (x0 + (c + 0.5) dx, y0 + (r + 0.5) dy, 0)."""
     width: int
     height: int
     az0: float
@@ -228,6 +231,11 @@ class LidarSpec:
     elevations: np.ndarray
     near_range: float = 0.05
     attach_body: int = -1
+    pattern: int = 0
+    x0: float = 0.0
+    y0: float = 0.0
+    dx: float = 0.0
+    dy: float = 0.0
 
 
 @dataclass
@@ -256,6 +264,15 @@ def sector_lidar(beams: int, columns: int, az_deg: float, el_lo_deg: float, el_h
     a = math.radians(az_deg)
     return LidarSpec(width=columns, height=beams, az0=float(np.float32(-0.5 * a)),
                      az_step=float(np.float32(a / columns)), elevations=el, near_range=float(np.float32(near)))
+
+
+def height_grid(rows: int, cols: int, spacing: float, near: float = 0.05) -> LidarSpec:
+    """Heightmap scanner centred on the sensor: rows x cols parallel rays along
+    -z at ``spacing`` metres (float32 parameters)."""
+    f = lambda v: float(np.float32(v))
+    return LidarSpec(width=cols, height=rows, az0=0.0, az_step=0.0, elevations=np.zeros(0, np.float32),
+                     near_range=f(near), pattern=1, x0=f(-0.5 * cols * spacing), y0=f(-0.5 * rows * spacing),
+                     dx=f(spacing), dy=f(spacing))
 
 
 def sensor_viewmats(rng: np.random.Generator, n: int, r_lo: float, r_hi: float, z: float = 0.0) -> np.ndarray:

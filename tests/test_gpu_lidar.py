@@ -145,3 +145,81 @@ def test_lidar_invalid_arguments(R):
     R.render_lidar(sid, [good], vm_t, poses_t)         # and the good one still renders
     _torch().cuda.synchronize()
     R.remove_scene(sid)
+
+
+def _sampled_compare(R, scene, batch, lidars, got, n_samples, label, seed=0):
+    """Sampled rays of every slot and env against the per-ray oracle (the
+    primary result or one of its admissible variants)."""
+    from oracle import lidar_ray_variants
+    rng = np.random.default_rng(seed)
+    E = batch.n_envs
+    checked = hits = 0
+    for l, lid in enumerate(lidars):
+        rng_l, hit_l = got[l]
+        for e in range(E):
+            rows = rng.integers(0, lid.height, n_samples)
+            cols = rng.integers(0, lid.width, n_samples)
+            for r, c in zip(rows, cols):
+                rr, hh = lidar_ray_variants(scene, batch, l, e, int(r), int(c))
+                gr, gh = float(rng_l[e, r, c]), float(hit_l[e, r, c])
+                ok = (np.abs(gh - hh) <= HIT_TOL) & (np.abs(gr - rr) / np.maximum(1.0, rr) <= RANGE_REL)
+                assert ok.any(), (label, l, e, int(r), int(c), gr, gh, rr[0], hh[0])
+                checked += 1
+                hits += hh[0] > 0.1
+    print(f"[{label}] sampled rays {checked}, hit {hits}", flush=True)
+    assert hits >= checked // 10
+
+
+def test_heightmap_grid_and_rotating_slots_match_oracle(R):
+    """A heightmap grid and a rotating sensor in one call (both ray kinds in one
+    launch): every ray of both against the float64 oracle."""
+    scene = synth.make_scene(57, 4_000, 3, 800, sh_degree=0, half_box=2.0)
+    rng = np.random.default_rng(9)
+    E = 3
+    grid = synth.height_grid(24, 40, 0.08)
+    rot = synth.rotating_lidar(8, 96, -30, 10)
+    vm = synth.sensor_viewmats(rng, E, 0.0, 1.5, 1.2)     # sensors 1.2 m up, within 1.5 m of the axis
+    batch = synth.LidarBatch(cams=[grid, rot], viewmats=np.stack([vm, vm]), poses=synth.random_poses(rng, E, 3))
+    vmt, pt = _tensors(batch)
+    got = R.render_lidar(R.add_synth_scene(scene), [grid, rot], vmt, pt)
+    for l in range(2):
+        for e in range(E):
+            ref = lidar_ref(scene, batch, l, e)
+            _compare(got[l][0][e].cpu().numpy(), got[l][1][e].cpu().numpy(), ref, f"slot {l} env {e}", scene,
+                     batch, l, e, min_hits=10)
+
+
+def test_heightmap_sheet_reads_its_height(R):
+    """A flat sheet of Gaussians 0.7 m below the sensor plane: every ray over
+    the sheet reads range 0.7 (its centres' depth) and a high hit fraction."""
+    xs = np.arange(-1.0, 1.001, 0.04)
+    means = [[x, y, -0.7] for x in xs for y in xs]
+    scene = scene_from(means, [[0.04, 0.04, 0.003]] * len(means), opac=0.35, degree=0)
+    grid = synth.height_grid(32, 32, 0.05)
+    batch = synth.LidarBatch(cams=[grid], viewmats=np.concatenate([np.eye(3), np.zeros((3, 1))], 1)[None, None]
+                             .astype(np.float32), poses=np.zeros((1, 0, 7), np.float32))
+    vmt, pt = _tensors(batch)
+    (rg, hit), = R.render_lidar(R.add_synth_scene(scene), [grid], vmt, pt)
+    rg, hit = rg[0].cpu().numpy(), hit[0].cpu().numpy()
+    assert (hit > 0.5).all()
+    np.testing.assert_allclose(rg, np.float32(0.7), rtol=1e-5)
+    ref = lidar_ref(scene, batch)
+    _compare(rg, hit, ref, "sheet", scene, batch, 0, 0)
+
+
+def test_lidar_at_benchmark_scale_sampled(R):
+    """The benchmark's sensors on the 300k-Gaussian workload-2 scene (long
+    tile-row lists, segmented scatter): a rotating 32 x 1024 LiDAR and a
+    64 x 64 heightmap grid, rays sampled in every env against the oracle."""
+    scene, _ = synth.make_config(2, n_envs=1)
+    rng = np.random.default_rng(11)
+    E = 3
+    rot = synth.rotating_lidar(32, 1024, -25.0, 15.0)
+    grid = synth.height_grid(64, 64, 0.05)
+    vm = synth.sensor_viewmats(rng, E, 0.5, 3.0, 0.2)
+    poses = synth.make_poses(2, 0, E, scene.n_bodies)
+    batch = synth.LidarBatch(cams=[rot, grid], viewmats=np.stack([vm, vm]), poses=poses)
+    vmt, pt = _tensors(batch)
+    got = R.render_lidar(R.add_synth_scene(scene), [rot, grid], vmt, pt)
+    got = [(r.cpu().numpy(), h.cpu().numpy()) for r, h in got]
+    _sampled_compare(R, scene, batch, [rot, grid], got, 24, "benchmark scale")

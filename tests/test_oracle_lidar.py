@@ -162,3 +162,86 @@ def test_flagged_ray_lists_both_branches(delta):
     first, second = (taken, skipped) if delta > 0 else (skipped, taken)
     assert (rng[0], hit[0]) == first and (rng[1], hit[1]) == second
     assert rng[0] == ref.range[0, 2] and hit[0] == ref.hit[0, 2]
+
+
+# ------------------------------------------------------------------ heightmap grid
+def _grid(rows=5, cols=7, spacing=0.1, near=0.02):
+    return synth.height_grid(rows, cols, spacing, near)
+
+
+def test_height_grid_geometry():
+    from oracle.lidar import ray_origins
+    lid = _grid(4, 6, 0.25)
+    o = ray_origins(lid)
+    d = ray_directions(lid)
+    assert o.shape == (4, 6, 3) and d.shape == (4, 6, 3)
+    np.testing.assert_allclose(o[0, 0], [-0.75 + 0.125, -0.5 + 0.125, 0.0])
+    np.testing.assert_allclose(o[3, 5], [0.75 - 0.125, 0.5 - 0.125, 0.0])
+    np.testing.assert_array_equal(d[..., 2], -1.0)
+
+
+def test_isotropic_gaussian_below_a_grid():
+    # isotropic Gaussian at depth h below the plane: every vertical ray peaks at t* = h,
+    # with q = (horizontal distance / sigma)^2
+    lid = _grid(5, 7, 0.1)
+    f = lambda v: float(np.float32(v))          # the scene holds float32 attributes
+    h, sigma, o = 1.5, f(0.12), f(0.8)
+    cx, cy = f(0.03), f(-0.04)
+    scene = scene_from([[cx, cy, -h]], [sigma] * 3, opac=o, degree=0)
+    ref = lidar_ref(scene, _batch(lid))
+    for r in range(5):
+        for c in range(7):
+            x = float(np.float32(lid.x0)) + (c + 0.5) * float(np.float32(lid.dx))
+            y = float(np.float32(lid.y0)) + (r + 0.5) * float(np.float32(lid.dy))
+            a = min(0.99, o * math.exp(-0.5 * ((x - cx) ** 2 + (y - cy) ** 2) / sigma ** 2))
+            if a >= 1 / 255:
+                assert ref.hit[r, c] == pytest.approx(a, rel=1e-9)
+                assert ref.range[r, c] == pytest.approx(h, rel=1e-12)
+            else:
+                assert ref.hit[r, c] == 0.0 and ref.range[r, c] == 0.0
+
+
+def test_flat_sheet_gives_its_depth_everywhere():
+    # a ground sheet: overlapping flat axis-aligned Gaussians all at depth h; every
+    # contribution peaks at t* = h, so the range is h wherever the sheet is hit,
+    # and the hit fraction follows the product of (1 - alpha) over the sheet
+    lid = _grid(6, 6, 0.1)
+    h = 0.8
+    xs = np.arange(-0.5, 0.51, 0.05)
+    means = [[x, y, -h] for x in xs for y in xs]
+    n = len(means)
+    scene = scene_from(means, [[0.05, 0.05, 0.002]] * n, opac=0.3, degree=0)
+    ref = lidar_ref(scene, _batch(lid))
+    assert (ref.hit > 0.5).all()
+    np.testing.assert_allclose(ref.range, float(np.float32(h)), rtol=1e-12)   # the centres' float32 depth
+
+
+def test_gaussians_above_the_plane_are_not_seen():
+    lid = _grid(3, 3, 0.2)
+    scene = scene_from([[0.0, 0.0, 0.5], [0.0, 0.0, -1.0]], [0.1] * 3, opac=[0.9, 0.6], degree=0)
+    ref = lidar_ref(scene, _batch(lid))
+    assert ref.hit[1, 1] == pytest.approx(float(np.float32(0.6)), rel=1e-12)    # only the one below
+    assert ref.range[1, 1] == pytest.approx(1.0, rel=1e-12)
+
+
+def test_tilted_gaussian_peak_matches_line_search():
+    # anisotropic, rotated Gaussian: t* from the closed form equals a dense search along each ray
+    from oracle.lidar import _sensor_frame, ray_origins
+    lid = _grid(3, 4, 0.07)
+    q = quat_axis_angle([1.0, 2.0, 0.5], 0.7)
+    scene = scene_from([[0.02, -0.03, -0.9]], [[0.2, 0.05, 0.1]], quats=[q], opac=0.95, degree=0)
+    b = _batch(lid)
+    ref = lidar_ref(scene, b)
+    m_s, Wh, op = _sensor_frame(scene, b, 0, 0, None)
+    o = ray_origins(lid)
+    ts = np.linspace(0.0, 2.0, 400001)
+    for r in range(3):
+        for c in range(4):
+            pts = o[r, c][None] + ts[:, None] * np.array([0.0, 0.0, -1.0])[None]
+            qv = np.einsum("ij,nj->ni", Wh[0], pts - m_s[0][None])
+            qq = np.einsum("ni,ni->n", qv, qv)
+            k = int(np.argmin(qq))
+            a = min(0.99, 0.95 * math.exp(-0.5 * qq[k]))
+            if a >= 1 / 255 * 1.01:
+                assert ref.range[r, c] == pytest.approx(ts[k], abs=1e-5)
+                assert ref.hit[r, c] == pytest.approx(a, rel=1e-6)
