@@ -82,7 +82,13 @@ typedef struct {
                                a second working set, so one chunk's binning overlaps another's rasterisation
                                (default; a render whose second working set does not fit in device memory
                                runs on one stream); -1 = one stream, one working set */
-    int reserved[5];
+    int sync_lists;         /* 0 = the first gsr_render of a job shape (scene, image sizes, launch parameters) on a
+                               working set waits at every chunk for its list totals and sizes the tile-list buffers;
+                               later renders of that shape enqueue every chunk and return without waiting, the device
+                               checking each chunk's totals against the buffers (default); -1 = always wait */
+    int list_cap;           /* tests of the overflow path: > 0 caps the list capacity (entries) that asynchronous
+                               chunks may use, so that their lists overflow; 0 = off */
+    int reserved[3];
 } gsr_options;
 
 /* A scene: static background plus Gaussian clusters bound to rigid bodies
@@ -223,9 +229,16 @@ int gsr_scene_info(gsr_ctx* ctx, uint64_t scene_id, int64_t* n, int* n_bodies, i
  * batched pipeline: RLGK posing + EWA projection + SH colour, a segmented
  * depth radix sort, stable tile binning, and one rasterisation launch per
  * memory chunk.  Inputs and outputs are caller-owned device memory and must
- * stay valid until the stream passes this call.  The call blocks the host
- * thread once per chunk until that chunk's pair count is known (to size the
- * tile lists), then returns with rasterisation still in flight.  With several
+ * stay valid until the stream passes this call.  The first render of a job
+ * shape on a working set blocks the host thread once per chunk until that
+ * chunk's pair count is known, to size the tile-list buffers (with margin);
+ * later renders of the same shape enqueue everything and return without
+ * waiting for the device (see gsr_options.sync_lists).  A chunk whose lists
+ * then outgrow the buffers is detected on the device: it writes no lists and
+ * a fallback rasteriser composites it from the depth-ordered Gaussians (the
+ * same images, slower), and the next render of the shape on the working set
+ * that sees the overflow (once the earlier render has finished) plans the
+ * buffers again.  With several
  * chunks, odd chunks run on an internal stream of the context (see
  * gsr_options.overlap) that waits for the caller's stream at the call's start
  * and is joined back into it before the call returns, so work the caller

@@ -92,13 +92,15 @@ Workspace::~Workspace()
     if (!fixed)
         for (DevBuf* b : {&img, &xform, &keyz, &rect, &srect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &vis_count,
                       &tile_hist, &tile_range, &pair_count, &pair_base, &pairs, &row_hist, &row_range, &row_count,
-                          &row_base, &rows, &debug, &stage_vm, &stage_pose, &stage_elev, &seg_off, &counter})
+                          &row_base, &rows, &debug, &stage_vm, &stage_pose, &stage_elev, &seg_off, &counter,
+                          &ovf, &counter2})
             b->release();
     if (h_total) (void)hipHostFree(h_total);
     if (h_img) (void)hipHostFree(h_img);
     if (h_elev) (void)hipHostFree(h_elev);
     if (ev_total) (void)hipEventDestroy(ev_total);
     if (ev_done) (void)hipEventDestroy(ev_done);
+    if (ev_staged) (void)hipEventDestroy(ev_staged);
     for (auto& kv : graphs)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
@@ -319,7 +321,10 @@ hipError_t ensure_workspace(Workspace& ws, const SceneRes* sc, const ChunkPlan& 
     if (!ws.ev_total) {
         if ((e = hipEventCreateWithFlags(&ws.ev_total, hipEventDisableTiming)) != hipSuccess) return e;
         if ((e = hipEventCreateWithFlags(&ws.ev_done, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&ws.ev_staged, hipEventDisableTiming)) != hipSuccess) return e;
     }
+    if ((e = ws.ovf.ensure(256)) != hipSuccess) return e;
+    if ((e = ws.counter2.ensure(256)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -439,10 +444,23 @@ int run_stage(Workspace& ws, bool graph, int chunk_idx, int stage, uint64_t scen
 // Enqueue the pipeline of images [i0, i0 + n_img) of `job` (image descriptions
 // already on the device).  `pairs_total` receives the chunk's pair count.
 int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, const ChunkPlan& plan, int i0,
-              int n_img, int chunk_idx, hipStream_t st, Mode mode, bool graph, uint64_t* pairs_total)
+              int n_img, int chunk_idx, hipStream_t st, Mode mode, bool graph, uint64_t* pairs_total,
+              bool async_lists)
 {
     ChunkDev c = chunk_view(ws, sc, plan, i0, n_img, job.imgs);
     c.err = ctx->d_err;
+    c.ovf_count = ctx->d_err + 1;
+    c.acc = reinterpret_cast<unsigned long long*>(ctx->d_err + 16);
+    c.ovf = ws.ovf.as<uint32_t>();
+    // synchronous lists: the host sizes the buffers from the totals, nothing overflows
+    c.cap_pairs = async_lists ? ws.pairs.bytes / 4 : ~0ull;
+    c.cap_rows = async_lists ? ws.rows.bytes / 8 : ~0ull;
+    if (async_lists && ctx->list_cap) {            // a smaller capacity set for tests of the overflow path
+        c.cap_pairs = std::min<uint64_t>(c.cap_pairs, ctx->list_cap);
+        c.cap_rows = std::min<uint64_t>(c.cap_rows, ctx->list_cap);
+    }
+    if (async_lists && (int)ws.nseg_hint.size() <= chunk_idx)
+        return fail(GSR_E_INVALID, "asynchronous lists without a planned chunk");
     const SceneDev& s = sc->dev;
     const Tuning& tu = job.tune;
     const bool prof = ctx->opt.profile && mode == Mode::kRender && !ws.fixed;
@@ -488,7 +506,8 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
                                  (uint64_t)c.tile_blocks, (uint64_t)tu.ts, (uint64_t)tu.batch, (uint64_t)tu.ipt,
                                  (uint64_t)tu.persistent, (uint64_t)(uintptr_t)job.viewmats,
                                  (uint64_t)(uintptr_t)job.poses, (uint64_t)(uintptr_t)ws.h_total,
-                                 (uint64_t)(ctx->opt.cutoff * 1.0e6f), (uint64_t)tu.bin};
+                                 (uint64_t)(ctx->opt.cutoff * 1.0e6f), (uint64_t)tu.bin, (uint64_t)async_lists,
+                                 c.cap_pairs, c.cap_rows};
     if (graph) {
         for (void* ptr : {(void*)c.xform, (void*)c.keyz, (void*)c.rect, (void*)c.srect, (void*)c.rec, (void*)c.sk[0],
                           (void*)c.sk[1], (void*)c.sv[0], (void*)c.sv[1], (void*)c.sort_hist, (void*)c.vis_count,
@@ -514,6 +533,7 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[2], st));
     rc = run_stage(ws, graph, chunk_idx, 2, sc->uid, key, st, [&](hipStream_t q) {
         hipError_t e = launch_tile_count(s, c, q);
+        if (async_lists) return e;       // totals stay on the device
         if (e == hipSuccess)
             e = hipMemcpyAsync(ws.h_total, c.pair_base + n_img, sizeof(uint64_t), hipMemcpyDeviceToHost, q);
         if (e == hipSuccess)
@@ -525,26 +545,35 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
     });
     if (rc) return rc;
     if (prof) GSR_HIP_TRY(hipEventRecord(ev.e[3], st));
-    GSR_HIP_TRY(hipEventRecord(ws.ev_total, st));
-    GSR_HIP_TRY(hipEventSynchronize(ws.ev_total));
-    // kernels of this or an earlier chunk met an entry their inputs cannot hold
-    const uint32_t err = reinterpret_cast<const uint32_t*>(ws.h_total + 3)[0];
-    if (err) {
-        ctx->poisoned = true;
-        char msg[160];
-        std::snprintf(msg, sizeof msg, "device consistency check failed (error bits 0x%x: %s)", err,
-                      err & kErrListEntry ? "tile list entry out of range"
-                      : err & kErrSortSlot ? "depth-sort offset out of range" : "tile-row entry out of range");
-        return fail(GSR_E_DEVICE, msg);
-    }
-    const uint64_t total = ws.h_total[0];
-    const uint64_t row_total = ws.h_total[1];
-    *pairs_total = total;
-    if (prof) {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->count_pairs += (double)total;
-        ctx->count_rows += (double)row_total;
-        ctx->count_visible += (double)ws.h_total[2];
+    uint64_t total = 0, row_total = 0;
+    int n_seg = 1;
+    const uint64_t n_rows = (uint64_t)n_img * (uint64_t)c.ty_max;
+    if (async_lists) {
+        // the buffers hold what the planning render needed (with margin); the
+        // device checks this chunk's totals against them
+        n_seg = ws.nseg_hint[chunk_idx];
+        *pairs_total = 0;
+    } else {
+        GSR_HIP_TRY(hipEventRecord(ws.ev_total, st));
+        GSR_HIP_TRY(hipEventSynchronize(ws.ev_total));
+        // kernels of this or an earlier chunk met an entry their inputs cannot hold
+        const uint32_t err = reinterpret_cast<const uint32_t*>(ws.h_total + 3)[0];
+        if (err) {
+            ctx->poisoned = true;
+            char msg[160];
+            std::snprintf(msg, sizeof msg, "device consistency check failed (error bits 0x%x: %s)", err,
+                          err & kErrListEntry ? "tile list entry out of range"
+                          : err & kErrSortSlot ? "depth-sort offset out of range" : "tile-row entry out of range");
+            return fail(GSR_E_DEVICE, msg);
+        }
+        total = ws.h_total[0];
+        row_total = ws.h_total[1];
+        *pairs_total = total;
+        // long tile-row lists are split into segments of about kRowSegEntries entries (one wave each)
+        const uint64_t per_row = n_rows ? row_total / n_rows : 0;
+        n_seg = (int)std::min<uint64_t>(32, std::max<uint64_t>(1, (per_row + kRowSegEntries - 1) / kRowSegEntries));
+        if ((int)ws.nseg_hint.size() <= chunk_idx) ws.nseg_hint.resize((size_t)chunk_idx + 1, 1);
+        ws.nseg_hint[chunk_idx] = n_seg;
     }
     // everything enqueued before ev_total has completed, including earlier chunks: growing is safe
     auto grow = [&](DevBuf& b, uint64_t entries, size_t entry_bytes, const char* what) -> int {
@@ -558,10 +587,6 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
                       n_img, (unsigned long long)entries, want, hipGetErrorString(e));
         return fail(e == hipErrorOutOfMemory ? GSR_E_OOM : GSR_E_DEVICE, msg);
     };
-    // long tile-row lists are split into segments of about kRowSegEntries entries (one wave each)
-    const uint64_t n_rows = (uint64_t)n_img * (uint64_t)c.ty_max;
-    const uint64_t per_row = n_rows ? row_total / n_rows : 0;
-    const int n_seg = (int)std::min<uint64_t>(32, std::max<uint64_t>(1, (per_row + kRowSegEntries - 1) / kRowSegEntries));
     const size_t seg_bytes = n_seg > 1 ? (size_t)(n_rows * (uint64_t)n_seg * (uint64_t)c.tx_max * 4) : 0;
     if (ws.fixed) {
         // lists carved from the fixed list region; the caller re-plans on GSR_E_OVERFLOW
@@ -577,10 +602,12 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
         ws.pairs = {ws.list_base, bp};
         ws.rows = {ws.list_base + bp, br};
         ws.seg_off = {ws.list_base + bp + br, seg_bytes};
-    } else {
+    } else if (!async_lists) {
         if ((rc = grow(ws.pairs, total, 4, "tile")) != GSR_OK) return rc;
         if ((rc = grow(ws.rows, row_total, 8, "tile-row")) != GSR_OK) return rc;
         if (n_seg > 1) GSR_HIP_TRY(ws.seg_off.ensure(seg_bytes));
+    } else if (n_seg > 1 && ws.seg_off.bytes < seg_bytes) {
+        return fail(GSR_E_INVALID, "asynchronous lists: segment offsets not planned");
     }
     c.pairs = ws.pairs.as<uint32_t>();
     c.rows = ws.rows.as<uint2>();
@@ -632,7 +659,12 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
         rc = run_stage(ws, graph, chunk_idx, 4, sc->uid, key, st,
                        [&](hipStream_t q) { return launch_raster_lidar(s, c, rp, q); });
     } else {
-        rc = run_stage(ws, graph, chunk_idx, 4, sc->uid, key, st, [&](hipStream_t q) { return launch_raster(s, c, rp, q); });
+        rc = run_stage(ws, graph, chunk_idx, 4, sc->uid, key, st, [&](hipStream_t q) {
+            hipError_t e = launch_raster(s, c, rp, q);
+            // asynchronous lists: the fallback composites the chunk if its lists overflowed (else it exits at once)
+            if (e == hipSuccess && async_lists) e = launch_raster_fallback(s, c, rp, ws.counter2.as<uint32_t>(), q);
+            return e;
+        });
     }
     if (rc) return rc;
     if (prof) {
@@ -668,9 +700,38 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
     RenderJob job = job_in;
     const size_t rec_bytes = job.lidar ? 80 : 48;
     const ChunkPlan plan = plan_chunks(ctx, sc, job.imgs, plain, job.tune.chunk_images, rec_bytes, job.chunk_bytes);
-    // buffers may be reallocated: earlier work on this workspace must be finished
-    if (ws.used) GSR_HIP_TRY(hipEventSynchronize(ws.ev_done));
+    const int n_chunks = (int)((job.imgs.size() + plan.chunk - 1) / plan.chunk);
+    bool two = two_streams && !plain && ctx->opt.overlap >= 0 && n_chunks > 1;
+    // Asynchronous lists need a planning render of the same job shape on this
+    // workspace (and its twin), whose list buffers and segment counts they
+    // reuse, and no overflow seen since: the counter's copy made at the end of
+    // this workspace's last render is read once that render has finished.
+    std::vector<uint64_t> shape = {sc->uid, (uint64_t)plan.chunk, (uint64_t)job.imgs.size(), (uint64_t)job.tune.ts,
+                                   (uint64_t)job.tune.batch, (uint64_t)job.tune.ipt, (uint64_t)job.tune.bin,
+                                   (uint64_t)job.tune.persistent, (uint64_t)two, (uint64_t)ctx->list_cap};
+    {
+        uint64_t h = 1469598103934665603ull;          // FNV-1a over the image sizes
+        for (const ImageInfo& im : job.imgs) {
+            h = (h ^ (uint64_t)im.width) * 1099511628211ull;
+            h = (h ^ (uint64_t)im.height) * 1099511628211ull;
+        }
+        shape.push_back(h);
+    }
+    bool async = !plain && !job.lidar && job.mode == Mode::kRender && !job.stop && !ws.fixed &&
+                 ctx->opt.sync_lists >= 0 && ws.used && ws.plan_key == shape &&
+                 (!two || (ws.twin && ws.twin->plan_key == shape));
+    if (async && hipEventQuery(ws.ev_done) == hipSuccess) {
+        const uint32_t seen = reinterpret_cast<const uint32_t*>(ws.h_total + 5)[0];
+        if (seen != ctx->ovf_seen) {
+            ctx->ovf_seen = seen;
+            async = false;                              // a chunk overflowed: plan again (the buffers grow)
+        }
+    }
+    // synchronous renders may reallocate buffers: earlier work on this workspace must be finished
+    if (ws.used && !async) GSR_HIP_TRY(hipEventSynchronize(ws.ev_done));
     GSR_HIP_TRY(ensure_workspace(ws, sc, plan, job.imgs.size(), rec_bytes));
+    // the staging buffer of the image descriptions is free once its last copy has run
+    if (ws.used) GSR_HIP_TRY(hipEventSynchronize(ws.ev_staged));
     // per-step inputs staged at fixed addresses, so captured graphs replay across steps
     if (job.viewmats != ws.stage_vm.as<float>()) {
         GSR_HIP_TRY(ws.stage_vm.ensure(std::max<size_t>(job.viewmat_floats, 1) * 4));
@@ -691,8 +752,6 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
     // ends while chunk k still rasterises, and chunk k+1's lists and raster
     // follow on the other stream, so binning and raster of neighbouring
     // chunks share the GPU.  Each workspace is used by one stream only.
-    const int n_chunks = (int)((job.imgs.size() + plan.chunk - 1) / plan.chunk);
-    bool two = two_streams && !plain && ctx->opt.overlap >= 0 && n_chunks > 1;
     Workspace* wk[2] = {&ws, &ws};
     hipStream_t sq[2] = {st, st};
     if (two) {
@@ -714,20 +773,23 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
     }
     if (two) {
         Workspace& t = *ws.twin;
+        if (t.ev_staged) GSR_HIP_TRY(hipEventSynchronize(t.ev_staged));
         std::memcpy(t.h_img, job.imgs.data(), job.imgs.size() * sizeof(ImageInfo));
         GSR_HIP_TRY(hipMemcpyAsync(t.img.p, t.h_img, job.imgs.size() * sizeof(ImageInfo), hipMemcpyHostToDevice, st));
+        GSR_HIP_TRY(hipEventRecord(t.ev_staged, st));
         GSR_HIP_TRY(hipEventRecord(ws.ev_fork, st));
         GSR_HIP_TRY(hipStreamWaitEvent(ws.side, ws.ev_fork, 0));
         wk[1] = &t;
         sq[1] = ws.side;
     }
+    GSR_HIP_TRY(hipEventRecord(ws.ev_staged, st));
     int chunk_idx = 0;
     int rc = GSR_OK;
     for (int i0 = 0; i0 < (int)job.imgs.size() && !rc; i0 += plan.chunk, ++chunk_idx) {
         const int n_img = std::min<int>(plan.chunk, (int)job.imgs.size() - i0);
         const int h = chunk_idx & 1;
         uint64_t total = 0;
-        rc = run_chunk(ctx, *wk[h], sc, job, plan, i0, n_img, chunk_idx, sq[h], job.mode, use_graphs, &total);
+        rc = run_chunk(ctx, *wk[h], sc, job, plan, i0, n_img, chunk_idx, sq[h], job.mode, use_graphs, &total, async);
         if (!rc && job.stop && job.stop->image >= i0 && job.stop->image < i0 + n_img) {
             job.stop->ws = wk[h];
             job.stop->i0 = i0;
@@ -745,11 +807,20 @@ int render_job(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job_i
     }
     if (rc) {
         if (rc == GSR_E_DEVICE) ctx->poisoned = true;
+        ws.plan_key.clear();
+        if (ws.twin) ws.twin->plan_key.clear();
         return rc;
     }
+    // the overflow counter as of this render's end, read by a later render
+    GSR_HIP_TRY(hipMemcpyAsync(ws.h_total + 5, ctx->d_err + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     GSR_HIP_TRY(hipEventRecord(ws.ev_done, st));
     ws.used = true;
     ws.last_stream = st;
+    if (!async && !plain && !job.lidar && job.mode == Mode::kRender && !job.stop) {
+        // this render sized the list buffers of its shape: later ones may go asynchronously
+        ws.plan_key = shape;
+        if (two) ws.twin->plan_key = shape;
+    }
     return GSR_OK;
 }
 
@@ -886,6 +957,7 @@ GSR_EXPORT int gsr_create(int device, const gsr_options* opt, gsr_ctx** out)
         return fail(GSR_E_INVALID, "images_per_thread must be in 1..16");
     if (o.chunk_bytes < (int64_t)(64 << 20)) return fail(GSR_E_INVALID, "chunk_bytes must be >= 64 MiB");
     if (!(o.cutoff >= 1.0f && o.cutoff <= 8.0f)) return fail(GSR_E_INVALID, "cutoff must be in [1, 8]");
+    if (o.list_cap < 0) return fail(GSR_E_INVALID, "list_cap must be >= 0");
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || count == 0) return fail(GSR_E_DEVICE, "no HIP device available");
@@ -899,6 +971,7 @@ GSR_EXPORT int gsr_create(int device, const gsr_options* opt, gsr_ctx** out)
     if (!ctx) return fail(GSR_E_OOM, "context allocation failed");
     ctx->device = device;
     ctx->opt = o;
+    ctx->list_cap = (uint64_t)o.list_cap;
     ctx->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     int rc = noalloc_setup(device);
     if (!rc) {
@@ -1092,15 +1165,20 @@ GSR_EXPORT int gsr_stage_times(gsr_ctx* ctx, double* ms, int n, int reset)
     ms[5] = ctx->raster_launches;
     ms[6] = ctx->renders;
     if (n >= 10) {
-        ms[7] = ctx->count_visible;
-        ms[8] = ctx->count_pairs;
-        ms[9] = ctx->count_rows;
+        // device accumulators of every chunk's totals (since the last reset)
+        GSR_HIP_TRY(hipDeviceSynchronize());
+        unsigned long long acc[3];
+        GSR_HIP_TRY(hipMemcpy(acc, ctx->d_err + 16, sizeof acc, hipMemcpyDeviceToHost));
+        ms[7] = (double)(acc[0] - ctx->acc_base[0]);
+        ms[8] = (double)(acc[1] - ctx->acc_base[1]);
+        ms[9] = (double)(acc[2] - ctx->acc_base[2]);
     }
     if (reset) {
         for (double& v : ctx->stage_ms) v = 0.0;
         ctx->raster_launches = 0;
         ctx->renders = 0;
-        ctx->count_visible = ctx->count_pairs = ctx->count_rows = 0;
+        GSR_HIP_TRY(hipDeviceSynchronize());
+        GSR_HIP_TRY(hipMemcpy(ctx->acc_base, ctx->d_err + 16, sizeof ctx->acc_base, hipMemcpyDeviceToHost));
     }
     return GSR_OK;
 }

@@ -150,6 +150,14 @@ struct ChunkDev {
     uint2* rows;               // [total row entries] (Gaussian id, x0 | x1 << 16) per (row, depth)-sorted entry
     uint32_t* err;             // device word of the context: kErr* bits set by a kernel that meets an entry its
                                // inputs cannot contain (checked by the host at every chunk; poisons the context)
+    // List capacity of the chunk (entries of `pairs` and `rows`).  k_image_scan
+    // compares the chunk's totals with them and sets *ovf; an overflowed chunk
+    // writes no lists and is composited by the fallback rasteriser, which
+    // filters each tile's list from the depth-ordered Gaussians instead.
+    uint64_t cap_pairs, cap_rows;
+    uint32_t* ovf;             // device word of the workspace: 1 = this chunk's lists do not fit
+    uint32_t* ovf_count;       // device counter of the context: overflowed chunks so far
+    unsigned long long* acc;   // device accumulators of the context: visible Gaussians, pairs, row entries
 };
 
 // Bits of ChunkDev::err.
@@ -200,6 +208,10 @@ struct RasterParams {
 };
 hipError_t launch_raster_lidar(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream);
 hipError_t launch_raster(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream);
+// Fallback compositing of a chunk whose lists overflowed (a persistent grid
+// that exits at once when the chunk's lists fit); counter: kXcds words.
+hipError_t launch_raster_fallback(const SceneDev& s, const ChunkDev& c, const RasterParams& p, uint32_t* counter,
+                                  hipStream_t stream);
 
 // Scene upload: convert caller float32 attributes to resident storage.
 hipError_t launch_scene_convert(int storage, int64_t n, int64_t n_pad, int degree, const float* means,

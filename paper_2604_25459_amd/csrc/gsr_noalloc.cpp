@@ -50,11 +50,12 @@ NoallocDev* g_dev[kMaxDevices] = {};
 size_t align_up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
 
 // Bytes of the per-chunk buffers of a chunk of plan.chunk images (image
-// descriptions excluded), each 256-byte aligned, plus the raster counter.
+// descriptions excluded), each 256-byte aligned, plus the raster counters and
+// the overflow word.
 size_t chunk_fixed_bytes(const SceneRes* sc, const ChunkPlan& plan)
 {
     const WorkspaceSizes z = workspace_sizes(sc, plan, 0);
-    size_t b = kAlign;                // persistent-raster counter
+    size_t b = 3 * kAlign;            // persistent-raster counters and the chunk's overflow word
     for (int k = 0; k < z.count; ++k)
         if (z.b[k].buf != &Workspace::img) b += align_up(z.b[k].bytes);
     return b;
@@ -67,6 +68,10 @@ void carve(Workspace& ws, const SceneRes* sc, const ChunkPlan& plan, char* base,
     const WorkspaceSizes z = workspace_sizes(sc, plan, 0);
     char* p = base;
     ws.counter = {p, kAlign};
+    p += kAlign;
+    ws.counter2 = {p, kAlign};
+    p += kAlign;
+    ws.ovf = {p, kAlign};
     p += kAlign;
     for (int k = 0; k < z.count; ++k) {
         if (z.b[k].buf == &Workspace::img) continue;

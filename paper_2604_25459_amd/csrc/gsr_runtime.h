@@ -106,6 +106,14 @@ struct Workspace {
     bool fixed = false;
     char* list_base = nullptr;
     size_t list_bytes = 0;
+    // Asynchronous lists: after a synchronous render has sized the list buffers
+    // for a job shape (plan_key), renders of the same shape enqueue every
+    // chunk without reading its totals; the device flags a chunk whose lists
+    // would not fit (ovf) and composites it by the fallback rasteriser.
+    DevBuf ovf, counter2;                 // overflow word of the running chunk; fallback raster counters
+    std::vector<uint64_t> plan_key;       // job shape the list buffers were last sized for (empty: none)
+    std::vector<int> nseg_hint;           // level-2 segments per tile-row list, per chunk index, of that render
+    hipEvent_t ev_staged = nullptr;       // the image descriptions staged in h_img have been copied
     ~Workspace();
 };
 
@@ -172,7 +180,8 @@ WorkspaceSizes workspace_sizes(const SceneRes* sc, const ChunkPlan& p, size_t n_
 // descriptions already on the device); blocks until the chunk's list totals
 // are known.  `pairs_total` receives the chunk's pair count.
 int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, const ChunkPlan& plan, int i0,
-              int n_img, int chunk_idx, hipStream_t st, Mode mode, bool graph, uint64_t* pairs_total);
+              int n_img, int chunk_idx, hipStream_t st, Mode mode, bool graph, uint64_t* pairs_total,
+              bool async_lists = false);
 
 // Set-up of the allocation-free render path on `device` (the current device):
 // resolves the device address of its scratch array and allocates its pinned
@@ -207,9 +216,14 @@ struct gsr_ctx {
     std::vector<hipEvent_t> spare_events;             // read stage events, reused by later renders
     double stage_ms[5] = {0, 0, 0, 0, 0};
     double raster_launches = 0, renders = 0;
-    double count_visible = 0, count_pairs = 0, count_rows = 0;   // profiled renders
     std::atomic<bool> poisoned{false};
-    uint32_t* d_err = nullptr;                        // device consistency bits (ChunkDev::err), read at every chunk
+    uint32_t* d_err = nullptr;                        // device words: [0] consistency bits (ChunkDev::err), read
+                                                      // at every synchronous chunk; [1] overflowed chunks
+                                                      // (ChunkDev::ovf_count); from byte 64, three u64
+                                                      // accumulators (ChunkDev::acc)
+    uint32_t ovf_seen = 0;                            // overflow count the host has acted on
+    uint64_t list_cap = 0;                            // tests: list capacity (entries) of asynchronous chunks
+    unsigned long long acc_base[3] = {0, 0, 0};       // accumulator values at the last stage-timer reset
     std::map<std::string, gsr::Tuning> tuned;         // shape class -> launch parameters
     int cu_count = 256;
 };

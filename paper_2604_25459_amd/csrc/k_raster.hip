@@ -115,6 +115,14 @@ __device__ __forceinline__ float max_logalpha_rect(float a1, float b1, float c1,
     return lo - q;
 }
 
+// Fallback lists (a chunk whose tile lists do not fit their buffers): each
+// tile's list is the subsequence of its image's depth-ordered visible
+// Gaussians whose tile rectangle covers the tile -- the same sequence as the
+// tile list.  The workgroup filters kRowScan entries at a time into a ring of
+// kQueue ids, ahead of the batch being staged.
+constexpr int kQueue = 1024;
+constexpr int kRowScan = 512;
+
 template <int TS, int kBatch>
 struct RasterLds {
     float4 a[2][kBatch], b[2][kBatch], c[2][kBatch];    // staged records: (u, v, a1, b1), (c1, lo, z, r), rgb
@@ -129,10 +137,19 @@ struct RasterLds {
     uint32_t live[2][Layout<TS>::kWaves];
 };
 
-// Composites tile `bid` of the chunk (block id in segment order).
-template <int TS, int kBatch, bool COUNT>
+// Ring of the fallback lists: filtered ids and per-wave counts of one round.
+template <int TS>
+struct FilterLds {
+    uint32_t id[kQueue];
+    uint32_t wcount[kRowScan / Layout<TS>::kThreads][Layout<TS>::kWaves];
+};
+
+// Composites tile `bid` of the chunk (block id in segment order).  FILTER:
+// the tile's list is filtered on the fly from the image's depth-ordered
+// Gaussians (Q holds the ring); else it is read from the tile lists.
+template <int TS, int kBatch, bool COUNT, bool FILTER>
 __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c, const RasterParams& p, uint32_t bid,
-                                            RasterLds<TS, kBatch>& L_)
+                                            RasterLds<TS, kBatch>& L_, FilterLds<TS>* Q)
 {
     using L = Layout<TS>;
     constexpr int NT = L::kThreads;
@@ -190,9 +207,74 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         any_live = any_live || inside;
     }
 
-    const uint32_t* R = c.tile_range + ((size_t)i * c.t_max + t) * 2;
-    const uint32_t start = R[0], end = R[1];
-    const uint32_t* list = c.pairs + c.pair_base[i];
+    // tile list [start, end) of the pairs, or (FILTER) positions [0, qt) of the
+    // filtered list, qt growing as the depth-ordered list is filtered
+    uint32_t start = 0, end = 0;
+    const uint32_t* list = nullptr;
+    constexpr int F = kRowScan / NT;                   // entries per thread per filtering round
+    constexpr uint32_t QMASK = (uint32_t)kQueue - 1u;
+    static_assert(kBatch + kRowScan <= kQueue, "the ring must hold a batch and a filtering round");
+    const uint32_t* sv = nullptr;
+    uint32_t vend = 0, scan = 0, qt = 0;
+    uint32_t pre_g[F];
+    uint2 pre_r[F];
+    const size_t iseg = (size_t)i * (size_t)s.n;
+    auto load_round = [&]() {
+#pragma unroll
+        for (int k = 0; k < F; ++k) {
+            const uint32_t e = scan + (uint32_t)(k * NT + tid);
+            pre_g[k] = e < vend ? sv[iseg + e] : 0u;
+            pre_r[k] = e < vend ? raw_rect(c.srect, c.rect4, iseg + e) : make_uint2(0u, 0u);
+        }
+    };
+    if (FILTER) {
+        sv = c.sv[1];
+        vend = c.vis_count[i];
+        load_round();
+    } else {
+        const uint32_t* R = c.tile_range + ((size_t)i * c.t_max + t) * 2;
+        start = R[0];
+        end = R[1];
+        list = c.pairs + c.pair_base[i];
+    }
+    // Appends the depth-ordered Gaussians whose rectangle covers this tile to
+    // the ring, in order, until qt reaches `target` or the list ends; every
+    // round filters the entries loaded the round before and loads the next
+    // ones.  Block-uniform trip count (qt and scan are the same in every thread).
+    auto refill = [&](uint32_t target) {
+        while (qt < target && scan < vend) {
+            bool pk[F];
+            uint64_t bal[F];
+#pragma unroll
+            for (int k = 0; k < F; ++k) {
+                const uint32_t e = scan + (uint32_t)(k * NT + tid);
+                uint32_t x0, x1, y0, y1;
+                decode_rect(pre_r[k], c.rect4, &x0, &x1, &y0, &y1);
+                pk[k] = e < vend && x0 <= (uint32_t)tx && (uint32_t)tx < x1 && y0 <= (uint32_t)ty && (uint32_t)ty < y1;
+                bal[k] = __ballot(pk[k]);
+                if (lane == 0) Q->wcount[k][w] = (uint32_t)__popcll(bal[k]);
+            }
+            __syncthreads();
+            // entries in (round k, thread) order, which is the list order
+            uint32_t base = qt;
+#pragma unroll
+            for (int k = 0; k < F; ++k) {
+                uint32_t below = 0, tot = 0;
+#pragma unroll
+                for (int ww = 0; ww < L::kWaves; ++ww) {
+                    const uint32_t v = Q->wcount[k][ww];
+                    below += ww < w ? v : 0u;
+                    tot += v;
+                }
+                if (pk[k]) Q->id[(base + below + lanes_below(bal[k])) & QMASK] = pre_g[k];
+                base += tot;
+            }
+            qt = base;
+            scan += (uint32_t)kRowScan;
+            load_round();
+            __syncthreads();
+        }
+    };
     const float4* rec = c.rec + (size_t)i * (size_t)s.n * 3;
     const uint32_t n = (uint32_t)s.n;
 
@@ -204,8 +286,8 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         for (int q = 0; q < PER_THREAD; ++q) {
             const uint32_t slot = (uint32_t)(q * NT + tid);
             const uint32_t e = b0 + slot;
-            if (slot < (uint32_t)kBatch && e < end) {
-                uint32_t g = list[e];
+            if (slot < (uint32_t)kBatch && e < (FILTER ? qt : end)) {
+                uint32_t g = FILTER ? Q->id[e & QMASK] : list[e];
                 if (g >= n) {           // impossible by construction: reported at the end, a valid record read
                     bad_entry = true;
                     g = 0;
@@ -216,7 +298,8 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             }
         }
     };
-    if (start < end) fetch(start);
+    if (FILTER) refill((uint32_t)kBatch);
+    if (start < (FILTER ? qt : end)) fetch(start);
     int buf = 0;
     bool wave_live = __ballot(any_live) != 0ull;
     // pixel-centre rectangle still to be shaded (the live pixels' bounding
@@ -224,7 +307,7 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
     float lx0 = wx0, lx1 = wx1, ly0 = wy0, ly1 = wy1;
     uint64_t live_seen = 0;
 
-    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+    for (uint32_t b0 = start; b0 < (FILTER ? qt : end); b0 += kBatch) {
 #pragma unroll
         for (int q = 0; q < PER_THREAD; ++q) {
             const int slot = q * NT + tid;
@@ -243,8 +326,11 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
             for (int ww = 0; ww < L::kWaves; ++ww) any |= L_.live[buf ^ 1][ww];
             if (!any) break;
         }
-        if (b0 + kBatch < end) fetch(b0 + kBatch);
-        const int cnt = (int)min((uint32_t)kBatch, end - b0);
+        // the batch at b0 is staged: its ring slots may be reused
+        if (FILTER) refill(b0 + 2u * (uint32_t)kBatch);
+        const uint32_t lim = FILTER ? qt : end;
+        if (b0 + kBatch < lim) fetch(b0 + kBatch);
+        const int cnt = (int)min((uint32_t)kBatch, lim - b0);
         for (int sub = 0; sub < cnt && wave_live; sub += 64) {
             if (PPT == 1) {
                 const uint64_t M = __ballot(xl[0] < kDeadTest);  // lane = 8 * row + column
@@ -404,7 +490,7 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         im.out_depth[pix] = T[k] < 1.0f ? D[k] / (1.0f - T[k]) : 0.0f;
         if (im.out_alpha) im.out_alpha[pix] = 1.0f - T[k];
         if (COUNT && im.out_work) {
-            im.out_work[2 * pix] = stop_at[k] != 0xFFFFFFFFu ? stop_at[k] : end - start;
+            im.out_work[2 * pix] = stop_at[k] != 0xFFFFFFFFu ? stop_at[k] : (FILTER ? qt : end - start);
             im.out_work[2 * pix + 1] = blended[k];
         }
     }
@@ -415,7 +501,8 @@ template <int TS, int kBatch, bool COUNT>
 __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster(SceneDev s, ChunkDev c, RasterParams p)
 {
     __shared__ RasterLds<TS, kBatch> lds;
-    raster_tile<TS, kBatch, COUNT>(s, c, p, xcd_remap(blockIdx.x, gridDim.x), lds);
+    if (*c.ovf) return;                 // no tile lists: the fallback composites this chunk
+    raster_tile<TS, kBatch, COUNT, false>(s, c, p, xcd_remap(blockIdx.x, gridDim.x), lds, nullptr);
 }
 
 // Persistent workgroups.  The tiles are split into one contiguous range per
@@ -430,6 +517,7 @@ __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster_persistent(Scen
 {
     __shared__ RasterLds<TS, kBatch> lds;
     __shared__ uint32_t next;
+    if (*c.ovf) return;                 // no tile lists: the fallback composites this chunk
     const uint32_t parts = gridDim.x < (uint32_t)kXcds ? gridDim.x : (uint32_t)kXcds;
     const uint32_t x = blockIdx.x % (uint32_t)kXcds;       // < parts
     const uint32_t q = p.n_blocks / parts, r = p.n_blocks % parts;
@@ -440,7 +528,35 @@ __global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster_persistent(Scen
         const uint32_t k = next;
         __syncthreads();
         if (k >= count) break;
-        raster_tile<TS, kBatch, COUNT>(s, c, p, first + k, lds);
+        raster_tile<TS, kBatch, COUNT, false>(s, c, p, first + k, lds, nullptr);
+        __syncthreads();
+    }
+}
+
+// Fallback compositing of an overflowed chunk: persistent workgroups take the
+// chunk's tiles from per-XCD counters (as k_raster_persistent) and filter
+// each tile's list from the depth-ordered Gaussians.  Exits at once when the
+// chunk's lists fit.
+template <int TS, bool COUNT>
+__global__ __launch_bounds__(Layout<TS>::kThreads) void k_raster_fallback(SceneDev s, ChunkDev c, RasterParams p,
+                                                                          uint32_t* counter)
+{
+    constexpr int kB = 64;
+    __shared__ RasterLds<TS, kB> lds;
+    __shared__ FilterLds<TS> ring;
+    __shared__ uint32_t next;
+    if (!*c.ovf) return;
+    const uint32_t parts = gridDim.x < (uint32_t)kXcds ? gridDim.x : (uint32_t)kXcds;
+    const uint32_t x = blockIdx.x % (uint32_t)kXcds;       // < parts
+    const uint32_t q = p.n_blocks / parts, r = p.n_blocks % parts;
+    const uint32_t first = x * q + (x < r ? x : r), count = q + (x < r ? 1u : 0u);
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(&counter[x], 1u);
+        __syncthreads();
+        const uint32_t k = next;
+        __syncthreads();
+        if (k >= count) break;
+        raster_tile<TS, kB, COUNT, true>(s, c, p, first + k, lds, &ring);
         __syncthreads();
     }
 }
@@ -486,6 +602,29 @@ hipError_t launch_batch(const SceneDev& s, const ChunkDev& c, const RasterParams
 }
 
 }  // namespace
+
+hipError_t launch_raster_fallback(const SceneDev& s, const ChunkDev& c, const RasterParams& p, uint32_t* counter,
+                                  hipStream_t stream)
+{
+    if (p.n_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, counter);
+    const uint32_t grid = std::min<uint32_t>(p.n_blocks, (uint32_t)p.persistent_blocks);
+    switch (p.ts) {
+    case 8:
+        if (p.count_work) hipLaunchKernelGGL((k_raster_fallback<8, true>), dim3(grid), dim3(64), 0, stream, s, c, p, counter);
+        else hipLaunchKernelGGL((k_raster_fallback<8, false>), dim3(grid), dim3(64), 0, stream, s, c, p, counter);
+        break;
+    case 32:
+        if (p.count_work) hipLaunchKernelGGL((k_raster_fallback<32, true>), dim3(grid), dim3(256), 0, stream, s, c, p, counter);
+        else hipLaunchKernelGGL((k_raster_fallback<32, false>), dim3(grid), dim3(256), 0, stream, s, c, p, counter);
+        break;
+    default:
+        if (p.count_work) hipLaunchKernelGGL((k_raster_fallback<16, true>), dim3(grid), dim3(256), 0, stream, s, c, p, counter);
+        else hipLaunchKernelGGL((k_raster_fallback<16, false>), dim3(grid), dim3(256), 0, stream, s, c, p, counter);
+        break;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_raster(const SceneDev& s, const ChunkDev& c, const RasterParams& p, hipStream_t stream)
 {

@@ -318,6 +318,7 @@ __global__ __launch_bounds__(256) void k_image_scan(ChunkDev c)
     part[1][tid] = sr;
     part[2][tid] = sv;
     __syncthreads();
+    __shared__ uint64_t tot[3];
     if (tid < 3) {
         uint64_t run = 0;
         for (int k = 0; k < 256; ++k) {
@@ -325,11 +326,18 @@ __global__ __launch_bounds__(256) void k_image_scan(ChunkDev c)
             part[tid][k] = run;
             run += v;
         }
+        tot[tid] = run;
         if (tid == 0) c.pair_base[c.n_img] = run;
         else if (tid == 1) c.row_base[c.n_img] = run;
         else c.pair_base[c.n_img + 1] = run;
+        atomicAdd(&c.acc[tid == 2 ? 0 : tid + 1], (unsigned long long)run);   // visible, pairs, row entries
     }
     __syncthreads();
+    if (tid == 0) {
+        const uint32_t over = tot[0] > c.cap_pairs || tot[1] > c.cap_rows ? 1u : 0u;
+        *c.ovf = over;
+        if (over) atomicAdd(c.ovf_count, 1u);
+    }
     uint64_t rp = part[0][tid], rr = part[1][tid];
     for (int k = 0; k < per; ++k) {
         const int i = tid * per + k;
@@ -359,6 +367,7 @@ __host__ __device__ constexpr size_t expand_lds_words(int buckets)
 
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c, uint64_t n)
 {
+    if (*c.ovf) return;                 // the chunk's lists do not fit: no lists (fallback raster)
     extern __shared__ uint32_t lds[];
     const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
     uint32_t* mine = lds + (size_t)wv * expand_lds_words(c.ty_max);
@@ -442,6 +451,7 @@ __device__ __forceinline__ void segment_of(uint32_t r0, uint32_t r1, int sg, int
 
 __global__ __launch_bounds__(64) void k_rowseg_count(ChunkDev c, int n_seg, uint32_t* __restrict__ seg_off)
 {
+    if (*c.ovf) return;                 // the chunk's lists do not fit: no lists (fallback raster)
     extern __shared__ int32_t diff[];       // [TX + 1]
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), bx = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
@@ -477,6 +487,7 @@ __global__ __launch_bounds__(64) void k_rowseg_count(ChunkDev c, int n_seg, uint
 
 __global__ __launch_bounds__(64) void k_rowseg_scan(ChunkDev c, int n_seg, uint32_t* __restrict__ seg_off)
 {
+    if (*c.ovf) return;                 // the chunk's lists do not fit: no lists (fallback raster)
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), y = (int)(L - (uint32_t)i * gridDim.x), lane = __lane_id();
     const ImageInfo im = c.img[i];
@@ -499,6 +510,7 @@ __global__ __launch_bounds__(64) void k_rowseg_scan(ChunkDev c, int n_seg, uint3
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDev c, int n_seg,
                                                                          const uint32_t* __restrict__ seg_off)
 {
+    if (*c.ovf) return;                 // the chunk's lists do not fit: no lists (fallback raster)
     extern __shared__ uint32_t lds[];
     const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
     uint32_t* mine = lds + (size_t)wv * expand_lds_words(c.tx_max);
@@ -630,6 +642,7 @@ __device__ __forceinline__ uint64_t transpose_bits64(uint64_t w)
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_transpose(ChunkDev c, int n_seg, int n_cc,
                                                                            const uint32_t* __restrict__ seg_off)
 {
+    if (*c.ovf) return;                 // the chunk's lists do not fit: no lists (fallback raster)
     __shared__ uint32_t gs_all[kWavesPerBlock][64];
     const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
     uint32_t* gs = gs_all[wv];

@@ -35,7 +35,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 class Options(C.Structure):
     _fields_ = [("tile_size", C.c_int), ("images_per_thread", C.c_int), ("chunk_bytes", C.c_int64),
                 ("cutoff", C.c_float), ("profile", C.c_int), ("graphs", C.c_int), ("overlap", C.c_int),
-                ("reserved", C.c_int * 5)]
+                ("sync_lists", C.c_int), ("list_cap", C.c_int), ("reserved", C.c_int * 3)]
 
 
 class TuningDesc(C.Structure):
@@ -216,10 +216,12 @@ class Renderer:
     """One libgsr context on a device."""
 
     def __init__(self, device: int = 0, tile_size: int = 16, images_per_thread: int = 4, chunk_bytes: int = 0,
-                 cutoff: float = 0.0, profile: bool = False, graphs: bool = True, overlap: bool = True):
+                 cutoff: float = 0.0, profile: bool = False, graphs: bool = True, overlap: bool = True,
+                 sync_lists: bool = False, list_cap: int = 0):
         lib = load()
         opt = Options(tile_size=tile_size, images_per_thread=images_per_thread, chunk_bytes=chunk_bytes,
-                      cutoff=cutoff, profile=int(profile), graphs=0 if graphs else -1, overlap=0 if overlap else -1)
+                      cutoff=cutoff, profile=int(profile), graphs=0 if graphs else -1, overlap=0 if overlap else -1,
+                      sync_lists=-1 if sync_lists else 0, list_cap=int(list_cap))
         h = C.c_void_p()
         _check(lib.gsr_create(device, C.byref(opt), C.byref(h)))
         self._h = h

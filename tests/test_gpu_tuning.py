@@ -1,5 +1,7 @@
 """hipGraph replay and autotuned launch parameters change no pixel: every
 replay and every parameter set gives the bits of the eager default render."""
+import time
+
 import numpy as np
 import pytest
 
@@ -213,4 +215,68 @@ def test_transposed_schedule_on_a_wide_image():
             np.testing.assert_array_equal(got["ranges"], ref.ranges)
     for a, b in zip(outs[0][0], outs[1][0]):
         assert torch.equal(a, b)
+    R.close()
+
+
+def test_async_render_returns_before_the_device_finishes():
+    """After a render that sizes the tile lists of a job shape, renders of that
+    shape enqueue every chunk without waiting for its totals: the call returns
+    while the device still works, and the images equal a render that waits at
+    every chunk."""
+    torch = _torch()
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(2, n_envs=512)
+    Ra = gsr.Renderer(0)
+    Rs = gsr.Renderer(0, sync_lists=True)
+    sa, ss = Ra.add_synth_scene(scene), Rs.add_synth_scene(scene)
+    cams, vm, _ = gsr.batch_tensors(batch)
+    dev = vm.device
+    rgb_a, depth_a, _ = Ra.alloc_outputs(cams, 512)
+    rgb_s, depth_s, _ = Rs.alloc_outputs(cams, 512)
+    stream = torch.cuda.current_stream(dev)
+    for step in range(3):
+        poses = torch.from_numpy(synth.make_poses(2, step, 512, scene.n_bodies)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Ra.render_into(sa, cams, vm, poses, rgb_a, depth_a)
+        t_call = time.perf_counter() - t0
+        pending = not stream.query()
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t0
+        print(f"step {step}: call {1e3 * t_call:.2f} ms, render {1e3 * t_all:.2f} ms, pending {pending}", flush=True)
+        if step > 0:                   # step 0 plans the lists (waits at every chunk)
+            assert pending and t_call < 0.5 * t_all
+        Rs.render_into(ss, cams, vm, poses, rgb_s, depth_s)
+        torch.cuda.synchronize()
+        assert torch.equal(rgb_a, rgb_s) and torch.equal(depth_a, depth_s), f"step {step}"
+    Ra.close()
+    Rs.close()
+
+
+def test_list_overflow_falls_back_with_identical_bits():
+    """Asynchronous chunks whose tile lists exceed a small capacity set from
+    the host write no lists; the fallback rasteriser composites them from the
+    depth-ordered Gaussians, and images and work counts equal the planned
+    render's bit for bit (two camera sizes, chunks on two streams)."""
+    torch = _torch()
+    from paper_2604_25459_amd import gsr
+    scene, batch = synth.make_config(3, n_envs=6)
+    R = gsr.Renderer(0, list_cap=2000)
+    sid = R.add_synth_scene(scene)
+    cams, vm, poses = gsr.batch_tensors(batch)
+    R.set_tuning(sid, cams, vm, poses, chunk_images=4)     # three chunks, alternating streams
+    rgb, depth, alpha = R.alloc_outputs(cams, 6, alpha=True)
+    npx = rgb.numel() // 3
+    work = torch.zeros(npx * 2, dtype=torch.int32, device=rgb.device)
+    R.render_into(sid, cams, vm, poses, rgb, depth, alpha, work=work)      # plans the lists
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (rgb, depth, alpha, work)]
+    for k in range(3):
+        for t in (rgb, depth, alpha):
+            t.fill_(float("nan"))
+        work.fill_(-1)
+        R.render_into(sid, cams, vm, poses, rgb, depth, alpha, work=work)  # overflows into the fallback
+        torch.cuda.synchronize()
+        for a, b in zip(ref, (rgb, depth, alpha, work)):
+            assert torch.equal(a, b), f"render {k}"
     R.close()
