@@ -71,8 +71,9 @@ typedef struct gsr_server gsr_server;
 typedef struct {
     int tile_size;          /* 8, 16 or 32 pixels; 0 = 16 */
     int images_per_thread;  /* images one projection thread handles (1..16); 0 = 4 */
-    int64_t chunk_bytes;    /* device working-memory budget per render chunk; 0 = 24 GiB (with `overlap` on, a
-                               render of several chunks holds two such working sets) */
+    int64_t chunk_bytes;    /* device working-memory budget per render chunk; 0 = 48 GiB, and never above 40 % of
+                               the device memory free when a render is planned (with `overlap` on, a render of
+                               several chunks holds two such working sets); chunks of a render are of equal size */
     float cutoff;           /* splat radius in standard deviations; 0 = 3.33 (conservative for alpha >= 1/255) */
     int profile;            /* 1 = record HIP events around every pipeline stage (see gsr_stage_times) */
     int graphs;             /* 0 = capture the per-chunk stages of gsr_render into hipGraphs and replay them

@@ -261,8 +261,19 @@ ChunkPlan plan_chunks(const gsr_ctx* ctx, const SceneRes* sc, const std::vector<
         p.chunk = 1;
     } else {
         const size_t per = per_image_bytes(sc, p.t_max, p.ty_max, p.sort_blocks, p.tile_blocks, rec_bytes);
-        size_t c = std::max<size_t>(1, budget / std::max<size_t>(per, 1));
+        size_t cap = budget;
+        if (per * imgs.size() > cap) {
+            // a job larger than one chunk: keep a chunk's working set (two with the
+            // second stream) within 40 % of the device memory free now
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
+                cap = std::min<size_t>(cap, std::max<size_t>(free_b / 5 * 2, (size_t)1 << 30));
+        }
+        size_t c = std::max<size_t>(1, cap / std::max<size_t>(per, 1));
         if (chunk_images > 0) c = std::min<size_t>(c, (size_t)chunk_images);
+        // as many chunks as the budget needs, of equal size (no short last chunk)
+        const size_t n_chunks = (imgs.size() + c - 1) / c;
+        c = (imgs.size() + n_chunks - 1) / n_chunks;
         p.chunk = (int)std::min<size_t>(c, imgs.size());
     }
     return p;
@@ -949,7 +960,7 @@ GSR_EXPORT int gsr_create(int device, const gsr_options* opt, gsr_ctx** out)
     if (opt) o = *opt;
     if (o.tile_size == 0) o.tile_size = 16;
     if (o.images_per_thread == 0) o.images_per_thread = 4;
-    if (o.chunk_bytes == 0) o.chunk_bytes = (int64_t)24 << 30;
+    if (o.chunk_bytes == 0) o.chunk_bytes = (int64_t)48 << 30;
     if (o.cutoff == 0.0f) o.cutoff = 3.33f;
     if (o.tile_size != 8 && o.tile_size != 16 && o.tile_size != 32)
         return fail(GSR_E_INVALID, "tile_size must be 8, 16 or 32");
