@@ -81,6 +81,9 @@ def pmc_summary(fetch_csv, write_csv, out_path, command):
         out[f"{key}_dispatches"] = len(rast)
         out[f"{key}_bytes_per_launch"] = sum(rast) / len(rast) * 1024.0 * factor
     out["traffic_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    # the counted command renders one step of the 2048-image default workload:
+    # its rasteriser launches each cover this many images
+    out["images_per_launch"] = 2048 / out["fetch_dispatches"]
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
@@ -146,15 +149,18 @@ def measured_util():
     return {k: s[k] for k in ("valu_busy", "lds_busy", "lds_read_gbs", "lds_peak_gbs", "lds_read_frac", "clock_ghz")}
 
 
-def measured_traffic(tuning):
+def measured_traffic(tuning, images_per_launch):
     """HBM bytes per rasteriser launch from the committed counter summary, or
-    None when it was taken on other rasteriser sources or launch parameters."""
+    None when it was taken on other rasteriser sources, launch parameters or
+    launch sizes."""
     path = os.path.join(ROOT, PMC_SUMMARY)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         s = json.load(f)
     if s.get("source_sha256") != raster_source_hash():
+        return None
+    if s.get("images_per_launch") is None or abs(s["images_per_launch"] - images_per_launch) > 0.5:
         return None
     if tuning is not None and s.get("tuning") is not None:
         # only the launch parameters of the rasteriser itself matter here
@@ -623,7 +629,7 @@ def main():
         launches_per_step = st["raster_launches"] / args.steps
         flops_launch = flops_step / launches_per_step
         achieved = flops_launch / (raster_ms * 1e-3) / 1e12
-        traffic = measured_traffic(tuning)
+        traffic = measured_traffic(tuning, E * C / launches_per_step)
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
