@@ -580,9 +580,11 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
         total = ws.h_total[0];
         row_total = ws.h_total[1];
         *pairs_total = total;
-        // long tile-row lists are split into segments of about kRowSegEntries entries (one wave each)
+        // segments per tile-row list: enough level-2 waves for the launch, none shorter than kRowSegEntries
         const uint64_t per_row = n_rows ? row_total / n_rows : 0;
-        n_seg = (int)std::min<uint64_t>(32, std::max<uint64_t>(1, (per_row + kRowSegEntries - 1) / kRowSegEntries));
+        const uint64_t by_len = std::max<uint64_t>(1, per_row / kRowSegEntries);
+        const uint64_t by_waves = n_rows ? ((uint64_t)kLevel2Waves + n_rows - 1) / n_rows : 1;
+        n_seg = (int)std::min<uint64_t>(32, std::min(by_len, by_waves));
         if ((int)ws.nseg_hint.size() <= chunk_idx) ws.nseg_hint.resize((size_t)chunk_idx + 1, 1);
         ws.nseg_hint[chunk_idx] = n_seg;
     }

@@ -171,8 +171,13 @@ constexpr int kSortIpt = 16;
 constexpr int kSortItems = kSortBlock * kSortIpt;   // 4096 items per block
 // Tile pass geometry: one wave per block, kTileGauss depth-ordered Gaussians per block.
 constexpr int kTileGauss = 4096;
-// Target length of one level-2 segment of a tile-row list (one wave each).
+// Level 2 runs one wave per (image, tile row, segment).  Tile-row lists are
+// cut into segments only as far as the launch needs to have about
+// kLevel2Waves waves, and never into segments shorter than kRowSegEntries:
+// every extra segment costs a per-segment count pass over its entries, and
+// many short waves crowd out a rasteriser running beside them.
 constexpr int kRowSegEntries = 1024;
+constexpr int kLevel2Waves = 16384;
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `stream` and return hipGetLastError().

@@ -72,13 +72,17 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ 
     h[tid] = 0;
     __syncthreads();
     const uint32_t* kin = keys + (size_t)i * n;
+    // all loads first, then the LDS atomics: each thread's loads overlap
+    uint32_t key[kSortIpt];
 #pragma unroll
     for (int k = 0; k < kSortIpt; ++k) {
         const uint64_t idx = base + (uint64_t)k * 256 + tid;
-        if (idx < cnt) {
-            const uint32_t key = kin[idx];
-            if (!FIRST || key != kInvalidKey) atomicAdd(&h[(key >> shift) & 255u], 1u);
-        }
+        key[k] = idx < cnt ? kin[idx] : kInvalidKey;
+    }
+#pragma unroll
+    for (int k = 0; k < kSortIpt; ++k) {
+        const uint64_t idx = base + (uint64_t)k * 256 + tid;
+        if (idx < cnt && (!FIRST || key[k] != kInvalidKey)) atomicAdd(&h[(key[k] >> shift) & 255u], 1u);
     }
     __syncthreads();
     hist[((size_t)i * blocks + b) * 256 + tid] = h[tid];
@@ -100,10 +104,62 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
     uint32_t total;
     uint32_t run = block_excl_scan256(tot, &total, lds8);
     if (FIRST && d == 0) counts[i] = total;
-    for (int b = 0; b < nb; ++b) {
-        const uint32_t v = H[(size_t)b * 256 + d];
-        H[(size_t)b * 256 + d] = run;
-        run += v;
+    // offsets in place, 16 blocks at a time: the loads of a group are all
+    // complete (one wait) before its stores
+    for (int b0 = 0; b0 < nb; b0 += 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = b0 + q < nb ? H[(size_t)(b0 + q) * 256 + d] : 0u;
+        __builtin_amdgcn_s_waitcnt(0x0F70);     // vmcnt(0)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (b0 + q < nb) H[(size_t)(b0 + q) * 256 + d] = run;
+            run += v[q];
+        }
+    }
+}
+
+// Write-out of the last pass: the values, and each Gaussian's tile rectangle
+// gathered by its id into depth order.  Every gather of a thread is issued
+// before its first store, so the loads (random ids, mostly L2 hits) overlap
+// instead of each waiting out its own latency.  The final keys are not read
+// again and are not written.
+template <typename R>
+__device__ __forceinline__ void write_last(const uint32_t* skey, const uint32_t* sval, const uint32_t* lstart,
+                                           const uint32_t* gbase, uint32_t n_items, int shift, uint64_t n, size_t seg,
+                                           uint32_t* __restrict__ vout, const R* __restrict__ rect,
+                                           R* __restrict__ srect, uint32_t* __restrict__ err)
+{
+    constexpr int kPer = kSortItems / 256;
+    const uint32_t tid = threadIdx.x;
+    uint32_t pos[kPer], val[kPer];
+    R r[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t t = tid + 256u * (uint32_t)q;
+        pos[q] = 0xFFFFFFFFu;
+        val[q] = 0u;
+        r[q] = R{};
+        if (t < n_items) {
+            const uint32_t k = skey[t], v = sval[t];
+            const uint32_t dg = (k >> shift) & 255u;
+            const uint32_t p = gbase[dg] + (t - lstart[dg]);
+            if (p >= n) atomicOr(err, kErrSortSlot);     // offsets are consistent by construction
+            if (p < n) {
+                pos[q] = p;
+                val[q] = v;
+                if (v < n) r[q] = rect[seg + v];
+            }
+        }
+    }
+    // one wait for all of them (vmcnt(0); the compiler would otherwise wait
+    // before each store, as loads and stores share the counter)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        if (pos[q] == 0xFFFFFFFFu) continue;
+        vout[seg + pos[q]] = val[q];
+        if (val[q] < n) srect[seg + pos[q]] = r[q];
     }
 }
 
@@ -184,18 +240,20 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
     __syncthreads();
     // write out in block-local order: consecutive threads write consecutive
     // addresses inside each digit's run
+    if (LAST) {
+        if (rect4) write_last(skey, sval, lstart, gbase, n_items, shift, n, seg, vout,
+                              reinterpret_cast<const uint32_t*>(rect), reinterpret_cast<uint32_t*>(srect), err);
+        else write_last(skey, sval, lstart, gbase, n_items, shift, n, seg, vout, rect, srect, err);
+        return;
+    }
     for (uint32_t t = (uint32_t)tid; t < n_items; t += 256u) {
         const uint32_t k = skey[t], v = sval[t];
         const uint32_t dg = (k >> shift) & 255u;
         const uint32_t pos = gbase[dg] + (t - lstart[dg]);
         if (pos >= n) atomicOr(err, kErrSortSlot);     // offsets are consistent by construction
         if (pos < n) {
-            if (!LAST) kout[seg + pos] = k;     // the final keys are not read again
+            kout[seg + pos] = k;
             vout[seg + pos] = v;
-            if (LAST && v < n) {
-                if (rect4) reinterpret_cast<uint32_t*>(srect)[seg + pos] = reinterpret_cast<const uint32_t*>(rect)[seg + v];
-                else srect[seg + pos] = rect[seg + v];
-            }
         }
     }
 }

@@ -129,16 +129,6 @@ __device__ __forceinline__ void expand_group(ExpandLds& ex, uint64_t* occ, uint3
     }
 }
 
-// Tile rectangle (x0, x1, y0, y1) of the depth-ordered Gaussian j of image i.
-__device__ __forceinline__ bool sorted_rect(const ChunkDev& c, uint64_t n, int i, uint32_t j, uint32_t j1,
-                                            uint32_t* x0, uint32_t* x1, uint32_t* y0, uint32_t* y1)
-{
-    *x0 = *x1 = *y0 = *y1 = 0;
-    if (j >= j1) return false;
-    decode_rect(raw_rect(c.srect, c.rect4, (size_t)i * n + j), c.rect4, x0, x1, y0, y1);
-    return *x1 > *x0 && *y1 > *y0;
-}
-
 // ------------------------------------------------------------------ counts
 // A Gaussian adds one to every tile of its rectangle [x0, x1) x [y0, y1) and
 // one to every tile row [y0, y1).  Both are written as difference arrays --
@@ -171,10 +161,19 @@ __global__ __launch_bounds__(256) void k_tile_hist(ChunkDev c, uint64_t n)
     for (int t = tid; t < D; t += 256) diff[t] = 0;
     for (int y = tid; y < Q1; y += 256) rdiff[y] = 0;
     __syncthreads();
-    for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += 256) {
+    // all of the thread's rectangle loads first, then the LDS atomics
+    constexpr int kPer = kTileGauss / 256;
+    uint2 rr[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t j = j0 + (uint32_t)tid + 256u * (uint32_t)q;
+        rr[q] = j < j1 ? raw_rect(c.srect, c.rect4, (size_t)i * n + j) : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
         uint32_t x0, x1, y0, y1;
-        if (sorted_rect(c, n, i, j, j1, &x0, &x1, &y0, &y1) && x1 <= (uint32_t)im.tiles_x &&
-            y1 <= (uint32_t)im.tiles_y) {
+        decode_rect(rr[q], c.rect4, &x0, &x1, &y0, &y1);     // an empty rectangle past j1
+        if (x1 > x0 && y1 > y0 && x1 <= (uint32_t)im.tiles_x && y1 <= (uint32_t)im.tiles_y) {
             atomicAdd(&diff[y0 * P1 + x0], 1);
             atomicAdd(&diff[y0 * P1 + x1], -1);
             atomicAdd(&diff[y1 * P1 + x0], -1);
@@ -236,11 +235,19 @@ __device__ uint32_t scan_bins(uint32_t* H, int nb, int stride, int nbins, uint32
             range[2 * t] = start;
             range[2 * t + 1] = start + tot;
             if (block_offsets) {
+                // 16 blocks at a time: a group's loads all complete (one
+                // wait) before its stores
                 uint32_t o = start;
-                for (int b = 0; b < nb; ++b) {
-                    const uint32_t v = H[(size_t)b * stride + t];
-                    H[(size_t)b * stride + t] = o;
-                    o += v;
+                for (int b0 = 0; b0 < nb; b0 += 16) {
+                    uint32_t v[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) v[q] = b0 + q < nb ? H[(size_t)(b0 + q) * stride + t] : 0u;
+                    __builtin_amdgcn_s_waitcnt(0x0F70);     // vmcnt(0)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        if (b0 + q < nb) H[(size_t)(b0 + q) * stride + t] = o;
+                        o += v[q];
+                    }
                 }
             }
         }
@@ -465,12 +472,21 @@ __global__ __launch_bounds__(64) void k_rowseg_count(ChunkDev c, int n_seg, uint
     uint32_t s0, s1;
     segment_of(rr[0], rr[1], sg, n_seg, &s0, &s1);
     const uint2* list = c.rows + c.row_base[i];
-    for (uint32_t e = s0 + (uint32_t)lane; e < s1; e += 64) {
-        const uint32_t xr = list[e].y;
-        const uint32_t x0 = min(xr & 0xFFFFu, (uint32_t)TX), x1 = min(xr >> 16, (uint32_t)TX);
-        if (x1 > x0) {
-            atomicAdd(&diff[x0], 1);
-            atomicAdd(&diff[x1], -1);
+    // eight loads per lane in flight, then their LDS atomics
+    for (uint32_t e0 = s0; e0 < s1; e0 += 64u * 8u) {
+        uint32_t xr[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t e = e0 + 64u * (uint32_t)q + (uint32_t)lane;
+            xr[q] = e < s1 ? list[e].y : 0u;            // past s1: an empty range
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t x0 = min(xr[q] & 0xFFFFu, (uint32_t)TX), x1 = min(xr[q] >> 16, (uint32_t)TX);
+            if (x1 > x0) {
+                atomicAdd(&diff[x0], 1);
+                atomicAdd(&diff[x1], -1);
+            }
         }
     }
     __syncthreads();
