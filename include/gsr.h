@@ -429,8 +429,8 @@ typedef struct {
     int persistent;         /* 0 or 1 */
     int chunk_images;       /* 0 = from chunk_bytes, else images per memory chunk */
     float ms;               /* out: time of one render with these parameters (gsr_autotune) */
-    int bin_schedule;       /* tile lists from tile-row lists: 0 stable scatter (one wave per row),
-                               1 gather (one lane per tile column); identical lists */
+    int bin_schedule;       /* tile-row and tile lists: 0 by stable expansion (ranks from LDS lane masks),
+                               1 by transposed ranks (one lane per bucket); identical lists */
     int reserved[3];
 } gsr_tuning;
 

@@ -193,9 +193,10 @@ hipError_t launch_tile_count(const SceneDev& s, const ChunkDev& c, hipStream_t s
 hipError_t launch_project_lidar(const SceneDev& s, const ChunkDev& c, int ts, int ipt, hipStream_t stream);
 
 // Stable two-level scatter: depth-ordered Gaussians -> tile-row lists -> tile lists.
-// schedule 0: level 2 as a stable expansion (one wave per row segment, ranks
-// from per-bucket lane masks); 1: by a bit transpose (one lane per tile column
-// appends the group entries that cover it).  Both give identical tile lists.
+// schedule 0: both levels as stable expansions (two slots per lane, ranks
+// from per-bucket lane masks); 1: by transposed ranks (a 64 x 64 bit transpose
+// gives each bucket lane its items, each item places itself in its buckets).
+// Both give identical lists.
 // n_seg: segments per tile-row list (seg_off: n_img * ty_max * n_seg * tx_max
 // words of scratch when n_seg > 1).
 hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedule, int n_seg, uint32_t* seg_off,

@@ -62,7 +62,7 @@ struct Tuning {
     int ipt = 4;            // images per projection thread
     int persistent = 0;     // persistent raster workgroups
     int chunk_images = 0;   // images per memory chunk (0 = from the memory budget)
-    int bin = 0;            // tile-list schedule: 0 stable scatter, 1 gather
+    int bin = 1;            // tile-list schedule: 0 stable expansion, 1 transposed ranks
     float ms = 0.0f;        // measured step time when tuned
 };
 

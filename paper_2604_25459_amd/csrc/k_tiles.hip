@@ -593,15 +593,24 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDe
     }
 }
 
-// ------------------------------------------------------ level 2, bit transpose
-// One wave per (image, tile row, segment, 64 tile columns).  The row list is
-// read 64 entries at a time (lane = entry, in list order).  Each lane turns
-// its entry's x-range into a 64-bit mask over the wave's columns; a 64 x 64
-// bit transpose across the lanes (six butterfly stages) then leaves in lane x
-// the set of group entries that cover column x, in list order.  Lane x appends
-// them to its own tile list at a cursor held in a register, so every tile list
-// keeps the row list's (depth, index) order: the same lists as the stable
-// scatter, with no ranks, owners or per-column ballots.
+// ---------------------------------------- levels 1 and 2 by transposed ranks
+// Schedule 1 places a group of 64 items (lane = item, in list order) into a
+// window of up to 64 buckets (tile rows at level 1, tile columns at level 2)
+// without expansion slots or LDS atomics.  Each lane turns its item's bucket
+// range into a 64-bit mask over the window; a 64 x 64 bit transpose across the
+// lanes (six butterfly stages) leaves in lane b the set of group items in
+// bucket b, in list order.  Lane b owns bucket b's cursor.  An item's place in
+// bucket b is the cursor plus the number of lower items in b's set (one
+// mbcnt), so every bucket list keeps the (depth, index) order of the input:
+// the same lists as schedule 0.
+//
+// The lists leave in whole 128-byte lines.  A group adds a few entries to each
+// of tens of lists, so storing entries where they land writes every line in
+// many small pieces, spread over the whole pass; each bucket therefore keeps
+// the line that holds its cursor in LDS and writes it out once it is full.
+// Only lines that a single group fills from end to end go to memory
+// directly, and each list's first and last line are written in two parts
+// (the neighbouring list owns the rest of such a line).
 
 // Value of lane (lane ^ S): DPP within quads (S = 1, 2) and rows (S = 8,
 // row_ror:8), LDS-crossbar swizzles within 32 lanes (S = 4, 16), a backward
@@ -653,15 +662,166 @@ __device__ __forceinline__ uint64_t transpose_bits64(uint64_t w)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Block (gx, i), wave wv: task gx * kWavesPerBlock + wv over
-// ((tile row * n_seg + segment) * n_cc + column window).
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_transpose(ChunkDev c, int n_seg, int n_cc,
-                                                                           const uint32_t* __restrict__ seg_off)
+// Line-buffered lists of one wave's window: `out` the list array (absolute
+// positions, none at or past `limit`), `buf` a 128-byte line per bucket in
+// LDS, `info` a 64-entry LDS table.
+template <typename T>
+struct LineLists {
+    static constexpr uint32_t kLine = 128 / sizeof(T);     // entries per line
+    T* out;
+    uint32_t limit;
+    T* buf;
+    uint4* info;
+};
+
+// Writes, for each bucket b in `mask` (lane b holds its cursor, first
+// position and end), the line holding the cursor: positions in
+// [max(line start, first), min(line end, end)).  64 / kLine buckets a round.
+template <typename T>
+__device__ __forceinline__ void flush_lines(const LineLists<T>& L, uint64_t mask, uint32_t cur, uint32_t first,
+                                            uint32_t end)
+{
+    constexpr uint32_t LINE = LineLists<T>::kLine, PER = 64u / LINE;
+    const uint32_t lane = (uint32_t)__lane_id(), k = lane / LINE, j = lane % LINE;
+    while (mask) {                      // wave-uniform
+        uint32_t b = 64u;
+#pragma unroll
+        for (uint32_t q = 0; q < PER; ++q) {
+            const uint32_t bq = mask ? (uint32_t)__builtin_ctzll(mask) : 64u;
+            if (q == k) b = bq;
+            mask &= mask - 1ull;
+        }
+        const int src = b < 64u ? (int)b : (int)lane;
+        const uint32_t cb = (uint32_t)__shfl((int)cur, src), fb = (uint32_t)__shfl((int)first, src),
+                       eb = (uint32_t)__shfl((int)end, src);
+        const uint32_t p = cb / LINE * LINE + j;
+        if (b < 64u && p >= fb && p < eb && p < L.limit) L.out[p] = L.buf[b * LINE + j];
+    }
+}
+
+// One group: this lane's item covers buckets [lo, hi) of the window (empty
+// when hi <= lo) and is stored as `v`; `cur` and `first` are the cursor and
+// first position of bucket `lane`.
+template <typename T>
+__device__ __forceinline__ void line_group(const LineLists<T>& L, uint32_t& cur, uint32_t first, uint32_t lo,
+                                           uint32_t hi, T v)
+{
+    constexpr uint32_t LINE = LineLists<T>::kLine;
+    const int lane = __lane_id();
+    const uint64_t below_hi = hi >= 64u ? ~0ull : ((1ull << hi) - 1ull);
+    const uint64_t below_lo = lo >= 64u ? ~0ull : ((1ull << lo) - 1ull);
+    const uint64_t set = transpose_bits64(below_hi & ~below_lo);
+    const uint32_t next = cur + (uint32_t)__popcll(set);
+    L.info[lane] = make_uint4((uint32_t)set, (uint32_t)(set >> 32), cur, next);
+    wave_lds_sync();
+    // entries of a bucket's buffered line go to its buffer; entries of lines
+    // that this group fills past it go to memory; the rest wait for pass 2
+    for (uint32_t b = lo; b < hi; ++b) {
+        const uint4 in = L.info[b];
+        const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
+        const uint32_t l = pos / LINE;
+        if (l == in.z / LINE) L.buf[b * LINE + pos % LINE] = v;
+        else if (l < in.w / LINE && pos < L.limit) L.out[pos] = v;
+    }
+    wave_lds_sync();
+    flush_lines(L, __ballot(next / LINE > cur / LINE), cur, first, 0xFFFFFFFFu);   // lines this group filled
+    wave_lds_sync();
+    // pass 2: entries of the new partial lines, into the buffers just written out
+    for (uint32_t b = lo; b < hi; ++b) {
+        const uint4 in = L.info[b];
+        const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
+        const uint32_t l = pos / LINE, le = in.w / LINE;
+        if (l == le && le != in.z / LINE) L.buf[b * LINE + pos % LINE] = v;
+    }
+    wave_lds_sync();
+    cur = next;
+}
+
+// The last, partial line of every bucket of the window.
+template <typename T>
+__device__ __forceinline__ void line_finish(const LineLists<T>& L, uint32_t cur, uint32_t first)
+{
+    constexpr uint32_t LINE = LineLists<T>::kLine;
+    flush_lines(L, __ballot(cur % LINE != 0u && cur > first), cur, first, cur);
+}
+
+// LDS bytes of one wave of the schedule-1 kernels: the info table and a
+// 128-byte line for each of up to 64 buckets.
+__host__ __device__ constexpr size_t line_lds_bytes(int buckets) { return 1024 + 128 * (size_t)buckets; }
+
+// Level 1, schedule 1.  Block (gx, i), wave wv: task gx * kWavesPerBlock + wv
+// over (kTileGauss block b of image i's depth-ordered Gaussians, window of 64
+// tile rows); the block's rows start at its per-block row offsets.
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_rank(ChunkDev c, uint64_t n, int n_rw, int nb)
 {
     if (*c.ovf) return;                 // the chunk's lists do not fit: no lists (fallback raster)
-    __shared__ uint32_t gs_all[kWavesPerBlock][64];
+    extern __shared__ uint4 lds4[];
     const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
-    uint32_t* gs = gs_all[wv];
+    uint4* mine = lds4 + (size_t)wv * (line_lds_bytes(nb) / 16);
+    const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int i = (int)(L / gridDim.x), task = (int)(L - (uint32_t)i * gridDim.x) * kWavesPerBlock + wv;
+    const int b = task / n_rw, rw = task - b * n_rw;
+    const uint32_t V = c.n ? c.vis_count[i] : 0u;
+    const uint32_t j0 = (uint32_t)b * kTileGauss;
+    if (b >= c.tile_blocks || j0 >= V) return;     // wave-uniform; the waves of a block never wait on each other
+    const uint32_t j1 = min(j0 + (uint32_t)kTileGauss, V);
+    const ImageInfo im = c.img[i];
+    const uint32_t TY = (uint32_t)im.tiles_y, TX = (uint32_t)im.tiles_x;
+    const uint32_t rbase = (uint32_t)rw * 64u;
+    if (rbase >= TY) return;
+    const uint32_t row = rbase + (uint32_t)lane;
+    uint32_t cur = row < TY ? c.row_hist[((size_t)i * c.tile_blocks + b) * c.ty_max + row] : 0u;
+    const uint32_t first = cur;
+    const LineLists<uint2> lists{c.rows + c.row_base[i], c.row_count[i], reinterpret_cast<uint2*>(mine + 64), mine};
+    const size_t seg = (size_t)i * n;
+    uint32_t gn[kAhead];
+    uint2 rn[kAhead];
+    auto load = [&](uint32_t jb) {
+#pragma unroll
+        for (int w = 0; w < kAhead; ++w) {
+            const uint32_t j = jb + 64u * w + (uint32_t)lane;
+            gn[w] = j < j1 ? c.sv[1][seg + j] : 0u;
+            rn[w] = j < j1 ? raw_rect(c.srect, c.rect4, seg + j) : make_uint2(0u, 0u);
+        }
+    };
+    load(j0);
+    for (uint32_t jb = j0; jb < j1; jb += 64u * kAhead) {
+        uint32_t gc[kAhead];
+        uint2 rc[kAhead];
+#pragma unroll
+        for (int w = 0; w < kAhead; ++w) {
+            gc[w] = gn[w];
+            rc[w] = rn[w];
+        }
+        if (jb + 64u * kAhead < j1) load(jb + 64u * kAhead);
+#pragma unroll
+        for (int w = 0; w < kAhead; ++w) {
+            const uint32_t jw = jb + 64u * w;
+            if (jw >= j1) break;
+            const uint32_t g = gc[w];
+            uint32_t x0, x1, y0, y1;
+            decode_rect(rc[w], c.rect4, &x0, &x1, &y0, &y1);
+            const bool inside = jw + (uint32_t)lane < j1;
+            if (inside && g >= n) atomicOr(c.err, kErrRowEntry);   // impossible by construction: report it
+            // the rows k_tile_hist counts: a non-empty rectangle inside the image
+            const bool okg = inside && g < n && x1 > x0 && y1 > y0 && x1 <= TX && y1 <= TY;
+            const uint32_t lo = okg ? min(max(y0, rbase) - rbase, 64u) : 0u;
+            const uint32_t hi = okg ? min(max(y1, rbase) - rbase, 64u) : 0u;
+            line_group(lists, cur, first, lo, hi, make_uint2(g, x0 | (x1 << 16)));
+        }
+    }
+    line_finish(lists, cur, first);
+}
+
+// Level 2, schedule 1.  Block (gx, i), wave wv: task gx * kWavesPerBlock + wv
+// over ((tile row * n_seg + segment) * n_cc + window of 64 tile columns).
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_rank(ChunkDev c, int n_seg, int n_cc,
+                                                                      const uint32_t* __restrict__ seg_off, int nb)
+{
+    if (*c.ovf) return;                 // the chunk's lists do not fit: no lists (fallback raster)
+    extern __shared__ uint4 lds4[];
+    const int wv = (int)(threadIdx.x >> 6), lane = __lane_id();
+    uint4* mine = lds4 + (size_t)wv * (line_lds_bytes(nb) / 16);
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), task = (int)(L - (uint32_t)i * gridDim.x) * kWavesPerBlock + wv;
     const int cc = task % n_cc, ys = task / n_cc;
@@ -675,28 +835,21 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_transpose(Chunk
     segment_of(rr[0], rr[1], sg, n_seg, &r0, &r1);
     if (r0 >= r1) return;
     const uint2* list = c.rows + c.row_base[i];
-    uint32_t* out = c.pairs + c.pair_base[i];
-    const uint32_t P = c.pair_count[i];
     const uint32_t tx = base + (uint32_t)lane;
-    uint32_t cur = 0, lim = 0;
+    uint32_t cur = 0;
     if (tx < TX) {
         const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX + tx) * 2;
         cur = n_seg == 1 ? tr[0] : seg_off[(((size_t)i * c.ty_max + y) * n_seg + sg) * c.tx_max + tx];
-        lim = min(tr[1], P);
     }
-    auto cover_of = [&](uint2 en) {
-        const uint32_t x0 = en.y & 0xFFFFu, x1 = en.y >> 16;
-        const uint32_t lo = min(max(x0, base) - base, 64u), hi = min(max(x1, base) - base, 64u);
-        const uint64_t below_hi = hi >= 64u ? ~0ull : ((1ull << hi) - 1ull);
-        const uint64_t below_lo = lo >= 64u ? ~0ull : ((1ull << lo) - 1ull);
-        return below_hi & ~below_lo;
-    };
+    const uint32_t first = cur;
+    const LineLists<uint32_t> lists{c.pairs + c.pair_base[i], c.pair_count[i], reinterpret_cast<uint32_t*>(mine + 64),
+                                    mine};
     uint2 nx[kAhead];
     auto load = [&](uint32_t eb) {
 #pragma unroll
         for (int w = 0; w < kAhead; ++w) {
             const uint32_t e = eb + 64u * w + (uint32_t)lane;
-            nx[w] = e < r1 ? list[e] : make_uint2(0u, 0u);
+            nx[w] = e < r1 ? list[e] : make_uint2(0u, 0u);     // past r1: an empty range
         }
     };
     load(r0);
@@ -708,19 +861,12 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_transpose(Chunk
 #pragma unroll
         for (int w = 0; w < kAhead; ++w) {
             if (eb + 64u * w >= r1) break;
-            // entries past r1 were loaded as empty ranges and cover no column
-            gs[lane] = en[w].x;
-            uint64_t m = transpose_bits64(cover_of(en[w]));
-            wave_lds_sync();
-            while (m) {
-                const int e = __builtin_ctzll(m);
-                m &= m - 1ull;
-                if (cur < lim) out[cur] = gs[e];
-                ++cur;
-            }
-            wave_lds_sync();
+            const uint32_t x0 = en[w].y & 0xFFFFu, x1 = min(en[w].y >> 16, TX);
+            const uint32_t lo = min(max(x0, base) - base, 64u), hi = min(max(x1, base) - base, 64u);
+            line_group(lists, cur, first, lo, hi, en[w].x);
         }
     }
+    line_finish(lists, cur, first);
 }
 
 // Keys of one image: key = (global tile << 32) | depth bits of the Gaussian.
@@ -761,9 +907,16 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
 {
     if (c.n_img == 0 || s.n == 0) return hipSuccess;
     const uint64_t n = (uint64_t)s.n;
-    const unsigned rb = (unsigned)((c.tile_blocks + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(k_row_scatter, dim3(rb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
-                       kWavesPerBlock * expand_lds_words(c.ty_max) * 4, stream, c, n);
+    if (schedule == 1) {
+        const int n_rw = (c.ty_max + 63) / 64, nb = std::min(c.ty_max, 64);
+        const unsigned rb = (unsigned)((c.tile_blocks * n_rw + kWavesPerBlock - 1) / kWavesPerBlock);
+        hipLaunchKernelGGL(k_row_rank, dim3(rb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
+                           kWavesPerBlock * line_lds_bytes(nb), stream, c, n, n_rw, nb);
+    } else {
+        const unsigned rb = (unsigned)((c.tile_blocks + kWavesPerBlock - 1) / kWavesPerBlock);
+        hipLaunchKernelGGL(k_row_scatter, dim3(rb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
+                           kWavesPerBlock * expand_lds_words(c.ty_max) * 4, stream, c, n);
+    }
     if (n_seg < 1 || !seg_off) n_seg = 1;
     const dim3 grid((unsigned)(c.ty_max * n_seg), (unsigned)c.n_img);
     if (n_seg > 1) {
@@ -774,8 +927,9 @@ hipError_t launch_tile_scatter(const SceneDev& s, const ChunkDev& c, int schedul
     if (schedule == 1) {
         const int n_cc = (c.tx_max + 63) / 64;
         const unsigned tb = (unsigned)((c.ty_max * n_seg * n_cc + kWavesPerBlock - 1) / kWavesPerBlock);
-        hipLaunchKernelGGL(k_rowtile_transpose, dim3(tb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock), 0, stream, c,
-                           n_seg, n_cc, (const uint32_t*)seg_off);
+        const int nb = std::min(c.tx_max, 64);
+        hipLaunchKernelGGL(k_rowtile_rank, dim3(tb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
+                           kWavesPerBlock * line_lds_bytes(nb), stream, c, n_seg, n_cc, (const uint32_t*)seg_off, nb);
     } else {
         const unsigned tb = (unsigned)((c.ty_max * n_seg + kWavesPerBlock - 1) / kWavesPerBlock);
         hipLaunchKernelGGL(k_rowtile_scatter, dim3(tb, (unsigned)c.n_img), dim3(64 * kWavesPerBlock),
