@@ -663,8 +663,8 @@ __device__ __forceinline__ uint64_t transpose_bits64(uint64_t w)
 }
 
 // Line-buffered lists of one wave's window: `out` the list array (absolute
-// positions, none at or past `limit`), `buf` a 128-byte line per bucket in
-// LDS, `info` a 64-entry LDS table.
+// positions, none at or past `limit`), `buf` two 128-byte lines per bucket in
+// LDS (line l of a bucket in slot l & 1), `info` a 64-entry LDS table.
 template <typename T>
 struct LineLists {
     static constexpr uint32_t kLine = 128 / sizeof(T);     // entries per line
@@ -676,17 +676,18 @@ struct LineLists {
 
 // Writes, for each bucket b in `mask` (lane b holds its cursor, first
 // position and end), the line holding the cursor: positions in
-// [max(line start, first), min(line end, end)).  64 / kLine buckets a round.
+// [max(line start, first), min(line end, end)).  Eight lanes write a line,
+// 16 bytes each, so a round covers eight buckets.
 template <typename T>
 __device__ __forceinline__ void flush_lines(const LineLists<T>& L, uint64_t mask, uint32_t cur, uint32_t first,
                                             uint32_t end)
 {
-    constexpr uint32_t LINE = LineLists<T>::kLine, PER = 64u / LINE;
-    const uint32_t lane = (uint32_t)__lane_id(), k = lane / LINE, j = lane % LINE;
+    constexpr uint32_t LINE = LineLists<T>::kLine, EPL = 16u / sizeof(T);
+    const uint32_t lane = (uint32_t)__lane_id(), k = lane / 8u, j = lane % 8u;
     while (mask) {                      // wave-uniform
         uint32_t b = 64u;
 #pragma unroll
-        for (uint32_t q = 0; q < PER; ++q) {
+        for (uint32_t q = 0; q < 8u; ++q) {
             const uint32_t bq = mask ? (uint32_t)__builtin_ctzll(mask) : 64u;
             if (q == k) b = bq;
             mask &= mask - 1ull;
@@ -694,8 +695,19 @@ __device__ __forceinline__ void flush_lines(const LineLists<T>& L, uint64_t mask
         const int src = b < 64u ? (int)b : (int)lane;
         const uint32_t cb = (uint32_t)__shfl((int)cur, src), fb = (uint32_t)__shfl((int)first, src),
                        eb = (uint32_t)__shfl((int)end, src);
-        const uint32_t p = cb / LINE * LINE + j;
-        if (b < 64u && p >= fb && p < eb && p < L.limit) L.out[p] = L.buf[b * LINE + j];
+        if (b < 64u) {
+            const uint32_t line = cb / LINE;
+            const uint32_t p0 = line * LINE + j * EPL;
+            const uint4 w = *reinterpret_cast<const uint4*>(L.buf + (2u * b + (line & 1u)) * LINE + j * EPL);
+            if (p0 >= fb && p0 + EPL <= eb && p0 + EPL <= L.limit) {
+                *reinterpret_cast<uint4*>(L.out + p0) = w;          // 16-byte aligned: lines are
+            } else {
+                const T* e = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                for (uint32_t q = 0; q < EPL; ++q)
+                    if (p0 + q >= fb && p0 + q < eb && p0 + q < L.limit) L.out[p0 + q] = e[q];
+            }
+        }
     }
 }
 
@@ -713,27 +725,43 @@ __device__ __forceinline__ void line_group(const LineLists<T>& L, uint32_t& cur,
     const uint64_t set = transpose_bits64(below_hi & ~below_lo);
     const uint32_t next = cur + (uint32_t)__popcll(set);
     L.info[lane] = make_uint4((uint32_t)set, (uint32_t)(set >> 32), cur, next);
+    const uint64_t done = __ballot(next / LINE > cur / LINE);            // buckets whose buffered line fills
+    const bool far = __ballot(next / LINE > cur / LINE + 1u) != 0ull;    // some bucket fills two lines or more
     wave_lds_sync();
-    // entries of a bucket's buffered line go to its buffer; entries of lines
-    // that this group fills past it go to memory; the rest wait for pass 2
-    for (uint32_t b = lo; b < hi; ++b) {
-        const uint4 in = L.info[b];
-        const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
-        const uint32_t l = pos / LINE;
-        if (l == in.z / LINE) L.buf[b * LINE + pos % LINE] = v;
-        else if (l < in.w / LINE && pos < L.limit) L.out[pos] = v;
+    if (!far) {
+        // every entry lies in its bucket's buffered line or the next one: the
+        // two lines of a bucket sit in different slots, so one pass places
+        // all entries and the full lines leave afterwards
+        for (uint32_t b = lo; b < hi; ++b) {
+            const uint4 in = L.info[b];
+            const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
+            L.buf[(2u * b + (pos / LINE & 1u)) * LINE + pos % LINE] = v;
+        }
+        wave_lds_sync();
+        flush_lines(L, done, cur, first, 0xFFFFFFFFu);
+    } else {
+        // rare (a bucket takes more than a line in one group): entries of the
+        // buffered line to LDS, of lines filled inside the group to memory;
+        // the buffered lines leave; then the entries of the new partial lines
+        for (uint32_t b = lo; b < hi; ++b) {
+            const uint4 in = L.info[b];
+            const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
+            const uint32_t l = pos / LINE;
+            if (l == in.z / LINE) L.buf[(2u * b + (l & 1u)) * LINE + pos % LINE] = v;
+            else if (l < in.w / LINE && pos < L.limit) L.out[pos] = v;
+        }
+        wave_lds_sync();
+        flush_lines(L, done, cur, first, 0xFFFFFFFFu);
+        wave_lds_sync();
+        for (uint32_t b = lo; b < hi; ++b) {
+            const uint4 in = L.info[b];
+            const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
+            const uint32_t l = pos / LINE, le = in.w / LINE;
+            if (l == le && le != in.z / LINE) L.buf[(2u * b + (l & 1u)) * LINE + pos % LINE] = v;
+        }
     }
-    wave_lds_sync();
-    flush_lines(L, __ballot(next / LINE > cur / LINE), cur, first, 0xFFFFFFFFu);   // lines this group filled
-    wave_lds_sync();
-    // pass 2: entries of the new partial lines, into the buffers just written out
-    for (uint32_t b = lo; b < hi; ++b) {
-        const uint4 in = L.info[b];
-        const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
-        const uint32_t l = pos / LINE, le = in.w / LINE;
-        if (l == le && le != in.z / LINE) L.buf[b * LINE + pos % LINE] = v;
-    }
-    wave_lds_sync();
+    // the next group's table write and barrier order these LDS reads and
+    // writes before its own (a wave's LDS requests are served in order)
     cur = next;
 }
 
@@ -742,12 +770,13 @@ template <typename T>
 __device__ __forceinline__ void line_finish(const LineLists<T>& L, uint32_t cur, uint32_t first)
 {
     constexpr uint32_t LINE = LineLists<T>::kLine;
+    wave_lds_sync();
     flush_lines(L, __ballot(cur % LINE != 0u && cur > first), cur, first, cur);
 }
 
-// LDS bytes of one wave of the schedule-1 kernels: the info table and a
-// 128-byte line for each of up to 64 buckets.
-__host__ __device__ constexpr size_t line_lds_bytes(int buckets) { return 1024 + 128 * (size_t)buckets; }
+// LDS bytes of one wave of the schedule-1 kernels: the info table and two
+// 128-byte lines for each of up to 64 buckets.
+__host__ __device__ constexpr size_t line_lds_bytes(int buckets) { return 1024 + 256 * (size_t)buckets; }
 
 // Level 1, schedule 1.  Block (gx, i), wave wv: task gx * kWavesPerBlock + wv
 // over (kTileGauss block b of image i's depth-ordered Gaussians, window of 64
@@ -770,9 +799,13 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_rank(ChunkDev c, ui
     const uint32_t rbase = (uint32_t)rw * 64u;
     if (rbase >= TY) return;
     const uint32_t row = rbase + (uint32_t)lane;
-    uint32_t cur = row < TY ? c.row_hist[((size_t)i * c.tile_blocks + b) * c.ty_max + row] : 0u;
+    // positions are shifted by the image's offset within a line, so that
+    // list lines are the array's 128-byte lines
+    const uint32_t sh = (uint32_t)(c.row_base[i] % LineLists<uint2>::kLine);
+    uint32_t cur = sh + (row < TY ? c.row_hist[((size_t)i * c.tile_blocks + b) * c.ty_max + row] : 0u);
     const uint32_t first = cur;
-    const LineLists<uint2> lists{c.rows + c.row_base[i], c.row_count[i], reinterpret_cast<uint2*>(mine + 64), mine};
+    const LineLists<uint2> lists{c.rows + (c.row_base[i] - sh), c.row_count[i] + sh, reinterpret_cast<uint2*>(mine + 64),
+                                 mine};
     const size_t seg = (size_t)i * n;
     uint32_t gn[kAhead];
     uint2 rn[kAhead];
@@ -836,14 +869,16 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_rank(ChunkDev c
     if (r0 >= r1) return;
     const uint2* list = c.rows + c.row_base[i];
     const uint32_t tx = base + (uint32_t)lane;
-    uint32_t cur = 0;
+    // positions shifted as in level 1: list lines are the array's lines
+    const uint32_t sh = (uint32_t)(c.pair_base[i] % LineLists<uint32_t>::kLine);
+    uint32_t cur = sh;
     if (tx < TX) {
         const uint32_t* tr = c.tile_range + ((size_t)i * c.t_max + (size_t)y * TX + tx) * 2;
-        cur = n_seg == 1 ? tr[0] : seg_off[(((size_t)i * c.ty_max + y) * n_seg + sg) * c.tx_max + tx];
+        cur += n_seg == 1 ? tr[0] : seg_off[(((size_t)i * c.ty_max + y) * n_seg + sg) * c.tx_max + tx];
     }
     const uint32_t first = cur;
-    const LineLists<uint32_t> lists{c.pairs + c.pair_base[i], c.pair_count[i], reinterpret_cast<uint32_t*>(mine + 64),
-                                    mine};
+    const LineLists<uint32_t> lists{c.pairs + (c.pair_base[i] - sh), c.pair_count[i] + sh,
+                                    reinterpret_cast<uint32_t*>(mine + 64), mine};
     uint2 nx[kAhead];
     auto load = [&](uint32_t eb) {
 #pragma unroll
