@@ -37,7 +37,7 @@ RASTER_SOURCES = ("paper_2604_25459_amd/csrc/k_raster.hip",)
 PMC_SUMMARY = "profiles/k_raster_cfg2_2048env_640x480_f32_pmc.json"
 UTIL_SUMMARY = "profiles/k_raster_cfg2_2048env_640x480_f32_valu_lds.json"
 UTIL_COUNTERS = ("SQ_ACTIVE_INST_VALU", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_LDS_LOAD_BANDWIDTH", "SQ_BUSY_CU_CYCLES",
-                 "GRBM_GUI_ACTIVE")
+                 "SQ_INSTS_VALU", "GRBM_GUI_ACTIVE")
 # LDS read bandwidth of a CDNA4 compute unit (bytes per clock)
 LDS_BYTES_PER_CLK = 256
 CALIB_BYTES = 1 << 30
@@ -81,6 +81,21 @@ def pmc_summary(fetch_csv, write_csv, out_path, command):
         out[f"{key}_dispatches"] = len(rast)
         out[f"{key}_bytes_per_launch"] = sum(rast) / len(rast) * 1024.0 * factor
     out["traffic_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    # every kernel of the counted step: calibrated HBM bytes per dispatch
+    kern = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        key = counter.split("_")[0].lower()
+        for r in _pmc_rows(path, counter):
+            name = r["Kernel_Name"]
+            if "copyBuffer" in name or "elementwise" in name or "fillBuffer" in name:
+                continue
+            short = name.replace("void ", "").replace("gsr::", "").replace("(anonymous namespace)::", "").split("(")[0]
+            k = kern.setdefault(short, {})
+            k.setdefault(f"{key}_bytes", []).append(float(r["Counter_Value"]) * 1024.0 * out[f"{key}_factor"])
+    out["kernels"] = {n: {"dispatches": len(v.get("fetch_bytes", [])),
+                          "fetch_bytes_per_dispatch": sum(v.get("fetch_bytes", [0])) / max(1, len(v.get("fetch_bytes", []))),
+                          "write_bytes_per_dispatch": sum(v.get("write_bytes", [0])) / max(1, len(v.get("write_bytes", [])))}
+                      for n, v in sorted(kern.items())}
     # the counted command renders one step of the 2048-image default workload:
     # its rasteriser launches each cover this many images
     out["images_per_launch"] = 2048 / out["fetch_dispatches"]
@@ -118,6 +133,8 @@ def util_summary(counter_csv, agent_csv, out_path, command):
         clocks = d["GRBM_GUI_ACTIVE"] / n_xcc
         rows.append({"ms": d["ns"] * 1e-6, "clock_ghz": clocks / d["ns"],
                      "valu_busy": d["SQ_ACTIVE_INST_VALU"] * 4.0 / (simds * clocks),
+                     "valu_instr": d["SQ_INSTS_VALU"],
+                     "valu_issue": d["SQ_INSTS_VALU"] * 4.0 / (simds * clocks),
                      "cu_busy": d["SQ_BUSY_CU_CYCLES"] * 4.0 / (simds * clocks),
                      "lds_busy": d["SQ_LDS_IDX_ACTIVE"] / (cus * clocks),
                      "lds_bytes": d["SQ_INSTS_LDS_LOAD_BANDWIDTH"] * 64.0})
@@ -127,6 +144,8 @@ def util_summary(counter_csv, agent_csv, out_path, command):
     out = {"command": command, "source_sha256": raster_source_hash(), "sources": list(RASTER_SOURCES),
            "counters": list(UTIL_COUNTERS), "dispatches": len(rows), "cus": cus, "simds": simds, "xcds": n_xcc,
            "avg_ms": mean["ms"], "clock_ghz": mean["clock_ghz"], "valu_busy": mean["valu_busy"],
+           "valu_instr_per_launch": mean["valu_instr"], "valu_issue_frac": mean["valu_issue"],
+           "valu_issue_basis": "wave64 VALU instructions x 4 cycles (16-lane SIMDs) / (SIMDs x shader clocks)",
            "cu_busy": mean["cu_busy"], "lds_busy": mean["lds_busy"], "lds_read_bytes_per_launch": mean["lds_bytes"],
            "lds_read_gbs": lds_gbs, "lds_peak_gbs": lds_peak, "lds_read_frac": lds_gbs / lds_peak,
            "lds_peak_basis": f"{cus} CUs x {LDS_BYTES_PER_CLK} B/clock x {clk_mhz:.0f} MHz"}
@@ -146,7 +165,8 @@ def measured_util():
         s = json.load(f)
     if s.get("source_sha256") != raster_source_hash():
         return None
-    return {k: s[k] for k in ("valu_busy", "lds_busy", "lds_read_gbs", "lds_peak_gbs", "lds_read_frac", "clock_ghz")}
+    return {k: s[k] for k in ("valu_busy", "valu_issue_frac", "lds_busy", "lds_read_gbs", "lds_peak_gbs",
+                              "lds_read_frac", "clock_ghz") if k in s}
 
 
 def measured_traffic(tuning, images_per_launch):

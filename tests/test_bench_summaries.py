@@ -40,10 +40,13 @@ def test_traffic_summary_scales_by_the_calibration_copy(tmp_path):
     fetch = tmp_path / "fetch.csv"
     write = tmp_path / "write.csv"
     # the copy reads 1 GiB but FETCH_SIZE shows half of it (factor 2); WRITE_SIZE shows all of it
+    level2 = "gsr::(anonymous namespace)::k_rowtile_rank(gsr::ChunkDev, int, int, unsigned int const*, int)"
     _write_counters(fetch, [(1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", kib / 2, 0, 10),
-                            (2, RASTER, "FETCH_SIZE", 1000.0, 10, 20), (3, RASTER, "FETCH_SIZE", 3000.0, 20, 30)])
+                            (2, RASTER, "FETCH_SIZE", 1000.0, 10, 20), (3, RASTER, "FETCH_SIZE", 3000.0, 20, 30),
+                            (4, level2, "FETCH_SIZE", 100.0, 30, 40)])
     _write_counters(write, [(1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", kib, 0, 10),
-                            (2, RASTER, "WRITE_SIZE", 500.0, 10, 20), (3, RASTER, "WRITE_SIZE", 700.0, 20, 30)])
+                            (2, RASTER, "WRITE_SIZE", 500.0, 10, 20), (3, RASTER, "WRITE_SIZE", 700.0, 20, 30),
+                            (4, level2, "WRITE_SIZE", 50.0, 30, 40)])
     out = tmp_path / "pmc.json"
     bench.pmc_summary(str(fetch), str(write), str(out), "cmd")
     s = json.loads(out.read_text())
@@ -54,6 +57,11 @@ def test_traffic_summary_scales_by_the_calibration_copy(tmp_path):
     assert s["write_bytes_per_launch"] == pytest.approx(600.0 * 1024)
     assert s["traffic_bytes_per_launch"] == pytest.approx(2000.0 * 2048 + 600.0 * 1024)
     assert s["source_sha256"] == bench.raster_source_hash()
+    # every kernel's calibrated bytes per dispatch, the copy excluded
+    assert set(s["kernels"]) == {"k_raster<16, 64, false>", "k_rowtile_rank"}
+    assert s["kernels"]["k_rowtile_rank"]["fetch_bytes_per_dispatch"] == pytest.approx(100.0 * 2048)
+    assert s["kernels"]["k_rowtile_rank"]["write_bytes_per_dispatch"] == pytest.approx(50.0 * 1024)
+    assert s["kernels"]["k_raster<16, 64, false>"]["dispatches"] == 2
 
 
 def test_traffic_summary_rejects_a_bad_calibration(tmp_path):
@@ -82,6 +90,7 @@ def test_valu_lds_summary(tmp_path):
             (5, RASTER, "SQ_BUSY_CU_CYCLES", 1024 * clocks / 4, 0, ns),
             (5, RASTER, "SQ_LDS_IDX_ACTIVE", 0.5 * 256 * clocks, 0, ns),
             (5, RASTER, "SQ_INSTS_LDS_LOAD_BANDWIDTH", 1e12 / 64, 0, ns),  # 1 TB read
+            (5, RASTER, "SQ_INSTS_VALU", 0.9 * 1024 * clocks / 4, 0, ns),  # wave64 instructions: 90 % of issue
             (6, "k_project<0, 3>", "GRBM_GUI_ACTIVE", 1.0, 0, 1)]
     _write_counters(counters, rows)
     out = tmp_path / "util.json"
@@ -95,6 +104,8 @@ def test_valu_lds_summary(tmp_path):
     assert s["lds_read_gbs"] == pytest.approx(1e12 / 0.01 / 1e9)
     assert s["lds_peak_gbs"] == pytest.approx(256 * 256 * 2.4)
     assert s["lds_read_frac"] == pytest.approx(s["lds_read_gbs"] / s["lds_peak_gbs"])
+    assert s["valu_issue_frac"] == pytest.approx(0.9)
+    assert s["valu_instr_per_launch"] == pytest.approx(0.9 * 1024 * clocks / 4)
 
 
 def test_bench_refuses_more_than_one_gpu():
