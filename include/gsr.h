@@ -70,7 +70,7 @@ typedef struct gsr_server gsr_server;
 /* Context options; zero-initialise for defaults. */
 typedef struct {
     int tile_size;          /* 8, 16 or 32 pixels; 0 = 16 */
-    int images_per_thread;  /* images one projection thread handles (1..16); 0 = 4 */
+    int images_per_thread;  /* images one projection thread handles (1..16); 0 = 16 */
     int64_t chunk_bytes;    /* device working-memory budget per render chunk; 0 = 48 GiB, and never above 40 % of
                                the device memory free when a render is planned (with `overlap` on, a render of
                                several chunks holds two such working sets); chunks of a render are of equal size */

@@ -961,7 +961,7 @@ GSR_EXPORT int gsr_create(int device, const gsr_options* opt, gsr_ctx** out)
     gsr_options o{};
     if (opt) o = *opt;
     if (o.tile_size == 0) o.tile_size = 16;
-    if (o.images_per_thread == 0) o.images_per_thread = 4;
+    if (o.images_per_thread == 0) o.images_per_thread = 16;
     if (o.chunk_bytes == 0) o.chunk_bytes = (int64_t)48 << 30;
     if (o.cutoff == 0.0f) o.cutoff = 3.33f;
     if (o.tile_size != 8 && o.tile_size != 16 && o.tile_size != 32)
@@ -1589,13 +1589,14 @@ GSR_EXPORT int gsr_autotune(gsr_ctx* ctx, const gsr_render_desc* d, void* stream
         int r = render_impl(ctx, d, stream, false, &t);     // warm-up (captures graphs, grows buffers)
         if (r) return r;
         if (hipEventRecord(e0, st) != hipSuccess) return fail(GSR_E_DEVICE, "event record");
-        for (int k = 0; k < 2 && !r; ++k) r = render_impl(ctx, d, stream, false, &t);
+        // four renders: candidates differ by a few per cent, about the spread of single renders
+        for (int k = 0; k < 4 && !r; ++k) r = render_impl(ctx, d, stream, false, &t);
         if (r) return r;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
             return fail(GSR_E_DEVICE, "event sync");
         float f = 0.0f;
         if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return fail(GSR_E_DEVICE, "event time");
-        *ms = f / 2.0;
+        *ms = f / 4.0;
         return GSR_OK;
     };
     double best_ms = 0.0;

@@ -215,7 +215,7 @@ class Observation:
 class Renderer:
     """One libgsr context on a device."""
 
-    def __init__(self, device: int = 0, tile_size: int = 16, images_per_thread: int = 4, chunk_bytes: int = 0,
+    def __init__(self, device: int = 0, tile_size: int = 16, images_per_thread: int = 16, chunk_bytes: int = 0,
                  cutoff: float = 0.0, profile: bool = False, graphs: bool = True, overlap: bool = True,
                  sync_lists: bool = False, list_cap: int = 0):
         lib = load()
