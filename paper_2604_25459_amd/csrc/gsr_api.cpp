@@ -90,7 +90,7 @@ Workspace::~Workspace()
 {
     // a fixed workspace's buffers point into memory it does not own
     if (!fixed)
-        for (DevBuf* b : {&img, &xform, &keyz, &rect, &srect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &vis_count,
+        for (DevBuf* b : {&img, &xform, &keyz, &rect, &srect, &rec, &sk0, &sk1, &sv0, &sv1, &sort_hist, &kmm, &vis_count,
                       &tile_hist, &tile_range, &pair_count, &pair_base, &pairs, &row_hist, &row_range, &row_count,
                           &row_base, &rows, &debug, &stage_vm, &stage_pose, &stage_elev, &seg_off, &counter,
                           &ovf, &counter2})
@@ -226,7 +226,7 @@ size_t per_image_bytes(const SceneRes* sc, int t_max, int ty_max, int sort_block
     const size_t n = (size_t)sc->dev.n;
     size_t b = n * (4 + 16 + rec_bytes + 16);                          // key, rect + sorted rect, record, sort buffers
     b += (size_t)(sc->dev.n_bodies + 1) * 64;                          // transforms
-    b += (size_t)sort_blocks * 256 * 4 + (size_t)tile_blocks * ty_max * 4 + (size_t)(t_max + ty_max) * 8;
+    b += (size_t)sort_blocks * 512 * 4 + (size_t)tile_blocks * ty_max * 4 + (size_t)(t_max + ty_max) * 8 + 8;
     b += (size_t)(t_max + 2 * ty_max + 1) * 4;                         // tile difference array (bound)
     b += n * 8 * 4 + n * 3 * 8 + sizeof(ImageInfo) + 64;               // pair / row-entry estimates
     return b;
@@ -296,7 +296,8 @@ WorkspaceSizes workspace_sizes(const SceneRes* sc, const ChunkPlan& p, size_t n_
     add(&Workspace::sk1, I * n * 4);
     add(&Workspace::sv0, I * n * 4);
     add(&Workspace::sv1, I * n * 4);
-    add(&Workspace::sort_hist, I * p.sort_blocks * 256 * 4);
+    add(&Workspace::sort_hist, I * p.sort_blocks * 512 * 4);
+    add(&Workspace::kmm, I * 8);
     add(&Workspace::vis_count, I * 4);
     add(&Workspace::tile_hist, I * (size_t)(p.tx_max + 1) * (p.ty_max + 1) * 4);
     add(&Workspace::tile_range, I * (size_t)p.t_max * 8);
@@ -397,6 +398,7 @@ ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, int i
     c.sv[0] = ws.sv0.as<uint32_t>();
     c.sv[1] = ws.sv1.as<uint32_t>();
     c.sort_hist = ws.sort_hist.as<uint32_t>();
+    c.kmm = ws.kmm.as<uint32_t>();
     c.vis_count = ws.vis_count.as<uint32_t>();
     c.tile_hist = ws.tile_hist.as<int32_t>();
     c.tile_range = ws.tile_range.as<uint32_t>();
@@ -521,7 +523,8 @@ int run_chunk(gsr_ctx* ctx, Workspace& ws, SceneRes* sc, const RenderJob& job, c
                                  c.cap_pairs, c.cap_rows};
     if (graph) {
         for (void* ptr : {(void*)c.xform, (void*)c.keyz, (void*)c.rect, (void*)c.srect, (void*)c.rec, (void*)c.sk[0],
-                          (void*)c.sk[1], (void*)c.sv[0], (void*)c.sv[1], (void*)c.sort_hist, (void*)c.vis_count,
+                          (void*)c.sk[1], (void*)c.sv[0], (void*)c.sv[1], (void*)c.sort_hist, (void*)c.kmm,
+                          (void*)c.vis_count,
                           (void*)c.tile_hist, (void*)c.tile_range, (void*)c.pair_count, (void*)c.pair_base,
                           (void*)c.row_hist, (void*)c.row_range, (void*)c.row_count, (void*)c.row_base})
             key.push_back((uint64_t)(uintptr_t)ptr);

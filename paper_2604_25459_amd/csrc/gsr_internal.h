@@ -128,9 +128,10 @@ struct ChunkDev {
     uint2* rect;               // [n_img][n] tile rectangle (format: rect4 below)
     float4* rec;               // [n_img][n][3] raster records ([..][5] for LiDAR)
     uint32_t* sk[2];           // depth-sort keys, ping-pong [n_img][n]
-    uint32_t* sv[2];           // depth-sort values (Gaussian ids); sorted result in sv[1]
+    uint32_t* sv[2];           // depth-sort values (Gaussian ids); sorted result in sv[0]
     uint2* srect;              // [n_img][n] tile rectangle of the j-th depth-ordered Gaussian
-    uint32_t* sort_hist;       // [n_img][sort_blocks][256]
+    uint32_t* sort_hist;       // [n_img][sort_blocks][512]
+    uint32_t* kmm;             // [n_img][2] smallest and largest visible depth key (projection)
     uint32_t* vis_count;       // [n_img] visible Gaussians V_i
     int32_t* tile_hist;       // [n_img][(tx_max + 1) (ty_max + 1)] 2D difference array of tile counts
     uint32_t* tile_range;      // [n_img][t_max][2] local [start, end)

@@ -75,7 +75,7 @@ struct StageGraph {
 
 // Working memory of one render call at a time.
 struct Workspace {
-    DevBuf img, xform, keyz, rect, srect, rec, sk0, sk1, sv0, sv1, sort_hist, vis_count, tile_hist, tile_range,
+    DevBuf img, xform, keyz, rect, srect, rec, sk0, sk1, sv0, sv1, sort_hist, kmm, vis_count, tile_hist, tile_range,
         pair_count, pair_base, pairs, row_hist, row_range, row_count, row_base, rows, debug, stage_vm, stage_pose,
         stage_elev, seg_off;
     uint64_t* h_total = nullptr;   // pinned: [0] pairs, [1] row entries, [2] visible Gaussians of the current chunk,

@@ -33,6 +33,14 @@ __global__ __launch_bounds__(256) void k_compose(SceneDev s, ChunkDev c, const f
     const int i = idx / slots;
     const int slot = idx - i * slots;
     const ImageInfo im = c.img[i];
+    if (slot == 0) {
+        // the image's smallest and largest visible depth key, narrowed by the
+        // projection (scan grids keep the whole range: their sort runs on the
+        // full 32 bits)
+        const bool cam = im.kind == 0;
+        c.kmm[2 * i] = cam ? 0xFFFFFFFFu : 0u;
+        c.kmm[2 * i + 1] = cam ? 0u : 0xFFFFFFFFu;
+    }
     const float* vm = viewmats + im.vm_off;
     float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
     float tc[3] = {vm[3], vm[7], vm[11]};
@@ -282,6 +290,17 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, const I
         if (valid) c.keyz[o] = vis ? __float_as_uint(tz) : kInvalidKey;
         const uint64_t vmask = __ballot(vis);
         if (vmask == 0ull) return;              // wave-uniform
+        {
+            // the wave's smallest and largest visible key: the depth sort runs
+            // on keys relative to the image's smallest
+            const uint32_t kb = __float_as_uint(tz);
+            const uint32_t hi = wave_last(wave_incl_max(vis ? kb : 0u));
+            const uint32_t lo = ~wave_last(wave_incl_max(vis ? ~kb : 0u));
+            if (lane == 0) {
+                atomicMin(&c.kmm[2 * i], lo);
+                atomicMax(&c.kmm[2 * i + 1], hi);
+            }
+        }
         if (vis) {
             put_rect(c.rect, c.rect4, o, (uint32_t)ix0, (uint32_t)ix1, (uint32_t)iy0, (uint32_t)iy1);
 

@@ -228,7 +228,7 @@ __device__ __forceinline__ void raster_tile(const SceneDev& s, const ChunkDev& c
         }
     };
     if (FILTER) {
-        sv = c.sv[1];
+        sv = c.sv[0];
         vend = c.vis_count[i];
         load_round();
     } else {

@@ -5,19 +5,33 @@
 // key array in index order and drops culled entries, so equal depths keep
 // ascending index -- the tie rule of the key sort.
 //
-// Per pass (8-bit digit): a histogram kernel, a per-image scan kernel and a
-// scatter kernel.  No block waits on another block.  Local ranks inside a
-// block are stable: each wave owns a contiguous quarter of the block's items,
-// walks it in order 64 items at a time, and ranks equal digits with a ballot
-// match (peers = lanes with the same digit) and a per-wave running counter in
-// LDS.  The scatter first places the block's items in LDS in their stable
-// digit order, then writes them out in that order, so each digit's run of
-// the block leaves as consecutive addresses.
+// The sort runs on the key less the image's smallest visible key (the
+// projection records each image's smallest and largest key), in 9-bit
+// digits: three passes order an image whose keys lie within 2^27 of each
+// other (depths within a factor of about 2^16), a fourth pass (the top five
+// bits) runs only for images that need it.  The two ping-pong buffers are
+// used in opposite order by three- and four-pass images, so every image's
+// sorted values end in sv[0].
+//
+// Per pass: a histogram kernel, a per-image scan kernel and a scatter
+// kernel.  No block waits on another block.  Local ranks inside a block are
+// stable: each wave owns a contiguous quarter of the block's items, walks it
+// in order 64 items at a time, and ranks equal digits with a ballot match
+// (peers = lanes with the same digit) and a per-wave running counter in LDS.
+// The scatter first places the block's items in LDS in their stable digit
+// order, then writes them out in that order, so each digit's run of the
+// block leaves as consecutive addresses.
 #include "gsr_internal.h"
 #include "gsr_wave.h"
 
 namespace gsr {
 namespace {
+
+constexpr int kBits = 9;
+constexpr int kRadix = 1 << kBits;               // 512 digits
+constexpr int kDpt = kRadix / 256;               // digits per thread
+constexpr uint32_t kDigitMask = kRadix - 1;
+constexpr uint32_t kNarrowSpan = 1u << (3 * kBits);  // key span that three passes cover
 
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
@@ -59,19 +73,40 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* tot
     return pre + x - v;
 }
 
-template <bool FIRST>
-__global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ counts,
-                                                   uint64_t n, int shift, uint32_t* __restrict__ hist, int blocks)
+// Image i's keys span more than three passes cover (kmm: smallest, largest
+// visible key per image; an image with no visible Gaussian has smallest >
+// largest and needs no pass at all).
+__device__ __forceinline__ bool wide_image(const uint32_t* kmm, int i)
 {
-    __shared__ uint32_t h[256];
+    const uint32_t lo = kmm[2 * i], hi = kmm[2 * i + 1];
+    return hi >= lo && hi - lo >= kNarrowSpan;
+}
+// Buffer written by pass p of an image (three-pass images: 0, 1, 0; four-pass
+// images: 1, 0, 1, 0 -- the sorted values land in sv[0] either way).
+__device__ __forceinline__ int out_buf(int pass, bool wide) { return (pass + (wide ? 1 : 0)) & 1; }
+
+// Per-block digit counts of pass `pass` (FIRST: the dense keys, culled
+// entries dropped, digits of the key less the image's smallest).
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ k0, const uint32_t* __restrict__ k1,
+                                                   const uint32_t* __restrict__ counts,
+                                                   const uint32_t* __restrict__ kmm, uint64_t n, int pass,
+                                                   uint32_t* __restrict__ hist, int blocks)
+{
+    __shared__ uint32_t h[kRadix];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), tid = threadIdx.x;
+    const bool wide = wide_image(kmm, i);
+    if (pass == 3 && !wide) return;     // block-uniform: three passes order this image
     const uint64_t cnt = FIRST ? n : counts[i];
     const uint64_t base = (uint64_t)b * kSortItems;
     if (base >= cnt) return;            // block-uniform: no barrier skipped by part of the block
-    h[tid] = 0;
+#pragma unroll
+    for (int q = 0; q < kDpt; ++q) h[tid + 256 * q] = 0;
     __syncthreads();
-    const uint32_t* kin = keys + (size_t)i * n;
+    const uint32_t* kin = (FIRST || out_buf(pass - 1, wide) == 0 ? k0 : k1) + (size_t)i * n;
+    const uint32_t lo = FIRST ? kmm[2 * i] : 0u;
+    const int shift = kBits * pass;
     // all loads first, then the LDS atomics: each thread's loads overlap
     uint32_t key[kSortIpt];
 #pragma unroll
@@ -82,48 +117,58 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ 
 #pragma unroll
     for (int k = 0; k < kSortIpt; ++k) {
         const uint64_t idx = base + (uint64_t)k * 256 + tid;
-        if (idx < cnt && (!FIRST || key[k] != kInvalidKey)) atomicAdd(&h[(key[k] >> shift) & 255u], 1u);
+        if (idx < cnt && (!FIRST || key[k] != kInvalidKey)) atomicAdd(&h[((key[k] - lo) >> shift) & kDigitMask], 1u);
     }
     __syncthreads();
-    hist[((size_t)i * blocks + b) * 256 + tid] = h[tid];
+#pragma unroll
+    for (int q = 0; q < kDpt; ++q) hist[((size_t)i * blocks + b) * kRadix + tid + 256 * q] = h[tid + 256 * q];
 }
 
 // Per image: digit-major, block-minor exclusive offsets (in place).  Pass 0
 // also records the number of visible Gaussians.
 template <bool FIRST>
 __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, int blocks, uint32_t* __restrict__ counts,
-                                                   uint64_t n)
+                                                   const uint32_t* __restrict__ kmm, uint64_t n, int pass)
 {
     __shared__ uint32_t lds8[8];
     const int i = blockIdx.x, d = threadIdx.x;
+    if (pass == 3 && !wide_image(kmm, i)) return;
     const uint64_t cnt = FIRST ? n : counts[i];
     const int nb = (int)((cnt + kSortItems - 1) / kSortItems);
-    uint32_t* H = hist + (size_t)i * blocks * 256;
-    uint32_t tot = 0;
-    for (int b = 0; b < nb; ++b) tot += H[(size_t)b * 256 + d];
-    uint32_t total;
-    uint32_t run = block_excl_scan256(tot, &total, lds8);
-    if (FIRST && d == 0) counts[i] = total;
+    uint32_t* H = hist + (size_t)i * blocks * kRadix;
+    // thread d owns digits d and d + 256: the scan runs over the first half,
+    // then over the second half after the first half's total
+    uint32_t tot[kDpt] = {};
+    for (int b = 0; b < nb; ++b)
+#pragma unroll
+        for (int q = 0; q < kDpt; ++q) tot[q] += H[(size_t)b * kRadix + d + 256 * q];
+    uint32_t run[kDpt], all = 0;
+#pragma unroll
+    for (int q = 0; q < kDpt; ++q) {
+        uint32_t total;
+        run[q] = all + block_excl_scan256(tot[q], &total, lds8);
+        all += total;
+    }
+    if (FIRST && d == 0) counts[i] = all;
     // offsets in place, 16 blocks at a time: the loads of a group are all
     // complete (one wait) before its stores
     for (int b0 = 0; b0 < nb; b0 += 16) {
-        uint32_t v[16];
+        uint32_t v[16][kDpt];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = b0 + q < nb ? H[(size_t)(b0 + q) * 256 + d] : 0u;
+        for (int q = 0; q < 16; ++q)
+#pragma unroll
+            for (int r = 0; r < kDpt; ++r) v[q][r] = b0 + q < nb ? H[(size_t)(b0 + q) * kRadix + d + 256 * r] : 0u;
         __builtin_amdgcn_s_waitcnt(0x0F70);     // vmcnt(0)
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if (b0 + q < nb) H[(size_t)(b0 + q) * 256 + d] = run;
-            run += v[q];
-        }
+        for (int q = 0; q < 16; ++q)
+#pragma unroll
+            for (int r = 0; r < kDpt; ++r) {
+                if (b0 + q < nb) H[(size_t)(b0 + q) * kRadix + d + 256 * r] = run[r];
+                run[r] += v[q][r];
+            }
     }
 }
 
-// Write-out of the last pass: the values, and each Gaussian's tile rectangle
-// gathered by its id into depth order.  Every gather of a thread is issued
-// before its first store, so the loads (random ids, mostly L2 hits) overlap
-// instead of each waiting out its own latency.  The final keys are not read
-// again and are not written.
 template <typename R>
 __device__ __forceinline__ void write_last(const uint32_t* skey, const uint32_t* sval, const uint32_t* lstart,
                                            const uint32_t* gbase, uint32_t n_items, int shift, uint64_t n, size_t seg,
@@ -142,7 +187,7 @@ __device__ __forceinline__ void write_last(const uint32_t* skey, const uint32_t*
         r[q] = R{};
         if (t < n_items) {
             const uint32_t k = skey[t], v = sval[t];
-            const uint32_t dg = (k >> shift) & 255u;
+            const uint32_t dg = (k >> shift) & kDigitMask;
             const uint32_t p = gbase[dg] + (t - lstart[dg]);
             if (p >= n) atomicOr(err, kErrSortSlot);     // offsets are consistent by construction
             if (p < n) {
@@ -163,27 +208,39 @@ __device__ __forceinline__ void write_last(const uint32_t* skey, const uint32_t*
     }
 }
 
-// LAST: also gathers each Gaussian's tile rectangle into depth order (once,
-// so later stages read rectangles contiguously), and writes only the values:
-// later stages read the depth order, not the keys.
-template <bool FIRST, bool LAST>
-__global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                      const uint32_t* __restrict__ counts, uint64_t n, int shift,
+// Scatter of pass `pass`.  The last pass of an image (pass 2, or 3 for a
+// four-pass image) also gathers each Gaussian's tile rectangle into depth
+// order (once, so later stages read rectangles contiguously) and writes only
+// the values: later stages read the depth order, not the keys.
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict__ keyz, uint32_t* sk0, uint32_t* sk1,
+                                                      uint32_t* sv0, uint32_t* sv1, const uint32_t* __restrict__ counts,
+                                                      const uint32_t* __restrict__ kmm, uint64_t n, int pass,
                                                       const uint32_t* __restrict__ hist, int blocks,
                                                       const uint2* __restrict__ rect, uint2* __restrict__ srect,
                                                       int rect4, uint32_t* __restrict__ err)
 {
-    __shared__ uint32_t cnt[4][256];
-    __shared__ uint32_t lstart[256], gbase[256], lds8[8];
+    __shared__ uint32_t cnt[4][kRadix];
+    __shared__ uint32_t lstart[kRadix], gbase[kRadix], lds8[8];
     __shared__ uint32_t skey[kSortItems], sval[kSortItems];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), tid = threadIdx.x;
     const int w = tid >> 6, lane = __lane_id();
+    const bool wide = wide_image(kmm, i);
+    if (pass == 3 && !wide) return;     // block-uniform
+    const bool last = pass == (wide ? 3 : 2);
     const uint64_t count = FIRST ? n : counts[i];
     const uint64_t base = (uint64_t)b * kSortItems;
     if (base >= count) return;          // block-uniform
     const size_t seg = (size_t)i * n;
+    // this image's input and output buffers of the pass (never the same)
+    const int ib = FIRST ? 0 : out_buf(pass - 1, wide), ob = out_buf(pass, wide);
+    const uint32_t* kin = FIRST ? keyz : (ib ? sk1 : sk0);
+    const uint32_t* vin = ib ? sv1 : sv0;
+    uint32_t* kout = ob ? sk1 : sk0;
+    uint32_t* vout = ob ? sv1 : sv0;
+    const uint32_t lo = FIRST ? kmm[2 * i] : 0u;
+    const int shift = kBits * pass;
 
     uint32_t key[kSortIpt], val[kSortIpt];
     bool ok[kSortIpt];
@@ -194,37 +251,45 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
         key[k] = ok[k] ? kin[seg + idx] : kInvalidKey;
         if (FIRST) {
             ok[k] = ok[k] && key[k] != kInvalidKey;
+            key[k] = key[k] - lo;               // sorted from here on relative to the smallest key
             val[k] = (uint32_t)idx;
         } else {
             val[k] = ok[k] ? vin[seg + idx] : 0u;
         }
     }
 #pragma unroll
-    for (int ww = 0; ww < 4; ++ww) cnt[ww][tid] = 0;
+    for (int ww = 0; ww < 4; ++ww)
+#pragma unroll
+        for (int q = 0; q < kDpt; ++q) cnt[ww][tid + 256 * q] = 0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kSortIpt; ++k)
-        if (ok[k]) atomicAdd(&cnt[w][(key[k] >> shift) & 255u], 1u);
+        if (ok[k]) atomicAdd(&cnt[w][(key[k] >> shift) & kDigitMask], 1u);
     __syncthreads();
     // block-local layout: digit-major, and within a digit wave-major, each
-    // wave's items in order -- the stable order of the block's items
-    uint32_t n_items;
-    {
-        const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid], c3 = cnt[3][tid];
-        const uint32_t start = block_excl_scan256(c0 + c1 + c2 + c3, &n_items, lds8);
-        lstart[tid] = start;
-        gbase[tid] = hist[((size_t)i * blocks + b) * 256 + tid];
-        cnt[0][tid] = start;
-        cnt[1][tid] = start + c0;
-        cnt[2][tid] = start + c0 + c1;
-        cnt[3][tid] = start + c0 + c1 + c2;
+    // wave's items in order -- the stable order of the block's items.  Thread
+    // tid owns digits tid and tid + 256 (scanned half after half).
+    uint32_t n_items = 0;
+#pragma unroll
+    for (int q = 0; q < kDpt; ++q) {
+        const int dg = tid + 256 * q;
+        const uint32_t c0 = cnt[0][dg], c1 = cnt[1][dg], c2 = cnt[2][dg], c3 = cnt[3][dg];
+        uint32_t total;
+        const uint32_t start = n_items + block_excl_scan256(c0 + c1 + c2 + c3, &total, lds8);
+        n_items += total;
+        lstart[dg] = start;
+        gbase[dg] = hist[((size_t)i * blocks + b) * kRadix + dg];
+        cnt[0][dg] = start;
+        cnt[1][dg] = start + c0;
+        cnt[2][dg] = start + c0 + c1;
+        cnt[3][dg] = start + c0 + c1 + c2;
     }
     __syncthreads();
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int k = 0; k < kSortIpt; ++k) {
-        const uint32_t dg = (key[k] >> shift) & 255u;
-        const uint64_t peers = match_bits<8>(dg, ok[k]);
+        const uint32_t dg = (key[k] >> shift) & kDigitMask;
+        const uint64_t peers = match_bits<kBits>(dg, ok[k]);
         if (ok[k]) {
             const uint32_t basev = cnt[w][dg];
             const uint32_t lpos = basev + (uint32_t)__popcll(peers & lt);
@@ -240,7 +305,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
     __syncthreads();
     // write out in block-local order: consecutive threads write consecutive
     // addresses inside each digit's run
-    if (LAST) {
+    if (last) {
         if (rect4) write_last(skey, sval, lstart, gbase, n_items, shift, n, seg, vout,
                               reinterpret_cast<const uint32_t*>(rect), reinterpret_cast<uint32_t*>(srect), err);
         else write_last(skey, sval, lstart, gbase, n_items, shift, n, seg, vout, rect, srect, err);
@@ -248,7 +313,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
     }
     for (uint32_t t = (uint32_t)tid; t < n_items; t += 256u) {
         const uint32_t k = skey[t], v = sval[t];
-        const uint32_t dg = (k >> shift) & 255u;
+        const uint32_t dg = (k >> shift) & kDigitMask;
         const uint32_t pos = gbase[dg] + (t - lstart[dg]);
         if (pos >= n) atomicOr(err, kErrSortSlot);     // offsets are consistent by construction
         if (pos < n) {
@@ -265,33 +330,25 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
     if (s.n == 0 || c.n_img == 0) return hipSuccess;
     const uint64_t n = (uint64_t)s.n;
     const dim3 grid((unsigned)c.sort_blocks, (unsigned)c.n_img);
-    // pass 0: dense keys (index order) -> compacted, digit 0
-    hipLaunchKernelGGL(k_sort_hist<true>, grid, dim3(256), 0, stream, c.keyz, c.vis_count, n, 0, c.sort_hist,
-                       c.sort_blocks);
+    // pass 0: dense keys (index order) -> compacted keys relative to the image's smallest, digit 0
+    hipLaunchKernelGGL(k_sort_hist<true>, grid, dim3(256), 0, stream, c.keyz, (const uint32_t*)nullptr, c.vis_count,
+                       c.kmm, n, 0, c.sort_hist, c.sort_blocks);
     hipLaunchKernelGGL(k_sort_scan<true>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
-                       c.vis_count, n);
-    hipLaunchKernelGGL((k_sort_scatter<true, false>), grid, dim3(256), 0, stream, c.keyz, (const uint32_t*)nullptr,
-                       c.sk[0], c.sv[0], c.vis_count, n, 0, c.sort_hist, c.sort_blocks, c.rect, c.srect, c.rect4,
-                       c.err);
-    int src = 0;
+                       c.vis_count, c.kmm, n, 0);
+    hipLaunchKernelGGL(k_sort_scatter<true>, grid, dim3(256), 0, stream, c.keyz, c.sk[0], c.sk[1], c.sv[0], c.sv[1],
+                       c.vis_count, c.kmm, n, 0, c.sort_hist, c.sort_blocks, c.rect, c.srect, c.rect4, c.err);
+    // passes 1, 2 and (for images whose keys span 2^27 or more) 3; the blocks of
+    // images that need no fourth pass leave at once
     for (int pass = 1; pass < 4; ++pass) {
-        const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_sort_hist<false>, grid, dim3(256), 0, stream, c.sk[src], c.vis_count, n, shift,
-                           c.sort_hist, c.sort_blocks);
+        hipLaunchKernelGGL(k_sort_hist<false>, grid, dim3(256), 0, stream, c.sk[0], c.sk[1], c.vis_count, c.kmm, n,
+                           pass, c.sort_hist, c.sort_blocks);
         hipLaunchKernelGGL(k_sort_scan<false>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
-                           c.vis_count, n);
-        if (pass == 3)
-            hipLaunchKernelGGL((k_sort_scatter<false, true>), grid, dim3(256), 0, stream, c.sk[src], c.sv[src],
-                               c.sk[src ^ 1], c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks, c.rect,
-                               c.srect, c.rect4, c.err);
-        else
-            hipLaunchKernelGGL((k_sort_scatter<false, false>), grid, dim3(256), 0, stream, c.sk[src], c.sv[src],
-                               c.sk[src ^ 1], c.sv[src ^ 1], c.vis_count, n, shift, c.sort_hist, c.sort_blocks,
-                               c.rect, c.srect, c.rect4, c.err);
-        src ^= 1;
+                           c.vis_count, c.kmm, n, pass);
+        hipLaunchKernelGGL(k_sort_scatter<false>, grid, dim3(256), 0, stream, (const uint32_t*)nullptr, c.sk[0],
+                           c.sk[1], c.sv[0], c.sv[1], c.vis_count, c.kmm, n, pass, c.sort_hist, c.sort_blocks, c.rect,
+                           c.srect, c.rect4, c.err);
     }
-    // pass 0 wrote buffer 0; passes 1..3 alternate, so the sorted values are in sv[1] (the last
-    // pass writes no keys)
+    // every image's sorted values are in sv[0]
     return hipGetLastError();
 }
 

@@ -406,7 +406,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_scatter(ChunkDev c,
 #pragma unroll
         for (int w = 0; w < kAhead; ++w) {
             const uint32_t j = jb + 64u * w + (uint32_t)lane;
-            gn[w] = j < j1 ? c.sv[1][seg + j] : 0u;
+            gn[w] = j < j1 ? c.sv[0][seg + j] : 0u;
             rn[w] = j < j1 ? raw_rect(c.srect, c.rect4, seg + j) : make_uint2(0u, 0u);
         }
     };
@@ -813,7 +813,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_row_rank(ChunkDev c, ui
 #pragma unroll
         for (int w = 0; w < kAhead; ++w) {
             const uint32_t j = jb + 64u * w + (uint32_t)lane;
-            gn[w] = j < j1 ? c.sv[1][seg + j] : 0u;
+            gn[w] = j < j1 ? c.sv[0][seg + j] : 0u;
             rn[w] = j < j1 ? raw_rect(c.srect, c.rect4, seg + j) : make_uint2(0u, 0u);
         }
     };

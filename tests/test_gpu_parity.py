@@ -467,6 +467,40 @@ def test_rectangles_beyond_255_tiles_per_axis(R):
     R.remove_scene(sid)
 
 
+def test_depth_sort_with_wide_and_narrow_key_spans(R):
+    """One chunk with an image whose visible depths span 0.02 m .. 4 km (keys
+    2^27 or more apart: the depth sort takes its fourth pass) and an image whose
+    depths lie within 4 .. 6 m (three passes): keys, ids and ranges of both
+    equal the oracle's bit for bit, and so do the pixels within tolerance."""
+    rng = np.random.default_rng(23)
+    n1, n2 = 3000, 2000
+    z = np.exp(rng.uniform(np.log(0.02), np.log(4000.0), n1))
+    far = np.stack([rng.uniform(-0.4, 0.4, n1) * z, rng.uniform(-0.3, 0.3, n1) * z, z], 1)
+    near = np.stack([rng.uniform(-2.0, 2.0, n2), rng.uniform(-1.5, 1.5, n2), rng.uniform(-6.0, -4.0, n2)], 1)
+    means = np.concatenate([far, near])
+    scales = np.concatenate([np.repeat((0.01 * z)[:, None], 3, 1), np.full((n2, 3), 0.05)])
+    scene = scene_from(means, scales * np.exp(rng.normal(0, 0.2, (n1 + n2, 3))), rng.standard_normal((n1 + n2, 4)),
+                       rng.uniform(0.1, 0.9, n1 + n2), rng.uniform(0, 1, (n1 + n2, 1, 3)), degree=0)
+    cam = one_camera(320, 240, 200.0).cams[0]
+    back = np.array([[-1, 0, 0, 0], [0, 1, 0, 0], [0, 0, -1, 0]], np.float32)   # looks along -z
+    vms = np.stack([np.eye(3, 4, dtype=np.float32), back])[None]
+    batch = synth.Batch(cams=[cam], viewmats=vms, poses=np.zeros((2, 0, 7), np.float32),
+                        bg=np.zeros(3, np.float32))
+    spans = []
+    for e in range(2):
+        p = project32(scene, batch, 0, e)
+        zb = p["zbits"][p["visible"]].astype(np.int64)
+        spans.append(int(zb.max() - zb.min()))
+    assert spans[0] >= 1 << 27 and spans[1] < 1 << 27
+    sid = _upload(R, scene)
+    for e in range(2):
+        _check_bins(R, sid, scene, batch, 0, e)
+    got = _render(R, sid, batch)
+    for e in range(2):
+        _check_image(_img(got, 0, e), render_ref(scene, batch, 0, e, R.tile_size), f"span env {e}")
+    R.remove_scene(sid)
+
+
 def test_stage_totals_match_oracle_bins():
     """The profiled renderer's totals of visible Gaussians and (tile,
     Gaussian) pairs equal the sums of the oracle's binning over the images."""
