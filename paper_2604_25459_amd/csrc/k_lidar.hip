@@ -23,6 +23,7 @@
 // log2 e; then the compositing rules of the camera path with the range t* in
 // place of the depth.
 #include "gsr_device.h"
+#include "gsr_wave.h"
 
 #include <algorithm>
 
@@ -78,8 +79,11 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
 {
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
-    const int64_t g = (int64_t)bx * 256 + threadIdx.x;
-    if (g >= s.n) return;
+    const int64_t g_lane = (int64_t)bx * 256 + threadIdx.x;
+    // lanes past the last Gaussian stay (invisible) for the wave-wide key range
+    const bool valid = g_lane < s.n;
+    const int64_t g = valid ? g_lane : s.n - 1;
+    const int lane = __lane_id();
     const int i_begin = (int)by * ipt;
     const int slot = body_slot(s, g);
     const float4 pm = s.pos[g];
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
         // key: centre distance (angular), depth of the centre below the sensor plane (grid)
         const float D = grid ? (-tz > 0.0f ? -tz : 0.0f) : sqrtf((tx * tx + ty * ty) + tz * tz);
         const size_t o = (size_t)i * (size_t)s.n + (size_t)g;
-        bool ok = isfinite(tx) && isfinite(ty) && isfinite(tz) && op >= 1.0f / 255.0f && isfinite(D) &&
+        bool ok = valid && isfinite(tx) && isfinite(ty) && isfinite(tz) && op >= 1.0f / 255.0f && isfinite(D) &&
                   sc[0] > 0.0f && sc[1] > 0.0f && sc[2] > 0.0f;
         int r0 = 0, r1 = 0, c0 = 0, c1 = 0;
         float cone_c = -2.0f;                           // cosine of the cone half-angle; -2 = every direction
@@ -164,7 +168,18 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
             }
         }
         const bool vis = ok && r1 > r0 && c1 > c0;
-        c.keyz[o] = vis ? __float_as_uint(D) : kInvalidKey;
+        if (valid) c.keyz[o] = vis ? __float_as_uint(D) : kInvalidKey;
+        if (__ballot(vis) != 0ull) {            // wave-uniform; every lane takes part
+            // the wave's smallest and largest visible key: the depth sort runs
+            // on keys relative to the image's smallest
+            const uint32_t kb = __float_as_uint(D);
+            const uint32_t hi = wave_last(wave_incl_max(vis ? kb : 0u));
+            const uint32_t lo = ~wave_last(wave_incl_max(vis ? ~kb : 0u));
+            if (lane == 0) {
+                atomicMin(&c.kmm[2 * i], lo);
+                atomicMax(&c.kmm[2 * i + 1], hi);
+            }
+        }
         if (!vis) continue;
         const int x0 = c0 / ts, x1 = (c1 + ts - 1) / ts, y0 = r0 / ts, y1 = (r1 + ts - 1) / ts;
         put_rect(c.rect, c.rect4, o, (uint32_t)x0, (uint32_t)x1, (uint32_t)y0, (uint32_t)y1);

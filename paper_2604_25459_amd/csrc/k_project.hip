@@ -35,11 +35,9 @@ __global__ __launch_bounds__(256) void k_compose(SceneDev s, ChunkDev c, const f
     const ImageInfo im = c.img[i];
     if (slot == 0) {
         // the image's smallest and largest visible depth key, narrowed by the
-        // projection (scan grids keep the whole range: their sort runs on the
-        // full 32 bits)
-        const bool cam = im.kind == 0;
-        c.kmm[2 * i] = cam ? 0xFFFFFFFFu : 0u;
-        c.kmm[2 * i + 1] = cam ? 0u : 0xFFFFFFFFu;
+        // projection from (no key: smallest > largest)
+        c.kmm[2 * i] = 0xFFFFFFFFu;
+        c.kmm[2 * i + 1] = 0u;
     }
     const float* vm = viewmats + im.vm_off;
     float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
