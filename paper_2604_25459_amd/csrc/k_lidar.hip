@@ -74,9 +74,17 @@ __device__ __forceinline__ void column_range_grid(float a0, float a1, float c0, 
     *k1 = min(x1, n);
 }
 
+// Records leave through LDS as in the camera projection: a wave's 64 records
+// (80 bytes each) are written to LDS and stored back lane-contiguously, so
+// each store instruction writes 1 KB of consecutive records.  The image
+// descriptions come in as a restrict argument (uniform reads become scalar
+// loads).
 template <int ST>
-__global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, int ts, int ipt)
+__global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, const ImageInfo* __restrict__ imgs,
+                                                       int ts, int ipt)
 {
+    __shared__ float4 stage[4][kLidarRec * 64];
+    float4* const st = stage[threadIdx.x >> 6];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
     const int64_t g_lane = (int64_t)bx * 256 + threadIdx.x;
@@ -98,9 +106,9 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
     const float isc[3] = {1.0f / sc[0], 1.0f / sc[1], 1.0f / sc[2]};
 
     for (int ii = 0; ii < ipt; ++ii) {
-        const int i = i_begin + ii;
+        const int i = __builtin_amdgcn_readfirstlane(i_begin + ii);     // the same in every lane
         if (i >= c.n_img) break;
-        const ImageInfo im = c.img[i];
+        const ImageInfo im = imgs[i];
         const float* X = c.xform + ((size_t)i * (s.n_bodies + 1) + slot) * 16;
         float A[9];
 #pragma unroll
@@ -169,7 +177,9 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
         }
         const bool vis = ok && r1 > r0 && c1 > c0;
         if (valid) c.keyz[o] = vis ? __float_as_uint(D) : kInvalidKey;
-        if (__ballot(vis) != 0ull) {            // wave-uniform; every lane takes part
+        const uint64_t vmask = __ballot(vis);
+        if (vmask == 0ull) continue;            // wave-uniform
+        {
             // the wave's smallest and largest visible key: the depth sort runs
             // on keys relative to the image's smallest
             const uint32_t kb = __float_as_uint(D);
@@ -180,31 +190,41 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, i
                 atomicMax(&c.kmm[2 * i + 1], hi);
             }
         }
-        if (!vis) continue;
-        const int x0 = c0 / ts, x1 = (c1 + ts - 1) / ts, y0 = r0 / ts, y1 = (r1 + ts - 1) / ts;
-        put_rect(c.rect, c.rect4, o, (uint32_t)x0, (uint32_t)x1, (uint32_t)y0, (uint32_t)y1);
-        // whitening W = S^-1 (A Rg)^T: row k = (A Rg)[:, k] / s_k
-        float Rs[9];
-        mat3_mul(A, Rg, Rs);
-        float W[9];
+        if (vis) {
+            const int x0 = c0 / ts, x1 = (c1 + ts - 1) / ts, y0 = r0 / ts, y1 = (r1 + ts - 1) / ts;
+            put_rect(c.rect, c.rect4, o, (uint32_t)x0, (uint32_t)x1, (uint32_t)y0, (uint32_t)y1);
+            // whitening W = S^-1 (A Rg)^T: row k = (A Rg)[:, k] / s_k
+            float Rs[9];
+            mat3_mul(A, Rg, Rs);
+            float W[9];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) W[3 * k + j] = Rs[3 * j + k] * isc[k];
-        const float w0 = (W[0] * tx + W[1] * ty) + W[2] * tz;
-        const float w1 = (W[3] * tx + W[4] * ty) + W[5] * tz;
-        const float w2 = (W[6] * tx + W[7] * ty) + W[8] * tz;
-        float4* rec = c.rec + kLidarRec * o;
-        rec[0] = make_float4(W[0], W[1], W[2], tx);
-        rec[1] = make_float4(W[3], W[4], W[5], ty);
-        rec[2] = make_float4(W[6], W[7], W[8], tz);
-        rec[3] = make_float4(log2o, w0, w1, w2);
-        if (grid) {
-            rec[4] = make_float4(tx, ty, disc, 0.0f);
-        } else {
-            const float iD = 1.0f / D;
-            rec[4] = make_float4(tx * iD, ty * iD, tz * iD, cone_c);
+                for (int j = 0; j < 3; ++j) W[3 * k + j] = Rs[3 * j + k] * isc[k];
+            const float w0 = (W[0] * tx + W[1] * ty) + W[2] * tz;
+            const float w1 = (W[3] * tx + W[4] * ty) + W[5] * tz;
+            const float w2 = (W[6] * tx + W[7] * ty) + W[8] * tz;
+            float4* r = st + kLidarRec * lane;
+            r[0] = make_float4(W[0], W[1], W[2], tx);
+            r[1] = make_float4(W[3], W[4], W[5], ty);
+            r[2] = make_float4(W[6], W[7], W[8], tz);
+            r[3] = make_float4(log2o, w0, w1, w2);
+            if (grid) {
+                r[4] = make_float4(tx, ty, disc, 0.0f);
+            } else {
+                const float iD = 1.0f / D;
+                r[4] = make_float4(tx * iD, ty * iD, tz * iD, cone_c);
+            }
         }
+        wave_lds_sync();
+        // float4 q of the wave's records belongs to lane q / kLidarRec
+        float4* rec = c.rec + kLidarRec * ((size_t)i * (size_t)s.n + (size_t)(g_lane - lane));
+#pragma unroll
+        for (int k = 0; k < kLidarRec; ++k) {
+            const int q = lane + 64 * k;
+            if ((vmask >> (q / kLidarRec)) & 1ull) store_stream(rec + q, st[q]);
+        }
+        wave_lds_sync();
     }
 }
 
@@ -414,7 +434,7 @@ template <int ST>
 hipError_t project_lidar_st(const SceneDev& s, const ChunkDev& c, int ts, int ipt, hipStream_t st)
 {
     const dim3 grid((unsigned)((s.n + 255) / 256), (unsigned)((c.n_img + ipt - 1) / ipt));
-    hipLaunchKernelGGL((k_project_lidar<ST>), grid, dim3(256), 0, st, s, c, ts, ipt);
+    hipLaunchKernelGGL((k_project_lidar<ST>), grid, dim3(256), 0, st, s, c, c.img, ts, ipt);
     return hipGetLastError();
 }
 
