@@ -170,8 +170,8 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, 
 }
 
 template <typename R>
-__device__ __forceinline__ void write_last(const uint32_t* skey, const uint32_t* sval, const uint32_t* lstart,
-                                           const uint32_t* gbase, uint32_t n_items, int shift, uint64_t n, size_t seg,
+__device__ __forceinline__ void write_last(const uint32_t* skey, const uint32_t* sval, const uint32_t* delta,
+                                           uint32_t n_items, int shift, uint64_t n, size_t seg,
                                            uint32_t* __restrict__ vout, const R* __restrict__ rect,
                                            R* __restrict__ srect, uint32_t* __restrict__ err)
 {
@@ -188,7 +188,7 @@ __device__ __forceinline__ void write_last(const uint32_t* skey, const uint32_t*
         if (t < n_items) {
             const uint32_t k = skey[t], v = sval[t];
             const uint32_t dg = (k >> shift) & kDigitMask;
-            const uint32_t p = gbase[dg] + (t - lstart[dg]);
+            const uint32_t p = delta[dg] + t;
             if (p >= n) atomicOr(err, kErrSortSlot);     // offsets are consistent by construction
             if (p < n) {
                 pos[q] = p;
@@ -220,9 +220,13 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
                                                       const uint2* __restrict__ rect, uint2* __restrict__ srect,
                                                       int rect4, uint32_t* __restrict__ err)
 {
-    __shared__ uint32_t cnt[4][kRadix];
-    __shared__ uint32_t lstart[kRadix], gbase[kRadix], lds8[8];
+    // per-wave digit counts, then per-wave running positions, as 16-bit
+    // halves (a wave counts at most 1024 items, a block places 4096): with
+    // one offset per digit the block's LDS fits four blocks per CU
+    __shared__ uint32_t cnt32[4][kRadix / 2];
+    __shared__ uint32_t delta[kRadix], lds8[8];          // global position - block-local position, per digit
     __shared__ uint32_t skey[kSortItems], sval[kSortItems];
+    uint16_t (*cnt)[kRadix] = reinterpret_cast<uint16_t (*)[kRadix]>(cnt32);
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), tid = threadIdx.x;
     const int w = tid >> 6, lane = __lane_id();
@@ -258,13 +262,14 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
         }
     }
 #pragma unroll
-    for (int ww = 0; ww < 4; ++ww)
-#pragma unroll
-        for (int q = 0; q < kDpt; ++q) cnt[ww][tid + 256 * q] = 0;
+    for (int ww = 0; ww < 4; ++ww) cnt32[ww][tid] = 0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kSortIpt; ++k)
-        if (ok[k]) atomicAdd(&cnt[w][(key[k] >> shift) & kDigitMask], 1u);
+        if (ok[k]) {
+            const uint32_t dg = (key[k] >> shift) & kDigitMask;
+            atomicAdd(&cnt32[w][dg >> 1], 1u << (16 * (dg & 1u)));
+        }
     __syncthreads();
     // block-local layout: digit-major, and within a digit wave-major, each
     // wave's items in order -- the stable order of the block's items.  Thread
@@ -277,12 +282,11 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
         uint32_t total;
         const uint32_t start = n_items + block_excl_scan256(c0 + c1 + c2 + c3, &total, lds8);
         n_items += total;
-        lstart[dg] = start;
-        gbase[dg] = hist[((size_t)i * blocks + b) * kRadix + dg];
-        cnt[0][dg] = start;
-        cnt[1][dg] = start + c0;
-        cnt[2][dg] = start + c0 + c1;
-        cnt[3][dg] = start + c0 + c1 + c2;
+        delta[dg] = hist[((size_t)i * blocks + b) * kRadix + dg] - start;
+        cnt[0][dg] = (uint16_t)start;
+        cnt[1][dg] = (uint16_t)(start + c0);
+        cnt[2][dg] = (uint16_t)(start + c0 + c1);
+        cnt[3][dg] = (uint16_t)(start + c0 + c1 + c2);
     }
     __syncthreads();
     const uint64_t lt = lanemask_lt();
@@ -293,7 +297,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
         if (ok[k]) {
             const uint32_t basev = cnt[w][dg];
             const uint32_t lpos = basev + (uint32_t)__popcll(peers & lt);
-            if (lane == __ffsll((unsigned long long)peers) - 1) cnt[w][dg] = basev + (uint32_t)__popcll(peers);
+            if (lane == __ffsll((unsigned long long)peers) - 1) cnt[w][dg] = (uint16_t)(basev + (uint32_t)__popcll(peers));
             if (lpos < (uint32_t)kSortItems) {     // lpos < n_items <= kSortItems by construction
                 skey[lpos] = key[k];
                 sval[lpos] = val[k];
@@ -306,15 +310,15 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
     // write out in block-local order: consecutive threads write consecutive
     // addresses inside each digit's run
     if (last) {
-        if (rect4) write_last(skey, sval, lstart, gbase, n_items, shift, n, seg, vout,
+        if (rect4) write_last(skey, sval, delta, n_items, shift, n, seg, vout,
                               reinterpret_cast<const uint32_t*>(rect), reinterpret_cast<uint32_t*>(srect), err);
-        else write_last(skey, sval, lstart, gbase, n_items, shift, n, seg, vout, rect, srect, err);
+        else write_last(skey, sval, delta, n_items, shift, n, seg, vout, rect, srect, err);
         return;
     }
     for (uint32_t t = (uint32_t)tid; t < n_items; t += 256u) {
         const uint32_t k = skey[t], v = sval[t];
         const uint32_t dg = (k >> shift) & kDigitMask;
-        const uint32_t pos = gbase[dg] + (t - lstart[dg]);
+        const uint32_t pos = delta[dg] + t;
         if (pos >= n) atomicOr(err, kErrSortSlot);     // offsets are consistent by construction
         if (pos < n) {
             kout[seg + pos] = k;
