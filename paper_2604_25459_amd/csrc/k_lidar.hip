@@ -33,6 +33,7 @@ namespace {
 constexpr float kLidarLogAlphaMin = -7.99435343685886f;   // log2(1/255)
 constexpr float kHalfPi = 1.5707963267948966f;
 constexpr float kTwoPi = 6.283185307179586f;
+constexpr int kLdsBeams = 256;      // angular scans with at most this many beams search their elevations in LDS
 constexpr int kLidarRec = 5;        // float4s per record: whitening rows + centre, log2 o + W t, cone
 
 // First index r in [0, H) with v[r] >= x (strict = false) or v[r] > x
@@ -84,6 +85,9 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
                                                        int ts, int ipt)
 {
     __shared__ float4 stage[4][kLidarRec * 64];
+    // the elevation table of the current angular image (up to kLdsBeams beams;
+    // the row search reads it ten times per Gaussian)
+    __shared__ float elev_s[kLdsBeams];
     float4* const st = stage[threadIdx.x >> 6];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
@@ -109,6 +113,13 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
         const int i = __builtin_amdgcn_readfirstlane(i_begin + ii);     // the same in every lane
         if (i >= c.n_img) break;
         const ImageInfo im = imgs[i];
+        const bool lds_elev = im.kind == 1 && im.height <= kLdsBeams;     // block-uniform
+        if (lds_elev) {
+            __syncthreads();                    // the previous image's table is no longer read
+            if ((int)threadIdx.x < im.height) elev_s[threadIdx.x] = im.elev[threadIdx.x];
+            __syncthreads();
+        }
+        const float* ev = lds_elev ? elev_s : im.elev;
         const float* X = c.xform + ((size_t)i * (s.n_bodies + 1) + slot) * 16;
         float A[9];
 #pragma unroll
@@ -145,8 +156,8 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
                 const float ang = asinf(rho / D) * 1.0001f + 2e-6f;
                 cone_c = cosf(ang);
                 const float el = asinf(fminf(1.0f, fmaxf(-1.0f, tz / D)));
-                r0 = first_at_least(im.elev, im.height, el - ang, false);   // rows with el - ang <= elev
-                r1 = first_at_least(im.elev, im.height, el + ang, true);    // ... <= el + ang
+                r0 = first_at_least(ev, im.height, el - ang, false);   // rows with el - ang <= elev
+                r1 = first_at_least(ev, im.height, el + ang, true);    // ... <= el + ang
                 if (fabsf(el) + ang >= kHalfPi - 1e-4f) {
                     c0 = 0;
                     c1 = im.width;
