@@ -164,8 +164,9 @@ def test_autotune_and_cache_roundtrip(tmp_path):
 
 def test_schedules_agree_on_wide_splats():
     """Splats wider than the image cover every column of a transposed group
-    (64 entries x 64 columns all set); both level-2 schedules must still
-    produce the same pixels bit for bit."""
+    (64 entries x 64 columns all set, so a tile list takes more than one
+    128-byte line per group); both list schedules must still produce the same
+    pixels bit for bit."""
     torch = _torch()
     from paper_2604_25459_amd import gsr
     from tests.scenes import one_camera, scene_from
@@ -189,8 +190,9 @@ def test_schedules_agree_on_wide_splats():
 
 
 def test_transposed_schedule_on_a_wide_image():
-    """1920 x 1080 at 16-pixel tiles: 120 tile columns, so the transposed
-    level-2 schedule runs two 64-column windows per row segment.  Its tile lists
+    """1920 x 1080 at 16-pixel tiles: 120 tile columns and 68 tile rows, so
+    the transposed schedule runs two 64-column windows per row segment at
+    level 2 and two 64-row windows per block at level 1.  Its tile lists
     equal the oracle's bit for bit, and both schedules give the same pixels."""
     torch = _torch()
     from paper_2604_25459_amd import gsr, synth
