@@ -88,6 +88,7 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
     // the elevation table of the current angular image (up to kLdsBeams beams;
     // the row search reads it ten times per Gaussian)
     __shared__ float elev_s[kLdsBeams];
+    __shared__ uint32_t red[8];
     float4* const st = stage[threadIdx.x >> 6];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
@@ -189,18 +190,10 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
         const bool vis = ok && r1 > r0 && c1 > c0;
         if (valid) c.keyz[o] = vis ? __float_as_uint(D) : kInvalidKey;
         const uint64_t vmask = __ballot(vis);
+        // the image's key range (the depth sort runs on keys relative to its
+        // smallest); every wave of the block takes part
+        fold_key_range(&c.kmm[kKmmStride * i], __float_as_uint(D), vis, red);
         if (vmask == 0ull) continue;            // wave-uniform
-        {
-            // the wave's smallest and largest visible key: the depth sort runs
-            // on keys relative to the image's smallest
-            const uint32_t kb = __float_as_uint(D);
-            const uint32_t hi = wave_last(wave_incl_max(vis ? kb : 0u));
-            const uint32_t lo = ~wave_last(wave_incl_max(vis ? ~kb : 0u));
-            if (lane == 0) {
-                atomicMin(&c.kmm[2 * i], lo);
-                atomicMax(&c.kmm[2 * i + 1], hi);
-            }
-        }
         if (vis) {
             const int x0 = c0 / ts, x1 = (c1 + ts - 1) / ts, y0 = r0 / ts, y1 = (r1 + ts - 1) / ts;
             put_rect(c.rect, c.rect4, o, (uint32_t)x0, (uint32_t)x1, (uint32_t)y0, (uint32_t)y1);
@@ -454,6 +447,7 @@ hipError_t project_lidar_st(const SceneDev& s, const ChunkDev& c, int ts, int ip
 hipError_t launch_project_lidar(const SceneDev& s, const ChunkDev& c, int ts, int ipt, hipStream_t stream)
 {
     if (s.n == 0 || c.n_img == 0) return hipSuccess;
+    ipt = std::max(1, std::min(ipt, c.n_img / 32));     // small chunks: more threads, fewer images each
     if (s.storage == kF16) return project_lidar_st<kF16>(s, c, ts, ipt, stream);
     if (s.storage == kBF16) return project_lidar_st<kBF16>(s, c, ts, ipt, stream);
     return project_lidar_st<kF32>(s, c, ts, ipt, stream);

@@ -36,8 +36,8 @@ __global__ __launch_bounds__(256) void k_compose(SceneDev s, ChunkDev c, const f
     if (slot == 0) {
         // the image's smallest and largest visible depth key, narrowed by the
         // projection from (no key: smallest > largest)
-        c.kmm[2 * i] = 0xFFFFFFFFu;
-        c.kmm[2 * i + 1] = 0u;
+        c.kmm[kKmmStride * i] = 0xFFFFFFFFu;
+        c.kmm[kKmmStride * i + 1] = 0u;
     }
     const float* vm = viewmats + im.vm_off;
     float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
@@ -154,6 +154,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, const I
                                                  const float* __restrict__ xform, int ts, float cutoff, int ipt)
 {
     __shared__ float4 stage[4][3 * 64];
+    __shared__ uint32_t red[8];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
     const int64_t g_lane = (int64_t)bx * 256 + threadIdx.x;
@@ -287,18 +288,10 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, const I
         const size_t o = (size_t)i * (size_t)s.n + (size_t)g_lane;
         if (valid) c.keyz[o] = vis ? __float_as_uint(tz) : kInvalidKey;
         const uint64_t vmask = __ballot(vis);
+        // the image's key range (the depth sort runs on keys relative to its
+        // smallest); every wave of the block takes part
+        fold_key_range(&c.kmm[kKmmStride * i], __float_as_uint(tz), vis, red);
         if (vmask == 0ull) return;              // wave-uniform
-        {
-            // the wave's smallest and largest visible key: the depth sort runs
-            // on keys relative to the image's smallest
-            const uint32_t kb = __float_as_uint(tz);
-            const uint32_t hi = wave_last(wave_incl_max(vis ? kb : 0u));
-            const uint32_t lo = ~wave_last(wave_incl_max(vis ? ~kb : 0u));
-            if (lane == 0) {
-                atomicMin(&c.kmm[2 * i], lo);
-                atomicMax(&c.kmm[2 * i + 1], hi);
-            }
-        }
         if (vis) {
             put_rect(c.rect, c.rect4, o, (uint32_t)ix0, (uint32_t)ix1, (uint32_t)iy0, (uint32_t)iy1);
 
@@ -419,6 +412,9 @@ static hipError_t project_st(const SceneDev& s, const ChunkDev& c, int ts, float
 hipError_t launch_project(const SceneDev& s, const ChunkDev& c, int ts, float cutoff, int ipt, hipStream_t stream)
 {
     if (s.n == 0 || c.n_img == 0) return hipSuccess;
+    // small chunks (serving requests of a few dozen images) spread their
+    // images over more threads: a thread's images run one after another
+    ipt = std::max(1, std::min(ipt, c.n_img / 32));
     if (s.storage == kF16) return project_st<kF16>(s, c, ts, cutoff, ipt, stream);
     if (s.storage == kBF16) return project_st<kBF16>(s, c, ts, cutoff, ipt, stream);
     return project_st<kF32>(s, c, ts, cutoff, ipt, stream);

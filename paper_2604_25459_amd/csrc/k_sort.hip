@@ -78,7 +78,7 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* tot
 // largest and needs no pass at all).
 __device__ __forceinline__ bool wide_image(const uint32_t* kmm, int i)
 {
-    const uint32_t lo = kmm[2 * i], hi = kmm[2 * i + 1];
+    const uint32_t lo = kmm[kKmmStride * i], hi = kmm[kKmmStride * i + 1];
     return hi >= lo && hi - lo >= kNarrowSpan;
 }
 // Buffer written by pass p of an image (three-pass images: 0, 1, 0; four-pass
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ 
     for (int q = 0; q < kDpt; ++q) h[tid + 256 * q] = 0;
     __syncthreads();
     const uint32_t* kin = (FIRST || out_buf(pass - 1, wide) == 0 ? k0 : k1) + (size_t)i * n;
-    const uint32_t lo = FIRST ? kmm[2 * i] : 0u;
+    const uint32_t lo = FIRST ? kmm[kKmmStride * i] : 0u;
     const int shift = kBits * pass;
     // all loads first, then the LDS atomics: each thread's loads overlap
     uint32_t key[kSortIpt];
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t* __restrict
     const uint32_t* vin = ib ? sv1 : sv0;
     uint32_t* kout = ob ? sk1 : sk0;
     uint32_t* vout = ob ? sv1 : sv0;
-    const uint32_t lo = FIRST ? kmm[2 * i] : 0u;
+    const uint32_t lo = FIRST ? kmm[kKmmStride * i] : 0u;
     const int shift = kBits * pass;
 
     uint32_t key[kSortIpt], val[kSortIpt];
