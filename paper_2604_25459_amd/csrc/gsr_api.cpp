@@ -226,7 +226,7 @@ size_t per_image_bytes(const SceneRes* sc, int t_max, int ty_max, int sort_block
     const size_t n = (size_t)sc->dev.n;
     size_t b = n * (4 + 16 + rec_bytes + 16);                          // key, rect + sorted rect, record, sort buffers
     b += (size_t)(sc->dev.n_bodies + 1) * 64;                          // transforms
-    b += (size_t)sort_blocks * 512 * 4 + (size_t)tile_blocks * ty_max * 4 + (size_t)(t_max + ty_max) * 8 + kKmmStride * 4;
+    b += (size_t)sort_blocks * (512 + 2) * 4 + (size_t)tile_blocks * ty_max * 4 + (size_t)(t_max + ty_max) * 8 + kKmmStride * 4;
     b += (size_t)(t_max + 2 * ty_max + 1) * 4;                         // tile difference array (bound)
     b += n * 8 * 4 + n * 3 * 8 + sizeof(ImageInfo) + 64;               // pair / row-entry estimates
     return b;
@@ -296,7 +296,7 @@ WorkspaceSizes workspace_sizes(const SceneRes* sc, const ChunkPlan& p, size_t n_
     add(&Workspace::sk1, I * n * 4);
     add(&Workspace::sv0, I * n * 4);
     add(&Workspace::sv1, I * n * 4);
-    add(&Workspace::sort_hist, I * p.sort_blocks * 512 * 4);
+    add(&Workspace::sort_hist, I * p.sort_blocks * (512 + 2) * 4);     // digit counts, then per-block key ranges
     add(&Workspace::kmm, I * kKmmStride * 4);
     add(&Workspace::vis_count, I * 4);
     add(&Workspace::tile_hist, I * (size_t)(p.tx_max + 1) * (p.ty_max + 1) * 4);
@@ -399,6 +399,7 @@ ChunkDev chunk_view(Workspace& ws, const SceneRes* sc, const ChunkPlan& p, int i
     c.sv[1] = ws.sv1.as<uint32_t>();
     c.sort_hist = ws.sort_hist.as<uint32_t>();
     c.kmm = ws.kmm.as<uint32_t>();
+    c.kblk = c.sort_hist + (size_t)p.chunk * p.sort_blocks * 512;
     c.vis_count = ws.vis_count.as<uint32_t>();
     c.tile_hist = ws.tile_hist.as<int32_t>();
     c.tile_range = ws.tile_range.as<uint32_t>();

@@ -131,7 +131,8 @@ struct ChunkDev {
     uint32_t* sv[2];           // depth-sort values (Gaussian ids); sorted result in sv[0]
     uint2* srect;              // [n_img][n] tile rectangle of the j-th depth-ordered Gaussian
     uint32_t* sort_hist;       // [n_img][sort_blocks][512]
-    uint32_t* kmm;             // [n_img][kKmmStride]: smallest, largest visible depth key (projection)
+    uint32_t* kmm;             // [n_img][kKmmStride]: smallest visible key rounded down to 512, largest
+    uint32_t* kblk;            // [n_img][sort_blocks][2] smallest, largest visible key of each pass-0 block
     uint32_t* vis_count;       // [n_img] visible Gaussians V_i
     int32_t* tile_hist;       // [n_img][(tx_max + 1) (ty_max + 1)] 2D difference array of tile counts
     uint32_t* tile_range;      // [n_img][t_max][2] local [start, end)
@@ -167,9 +168,8 @@ constexpr uint32_t kErrSortSlot = 2u;     // a depth-sort rank or offset fell ou
 constexpr uint32_t kErrRowEntry = 4u;     // a depth-ordered id >= n reached the tile-row expansion
 
 // Depth sort geometry.
-// Words per image of ChunkDev::kmm: one 128-byte line each, so that the
-// projection's atomics on different images go to different L2 channels.
-constexpr int kKmmStride = 32;
+// Words per image of ChunkDev::kmm (smallest and largest visible key).
+constexpr int kKmmStride = 2;
 constexpr int kSortBlock = 256;
 constexpr int kSortIpt = 16;
 constexpr int kSortItems = kSortBlock * kSortIpt;   // 4096 items per block

@@ -54,34 +54,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Folds the smallest and largest `key` among this block's lanes with `vis`
-// into range[0] (atomic min) and range[1] (atomic max): waves combine through
-// `red` (8 words of LDS), one thread issues the two atomics.  Every thread of
-// the (256-thread) block must call it.
-__device__ __forceinline__ void fold_key_range(uint32_t* range, uint32_t key, bool vis, uint32_t* red)
-{
-    const uint32_t hi = wave_last(wave_incl_max(vis ? key : 0u));
-    const uint32_t lo = ~wave_last(wave_incl_max(vis ? ~key : 0u));
-    const int w = (int)(threadIdx.x >> 6);
-    if (__lane_id() == 0) {
-        red[2 * w] = lo;
-        red[2 * w + 1] = hi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t l = red[0], h = red[1];
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
-            l = min(l, red[2 * k]);
-            h = max(h, red[2 * k + 1]);
-        }
-        if (l <= h) {                   // some lane of the block holds a key
-            atomicMin(range, l);
-            atomicMax(range + 1, h);
-        }
-    }
-    __syncthreads();
-}
-
 // Orders this wave's LDS writes before its later LDS reads (no instruction:
 // LDS requests of one wave are served in order; this keeps the compiler from
 // moving accesses across it).

@@ -88,7 +88,6 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
     // the elevation table of the current angular image (up to kLdsBeams beams;
     // the row search reads it ten times per Gaussian)
     __shared__ float elev_s[kLdsBeams];
-    __shared__ uint32_t red[8];
     float4* const st = stage[threadIdx.x >> 6];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
@@ -190,9 +189,6 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
         const bool vis = ok && r1 > r0 && c1 > c0;
         if (valid) c.keyz[o] = vis ? __float_as_uint(D) : kInvalidKey;
         const uint64_t vmask = __ballot(vis);
-        // the image's key range (the depth sort runs on keys relative to its
-        // smallest); every wave of the block takes part
-        fold_key_range(&c.kmm[kKmmStride * i], __float_as_uint(D), vis, red);
         if (vmask == 0ull) continue;            // wave-uniform
         if (vis) {
             const int x0 = c0 / ts, x1 = (c1 + ts - 1) / ts, y0 = r0 / ts, y1 = (r1 + ts - 1) / ts;

@@ -33,12 +33,6 @@ __global__ __launch_bounds__(256) void k_compose(SceneDev s, ChunkDev c, const f
     const int i = idx / slots;
     const int slot = idx - i * slots;
     const ImageInfo im = c.img[i];
-    if (slot == 0) {
-        // the image's smallest and largest visible depth key, narrowed by the
-        // projection from (no key: smallest > largest)
-        c.kmm[kKmmStride * i] = 0xFFFFFFFFu;
-        c.kmm[kKmmStride * i + 1] = 0u;
-    }
     const float* vm = viewmats + im.vm_off;
     float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
     float tc[3] = {vm[3], vm[7], vm[11]};
@@ -154,7 +148,6 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, const I
                                                  const float* __restrict__ xform, int ts, float cutoff, int ipt)
 {
     __shared__ float4 stage[4][3 * 64];
-    __shared__ uint32_t red[8];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
     const int64_t g_lane = (int64_t)bx * 256 + threadIdx.x;
@@ -288,9 +281,6 @@ __global__ __launch_bounds__(256) void k_project(SceneDev s, ChunkDev c, const I
         const size_t o = (size_t)i * (size_t)s.n + (size_t)g_lane;
         if (valid) c.keyz[o] = vis ? __float_as_uint(tz) : kInvalidKey;
         const uint64_t vmask = __ballot(vis);
-        // the image's key range (the depth sort runs on keys relative to its
-        // smallest); every wave of the block takes part
-        fold_key_range(&c.kmm[kKmmStride * i], __float_as_uint(tz), vis, red);
         if (vmask == 0ull) return;              // wave-uniform
         if (vis) {
             put_rect(c.rect, c.rect4, o, (uint32_t)ix0, (uint32_t)ix1, (uint32_t)iy0, (uint32_t)iy1);

@@ -5,9 +5,9 @@
 // key array in index order and drops culled entries, so equal depths keep
 // ascending index -- the tie rule of the key sort.
 //
-// The sort runs on the key less the image's smallest visible key (the
-// projection records each image's smallest and largest key), in 9-bit
-// digits: three passes order an image whose keys lie within 2^27 of each
+// The sort runs on the key less the image's smallest visible key (rounded
+// down to a multiple of 512; the first pass's histogram blocks record their
+// key ranges and its scan combines them), in 9-bit digits: three passes order an image whose keys lie within 2^27 of each
 // other (depths within a factor of about 2^16), a fourth pass (the top five
 // bits) runs only for images that need it.  The two ping-pong buffers are
 // used in opposite order by three- and four-pass images, so every image's
@@ -85,18 +85,22 @@ __device__ __forceinline__ bool wide_image(const uint32_t* kmm, int i)
 // images: 1, 0, 1, 0 -- the sorted values land in sv[0] either way).
 __device__ __forceinline__ int out_buf(int pass, bool wide) { return (pass + (wide ? 1 : 0)) & 1; }
 
-// Per-block digit counts of pass `pass` (FIRST: the dense keys, culled
-// entries dropped, digits of the key less the image's smallest).
+// Per-block digit counts of pass `pass`.  FIRST: the dense keys, culled
+// entries dropped; the image's smallest key is not known yet, but it is
+// taken rounded down to a multiple of 512, so the lowest digit of a key less
+// it is the key's own lowest digit; the block also records its smallest and
+// largest visible key (kblk) for the scan to combine.
 template <bool FIRST>
 __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ k0, const uint32_t* __restrict__ k1,
                                                    const uint32_t* __restrict__ counts,
                                                    const uint32_t* __restrict__ kmm, uint64_t n, int pass,
-                                                   uint32_t* __restrict__ hist, int blocks)
+                                                   uint32_t* __restrict__ hist, int blocks, uint32_t* __restrict__ kblk)
 {
     __shared__ uint32_t h[kRadix];
+    __shared__ uint32_t red[8];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int i = (int)(L / gridDim.x), b = (int)(L - (uint32_t)i * gridDim.x), tid = threadIdx.x;
-    const bool wide = wide_image(kmm, i);
+    const bool wide = !FIRST && wide_image(kmm, i);
     if (pass == 3 && !wide) return;     // block-uniform: three passes order this image
     const uint64_t cnt = FIRST ? n : counts[i];
     const uint64_t base = (uint64_t)b * kSortItems;
@@ -105,7 +109,6 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ 
     for (int q = 0; q < kDpt; ++q) h[tid + 256 * q] = 0;
     __syncthreads();
     const uint32_t* kin = (FIRST || out_buf(pass - 1, wide) == 0 ? k0 : k1) + (size_t)i * n;
-    const uint32_t lo = FIRST ? kmm[kKmmStride * i] : 0u;
     const int shift = kBits * pass;
     // all loads first, then the LDS atomics: each thread's loads overlap
     uint32_t key[kSortIpt];
@@ -114,27 +117,65 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ 
         const uint64_t idx = base + (uint64_t)k * 256 + tid;
         key[k] = idx < cnt ? kin[idx] : kInvalidKey;
     }
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
 #pragma unroll
     for (int k = 0; k < kSortIpt; ++k) {
         const uint64_t idx = base + (uint64_t)k * 256 + tid;
-        if (idx < cnt && (!FIRST || key[k] != kInvalidKey)) atomicAdd(&h[((key[k] - lo) >> shift) & kDigitMask], 1u);
+        if (idx < cnt && (!FIRST || key[k] != kInvalidKey)) {
+            atomicAdd(&h[(key[k] >> shift) & kDigitMask], 1u);
+            kmin = min(kmin, key[k]);
+            kmax = max(kmax, key[k]);
+        }
+    }
+    if (FIRST) {
+        // the wave's smallest and largest visible key (prefix maxima of the key and its complement)
+        const uint32_t hi = wave_last(wave_incl_max(kmax)), lo = ~wave_last(wave_incl_max(~kmin));
+        if (__lane_id() == 0) {
+            red[2 * (tid >> 6)] = lo;
+            red[2 * (tid >> 6) + 1] = hi;
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kDpt; ++q) hist[((size_t)i * blocks + b) * kRadix + tid + 256 * q] = h[tid + 256 * q];
+    if (FIRST && tid == 0) {
+        kblk[((size_t)i * blocks + b) * 2] = min(min(red[0], red[2]), min(red[4], red[6]));
+        kblk[((size_t)i * blocks + b) * 2 + 1] = max(max(red[1], red[3]), max(red[5], red[7]));
+    }
 }
 
 // Per image: digit-major, block-minor exclusive offsets (in place).  Pass 0
 // also records the number of visible Gaussians.
 template <bool FIRST>
 __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, int blocks, uint32_t* __restrict__ counts,
-                                                   const uint32_t* __restrict__ kmm, uint64_t n, int pass)
+                                                   uint32_t* __restrict__ kmm, uint64_t n, int pass,
+                                                   const uint32_t* __restrict__ kblk)
 {
-    __shared__ uint32_t lds8[8];
+    __shared__ uint32_t lds8[8], red[8];
     const int i = blockIdx.x, d = threadIdx.x;
     if (pass == 3 && !wide_image(kmm, i)) return;
     const uint64_t cnt = FIRST ? n : counts[i];
     const int nb = (int)((cnt + kSortItems - 1) / kSortItems);
+    if (FIRST) {
+        // the image's key range from its blocks' ranges; the smallest key is
+        // kept rounded down to a multiple of 512 (see k_sort_hist)
+        uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+        for (int b = d; b < nb; b += 256) {
+            kmin = min(kmin, kblk[((size_t)i * blocks + b) * 2]);
+            kmax = max(kmax, kblk[((size_t)i * blocks + b) * 2 + 1]);
+        }
+        const uint32_t hi = wave_last(wave_incl_max(kmax)), lo = ~wave_last(wave_incl_max(~kmin));
+        if (__lane_id() == 0) {
+            red[2 * (d >> 6)] = lo;
+            red[2 * (d >> 6) + 1] = hi;
+        }
+        __syncthreads();
+        if (d == 0) {
+            const uint32_t l = min(min(red[0], red[2]), min(red[4], red[6]));
+            kmm[kKmmStride * i] = l <= max(max(red[1], red[3]), max(red[5], red[7])) ? (l & ~kDigitMask) : l;
+            kmm[kKmmStride * i + 1] = max(max(red[1], red[3]), max(red[5], red[7]));
+        }
+    }
     uint32_t* H = hist + (size_t)i * blocks * kRadix;
     // thread d owns digits d and d + 256: the scan runs over the first half,
     // then over the second half after the first half's total
@@ -336,18 +377,18 @@ hipError_t launch_depth_sort(const SceneDev& s, const ChunkDev& c, hipStream_t s
     const dim3 grid((unsigned)c.sort_blocks, (unsigned)c.n_img);
     // pass 0: dense keys (index order) -> compacted keys relative to the image's smallest, digit 0
     hipLaunchKernelGGL(k_sort_hist<true>, grid, dim3(256), 0, stream, c.keyz, (const uint32_t*)nullptr, c.vis_count,
-                       c.kmm, n, 0, c.sort_hist, c.sort_blocks);
+                       c.kmm, n, 0, c.sort_hist, c.sort_blocks, c.kblk);
     hipLaunchKernelGGL(k_sort_scan<true>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
-                       c.vis_count, c.kmm, n, 0);
+                       c.vis_count, c.kmm, n, 0, (const uint32_t*)c.kblk);
     hipLaunchKernelGGL(k_sort_scatter<true>, grid, dim3(256), 0, stream, c.keyz, c.sk[0], c.sk[1], c.sv[0], c.sv[1],
                        c.vis_count, c.kmm, n, 0, c.sort_hist, c.sort_blocks, c.rect, c.srect, c.rect4, c.err);
     // passes 1, 2 and (for images whose keys span 2^27 or more) 3; the blocks of
     // images that need no fourth pass leave at once
     for (int pass = 1; pass < 4; ++pass) {
         hipLaunchKernelGGL(k_sort_hist<false>, grid, dim3(256), 0, stream, c.sk[0], c.sk[1], c.vis_count, c.kmm, n,
-                           pass, c.sort_hist, c.sort_blocks);
+                           pass, c.sort_hist, c.sort_blocks, c.kblk);
         hipLaunchKernelGGL(k_sort_scan<false>, dim3(c.n_img), dim3(256), 0, stream, c.sort_hist, c.sort_blocks,
-                           c.vis_count, c.kmm, n, pass);
+                           c.vis_count, c.kmm, n, pass, (const uint32_t*)c.kblk);
         hipLaunchKernelGGL(k_sort_scatter<false>, grid, dim3(256), 0, stream, (const uint32_t*)nullptr, c.sk[0],
                            c.sk[1], c.sv[0], c.sv[1], c.vis_count, c.kmm, n, pass, c.sort_hist, c.sort_blocks, c.rect,
                            c.srect, c.rect4, c.err);
