@@ -107,7 +107,8 @@ def pmc_summary(fetch_csv, write_csv, out_path, command):
 
 def util_summary(counter_csv, agent_csv, out_path, command):
     """Condense one counter run (UTIL_COUNTERS) into the rasteriser's VALU
-    and LDS use per launch.  The SQ counters are summed over the SIMDs of
+    and LDS use per launch (and the same figures for every other kernel of
+    the run under "kernels").  The SQ counters are summed over the SIMDs of
     the chip; GRBM_GUI_ACTIVE over its XCDs, so it divided by their number is
     the launch's duration in shader clocks.  VALU busy = quad-cycles of VALU
     issue x 4 / (SIMDs x clocks); LDS busy = cycles with indexed LDS work /
@@ -117,28 +118,44 @@ def util_summary(counter_csv, agent_csv, out_path, command):
     n_xcc, cus = int(agent["Num_Xcc"]), int(agent["Cu_Count"])
     simds = cus * int(agent["Simd_Per_Cu"])
     clk_mhz = float(agent["Max_Engine_Clk_Fcompute"])
-    per = {}
+    per, names = {}, {}
     with open(counter_csv) as f:
         for r in csv.DictReader(f):
-            if "k_raster<" not in r["Kernel_Name"]:
+            name = r["Kernel_Name"]
+            if "copyBuffer" in name or "elementwise" in name or "fillBuffer" in name or "reduce_kernel" in name:
                 continue
             d = per.setdefault(r["Dispatch_Id"], {})
             d[r["Counter_Name"]] = float(r["Counter_Value"])
             d["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-    launches = [d for d in per.values() if all(c in d for c in UTIL_COUNTERS)]
-    if not launches:
-        raise SystemExit(f"no rasteriser dispatch with all of {UTIL_COUNTERS} in {counter_csv}")
-    rows = []
-    for d in launches:
+            names[r["Dispatch_Id"]] = (name.replace("void ", "").replace("gsr::", "")
+                                       .replace("(anonymous namespace)::", "").split("(")[0])
+
+    def util_row(d):
         clocks = d["GRBM_GUI_ACTIVE"] / n_xcc
-        rows.append({"ms": d["ns"] * 1e-6, "clock_ghz": clocks / d["ns"],
-                     "valu_busy": d["SQ_ACTIVE_INST_VALU"] * 4.0 / (simds * clocks),
-                     "valu_instr": d["SQ_INSTS_VALU"],
-                     "valu_issue": d["SQ_INSTS_VALU"] * 4.0 / (simds * clocks),
-                     "cu_busy": d["SQ_BUSY_CU_CYCLES"] * 4.0 / (simds * clocks),
-                     "lds_busy": d["SQ_LDS_IDX_ACTIVE"] / (cus * clocks),
-                     "lds_bytes": d["SQ_INSTS_LDS_LOAD_BANDWIDTH"] * 64.0})
+        return {"ms": d["ns"] * 1e-6, "clock_ghz": clocks / d["ns"],
+                "valu_busy": d["SQ_ACTIVE_INST_VALU"] * 4.0 / (simds * clocks),
+                "valu_instr": d["SQ_INSTS_VALU"],
+                "valu_issue": d["SQ_INSTS_VALU"] * 4.0 / (simds * clocks),
+                "cu_busy": d["SQ_BUSY_CU_CYCLES"] * 4.0 / (simds * clocks),
+                "lds_busy": d["SQ_LDS_IDX_ACTIVE"] / (cus * clocks),
+                "lds_bytes": d["SQ_INSTS_LDS_LOAD_BANDWIDTH"] * 64.0}
+
+    complete = {k: d for k, d in per.items() if all(c in d for c in UTIL_COUNTERS) and d["GRBM_GUI_ACTIVE"] > 0}
+    rows = [util_row(d) for k, d in complete.items() if names[k].startswith("k_raster<")]
+    if not rows:
+        raise SystemExit(f"no rasteriser dispatch with all of {UTIL_COUNTERS} in {counter_csv}")
     mean = {k: sum(r[k] for r in rows) / len(rows) for k in rows[0]}
+    # every other kernel of the run, launches of 50 us or more (shorter ones
+    # are mostly launch overhead and clock ramp)
+    by_kernel = {}
+    for k, d in complete.items():
+        if d["ns"] >= 50_000:
+            by_kernel.setdefault(names[k], []).append(util_row(d))
+    kernels = {}
+    for name, rs in sorted(by_kernel.items()):
+        m = {k: sum(r[k] for r in rs) / len(rs) for k in rs[0]}
+        kernels[name] = {"dispatches": len(rs), "avg_ms": m["ms"], "valu_issue_frac": m["valu_issue"],
+                         "valu_busy": m["valu_busy"], "lds_busy": m["lds_busy"]}
     lds_gbs = mean["lds_bytes"] / (mean["ms"] * 1e-3) / 1e9
     lds_peak = cus * LDS_BYTES_PER_CLK * clk_mhz * 1e6 / 1e9
     out = {"command": command, "source_sha256": raster_source_hash(), "sources": list(RASTER_SOURCES),
@@ -148,7 +165,7 @@ def util_summary(counter_csv, agent_csv, out_path, command):
            "valu_issue_basis": "wave64 VALU instructions x 4 cycles (16-lane SIMDs) / (SIMDs x shader clocks)",
            "cu_busy": mean["cu_busy"], "lds_busy": mean["lds_busy"], "lds_read_bytes_per_launch": mean["lds_bytes"],
            "lds_read_gbs": lds_gbs, "lds_peak_gbs": lds_peak, "lds_read_frac": lds_gbs / lds_peak,
-           "lds_peak_basis": f"{cus} CUs x {LDS_BYTES_PER_CLK} B/clock x {clk_mhz:.0f} MHz"}
+           "lds_peak_basis": f"{cus} CUs x {LDS_BYTES_PER_CLK} B/clock x {clk_mhz:.0f} MHz", "kernels": kernels}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")

@@ -39,18 +39,22 @@ __device__ __forceinline__ uint64_t lanemask_lt()
     return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 }
 
-// Lanes whose `key` equals this lane's, among lanes with `active` set.
+// Lanes whose `key` equals this lane's in its low BITS bits, among lanes
+// with `active` set: one ballot per bit; a lane differs from this one where
+// the ballot differs from this lane's bit (the bit spread to a whole word),
+// and the differences of all bits are ORed (three VALU per bit and half).
 template <int BITS>
 __device__ __forceinline__ uint64_t match_bits(uint32_t key, bool active)
 {
-    uint64_t peers = __ballot(active);
+    uint32_t dlo = 0u, dhi = 0u;
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
-        const bool bit = (key >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
+        const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int)key, b, 1);   // 0 or all ones
+        const uint64_t m = __builtin_amdgcn_uicmp(s, 0u, 33);                // ballot of s != 0
+        dlo |= (uint32_t)m ^ s;
+        dhi |= (uint32_t)(m >> 32) ^ s;
     }
-    return peers;
+    return __ballot(active) & ~(((uint64_t)dhi << 32) | dlo);
 }
 
 // Exclusive scan over the 256 threads of a block; returns the block total.

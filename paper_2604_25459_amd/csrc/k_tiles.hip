@@ -731,11 +731,20 @@ __device__ __forceinline__ void line_group(const LineLists<T>& L, uint32_t& cur,
     if (!far) {
         // every entry lies in its bucket's buffered line or the next one: the
         // two lines of a bucket sit in different slots, so one pass places
-        // all entries and the full lines leave afterwards
-        for (uint32_t b = lo; b < hi; ++b) {
-            const uint4 in = L.info[b];
-            const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
-            L.buf[(2u * b + (pos / LINE & 1u)) * LINE + pos % LINE] = v;
+        // all entries and the full lines leave afterwards.  Four buckets'
+        // table entries are read before their stores, so the wave waits for
+        // the LDS once per four buckets rather than once per bucket.
+        for (uint32_t b = lo; b < hi; b += 4u) {
+            uint4 in[4];
+#pragma unroll
+            for (uint32_t q = 0; q < 4u; ++q) in[q] = b + q < hi ? L.info[b + q] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (uint32_t q = 0; q < 4u; ++q) {
+                if (b + q >= hi) break;
+                const uint32_t pos =
+                    in[q].z + __builtin_amdgcn_mbcnt_hi(in[q].y, __builtin_amdgcn_mbcnt_lo(in[q].x, 0u));
+                L.buf[(2u * (b + q) + (pos / LINE & 1u)) * LINE + pos % LINE] = v;
+            }
         }
         wave_lds_sync();
         flush_lines(L, done, cur, first, 0xFFFFFFFFu);

@@ -92,6 +92,14 @@ def test_valu_lds_summary(tmp_path):
             (5, RASTER, "SQ_INSTS_LDS_LOAD_BANDWIDTH", 1e12 / 64, 0, ns),  # 1 TB read
             (5, RASTER, "SQ_INSTS_VALU", 0.9 * 1024 * clocks / 4, 0, ns),  # wave64 instructions: 90 % of issue
             (6, "k_project<0, 3>", "GRBM_GUI_ACTIVE", 1.0, 0, 1)]
+    # a 1 ms launch of another kernel at half the VALU issue rate
+    ns2, clocks2 = 1_000_000, 2.0 * 1_000_000
+    rows += [(7, "k_rowtile_rank", "GRBM_GUI_ACTIVE", clocks2 * 8, ns, ns + ns2),
+             (7, "k_rowtile_rank", "SQ_ACTIVE_INST_VALU", 0.5 * 1024 * clocks2 / 4, ns, ns + ns2),
+             (7, "k_rowtile_rank", "SQ_BUSY_CU_CYCLES", 1024 * clocks2 / 4, ns, ns + ns2),
+             (7, "k_rowtile_rank", "SQ_LDS_IDX_ACTIVE", 0.25 * 256 * clocks2, ns, ns + ns2),
+             (7, "k_rowtile_rank", "SQ_INSTS_LDS_LOAD_BANDWIDTH", 1e9 / 64, ns, ns + ns2),
+             (7, "k_rowtile_rank", "SQ_INSTS_VALU", 0.5 * 1024 * clocks2 / 4, ns, ns + ns2)]
     _write_counters(counters, rows)
     out = tmp_path / "util.json"
     bench.util_summary(str(counters), str(agent), str(out), "cmd")
@@ -106,6 +114,13 @@ def test_valu_lds_summary(tmp_path):
     assert s["lds_read_frac"] == pytest.approx(s["lds_read_gbs"] / s["lds_peak_gbs"])
     assert s["valu_issue_frac"] == pytest.approx(0.9)
     assert s["valu_instr_per_launch"] == pytest.approx(0.9 * 1024 * clocks / 4)
+    # per-kernel figures: complete launches only (the project row lacks counters)
+    assert set(s["kernels"]) == {"k_raster<16, 64, false>", "k_rowtile_rank"}
+    k = s["kernels"]["k_rowtile_rank"]
+    assert k["dispatches"] == 1 and k["avg_ms"] == pytest.approx(1.0)
+    assert k["valu_issue_frac"] == pytest.approx(0.5)
+    assert k["lds_busy"] == pytest.approx(0.25)
+    assert s["kernels"]["k_raster<16, 64, false>"]["valu_issue_frac"] == pytest.approx(0.9)
 
 
 def test_bench_refuses_more_than_one_gpu():
