@@ -358,8 +358,11 @@ __global__ __launch_bounds__(256) void k_image_scan(ChunkDev c)
 }
 
 // ------------------------------------------------------------------ level 1
-// Items are loaded this many groups of 64 ahead (see the header).
-constexpr int kAhead = 8;
+// Items are loaded this many groups of 64 ahead (see the header).  Two
+// rather than eight: the registers saved raise the transposed-rank kernels'
+// occupancy (level 2 from three to six waves per SIMD, with one line buffer
+// per bucket), which hides more latency than the deeper prefetch did.
+constexpr int kAhead = 2;
 // Independent waves per workgroup in the expansion kernels (each wave has its
 // own item range and LDS; more waves per CU than one-wave workgroups allow).
 constexpr int kWavesPerBlock = 4;
@@ -610,7 +613,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_rowtile_scatter(ChunkDe
 // the line that holds its cursor in LDS and writes it out once it is full.
 // Only lines that a single group fills from end to end go to memory
 // directly, and each list's first and last line are written in two parts
-// (the neighbouring list owns the rest of such a line).
+// (the neighbouring list owns the rest of such a line).  One line buffer per
+// bucket (6 KB per wave for 40 buckets) keeps the LDS below what the
+// registers allow (five waves per SIMD): the occupancy these kernels need to
+// hide their LDS and cross-lane latencies.
 
 // Value of lane (lane ^ S): DPP within quads (S = 1, 2) and rows (S = 8,
 // row_ror:8), LDS-crossbar swizzles within 32 lanes (S = 4, 16), a backward
@@ -663,8 +669,8 @@ __device__ __forceinline__ uint64_t transpose_bits64(uint64_t w)
 }
 
 // Line-buffered lists of one wave's window: `out` the list array (absolute
-// positions, none at or past `limit`), `buf` two 128-byte lines per bucket in
-// LDS (line l of a bucket in slot l & 1), `info` a 64-entry LDS table.
+// positions, none at or past `limit`), `buf` one 128-byte line per bucket in
+// LDS (the line that holds the bucket's cursor), `info` a 64-entry LDS table.
 template <typename T>
 struct LineLists {
     static constexpr uint32_t kLine = 128 / sizeof(T);     // entries per line
@@ -698,7 +704,7 @@ __device__ __forceinline__ void flush_lines(const LineLists<T>& L, uint64_t mask
         if (b < 64u) {
             const uint32_t line = cb / LINE;
             const uint32_t p0 = line * LINE + j * EPL;
-            const uint4 w = *reinterpret_cast<const uint4*>(L.buf + (2u * b + (line & 1u)) * LINE + j * EPL);
+            const uint4 w = *reinterpret_cast<const uint4*>(L.buf + b * LINE + j * EPL);
             if (p0 >= fb && p0 + EPL <= eb && p0 + EPL <= L.limit) {
                 *reinterpret_cast<uint4*>(L.out + p0) = w;          // 16-byte aligned: lines are
             } else {
@@ -713,7 +719,10 @@ __device__ __forceinline__ void flush_lines(const LineLists<T>& L, uint64_t mask
 
 // One group: this lane's item covers buckets [lo, hi) of the window (empty
 // when hi <= lo) and is stored as `v`; `cur` and `first` are the cursor and
-// first position of bucket `lane`.
+// first position of bucket `lane`.  An entry goes to its bucket's buffered
+// line if it lies there, to memory if it lies in a line the group fills from
+// end to end, and otherwise (a new, partial last line) to the line buffer
+// once the full buffered lines have left.
 template <typename T>
 __device__ __forceinline__ void line_group(const LineLists<T>& L, uint32_t& cur, uint32_t first, uint32_t lo,
                                            uint32_t hi, T v)
@@ -726,47 +735,39 @@ __device__ __forceinline__ void line_group(const LineLists<T>& L, uint32_t& cur,
     const uint32_t next = cur + (uint32_t)__popcll(set);
     L.info[lane] = make_uint4((uint32_t)set, (uint32_t)(set >> 32), cur, next);
     const uint64_t done = __ballot(next / LINE > cur / LINE);            // buckets whose buffered line fills
-    const bool far = __ballot(next / LINE > cur / LINE + 1u) != 0ull;    // some bucket fills two lines or more
     wave_lds_sync();
-    if (!far) {
-        // every entry lies in its bucket's buffered line or the next one: the
-        // two lines of a bucket sit in different slots, so one pass places
-        // all entries and the full lines leave afterwards.  Four buckets'
-        // table entries are read before their stores, so the wave waits for
-        // the LDS once per four buckets rather than once per bucket.
-        for (uint32_t b = lo; b < hi; b += 4u) {
-            uint4 in[4];
+    // four buckets' table entries are read before their stores, so the wave
+    // waits for the LDS once per four buckets; bit q of `later`: bucket lo + q
+    // has an entry in a new partial line
+    uint64_t later = 0;
+    for (uint32_t b = lo; b < hi; b += 4u) {
+        uint4 in[4];
 #pragma unroll
-            for (uint32_t q = 0; q < 4u; ++q) in[q] = b + q < hi ? L.info[b + q] : make_uint4(0u, 0u, 0u, 0u);
+        for (uint32_t q = 0; q < 4u; ++q) in[q] = b + q < hi ? L.info[b + q] : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-            for (uint32_t q = 0; q < 4u; ++q) {
-                if (b + q >= hi) break;
-                const uint32_t pos =
-                    in[q].z + __builtin_amdgcn_mbcnt_hi(in[q].y, __builtin_amdgcn_mbcnt_lo(in[q].x, 0u));
-                L.buf[(2u * (b + q) + (pos / LINE & 1u)) * LINE + pos % LINE] = v;
-            }
-        }
-        wave_lds_sync();
-        flush_lines(L, done, cur, first, 0xFFFFFFFFu);
-    } else {
-        // rare (a bucket takes more than a line in one group): entries of the
-        // buffered line to LDS, of lines filled inside the group to memory;
-        // the buffered lines leave; then the entries of the new partial lines
-        for (uint32_t b = lo; b < hi; ++b) {
-            const uint4 in = L.info[b];
-            const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
+        for (uint32_t q = 0; q < 4u; ++q) {
+            if (b + q >= hi) break;
+            const uint32_t pos =
+                in[q].z + __builtin_amdgcn_mbcnt_hi(in[q].y, __builtin_amdgcn_mbcnt_lo(in[q].x, 0u));
             const uint32_t l = pos / LINE;
-            if (l == in.z / LINE) L.buf[(2u * b + (l & 1u)) * LINE + pos % LINE] = v;
-            else if (l < in.w / LINE && pos < L.limit) L.out[pos] = v;
+            if (l == in[q].z / LINE) L.buf[(b + q) * LINE + pos % LINE] = v;
+            else if (l < in[q].w / LINE) { if (pos < L.limit) L.out[pos] = v; }
+            else later |= 1ull << (b + q - lo);
         }
+    }
+    if (done != 0ull) {                 // wave-uniform
         wave_lds_sync();
         flush_lines(L, done, cur, first, 0xFFFFFFFFu);
-        wave_lds_sync();
-        for (uint32_t b = lo; b < hi; ++b) {
-            const uint4 in = L.info[b];
-            const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
-            const uint32_t l = pos / LINE, le = in.w / LINE;
-            if (l == le && le != in.z / LINE) L.buf[(2u * b + (l & 1u)) * LINE + pos % LINE] = v;
+        if (__ballot(later != 0ull) != 0ull) {
+            // a wave's LDS requests are served in order: the flush's reads
+            // of a line precede the writes that reuse its buffer
+            while (later != 0ull) {
+                const uint32_t b = lo + (uint32_t)__builtin_ctzll(later);
+                later &= later - 1ull;
+                const uint4 in = L.info[b];
+                const uint32_t pos = in.z + __builtin_amdgcn_mbcnt_hi(in.y, __builtin_amdgcn_mbcnt_lo(in.x, 0u));
+                L.buf[b * LINE + pos % LINE] = v;
+            }
         }
     }
     // the next group's table write and barrier order these LDS reads and
@@ -783,9 +784,9 @@ __device__ __forceinline__ void line_finish(const LineLists<T>& L, uint32_t cur,
     flush_lines(L, __ballot(cur % LINE != 0u && cur > first), cur, first, cur);
 }
 
-// LDS bytes of one wave of the schedule-1 kernels: the info table and two
-// 128-byte lines for each of up to 64 buckets.
-__host__ __device__ constexpr size_t line_lds_bytes(int buckets) { return 1024 + 256 * (size_t)buckets; }
+// LDS bytes of one wave of the schedule-1 kernels: the info table and one
+// 128-byte line for each of up to 64 buckets.
+__host__ __device__ constexpr size_t line_lds_bytes(int buckets) { return 1024 + 128 * (size_t)buckets; }
 
 // Level 1, schedule 1.  Block (gx, i), wave wv: task gx * kWavesPerBlock + wv
 // over (kTileGauss block b of image i's depth-ordered Gaussians, window of 64
