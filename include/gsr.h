@@ -285,8 +285,18 @@ int gsr_render_noalloc(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
  * H beams (rows) x W columns: ray (r, c) has azimuth az0 + (c + 0.5) az_step
  * and elevation elevations[r] (radians), direction
  * (cos el cos az, cos el sin az, sin el).  A rotating LiDAR spans a full
- * turn (W az_step = 2 pi); a solid-state one a sector.  Non-repetitive scan
- * patterns are not supported.
+ * turn (W az_step = 2 pi); a solid-state one a sector.
+ *
+ * Non-repetitive scan patterns (pattern GSR_LIDAR_RAYS; the paper's
+ * non-repetitive scan LiDAR, Table "tab:lidar"): the H x W rays of one scan
+ * are listed one by one, ray k with azimuth ray_az[k] and elevation
+ * ray_el[k] (any arrangement, e.g. the points of a rosette pattern at one
+ * instant); results come back in the same order (out index k).  The library
+ * sorts the rays into H elevation bands of W rays (azimuth order within a
+ * band) and bins each Gaussian to the bands its cone crosses and, within
+ * them, to the rays its azimuth window covers (the hull over the bands;
+ * every ray of the bands when the cone spans more than 8 of them), so the
+ * result is again that of casting every ray against every Gaussian.
  *
  * Per ray and Gaussian (posed mean m, rotation R, scales S, opacity o in the
  * sensor frame), the Gaussian's response along the ray x(t) = t d peaks at
@@ -313,14 +323,17 @@ int gsr_render_noalloc(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
  * ellipsoid (a disc, widened by a relative 1e-4 against rounding). */
 #define GSR_LIDAR_ANGULAR 0   /* rays from the sensor origin: beam elevations x azimuth columns */
 #define GSR_LIDAR_GRID 1      /* heightmap: parallel rays along -z from a grid on the sensor's z = 0 plane */
+#define GSR_LIDAR_RAYS 2      /* rays from the sensor origin, listed one by one (non-repetitive patterns) */
 typedef struct {
     int width, height;            /* W columns, H beams (grid: W along x, H along y); 1..8192 each */
     float az0, az_step;           /* ANGULAR: radians; az_step > 0, W az_step <= 2 pi */
     const float* elevations;      /* ANGULAR: host [H], radians, strictly ascending, within (-pi/2, pi/2) */
     float near_range;             /* returns at t* <= near_range are ignored; > 0 */
     int attach_body;              /* -1: viewmats are world -> sensor; b: body-b -> sensor (as for cameras) */
-    int pattern;                  /* GSR_LIDAR_ANGULAR (0) or GSR_LIDAR_GRID */
+    int pattern;                  /* GSR_LIDAR_ANGULAR (0), GSR_LIDAR_GRID (1) or GSR_LIDAR_RAYS (2) */
     float x0, y0, dx, dy;         /* GRID: metres in the sensor frame; dx, dy > 0 */
+    const float* ray_az;          /* RAYS: host [H * W] azimuths, radians in [-pi, pi] */
+    const float* ray_el;          /* RAYS: host [H * W] elevations, radians in (-pi/2, pi/2) */
 } gsr_lidar;
 
 typedef struct {

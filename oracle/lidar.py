@@ -16,6 +16,9 @@ formulas; the reading used here (also in the design notes):
   rules: skip alpha < 1/255, stop before adding when T (1 - alpha) < 1e-4;
   range = sum t* alpha T / (1 - T) (0 where nothing was added), hit = 1 - T.
 
+* listed rays (pattern 2; the paper's non-repetitive scan LiDAR): ray k of
+  the scan has its own azimuth and elevation (float32 values), direction as
+  above, results in the order the rays are listed;
 * a heightmap scanner (pattern 1) is a grid of parallel rays x(t) = o + t d
   with d = (0, 0, -1) from the points o = (x0 + (c + 0.5) dx, y0 + (r + 0.5)
   dy, 0) of the sensor plane; the same peak response along each ray, and the
@@ -65,9 +68,14 @@ def ray_origins(lid) -> np.ndarray:
 
 
 def ray_directions(lid) -> np.ndarray:
-    """(H, W, 3) float64 unit directions of a LiDAR grid."""
+    """(H, W, 3) float64 unit directions of a LiDAR grid (listed rays: in
+    their listed order, row-major)."""
     if is_grid(lid):
         return np.broadcast_to(np.array([0.0, 0.0, -1.0]), (lid.height, lid.width, 3)).copy()
+    if int(getattr(lid, "pattern", 0)) == 2:
+        az = np.asarray(lid.ray_az, np.float32).astype(np.float64).reshape(lid.height, lid.width)
+        el = np.asarray(lid.ray_el, np.float32).astype(np.float64).reshape(lid.height, lid.width)
+        return np.stack([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)], axis=-1)
     az = float(np.float32(lid.az0)) + (np.arange(lid.width) + 0.5) * float(np.float32(lid.az_step))
     el = np.asarray(lid.elevations, np.float32).astype(np.float64)
     ce, se = np.cos(el)[:, None], np.sin(el)[:, None]

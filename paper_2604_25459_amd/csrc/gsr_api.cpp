@@ -1214,6 +1214,36 @@ GSR_EXPORT int gsr_render_plain(gsr_ctx* ctx, const gsr_render_desc* desc, void*
 
 namespace {
 
+// A listed-ray slot's device tables, written to `out` (floats; the caller
+// indices as their bit patterns): rays ordered by (elevation, index) and cut
+// into H bands of W; within a band by (azimuth, index).  out = [H] smallest
+// and [H] largest elevation of each band, then [H][W] azimuths, [H][W]
+// elevations and [H][W] caller indices in that order.
+void stage_ray_list(const gsr_lidar& L, float* out)
+{
+    const size_t H = (size_t)L.height, W = (size_t)L.width, n = H * W;
+    std::vector<uint32_t> idx(n);
+    for (size_t k = 0; k < n; ++k) idx[k] = (uint32_t)k;
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return L.ray_el[a] < L.ray_el[b]; });
+    float* lo = out;
+    float* hi = out + H;
+    float* az = out + 2 * H;
+    float* el = az + n;
+    float* perm = el + n;
+    for (size_t r = 0; r < H; ++r) {
+        uint32_t* band = idx.data() + r * W;
+        lo[r] = L.ray_el[band[0]];
+        hi[r] = L.ray_el[band[W - 1]];
+        std::stable_sort(band, band + W, [&](uint32_t a, uint32_t b) { return L.ray_az[a] < L.ray_az[b]; });
+        for (size_t c = 0; c < W; ++c) {
+            const uint32_t k = band[c];
+            az[r * W + c] = L.ray_az[k];
+            el[r * W + c] = L.ray_el[k];
+            std::memcpy(perm + r * W + c, &k, sizeof k);
+        }
+    }
+}
+
 int validate_lidar(const gsr_ctx* ctx, const gsr_lidar_desc* d, const SceneRes* sc)
 {
     if (d->n_envs < 1) return fail(GSR_E_INVALID, "n_envs must be >= 1");
@@ -1246,8 +1276,19 @@ int validate_lidar(const gsr_ctx* ctx, const gsr_lidar_desc* d, const SceneRes* 
                     return fail(GSR_E_INVALID, "elevations must lie in (-pi/2, pi/2)");
                 if (r > 0 && !(e > L.elevations[r - 1])) return fail(GSR_E_INVALID, "elevations must ascend strictly");
             }
+        } else if (L.pattern == GSR_LIDAR_RAYS) {
+            if (!L.ray_az || !L.ray_el) return fail(GSR_E_INVALID, "ray_az / ray_el is NULL");
+            const int64_t n = (int64_t)L.width * L.height;
+            if (n > (1 << 22)) return fail(GSR_E_INVALID, "more than 2^22 listed rays in one LiDAR slot");
+            for (int64_t k = 0; k < n; ++k) {
+                const float a = L.ray_az[k], e = L.ray_el[k];
+                if (!(a >= -3.14159265f && a <= 3.14159265f))
+                    return fail(GSR_E_INVALID, "ray azimuths must lie in [-pi, pi]");
+                if (!(e > -1.5707963f && e < 1.5707963f))
+                    return fail(GSR_E_INVALID, "ray elevations must lie in (-pi/2, pi/2)");
+            }
         } else {
-            return fail(GSR_E_INVALID, "LiDAR pattern must be GSR_LIDAR_ANGULAR or GSR_LIDAR_GRID");
+            return fail(GSR_E_INVALID, "LiDAR pattern must be GSR_LIDAR_ANGULAR, GSR_LIDAR_GRID or GSR_LIDAR_RAYS");
         }
         if (!(L.near_range > 0.0f)) return fail(GSR_E_INVALID, "near_range must be > 0");
         if (L.attach_body < -1 || L.attach_body >= sc->dev.n_bodies)
@@ -1285,9 +1326,15 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
         // beam elevations of every slot, staged in pinned memory and copied to
         // the device (earlier work on this workspace must be done with them)
         if (ws->used) GSR_HIP_TRY(hipEventSynchronize(ws->ev_done));
+        // per slot: angular, its H beam elevations; listed rays, the band
+        // tables [2][H], azimuths, elevations and caller indices [H][W] each
+        auto staged = [](const gsr_lidar& L) -> size_t {
+            if (L.pattern == GSR_LIDAR_ANGULAR) return (size_t)L.height;
+            if (L.pattern == GSR_LIDAR_RAYS) return 2 * (size_t)L.height + 3 * (size_t)L.width * L.height;
+            return 0;
+        };
         size_t n_elev = 0;
-        for (int l = 0; l < d->n_lidars; ++l)
-            if (d->lidars[l].pattern == GSR_LIDAR_ANGULAR) n_elev += (size_t)d->lidars[l].height;
+        for (int l = 0; l < d->n_lidars; ++l) n_elev += staged(d->lidars[l]);
         n_elev = std::max<size_t>(n_elev, 1);
         if (ws->h_elev_cap < n_elev) {
             if (ws->h_elev) (void)hipHostFree(ws->h_elev);
@@ -1312,8 +1359,10 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
         size_t eo = 0;
         for (int l = 0; l < d->n_lidars; ++l) {
             const gsr_lidar& L = d->lidars[l];
-            const bool grid = L.pattern == GSR_LIDAR_GRID;
-            if (!grid) std::memcpy(ws->h_elev + eo, L.elevations, (size_t)L.height * sizeof(float));
+            const bool grid = L.pattern == GSR_LIDAR_GRID, rays = L.pattern == GSR_LIDAR_RAYS;
+            const size_t H = (size_t)L.height, W = (size_t)L.width;
+            if (L.pattern == GSR_LIDAR_ANGULAR) std::memcpy(ws->h_elev + eo, L.elevations, H * sizeof(float));
+            if (rays) stage_ray_list(L, ws->h_elev + eo);
             const int tx = (L.width + ts - 1) / ts, ty = (L.height + ts - 1) / ts;
             for (int e = 0; e < E; ++e) {
                 ImageInfo& im = job.imgs[(size_t)l * E + e];
@@ -1329,6 +1378,13 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
                     im.gy0 = L.y0;
                     im.gdx = L.dx;
                     im.gdy = L.dy;
+                } else if (rays) {
+                    im.kind = 3;
+                    const float* base = ws->stage_elev.as<float>() + eo;
+                    im.elev = base;
+                    im.ray_az = base + 2 * H;
+                    im.ray_el = base + 2 * H + H * W;
+                    im.ray_perm = reinterpret_cast<const uint32_t*>(base + 2 * H + 2 * H * W);
                 } else {
                     im.az0 = L.az0;
                     im.az_step = L.az_step;
@@ -1343,7 +1399,7 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
                 tile_base += (uint64_t)tx * ty;
                 ray_base += (uint64_t)L.width * L.height;
             }
-            if (!grid) eo += (size_t)L.height;
+            eo += staged(L);
         }
         GSR_HIP_TRY(hipMemcpyAsync(ws->stage_elev.p, ws->h_elev, n_elev * sizeof(float), hipMemcpyHostToDevice, st));
         // grids of equal size contiguous (one raster segment each)

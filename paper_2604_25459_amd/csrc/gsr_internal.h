@@ -44,11 +44,16 @@ struct ImageInfo {
     const float* obs_bright;
     int obs_fmt;              // GSR_OBS_U8 / GSR_OBS_F16
     uint32_t obs_idx;         // c * E + e within the image's request
-    // LiDAR images (kind 1 angular, 2 heightmap grid): width x height rays, range -> out_depth, hit -> out_alpha
-    int kind;                 // 0 camera, 1 angular LiDAR, 2 heightmap grid
+    // LiDAR images (kind 1 angular, 2 heightmap grid, 3 listed rays): width x height rays, range ->
+    // out_depth, hit -> out_alpha
+    int kind;                 // 0 camera, 1 angular LiDAR, 2 heightmap grid, 3 listed rays
     float az0, az_step;       // kind 1: ray azimuths az0 + (c + 0.5) az_step
-    const float* elev;        // kind 1: device [height] beam elevations, ascending
+    const float* elev;        // kind 1: device [height] beam elevations, ascending; kind 3: [2][height]
+                              // smallest, then largest elevation of each band (both ascending)
     float gx0, gy0, gdx, gdy; // kind 2: ray (r, c) starts at (gx0 + (c + 0.5) gdx, gy0 + (r + 0.5) gdy, 0), along -z
+    const float* ray_az;      // kind 3: device [height][width] azimuths, ascending within each band
+    const float* ray_el;      // kind 3: device [height][width] elevations
+    const uint32_t* ray_perm; // kind 3: device [height][width] caller's index of each ray (output position)
 };
 
 // Resident scene, device pointers.

@@ -1,6 +1,8 @@
 // Batch LiDAR: ray casting of the resident, rigidly posed Gaussians for grids
-// of rays (rotating or solid-state sensors), through the same sort and tile
-// binning as the cameras.
+// of rays (rotating or solid-state sensors) and for listed rays
+// (non-repetitive scan patterns, sorted on the host into elevation bands of
+// azimuth-ordered rays), through the same sort and tile binning as the
+// cameras.
 //
 // Projection (one thread per Gaussian, a group of scans per thread):
 //   * pose into the sensor frame with the binary32 specification of the
@@ -34,6 +36,7 @@ constexpr float kLidarLogAlphaMin = -7.99435343685886f;   // log2(1/255)
 constexpr float kHalfPi = 1.5707963267948966f;
 constexpr float kTwoPi = 6.283185307179586f;
 constexpr int kLdsBeams = 256;      // angular scans with at most this many beams search their elevations in LDS
+constexpr int kRayBandsSearched = 8;  // listed rays: a cone over more bands than this takes every column
 constexpr int kLidarRec = 5;        // float4s per record: whitening rows + centre, log2 o + W t, cone
 
 // First index r in [0, H) with v[r] >= x (strict = false) or v[r] > x
@@ -156,17 +159,43 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
                 const float ang = asinf(rho / D) * 1.0001f + 2e-6f;
                 cone_c = cosf(ang);
                 const float el = asinf(fminf(1.0f, fmaxf(-1.0f, tz / D)));
-                r0 = first_at_least(ev, im.height, el - ang, false);   // rows with el - ang <= elev
-                r1 = first_at_least(ev, im.height, el + ang, true);    // ... <= el + ang
+                if (im.kind == 3) {
+                    // bands whose elevation span [lo, hi] meets [el - ang, el + ang]
+                    r0 = first_at_least(im.elev + im.height, im.height, el - ang, false);   // hi >= el - ang
+                    r1 = first_at_least(im.elev, im.height, el + ang, true);                // lo <= el + ang
+                } else {
+                    r0 = first_at_least(ev, im.height, el - ang, false);   // rows with el - ang <= elev
+                    r1 = first_at_least(ev, im.height, el + ang, true);    // ... <= el + ang
+                }
                 if (fabsf(el) + ang >= kHalfPi - 1e-4f) {
                     c0 = 0;
                     c1 = im.width;
                 } else {
                     const float daz = asinf(fminf(1.0f, sinf(ang) / cosf(fabsf(el) + ang))) * 1.0001f + 2e-6f;
                     const float th = atan2f(ty, tx);
-                    if (2.0f * daz >= kTwoPi - 1e-4f) {
+                    if (2.0f * daz >= kTwoPi - 1e-4f || (im.kind == 3 && r1 - r0 > kRayBandsSearched)) {
                         c0 = 0;
                         c1 = im.width;
+                    } else if (im.kind == 3) {
+                        // per band, the rays (azimuth-ordered) inside the window at
+                        // each 2 pi shift that meets [-pi, pi]; the hull over the bands
+                        int lo = im.width, hi = 0;
+                        for (int r = r0; r < r1; ++r) {
+                            const float* az = im.ray_az + (size_t)r * im.width;
+#pragma unroll
+                            for (int k = -1; k <= 1; ++k) {
+                                const float a0 = th - daz + (float)k * kTwoPi, a1 = th + daz + (float)k * kTwoPi;
+                                if (a1 < -3.1416f || a0 > 3.1416f) continue;
+                                const int a = first_at_least(az, im.width, a0, false);
+                                const int b = first_at_least(az, im.width, a1, true);
+                                if (a < b) {
+                                    lo = min(lo, a);
+                                    hi = max(hi, b);
+                                }
+                            }
+                        }
+                        c0 = lo;
+                        c1 = hi;
                     } else {
                         // the azimuth window, tested at its three 2 pi shifts; the hull of the hits
                         int lo = im.width, hi = 0;
@@ -260,8 +289,14 @@ __device__ __forceinline__ void lidar_tile(const SceneDev& s, const ChunkDev& c,
         ox = im.gx0 + ((float)col + 0.5f) * im.gdx;
         oy = im.gy0 + ((float)row + 0.5f) * im.gdy;
     } else if (inside) {
-        const float az = im.az0 + ((float)col + 0.5f) * im.az_step;
-        const float el = im.elev[row];
+        float az, el;
+        if (im.kind == 3) {
+            az = im.ray_az[(size_t)row * im.width + col];
+            el = im.ray_el[(size_t)row * im.width + col];
+        } else {
+            az = im.az0 + ((float)col + 0.5f) * im.az_step;
+            el = im.elev[row];
+        }
         float sa, ca, se, ce;
         sincosf(az, &sa, &ca);
         sincosf(el, &se, &ce);
@@ -403,7 +438,9 @@ __device__ __forceinline__ void lidar_tile(const SceneDev& s, const ChunkDev& c,
     }
     if (bad_entry) atomicOr(c.err, kErrListEntry);
     if (inside) {
-        const size_t pix = (size_t)row * im.width + col;
+        // listed rays leave in the caller's order
+        const size_t pix = im.kind == 3 ? (size_t)im.ray_perm[(size_t)row * im.width + col]
+                                        : (size_t)row * im.width + col;
         im.out_depth[pix] = T < 1.0f ? Rg / (1.0f - T) : 0.0f;
         if (im.out_alpha) im.out_alpha[pix] = 1.0f - T;
     }

@@ -70,7 +70,8 @@ class RenderDesc(C.Structure):
 class LidarDesc(C.Structure):
     _fields_ = [("width", C.c_int), ("height", C.c_int), ("az0", C.c_float), ("az_step", C.c_float),
                 ("elevations", C.c_void_p), ("near_range", C.c_float), ("attach_body", C.c_int),
-                ("pattern", C.c_int), ("x0", C.c_float), ("y0", C.c_float), ("dx", C.c_float), ("dy", C.c_float)]
+                ("pattern", C.c_int), ("x0", C.c_float), ("y0", C.c_float), ("dx", C.c_float), ("dy", C.c_float),
+                ("ray_az", C.c_void_p), ("ray_el", C.c_void_p)]
 
 
 class LidarRenderDesc(C.Structure):
@@ -363,11 +364,20 @@ class Renderer:
         for k, l in enumerate(lidars):
             el = np.ascontiguousarray(np.asarray(l.elevations, np.float32))
             keep.append(el)
+            ray_az = ray_el = None
+            if int(getattr(l, "pattern", 0)) == 2:          # listed rays: [H * W] azimuths, elevations
+                ray_az = np.ascontiguousarray(np.asarray(l.ray_az, np.float32).reshape(-1))
+                ray_el = np.ascontiguousarray(np.asarray(l.ray_el, np.float32).reshape(-1))
+                if ray_az.size != l.width * l.height or ray_el.size != l.width * l.height:
+                    raise ValueError("ray_az / ray_el must hold width * height values")
+                keep += [ray_az, ray_el]
             arr[k] = LidarDesc(width=int(l.width), height=int(l.height), az0=float(l.az0), az_step=float(l.az_step),
                                elevations=el.ctypes.data if el.size else None, near_range=float(l.near_range),
                                attach_body=int(l.attach_body), pattern=int(getattr(l, "pattern", 0)),
                                x0=float(getattr(l, "x0", 0.0)), y0=float(getattr(l, "y0", 0.0)),
-                               dx=float(getattr(l, "dx", 0.0)), dy=float(getattr(l, "dy", 0.0)))
+                               dx=float(getattr(l, "dx", 0.0)), dy=float(getattr(l, "dy", 0.0)),
+                               ray_az=ray_az.ctypes.data if ray_az is not None else None,
+                               ray_el=ray_el.ctypes.data if ray_el is not None else None)
         d = LidarRenderDesc(scene_id=sid, n_envs=int(viewmats.shape[1]), n_lidars=len(lidars),
                             lidars=C.addressof(arr), viewmats=_ptr(viewmats),
                             body_poses=_ptr(poses) if poses is not None and poses.numel() else None,

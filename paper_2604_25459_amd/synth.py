@@ -223,7 +223,10 @@ class LidarSpec:
     ``width`` columns at azimuths az0 + (c + 0.5) az_step, rays from the
     sensor origin.  pattern 1 (heightmap grid): ``height`` x ``width``
     parallel rays along -z from the sensor's z = 0 plane, ray (r, c) starting
-    at (x0 + (c + 0.5) dx, y0 + (r + 0.5) dy, 0)."""
+    at (x0 + (c + 0.5) dx, y0 + (r + 0.5) dy, 0).  pattern 2 (listed rays):
+    ray k of the ``height`` x ``width`` rays at azimuth ray_az[k] and
+    elevation ray_el[k] (arrays of that shape, row-major), from the sensor
+    origin."""
     width: int
     height: int
     az0: float
@@ -236,6 +239,8 @@ class LidarSpec:
     y0: float = 0.0
     dx: float = 0.0
     dy: float = 0.0
+    ray_az: np.ndarray = None
+    ray_el: np.ndarray = None
 
 
 @dataclass
@@ -264,6 +269,22 @@ def sector_lidar(beams: int, columns: int, az_deg: float, el_lo_deg: float, el_h
     a = math.radians(az_deg)
     return LidarSpec(width=columns, height=beams, az0=float(np.float32(-0.5 * a)),
                      az_step=float(np.float32(a / columns)), elevations=el, near_range=float(np.float32(near)))
+
+
+def rosette_lidar(rows: int, cols: int, half_fov_deg: float = 35.0, petals: float = 5.0, s0: float = 0.0,
+                  near: float = 0.05) -> LidarSpec:
+    """Non-repetitive (rosette) scan of rows * cols rays: the points of the
+    rose curve rho(s) = A sin(petals s), (azimuth, elevation) = rho (cos s,
+    sin s), A = half_fov, at s = s0 + k ds with ds = pi (3 - sqrt 5) (the
+    golden angle), so no two scans of successive s0 repeat their rays.
+    Angles in float32, shape (rows, cols)."""
+    n = rows * cols
+    s = s0 + np.arange(n, dtype=np.float64) * (math.pi * (3.0 - math.sqrt(5.0)))
+    rho = math.radians(half_fov_deg) * np.sin(petals * s)
+    az = (rho * np.cos(s)).astype(np.float32).reshape(rows, cols)
+    el = (rho * np.sin(s)).astype(np.float32).reshape(rows, cols)
+    return LidarSpec(width=cols, height=rows, az0=0.0, az_step=0.0, elevations=np.zeros(0, np.float32),
+                     near_range=float(np.float32(near)), pattern=2, ray_az=az, ray_el=el)
 
 
 def height_grid(rows: int, cols: int, spacing: float, near: float = 0.05) -> LidarSpec:

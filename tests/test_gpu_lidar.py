@@ -138,12 +138,77 @@ def test_lidar_invalid_arguments(R):
     b = synth.rotating_lidar(4, 32, -10, 10)
     b.near_range = 0.0
     bad_cases.append(b)
+    b = synth.rosette_lidar(4, 32)
+    b.ray_az = b.ray_az.copy()
+    b.ray_az[1, 3] = 3.5                               # listed azimuth beyond pi
+    bad_cases.append(b)
+    b = synth.rosette_lidar(4, 32)
+    b.ray_el = b.ray_el.copy()
+    b.ray_el[0, 0] = 1.6                               # listed elevation beyond pi/2
+    bad_cases.append(b)
     for bad in bad_cases:
         with pytest.raises(gsr.GsrError) as ei:
             R.render_lidar(sid, [bad], vm_t, poses_t)
         assert ei.value.code == gsr.GSR_E_INVALID
     R.render_lidar(sid, [good], vm_t, poses_t)         # and the good one still renders
     _torch().cuda.synchronize()
+    R.remove_scene(sid)
+
+
+def test_listed_rays_rosette_match_oracle(R):
+    """Non-repetitive (rosette) scans, listed ray by ray, in one call with a
+    rotating grid: every ray against the float64 per-ray oracle."""
+    scene = synth.make_scene(53, 4_000, 3, 800, sh_degree=0, half_box=3.0)
+    rng = np.random.default_rng(8)
+    E = 2
+    ros = synth.rosette_lidar(16, 128, half_fov_deg=35.0, s0=0.3)
+    rot = synth.rotating_lidar(8, 64, -20, 20)
+    vm = np.stack([synth.sensor_viewmats(rng, E, 0.5, 2.5, 0.1), synth.sensor_viewmats(rng, E, 0.5, 2.5, 0.1)])
+    poses = synth.random_poses(rng, E, scene.n_bodies)
+    batch = synth.LidarBatch(cams=[ros, rot], viewmats=vm, poses=poses)
+    sid = R.add_synth_scene(scene)
+    vm_t, poses_t = _tensors(batch)
+    out = R.render_lidar(sid, [ros, rot], vm_t, poses_t)
+    for l, e in ((0, 0), (0, 1), (1, 1)):
+        ref = lidar_ref(scene, batch, l, e)
+        _compare(out[l][0][e].cpu().numpy(), out[l][1][e].cpu().numpy(), ref, f"listed {l} env {e}", scene, batch, l,
+                 e)
+    R.remove_scene(sid)
+
+
+def test_listed_rays_equal_the_grid_they_list(R):
+    """A rotating grid's rays (their binary32 angles, as the kernel forms
+    them), listed in a shuffled order and another band shape, give the grid's
+    own results ray for ray: the evaluation per (ray, Gaussian) does not
+    depend on how the rays are binned."""
+    scene = synth.make_scene(54, 3_000, 2, 500, sh_degree=0, half_box=3.0)
+    rng = np.random.default_rng(9)
+    E = 2
+    grid = synth.rotating_lidar(16, 96, -25, 15)
+    c = np.arange(grid.width, dtype=np.float32)
+    az = np.float32(grid.az0) + (c + np.float32(0.5)) * np.float32(grid.az_step)
+    az_all = np.broadcast_to(az[None, :], (grid.height, grid.width)).reshape(-1)
+    el_all = np.broadcast_to(np.asarray(grid.elevations, np.float32)[:, None], (grid.height, grid.width)).reshape(-1)
+    perm = rng.permutation(az_all.size)
+    listed = synth.LidarSpec(width=64, height=24, az0=0.0, az_step=0.0, elevations=np.zeros(0, np.float32),
+                             near_range=grid.near_range, pattern=2, ray_az=az_all[perm].reshape(24, 64),
+                             ray_el=el_all[perm].reshape(24, 64))
+    vm1 = synth.sensor_viewmats(rng, E, 0.5, 2.5, 0.1)
+    batch = synth.LidarBatch(cams=[grid, listed], viewmats=np.stack([vm1, vm1]),
+                             poses=synth.random_poses(rng, E, scene.n_bodies))
+    sid = R.add_synth_scene(scene)
+    vm_t, poses_t = _tensors(batch)
+    out = R.render_lidar(sid, [grid, listed], vm_t, poses_t)
+    for e in range(E):
+        g_rng = out[0][0][e].cpu().numpy().reshape(-1)[perm]
+        g_hit = out[0][1][e].cpu().numpy().reshape(-1)[perm]
+        l_rng = out[1][0][e].cpu().numpy().reshape(-1)
+        l_hit = out[1][1][e].cpu().numpy().reshape(-1)
+        print(f"[listed = grid] env {e} hits {(g_hit > 0.1).sum()} max |d range| {np.abs(l_rng - g_rng).max():.2e} "
+              f"max |d hit| {np.abs(l_hit - g_hit).max():.2e}", flush=True)
+        assert (g_hit > 0.1).sum() >= 20
+        np.testing.assert_array_equal(l_rng, g_rng)
+        np.testing.assert_array_equal(l_hit, g_hit)
     R.remove_scene(sid)
 
 

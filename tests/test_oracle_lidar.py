@@ -245,3 +245,61 @@ def test_tilted_gaussian_peak_matches_line_search():
             if a >= 1 / 255 * 1.01:
                 assert ref.range[r, c] == pytest.approx(ts[k], abs=1e-5)
                 assert ref.hit[r, c] == pytest.approx(a, rel=1e-6)
+
+
+def _listed(az, el, near=0.05):
+    az = np.asarray(az, np.float32)
+    el = np.asarray(el, np.float32)
+    return synth.LidarSpec(width=az.shape[1], height=az.shape[0], az0=0.0, az_step=0.0,
+                           elevations=np.zeros(0, np.float32), near_range=near, pattern=2, ray_az=az, ray_el=el)
+
+
+def test_listed_rays_closed_form():
+    # ray 1 points straight at an isotropic Gaussian (q = 0: alpha = o at t* = D); ray 2 passes it
+    # at elevation offset phi (closest approach h = D sin phi at t* = D cos phi); ray 0 looks away
+    az_g, el_g, phi = 0.7, 0.2, 0.015
+    lid = _listed([[-2.0, az_g, az_g]], [[0.0, el_g, el_g + phi]])
+    D, sigma, o = 5.0, 0.1, 0.8
+    a32, e32 = float(np.float32(az_g)), float(np.float32(el_g))
+    mean = D * np.array([math.cos(e32) * math.cos(a32), math.cos(e32) * math.sin(a32), math.sin(e32)])
+    scene = scene_from([mean], [sigma] * 3, opac=o, degree=0)
+    ref = lidar_ref(scene, _batch(lid))
+    assert ref.hit[0, 1] == pytest.approx(o, abs=1e-6)
+    assert ref.range[0, 1] == pytest.approx(D, rel=1e-6)
+    dphi = float(np.float32(el_g + phi)) - e32
+    h = D * math.sin(dphi)
+    assert ref.hit[0, 2] == pytest.approx(o * math.exp(-0.5 * h * h / sigma ** 2), rel=1e-5)
+    assert ref.range[0, 2] == pytest.approx(D * math.cos(dphi), rel=1e-6)
+    assert ref.hit[0, 0] == 0.0 and ref.range[0, 0] == 0.0
+
+
+def test_listed_rays_follow_their_listed_order():
+    # the rays of an angular grid, listed in a shuffled order, give that grid's results in that order
+    rng = np.random.default_rng(3)
+    grid = synth.rotating_lidar(4, 32, -20, 20)
+    d = ray_directions(grid)
+    az_g = np.arctan2(d[..., 1], d[..., 0]).astype(np.float32)
+    el_g = np.broadcast_to(np.asarray(grid.elevations, np.float32)[:, None], az_g.shape)
+    perm = rng.permutation(az_g.size)
+    lid = _listed(az_g.reshape(-1)[perm].reshape(8, 16), el_g.reshape(-1)[perm].reshape(8, 16))
+    scene = synth.make_scene(9, 600, 0, 0, sh_degree=0, half_box=3.0)
+    vm = synth.sensor_viewmats(rng, 1, 0.5, 1.0, 0.1)
+    ref_g = lidar_ref(scene, _batch(grid, vm))
+    ref_l = lidar_ref(scene, _batch(lid, vm))
+    # listed azimuths are float32 roundings of the grid's (float64) ones: up to 2e-7 rad apart,
+    # a few 1e-6 of hit; a ray out of place would differ by orders of magnitude more
+    np.testing.assert_allclose(ref_l.hit.reshape(-1), ref_g.hit.reshape(-1)[perm], atol=1e-4)
+    np.testing.assert_allclose(ref_l.range.reshape(-1), ref_g.range.reshape(-1)[perm], rtol=1e-4, atol=1e-4)
+    assert (ref_g.hit > 0.1).sum() >= 10
+
+
+def test_rosette_pattern_stays_in_its_field_and_does_not_repeat():
+    a = synth.rosette_lidar(8, 64, half_fov_deg=35.0, s0=0.0)
+    b = synth.rosette_lidar(8, 64, half_fov_deg=35.0, s0=a.width * a.height * math.pi * (3 - math.sqrt(5)))
+    lim = math.radians(35.0) * (1 + 1e-6)
+    for p in (a, b):
+        assert p.ray_az.shape == (8, 64) and p.ray_el.shape == (8, 64)
+        assert (np.hypot(p.ray_az.astype(np.float64), p.ray_el.astype(np.float64)) <= lim).all()
+    pa = set(zip(a.ray_az.reshape(-1).tolist(), a.ray_el.reshape(-1).tolist()))
+    pb = set(zip(b.ray_az.reshape(-1).tolist(), b.ray_el.reshape(-1).tolist()))
+    assert len(pa) == a.width * a.height and not (pa & pb)
