@@ -16,6 +16,7 @@ import argparse
 import csv
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -787,6 +788,30 @@ def main():
                           "ms_per_step": 1000.0 * hsec / args.lidar_steps,
                           "hit_fraction": float((h_hit > 0.5).float().mean())}
         log(f"[bench] heightmap {r['heightmap']['value']:.1f} env-scans/s")
+        # non-repetitive (rosette) scanner, 96 x 256 listed rays per scan over a
+        # 70 deg field; every scan takes the next phase of the rosette (new rays)
+        n_ros = 96 * 256
+        ds = math.pi * (3.0 - math.sqrt(5.0))
+        ros = [synth.rosette_lidar(96, 256, 35.0, s0=k * n_ros * ds) for k in range(args.lidar_steps + 1)]
+        o_range = torch.empty(E * n_ros, dtype=torch.float32, device=dev)
+        o_hit = torch.empty(E * n_ros, dtype=torch.float32, device=dev)
+        R.render_lidar_into(sid, [ros[0]], lvm, poses[args.warmup], o_range, o_hit)
+        torch.cuda.synchronize()
+        R.stage_times(reset=True)
+        t0 = time.perf_counter()
+        for s in range(args.lidar_steps):
+            R.render_lidar_into(sid, [ros[s + 1]], lvm, poses[args.warmup + s % args.steps], o_range, o_hit)
+        torch.cuda.synchronize()
+        osec = time.perf_counter() - t0
+        ost = R.stage_times(reset=True)
+        r["rosette"] = {"value": E * args.lidar_steps / osec, "unit": "env-scans/s",
+                        "rays_per_s": E * n_ros * args.lidar_steps / osec,
+                        "sensor": "non-repetitive rosette, 96 x 256 listed rays in a 70 deg field, new rays every scan",
+                        "envs": E, "ms_per_step": 1000.0 * osec / args.lidar_steps,
+                        "stages_ms_per_step": {k: v / args.lidar_steps for k, v in ost.items() if k in R.STAGES},
+                        "hit_fraction": float((o_hit > 0.5).float().mean())}
+        log(f"[bench] rosette LiDAR {r['rosette']['value']:.1f} env-scans/s "
+            f"({r['rosette']['rays_per_s'] / 1e9:.2f} G rays/s)")
         return r
 
     if args.lidar_steps:

@@ -294,9 +294,9 @@ int gsr_render_noalloc(gsr_ctx* ctx, const gsr_render_desc* desc, void* stream);
  * instant); results come back in the same order (out index k).  The library
  * sorts the rays into H elevation bands of W rays (azimuth order within a
  * band) and bins each Gaussian to the bands its cone crosses and, within
- * them, to the rays its azimuth window covers (the hull over the bands;
- * every ray of the bands when the cone spans more than 8 of them), so the
- * result is again that of casting every ray against every Gaussian.
+ * them, to the ray tiles whose azimuth span meets its azimuth window (the
+ * hull over the tile rows), so the result is again that of casting every
+ * ray against every Gaussian.
  *
  * Per ray and Gaussian (posed mean m, rotation R, scales S, opacity o in the
  * sensor frame), the Gaussian's response along the ray x(t) = t d peaks at

@@ -1218,8 +1218,17 @@ namespace {
 // indices as their bit patterns): rays ordered by (elevation, index) and cut
 // into H bands of W; within a band by (azimuth, index).  out = [H] smallest
 // and [H] largest elevation of each band, then [H][W] azimuths, [H][W]
-// elevations and [H][W] caller indices in that order.
-void stage_ray_list(const gsr_lidar& L, float* out)
+// elevations and [H][W] caller indices, then per ts x ts tile of rays the
+// smallest and the largest azimuth ([TY][TX] each; along a tile row both
+// ascend, since each band's azimuths do).
+size_t ray_list_floats(const gsr_lidar& L, int ts)
+{
+    const size_t H = (size_t)L.height, W = (size_t)L.width;
+    const size_t TX = (W + ts - 1) / ts, TY = (H + ts - 1) / ts;
+    return 2 * H + 3 * H * W + 2 * TX * TY;
+}
+
+void stage_ray_list(const gsr_lidar& L, int ts, float* out)
 {
     const size_t H = (size_t)L.height, W = (size_t)L.width, n = H * W;
     std::vector<uint32_t> idx(n);
@@ -1242,6 +1251,20 @@ void stage_ray_list(const gsr_lidar& L, float* out)
             std::memcpy(perm + r * W + c, &k, sizeof k);
         }
     }
+    const size_t TX = (W + ts - 1) / ts, TY = (H + ts - 1) / ts;
+    float* tmin = perm + n;
+    float* tmax = tmin + TX * TY;
+    for (size_t ty = 0; ty < TY; ++ty)
+        for (size_t tx = 0; tx < TX; ++tx) {
+            float a = az[ty * ts * W + tx * ts], b = a;
+            const size_t c_end = std::min(W, (tx + 1) * ts) - 1;
+            for (size_t r = ty * ts; r < std::min(H, (ty + 1) * ts); ++r) {
+                a = std::min(a, az[r * W + tx * ts]);
+                b = std::max(b, az[r * W + c_end]);
+            }
+            tmin[ty * TX + tx] = a;
+            tmax[ty * TX + tx] = b;
+        }
 }
 
 int validate_lidar(const gsr_ctx* ctx, const gsr_lidar_desc* d, const SceneRes* sc)
@@ -1328,9 +1351,10 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
         if (ws->used) GSR_HIP_TRY(hipEventSynchronize(ws->ev_done));
         // per slot: angular, its H beam elevations; listed rays, the band
         // tables [2][H], azimuths, elevations and caller indices [H][W] each
-        auto staged = [](const gsr_lidar& L) -> size_t {
+        // and the tiles' azimuth spans [2][TY][TX]
+        auto staged = [&](const gsr_lidar& L) -> size_t {
             if (L.pattern == GSR_LIDAR_ANGULAR) return (size_t)L.height;
-            if (L.pattern == GSR_LIDAR_RAYS) return 2 * (size_t)L.height + 3 * (size_t)L.width * L.height;
+            if (L.pattern == GSR_LIDAR_RAYS) return ray_list_floats(L, ctx->opt.tile_size);
             return 0;
         };
         size_t n_elev = 0;
@@ -1362,7 +1386,7 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
             const bool grid = L.pattern == GSR_LIDAR_GRID, rays = L.pattern == GSR_LIDAR_RAYS;
             const size_t H = (size_t)L.height, W = (size_t)L.width;
             if (L.pattern == GSR_LIDAR_ANGULAR) std::memcpy(ws->h_elev + eo, L.elevations, H * sizeof(float));
-            if (rays) stage_ray_list(L, ws->h_elev + eo);
+            if (rays) stage_ray_list(L, ts, ws->h_elev + eo);
             const int tx = (L.width + ts - 1) / ts, ty = (L.height + ts - 1) / ts;
             for (int e = 0; e < E; ++e) {
                 ImageInfo& im = job.imgs[(size_t)l * E + e];
@@ -1385,6 +1409,7 @@ GSR_EXPORT int gsr_render_lidar(gsr_ctx* ctx, const gsr_lidar_desc* d, void* str
                     im.ray_az = base + 2 * H;
                     im.ray_el = base + 2 * H + H * W;
                     im.ray_perm = reinterpret_cast<const uint32_t*>(base + 2 * H + 2 * H * W);
+                    im.ray_tile_az = base + 2 * H + 3 * H * W;
                 } else {
                     im.az0 = L.az0;
                     im.az_step = L.az_step;

@@ -54,6 +54,8 @@ struct ImageInfo {
     const float* ray_az;      // kind 3: device [height][width] azimuths, ascending within each band
     const float* ray_el;      // kind 3: device [height][width] elevations
     const uint32_t* ray_perm; // kind 3: device [height][width] caller's index of each ray (output position)
+    const float* ray_tile_az; // kind 3: device [2][tiles_y][tiles_x] smallest, then largest azimuth of each
+                              // ray tile (both ascending along a tile row)
 };
 
 // Resident scene, device pointers.

@@ -36,7 +36,7 @@ constexpr float kLidarLogAlphaMin = -7.99435343685886f;   // log2(1/255)
 constexpr float kHalfPi = 1.5707963267948966f;
 constexpr float kTwoPi = 6.283185307179586f;
 constexpr int kLdsBeams = 256;      // angular scans with at most this many beams search their elevations in LDS
-constexpr int kRayBandsSearched = 8;  // listed rays: a cone over more bands than this takes every column
+constexpr int kLdsTileAz = 1024;     // listed rays: tile azimuth tables up to this many floats are read from LDS
 constexpr int kLidarRec = 5;        // float4s per record: whitening rows + centre, log2 o + W t, cone
 
 // First index r in [0, H) with v[r] >= x (strict = false) or v[r] > x
@@ -89,8 +89,10 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
 {
     __shared__ float4 stage[4][kLidarRec * 64];
     // the elevation table of the current angular image (up to kLdsBeams beams;
-    // the row search reads it ten times per Gaussian)
+    // the row search reads it ten times per Gaussian), or a listed-ray image's
+    // band tables, and its tiles' azimuth spans
     __shared__ float elev_s[kLdsBeams];
+    __shared__ float taz_s[kLdsTileAz];
     float4* const st = stage[threadIdx.x >> 6];
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
@@ -116,13 +118,20 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
         const int i = __builtin_amdgcn_readfirstlane(i_begin + ii);     // the same in every lane
         if (i >= c.n_img) break;
         const ImageInfo im = imgs[i];
-        const bool lds_elev = im.kind == 1 && im.height <= kLdsBeams;     // block-uniform
-        if (lds_elev) {
-            __syncthreads();                    // the previous image's table is no longer read
-            if ((int)threadIdx.x < im.height) elev_s[threadIdx.x] = im.elev[threadIdx.x];
+        // block-uniform: every thread of the block projects into image i
+        const int n_ev = im.kind == 3 ? 2 * im.height : im.height;
+        const int n_taz = im.kind == 3 ? 2 * im.tiles_x * im.tiles_y : 0;
+        const bool lds_elev = (im.kind == 1 || im.kind == 3) && n_ev <= kLdsBeams;
+        const bool lds_taz = im.kind == 3 && n_taz <= kLdsTileAz;
+        if (lds_elev || lds_taz) {
+            __syncthreads();                    // the previous image's tables are no longer read
+            if (lds_elev && (int)threadIdx.x < n_ev) elev_s[threadIdx.x] = im.elev[threadIdx.x];
+            if (lds_taz)
+                for (int k = (int)threadIdx.x; k < n_taz; k += 256) taz_s[k] = im.ray_tile_az[k];
             __syncthreads();
         }
         const float* ev = lds_elev ? elev_s : im.elev;
+        const float* taz = lds_taz ? taz_s : im.ray_tile_az;
         const float* X = c.xform + ((size_t)i * (s.n_bodies + 1) + slot) * 16;
         float A[9];
 #pragma unroll
@@ -161,8 +170,8 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
                 const float el = asinf(fminf(1.0f, fmaxf(-1.0f, tz / D)));
                 if (im.kind == 3) {
                     // bands whose elevation span [lo, hi] meets [el - ang, el + ang]
-                    r0 = first_at_least(im.elev + im.height, im.height, el - ang, false);   // hi >= el - ang
-                    r1 = first_at_least(im.elev, im.height, el + ang, true);                // lo <= el + ang
+                    r0 = first_at_least(ev + im.height, im.height, el - ang, false);   // hi >= el - ang
+                    r1 = first_at_least(ev, im.height, el + ang, true);                // lo <= el + ang
                 } else {
                     r0 = first_at_least(ev, im.height, el - ang, false);   // rows with el - ang <= elev
                     r1 = first_at_least(ev, im.height, el + ang, true);    // ... <= el + ang
@@ -173,29 +182,32 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
                 } else {
                     const float daz = asinf(fminf(1.0f, sinf(ang) / cosf(fabsf(el) + ang))) * 1.0001f + 2e-6f;
                     const float th = atan2f(ty, tx);
-                    if (2.0f * daz >= kTwoPi - 1e-4f || (im.kind == 3 && r1 - r0 > kRayBandsSearched)) {
+                    if (2.0f * daz >= kTwoPi - 1e-4f) {
                         c0 = 0;
                         c1 = im.width;
                     } else if (im.kind == 3) {
-                        // per band, the rays (azimuth-ordered) inside the window at
-                        // each 2 pi shift that meets [-pi, pi]; the hull over the bands
-                        int lo = im.width, hi = 0;
-                        for (int r = r0; r < r1; ++r) {
-                            const float* az = im.ray_az + (size_t)r * im.width;
+                        // per tile row of the bands, the ray tiles whose azimuth span
+                        // [smallest, largest] meets the window, at each 2 pi shift that
+                        // meets [-pi, pi]; the hull over the tile rows, in rays
+                        const int TX = im.tiles_x, y0 = r0 / ts, y1 = (r1 + ts - 1) / ts;
+                        const float* tmin = taz;
+                        const float* tmax = taz + (size_t)TX * im.tiles_y;
+                        int lo = TX, hi = 0;
+                        for (int y = y0; y < y1; ++y) {
 #pragma unroll
                             for (int k = -1; k <= 1; ++k) {
                                 const float a0 = th - daz + (float)k * kTwoPi, a1 = th + daz + (float)k * kTwoPi;
                                 if (a1 < -3.1416f || a0 > 3.1416f) continue;
-                                const int a = first_at_least(az, im.width, a0, false);
-                                const int b = first_at_least(az, im.width, a1, true);
+                                const int a = first_at_least(tmax + (size_t)y * TX, TX, a0, false);   // largest >= a0
+                                const int b = first_at_least(tmin + (size_t)y * TX, TX, a1, true);    // smallest <= a1
                                 if (a < b) {
                                     lo = min(lo, a);
                                     hi = max(hi, b);
                                 }
                             }
                         }
-                        c0 = lo;
-                        c1 = hi;
+                        c0 = lo * ts;
+                        c1 = min(im.width, hi * ts);
                     } else {
                         // the azimuth window, tested at its three 2 pi shifts; the hull of the hits
                         int lo = im.width, hi = 0;
