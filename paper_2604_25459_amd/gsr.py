@@ -202,6 +202,24 @@ class Lidar:
 
 
 @dataclass
+class LidarRays:
+    """A non-repetitive scan as listed rays: ray k of the ``height`` x
+    ``width`` rays at azimuth ``ray_az[k]`` (radians, [-pi, pi]) and
+    elevation ``ray_el[k]`` (radians, (-pi/2, pi/2)), arrays of that shape
+    (row-major); ranges and hits come back in the same order."""
+    width: int
+    height: int
+    ray_az: object
+    ray_el: object
+    near_range: float = 0.05
+    attach_body: int = -1
+    pattern: int = 2
+    az0: float = 0.0
+    az_step: float = 0.0
+    elevations: object = ()
+
+
+@dataclass
 class Observation:
     """Fused observation epilogue request: ``out`` receives u8 or f16 pixels
     ([pixels * 3], the layout of rgb); gain / contrast / brightness are
