@@ -190,9 +190,9 @@ def test_listed_rays_equal_the_grid_they_list(R):
     az_all = np.broadcast_to(az[None, :], (grid.height, grid.width)).reshape(-1)
     el_all = np.broadcast_to(np.asarray(grid.elevations, np.float32)[:, None], (grid.height, grid.width)).reshape(-1)
     perm = rng.permutation(az_all.size)
-    listed = synth.LidarSpec(width=64, height=24, az0=0.0, az_step=0.0, elevations=np.zeros(0, np.float32),
-                             near_range=grid.near_range, pattern=2, ray_az=az_all[perm].reshape(24, 64),
-                             ray_el=el_all[perm].reshape(24, 64))
+    from paper_2604_25459_amd import gsr
+    listed = gsr.LidarRays(width=64, height=24, ray_az=az_all[perm].reshape(24, 64),
+                           ray_el=el_all[perm].reshape(24, 64), near_range=grid.near_range)
     vm1 = synth.sensor_viewmats(rng, E, 0.5, 2.5, 0.1)
     batch = synth.LidarBatch(cams=[grid, listed], viewmats=np.stack([vm1, vm1]),
                              poses=synth.random_poses(rng, E, scene.n_bodies))
