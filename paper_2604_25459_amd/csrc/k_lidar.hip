@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_project_lidar(SceneDev s, ChunkDev c, c
     const uint32_t L = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const uint32_t bx = L / gridDim.y, by = L - bx * gridDim.y;
     const int64_t g_lane = (int64_t)bx * 256 + threadIdx.x;
-    // lanes past the last Gaussian stay (invisible) for the wave-wide key range
+    // lanes past the last Gaussian stay (invisible) so that every record store slot of the wave has a lane
     const bool valid = g_lane < s.n;
     const int64_t g = valid ? g_lane : s.n - 1;
     const int lane = __lane_id();

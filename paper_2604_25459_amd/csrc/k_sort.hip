@@ -7,9 +7,10 @@
 //
 // The sort runs on the key less the image's smallest visible key (rounded
 // down to a multiple of 512; the first pass's histogram blocks record their
-// key ranges and its scan combines them), in 9-bit digits: three passes order an image whose keys lie within 2^27 of each
-// other (depths within a factor of about 2^16), a fourth pass (the top five
-// bits) runs only for images that need it.  The two ping-pong buffers are
+// key ranges and its scan combines them), in 9-bit digits: three passes
+// order an image whose keys lie within 2^27 of that offset (depths within a
+// factor of about 2^16), a fourth pass (the top five bits) runs only for
+// images that need it.  The two ping-pong buffers are
 // used in opposite order by three- and four-pass images, so every image's
 // sorted values end in sv[0].
 //
