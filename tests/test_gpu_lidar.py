@@ -179,8 +179,9 @@ def test_listed_rays_rosette_match_oracle(R):
 def test_listed_rays_equal_the_grid_they_list(R):
     """A rotating grid's rays (their binary32 angles, as the kernel forms
     them), listed in a shuffled order and another band shape, give the grid's
-    own results ray for ray: the evaluation per (ray, Gaussian) does not
-    depend on how the rays are binned."""
+    own results ray for ray, and both give the same bits with 8 x 8 ray
+    tiles: the evaluation per (ray, Gaussian) does not depend on how the rays
+    are binned."""
     scene = synth.make_scene(54, 3_000, 2, 500, sh_degree=0, half_box=3.0)
     rng = np.random.default_rng(9)
     E = 2
@@ -210,6 +211,17 @@ def test_listed_rays_equal_the_grid_they_list(R):
         np.testing.assert_array_equal(l_rng, g_rng)
         np.testing.assert_array_equal(l_hit, g_hit)
     R.remove_scene(sid)
+    # 8 x 8 ray tiles (other bands per tile row, other tile azimuth tables): the same bits again
+    R8 = gsr.Renderer(0, tile_size=8)
+    try:
+        sid8 = R8.add_synth_scene(scene)
+        out8 = R8.render_lidar(sid8, [grid, listed], vm_t, poses_t)
+        for l in range(2):
+            for k in range(2):
+                np.testing.assert_array_equal(out8[l][k].cpu().numpy(), out[l][k].cpu().numpy())
+        R8.remove_scene(sid8)
+    finally:
+        R8.close()
 
 
 def _sampled_compare(R, scene, batch, lidars, got, n_samples, label, seed=0):
