@@ -399,11 +399,9 @@ __device__ __forceinline__ void lidar_tile(const SceneDev& s, const ChunkDev& c,
                     keep = cn.x * w[0] + cn.y * w[1] + cn.z * w[2] >= cn.w * cb - sa * sb - 1e-6f;
                 }
             }
-            uint64_t mask = __ballot(keep);
-            while (mask) {
-                const int j = sub + (int)__builtin_ctzll(mask);
-                mask &= mask - 1ull;
-                if (!live) continue;
+            // survivors two at a time: both are evaluated (independent
+            // dependency chains the wave interleaves), then composited in list order
+            auto eval = [&](int j, float* ts_out, float* la_out) {
                 const float4 m0 = sr[0][j], m1 = sr[1][j], m2 = sr[2][j], m3 = sr[3][j];
                 // d' = W d
                 const float dx = fmaf(m0.z, d[2], fmaf(m0.y, d[1], m0.x * d[0]));
@@ -429,8 +427,11 @@ __device__ __forceinline__ void lidar_tile(const SceneDev& s, const ChunkDev& c,
                 const float wy = fmaf(m1.z, pz, fmaf(m1.y, py, m1.x * px));
                 const float wz = fmaf(m2.z, pz, fmaf(m2.y, py, m2.x * px));
                 const float qq = fmaf(wz, wz, fmaf(wy, wy, wx * wx));
-                const float la = fmaf(-0.72134752044448170f, qq, m3.x);      // log2 o - q/2 log2 e
-                if (tstar > near && la >= kLidarLogAlphaMin) {
+                *ts_out = tstar;
+                *la_out = fmaf(-0.72134752044448170f, qq, m3.x);      // log2 o - q/2 log2 e
+            };
+            auto take = [&](float tstar, float la) {
+                if (live && tstar > near && la >= kLidarLogAlphaMin) {
                     // only the rays that take the Gaussian run this (exec mask);
                     // the empty asm keeps it a branch rather than selects
                     asm volatile("");
@@ -443,6 +444,20 @@ __device__ __forceinline__ void lidar_tile(const SceneDev& s, const ChunkDev& c,
                         T = Tn;
                     }
                 }
+            };
+            uint64_t mask = __ballot(keep);
+            while (mask) {
+                const int j0 = sub + (int)__builtin_ctzll(mask);
+                mask &= mask - 1ull;
+                const bool two = mask != 0ull;                  // wave-uniform
+                const int j1 = two ? sub + (int)__builtin_ctzll(mask) : j0;
+                if (two) mask &= mask - 1ull;
+                if (!live) continue;
+                float t0, l0, t1, l1;
+                eval(j0, &t0, &l0);
+                eval(j1, &t1, &l1);
+                take(t0, l0);
+                if (two) take(t1, l1);
             }
             if (__ballot(live) == 0ull) wave_live = false;
         }
