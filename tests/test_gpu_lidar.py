@@ -176,6 +176,38 @@ def test_listed_rays_rosette_match_oracle(R):
     R.remove_scene(sid)
 
 
+def test_listed_rays_edge_cases(R):
+    """Listed rays at the seam (azimuth exactly -pi and pi), near the poles,
+    duplicated, and many sharing one elevation, in a 3 x 37 list (neither a
+    multiple of the tile size), around splats that straddle the seam behind
+    the sensor, sit above it and enclose it: every ray against the oracle."""
+    scene = scene_from([[-3.0, 0.0, 0.0], [0.05, 0.0, 0.0], [2.0, 1.0, 0.3], [0.3, 0.1, 4.0], [1.5, -0.2, 0.0]],
+                       [[0.3, 0.3, 0.3], [0.4, 0.4, 0.4], [0.2, 0.05, 0.1], [0.5, 0.5, 0.2], [0.1, 0.1, 0.1]],
+                       opac=[0.8, 0.3, 0.9, 0.7, 0.95], degree=0)
+    rng = np.random.default_rng(12)
+    n = 3 * 37
+    az = rng.uniform(-math.pi, math.pi, n)
+    el = rng.uniform(-0.4, 0.4, n)
+    az[:6] = [-math.pi, math.pi, -math.pi, math.pi, 0.0, 0.0]      # the seam, twice each
+    el[:6] = [0.0, 0.0, 0.05, -0.05, 0.0, 0.0]                     # and a duplicated ray straight ahead
+    el[6:10] = [1.55, -1.55, 1.5, -1.5]                            # near the poles
+    el[10:40] = 0.1                                                 # thirty rays on one elevation
+    az32 = np.clip(az.astype(np.float32), np.float32(-math.pi), np.float32(math.pi))
+    lid = synth.LidarSpec(width=37, height=3, az0=0.0, az_step=0.0, elevations=np.zeros(0, np.float32),
+                          near_range=0.05, pattern=2, ray_az=az32.reshape(3, 37),
+                          ray_el=el.astype(np.float32).reshape(3, 37))
+    vm = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1).astype(np.float32).reshape(1, 1, 3, 4)
+    batch = synth.LidarBatch(cams=[lid], viewmats=vm, poses=np.zeros((1, 0, 7), np.float32))
+    sid = R.add_synth_scene(scene)
+    vm_t, poses_t = _tensors(batch)
+    out = R.render_lidar(sid, [lid], vm_t, poses_t)
+    ref = lidar_ref(scene, batch, 0, 0)
+    _compare(out[0][0][0].cpu().numpy(), out[0][1][0].cpu().numpy(), ref, "listed edges", scene, batch, 0, 0,
+             min_hits=5)
+    assert ref.hit[0, 0] > 0.3 and ref.hit[0, 1] > 0.3              # the seam rays see the splat behind
+    R.remove_scene(sid)
+
+
 def test_listed_rays_equal_the_grid_they_list(R):
     """A rotating grid's rays (their binary32 angles, as the kernel forms
     them), listed in a shuffled order and another band shape, give the grid's
