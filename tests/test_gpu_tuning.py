@@ -94,18 +94,21 @@ def test_two_stream_lidar_chunks_match_one_stream():
     rng = np.random.default_rng(7)
     E = 12
     lid = synth.rotating_lidar(16, 256, -20, 20)
-    vm = torch.from_numpy(synth.sensor_viewmats(rng, E, 0.5, 2.5, 0.1)[None].copy()).cuda()
+    ros = synth.rosette_lidar(16, 128, half_fov_deg=35.0, s0=0.7)       # listed rays in the same call
+    vm = torch.from_numpy(np.stack([synth.sensor_viewmats(rng, E, 0.5, 2.5, 0.1),
+                                    synth.sensor_viewmats(rng, E, 0.5, 2.5, 0.1)])).cuda()
     poses = torch.from_numpy(synth.random_poses(rng, E, scene.n_bodies)).cuda()
     out = []
     for overlap in (False, True):
         R = gsr.Renderer(0, chunk_bytes=64 << 20, overlap=overlap)   # a few scans per chunk
         sid = R.add_synth_scene(scene)
-        rng_, hit = R.render_lidar(sid, [lid], vm, poses)[0]
-        out.append((rng_.clone(), hit.clone()))
+        res = R.render_lidar(sid, [lid, ros], vm, poses)
+        out.append([(r.clone(), h.clone()) for r, h in res])
         torch.cuda.synchronize()
         R.close()
-    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
-    assert (out[0][1] > 0.1).sum() > 100
+    for (r0, h0), (r1, h1) in zip(out[0], out[1]):
+        assert torch.equal(r0, r1) and torch.equal(h0, h1)
+    assert (out[0][0][1] > 0.1).sum() > 100 and (out[0][1][1] > 0.1).sum() > 100
 
 
 @pytest.mark.parametrize("params", [dict(tile_size=8, lds_batch=64), dict(tile_size=8, lds_batch=256),
