@@ -318,17 +318,19 @@ def test_heightmap_sheet_reads_its_height(R):
 
 def test_lidar_at_benchmark_scale_sampled(R):
     """The benchmark's sensors on the 300k-Gaussian workload-2 scene (long
-    tile-row lists, segmented scatter): a rotating 32 x 1024 LiDAR and a
-    64 x 64 heightmap grid, rays sampled in every env against the oracle."""
+    tile-row lists, segmented scatter): a rotating 32 x 1024 LiDAR, a 64 x 64
+    heightmap grid and a 96 x 256 rosette of listed rays, rays sampled in
+    every env against the oracle."""
     scene, _ = synth.make_config(2, n_envs=1)
     rng = np.random.default_rng(11)
     E = 3
     rot = synth.rotating_lidar(32, 1024, -25.0, 15.0)
     grid = synth.height_grid(64, 64, 0.05)
+    ros = synth.rosette_lidar(96, 256, 35.0)
     vm = synth.sensor_viewmats(rng, E, 0.5, 3.0, 0.2)
     poses = synth.make_poses(2, 0, E, scene.n_bodies)
-    batch = synth.LidarBatch(cams=[rot, grid], viewmats=np.stack([vm, vm]), poses=poses)
+    batch = synth.LidarBatch(cams=[rot, grid, ros], viewmats=np.stack([vm, vm, vm]), poses=poses)
     vmt, pt = _tensors(batch)
-    got = R.render_lidar(R.add_synth_scene(scene), [rot, grid], vmt, pt)
+    got = R.render_lidar(R.add_synth_scene(scene), [rot, grid, ros], vmt, pt)
     got = [(r.cpu().numpy(), h.cpu().numpy()) for r, h in got]
-    _sampled_compare(R, scene, batch, [rot, grid], got, 24, "benchmark scale")
+    _sampled_compare(R, scene, batch, [rot, grid, ros], got, 24, "benchmark scale")
