@@ -241,9 +241,9 @@ def test_cfg1_batch_independence_and_plain(R):
 
 def test_cfg2_full_batch_sampled(R):
     """The benchmark's launch configuration: the autotuner's parameters (as the
-    benchmark runs them), four 512-image chunks, alternate chunks on the second
-    stream, captured graphs; bins read from inside each sampled image's chunk,
-    envs from even and odd chunks."""
+    benchmark runs them), two 1024-image chunks from the 48 GiB working budget,
+    the second chunk on the second stream, captured graphs; bins read from
+    inside each sampled image's chunk, envs from both chunks."""
     scene, batch = synth.make_config(2)
     sid = _upload(R, scene)
     from paper_2604_25459_amd import gsr
